@@ -1,0 +1,367 @@
+/*
+ * lsp_oracle.c -- plain, slow, FP64 CPU oracle for the Lomb-Scargle periodogram.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; it exists so that tests, the smoke check and the CPU-baseline
+ * leg of the benchmark have an independent statement of what the method
+ * computes.  It shares no code, header, constant or table with the GPU path.
+ *
+ * What it computes (Gowanlock et al., arXiv 2105.04006, Section 2):
+ *   - the magnitudes are made zero-mean first (Section 2, first paragraph);
+ *   - tau from Eq. 1:  tan(2 w tau) = sum_j sin(2 w t_j) / sum_j cos(2 w t_j);
+ *   - the power from Eq. 2, literally, as a second pass over the series:
+ *       P_LS = 1/2 [ (sum X_j cos w(t_j-tau))^2 / sum cos^2 w(t_j-tau)
+ *                  + (sum X_j sin w(t_j-tau))^2 / sum sin^2 w(t_j-tau) ];
+ *   - the uniform half-open grid of Section 2: df = (f_max - f_min)/N_f,
+ *     f_i = f_min + i*df, i = 0..N_f-1;
+ *   - the best period from the argmax of the periodogram, first index on ties,
+ *     p = 2 pi / w (Section 3.3; equivalently 1/f when f is in cycles).
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - normalised power P_norm = 2 P_LS / sum_j (y_j - ybar)^2, which lies in [0,1];
+ *   - a term of Eq. 2 whose denominator is <= 1e-12 * N_t is dropped (this is the
+ *     projection onto the non-vanishing regressor; it makes w = 0 give P = 0);
+ *   - w = 0 gives tau = 0 (Eq. 1 is 0/0 there);
+ *   - an object with N_t < 2, or whose centred magnitudes have no variance
+ *     (S_yy <= 1e-20 * sum y^2), is DEGENERATE: power 0, peak index -1;
+ *   - an object with a non-finite time or magnitude is NONFINITE and a CSR range
+ *     that is negative, reversed or past the end is BADRANGE: power NaN, index -1.
+ *
+ * Sums use Neumaier's compensated summation so that the oracle is the more
+ * accurate side of every comparison.  Compile with -ffp-contract=off and no
+ * fast-math: every operation is the one written.
+ *
+ * Parallelism follows the paper's CPU port (Section 4.5): a static split over
+ * frequencies for one object, dynamic scheduling over objects for a batch.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORA_OK 0
+#define ORA_DEGENERATE 1
+#define ORA_BADRANGE 2
+#define ORA_NONFINITE 3
+
+#define ORA_UNIT_CYCLES 0
+#define ORA_UNIT_ANGULAR 1
+
+static const double ORA_TWO_PI = 6.283185307179586476925286766559;
+
+typedef struct {
+    int64_t index;
+    double freq;
+    double period;
+    double power;
+    int32_t status;
+    int32_t pad;
+} ora_peak;
+
+/* Neumaier compensated accumulator. */
+typedef struct {
+    double s;
+    double c;
+} ora_sum;
+
+static void ora_sum_add(ora_sum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double ora_sum_get(const ora_sum *a) { return a->s + a->c; }
+
+/* Section 2: df = (f_max - f_min) / N_f and f_i = f_min + i * df. */
+double ora_grid_freq(double f_min, double f_max, int64_t n_f, int64_t i)
+{
+    double df = (f_max - f_min) / (double)n_f;
+    return f_min + df * (double)i;
+}
+
+/* Section 2: w = 2 pi f.  The paper's code takes w directly (angular unit). */
+double ora_omega(double f, int32_t unit)
+{
+    if (unit == ORA_UNIT_ANGULAR)
+        return f;
+    return ORA_TWO_PI * f;
+}
+
+/* Section 3.3: period from the peak frequency, p = 2 pi / w. */
+double ora_period(double f, int32_t unit)
+{
+    return ORA_TWO_PI / ora_omega(f, unit);
+}
+
+/*
+ * Mean removal (Section 2 assumes zero-mean magnitudes).  Writes the centred
+ * magnitudes to yp[n] and their sum of squares to *syy; returns the object's
+ * status.
+ */
+int32_t ora_prep(const double *t, const double *y, int64_t n, int32_t subtract_mean,
+                 double *yp, double *syy)
+{
+    int64_t j;
+    ora_sum sy = {0.0, 0.0}, sq = {0.0, 0.0}, sraw = {0.0, 0.0};
+    double ybar = 0.0;
+    *syy = 0.0;
+    for (j = 0; j < n; j++)
+        if (!isfinite(t[j]) || !isfinite(y[j]))
+            return ORA_NONFINITE;
+    if (n < 2) {
+        for (j = 0; j < n; j++)
+            yp[j] = 0.0;
+        return ORA_DEGENERATE;
+    }
+    if (subtract_mean) {
+        for (j = 0; j < n; j++)
+            ora_sum_add(&sy, y[j]);
+        ybar = ora_sum_get(&sy) / (double)n;
+    }
+    for (j = 0; j < n; j++) {
+        yp[j] = y[j] - ybar;
+        ora_sum_add(&sq, yp[j] * yp[j]);
+        ora_sum_add(&sraw, y[j] * y[j]);
+    }
+    *syy = ora_sum_get(&sq);
+    if (*syy <= 1e-20 * ora_sum_get(&sraw) || *syy == 0.0)
+        return ORA_DEGENERATE;
+    return ORA_OK;
+}
+
+/* Eq. 1: tau = atan2(sum sin 2wt, sum cos 2wt) / (2w); tau = 0 at w = 0. */
+double ora_tau(const double *t, int64_t n, double w)
+{
+    int64_t j;
+    ora_sum ss = {0.0, 0.0}, sc = {0.0, 0.0};
+    if (w == 0.0)
+        return 0.0;
+    for (j = 0; j < n; j++) {
+        ora_sum_add(&ss, sin(2.0 * w * t[j]));
+        ora_sum_add(&sc, cos(2.0 * w * t[j]));
+    }
+    return atan2(ora_sum_get(&ss), ora_sum_get(&sc)) / (2.0 * w);
+}
+
+/*
+ * Eq. 2 at a given tau: the second pass over the series.  Returns P_LS and,
+ * when sums != NULL, stores {YC, YS, CC, SS} = {sum y cos, sum y sin,
+ * sum cos^2, sum sin^2} of the shifted phase w (t_j - tau).
+ */
+double ora_pls(const double *t, const double *yp, int64_t n, double w, double tau, double *sums)
+{
+    int64_t j;
+    ora_sum yc = {0.0, 0.0}, ys = {0.0, 0.0}, cc = {0.0, 0.0}, ss = {0.0, 0.0};
+    double YC, YS, CC, SS, p;
+    for (j = 0; j < n; j++) {
+        double arg = w * (t[j] - tau);
+        double c = cos(arg);
+        double s = sin(arg);
+        ora_sum_add(&yc, yp[j] * c);
+        ora_sum_add(&ys, yp[j] * s);
+        ora_sum_add(&cc, c * c);
+        ora_sum_add(&ss, s * s);
+    }
+    YC = ora_sum_get(&yc);
+    YS = ora_sum_get(&ys);
+    CC = ora_sum_get(&cc);
+    SS = ora_sum_get(&ss);
+    if (sums) {
+        sums[0] = YC;
+        sums[1] = YS;
+        sums[2] = CC;
+        sums[3] = SS;
+    }
+    p = 0.0;
+    if (CC > 1e-12 * (double)n)
+        p += YC * YC / CC;
+    if (SS > 1e-12 * (double)n)
+        p += YS * YS / SS;
+    return 0.5 * p;
+}
+
+/* Power of one object at one frequency (centred magnitudes, known S_yy). */
+static double ora_power_one(const double *t, const double *yp, int64_t n, double syy, double f,
+                            int32_t unit, int32_t normalize)
+{
+    double w = ora_omega(f, unit);
+    double tau = ora_tau(t, n, w);
+    double pls = ora_pls(t, yp, n, w, tau, NULL);
+    if (normalize)
+        return 2.0 * pls / syy;
+    return pls;
+}
+
+/* Section 3.3: argmax of the periodogram, first (lowest) index on ties. */
+int64_t ora_argmax(const double *p, int64_t n)
+{
+    int64_t i, best = -1;
+    double bp = 0.0;
+    for (i = 0; i < n; i++) {
+        if (isnan(p[i]))
+            continue;
+        if (best < 0 || p[i] > bp) {
+            best = i;
+            bp = p[i];
+        }
+    }
+    return best;
+}
+
+static void ora_fill_peak(ora_peak *pk, int32_t status, const double *pgram, int64_t n_f,
+                          double f_min, double f_max, int32_t unit)
+{
+    pk->status = status;
+    pk->pad = 0;
+    pk->index = -1;
+    pk->freq = NAN;
+    pk->period = NAN;
+    pk->power = (status == ORA_DEGENERATE) ? 0.0 : NAN;
+    if (status != ORA_OK)
+        return;
+    pk->index = ora_argmax(pgram, n_f);
+    if (pk->index < 0)
+        return;
+    pk->freq = ora_grid_freq(f_min, f_max, n_f, pk->index);
+    pk->period = ora_period(pk->freq, unit);
+    pk->power = pgram[pk->index];
+}
+
+static void ora_fill_row(double *row, int64_t n_f, int32_t status)
+{
+    int64_t i;
+    double v = (status == ORA_DEGENERATE) ? 0.0 : NAN;
+    for (i = 0; i < n_f; i++)
+        row[i] = v;
+}
+
+static int ora_threads(int32_t nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/*
+ * Single-object mode (Section 3.3): the whole periodogram of one series.
+ * yp is caller scratch of n doubles.  The frequency loop is split statically
+ * over threads as in the paper's CPU port.  pgram[n_f] must be non-NULL.
+ */
+int32_t ora_single(const double *t, const double *y, int64_t n, double f_min, double f_max,
+                   int64_t n_f, int32_t unit, int32_t normalize, int32_t subtract_mean,
+                   double *yp, double *pgram, ora_peak *peak, int32_t nthreads)
+{
+    double syy = 0.0;
+    int64_t i;
+    int32_t st = ora_prep(t, y, n, subtract_mean, yp, &syy);
+    if (st != ORA_OK) {
+        ora_fill_row(pgram, n_f, st);
+    } else {
+#pragma omp parallel for schedule(static) num_threads(ora_threads(nthreads))
+        for (i = 0; i < n_f; i++)
+            pgram[i] = ora_power_one(t, yp, n, syy, ora_grid_freq(f_min, f_max, n_f, i), unit,
+                                     normalize);
+    }
+    if (peak)
+        ora_fill_peak(peak, st, pgram, n_f, f_min, f_max, unit);
+    return st;
+}
+
+static int32_t ora_range_status(const int64_t *offsets, int64_t o, int64_t n_obs)
+{
+    int64_t a = offsets[o], b = offsets[o + 1];
+    if (a < 0 || b < a || b > n_obs)
+        return ORA_BADRANGE;
+    return ORA_OK;
+}
+
+/*
+ * Batch mode (Section 3.4): object o owns observations [offsets[o], offsets[o+1]).
+ * pgram is [n_obj * n_f] row-major, or NULL for peaks only; row_scratch must
+ * then hold n_threads * n_f doubles.  yp_scratch holds n_obs doubles.
+ * Objects are scheduled dynamically over threads as in the paper's CPU port.
+ */
+int32_t ora_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                  const double *y, double f_min, double f_max, int64_t n_f, int32_t unit,
+                  int32_t normalize, int32_t subtract_mean, double *yp_scratch, double *pgram,
+                  double *row_scratch, ora_peak *peaks, int32_t nthreads)
+{
+    int64_t o;
+#pragma omp parallel for schedule(dynamic) num_threads(ora_threads(nthreads))
+    for (o = 0; o < n_obj; o++) {
+        int tid = 0;
+        double *row;
+        int32_t st;
+        int64_t i;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        row = pgram ? pgram + o * n_f : row_scratch + (int64_t)tid * n_f;
+        st = ora_range_status(offsets, o, n_obs);
+        if (st == ORA_OK) {
+            int64_t a = offsets[o], n = offsets[o + 1] - offsets[o];
+            double syy = 0.0;
+            st = ora_prep(t + a, y + a, n, subtract_mean, yp_scratch + a, &syy);
+            if (st == ORA_OK)
+                for (i = 0; i < n_f; i++)
+                    row[i] = ora_power_one(t + a, yp_scratch + a, n, syy,
+                                           ora_grid_freq(f_min, f_max, n_f, i), unit, normalize);
+        }
+        if (st != ORA_OK)
+            ora_fill_row(row, n_f, st);
+        if (peaks)
+            ora_fill_peak(&peaks[o], st, row, n_f, f_min, f_max, unit);
+    }
+    return ORA_OK;
+}
+
+/*
+ * Power at selected (object, bin) pairs, for spot checks at sizes where the
+ * whole periodogram is too slow to compute here.  out[k] is the power of
+ * object obj[k] at grid index bin[k] (0 for DEGENERATE objects, NaN for
+ * BADRANGE/NONFINITE ones).  Returns -1 if scratch memory cannot be had.
+ */
+int32_t ora_eval_bins(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                      const double *y, double f_min, double f_max, int64_t n_f, int32_t unit,
+                      int32_t normalize, int32_t subtract_mean, const int64_t *obj,
+                      const int64_t *bin, int64_t n_req, double *out, int32_t nthreads)
+{
+    int64_t k;
+    int32_t failed = 0;
+    (void)n_obj;
+#pragma omp parallel for schedule(dynamic) num_threads(ora_threads(nthreads))
+    for (k = 0; k < n_req; k++) {
+        int64_t o = obj[k];
+        int32_t st = ora_range_status(offsets, o, n_obs);
+        double v = NAN;
+        if (st == ORA_OK) {
+            int64_t a = offsets[o], n = offsets[o + 1] - offsets[o];
+            double syy = 0.0;
+            double *yp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            if (!yp) {
+#pragma omp atomic write
+                failed = 1;
+            } else {
+                st = ora_prep(t + a, y + a, n, subtract_mean, yp, &syy);
+                if (st == ORA_OK)
+                    v = ora_power_one(t + a, yp, n, syy, ora_grid_freq(f_min, f_max, n_f, bin[k]),
+                                      unit, normalize);
+                else if (st == ORA_DEGENERATE)
+                    v = 0.0;
+                free(yp);
+            }
+        }
+        out[k] = v;
+    }
+    return failed ? -1 : ORA_OK;
+}

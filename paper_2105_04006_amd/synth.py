@@ -1,0 +1,195 @@
+"""Seeded synthetic light curves shaped like the paper's workloads.
+
+This module only draws inputs; it holds none of the periodogram's arithmetic,
+so both the GPU path's tests and the CPU oracle's tests can use it.
+
+The paper's own datasets (a 3,554-point synthetic object and ~1,000 ZTF-like
+synthetic asteroids, Section 4.2) are not available, so these stand in for
+them: times uniform over a 10-year baseline with a seasonal gap every year,
+sinusoidal light curves with asteroid-like periods (0.1-1 d) plus Gaussian
+noise, and CSR-packed batches with a spread of series lengths.
+
+Sampling: "t uniform in [0, 3650) d, dropping t mod 365 in [120, 240]" is drawn
+exactly, without rejection, by drawing u uniform over the 2,450 allowed days and
+mapping it onto the allowed intervals of its year; this has the same
+distribution as rejection sampling and yields exactly N_t points.
+
+Streams: per-object parameters, times, noise and mixture labels come from
+separate PCG64 streams, each consumed in object order, so the first k objects
+of a workload are identical whether k or all objects are generated.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 2105040060
+SPAN_DAYS = 3650.0
+YEAR_DAYS = 365.0
+GAP = (120.0, 240.0)
+AMP = 0.3
+NOISE_SIGMA = 0.05
+PERIOD_RANGE = (0.1, 1.0)
+
+# name -> (n_obj, (N_t min, N_t max), (f_min, f_max) cycles/day, N_f, mixture, seed id)
+WORKLOADS = {
+    "single_256": (1, (256, 256), (1.0, 12.0), 10_000, "sine", 1),
+    "single_4096": (1, (4096, 4096), (0.5, 24.0), 500_000, "sine", 2),
+    "batch_10k": (10_000, (50, 1000), (1.0, 12.0), 100_000, "sine", 3),
+    "learned_100k": (100_000, (50, 500), (1.0, 12.0), 200_000, "sine", 4),
+    "lsst_200k": (200_000, (20, 500), (0.5, 24.0), 250_000, "lsst", 5),
+}
+
+KIND_SINE, KIND_TWO_HARMONIC, KIND_NOISE = 0, 1, 2
+
+
+@dataclass
+class Workload:
+    name: str
+    offsets: np.ndarray  # int64 [n_obj + 1]
+    t: np.ndarray  # float64 [n_obs], days, ascending within each object
+    y: np.ndarray  # float64 [n_obs], magnitudes
+    f_min: float
+    f_max: float
+    n_f: int
+    unit: int = 0  # 0: cycles per day
+    true_freq: np.ndarray = field(default=None)  # cycles/day, NaN for pure noise
+    kind: np.ndarray = field(default=None)  # KIND_* per object
+    seed: int = 0
+
+    @property
+    def n_obj(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def n_obs(self) -> int:
+        return len(self.t)
+
+    @property
+    def n_t(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    @property
+    def evals(self) -> int:
+        return int(self.n_obs) * int(self.n_f)
+
+    def obj(self, o):
+        a, b = self.offsets[o], self.offsets[o + 1]
+        return self.t[a:b], self.y[a:b]
+
+    def subset(self, k: int) -> "Workload":
+        """The first k objects (identical to generating only k)."""
+        off = self.offsets[: k + 1].copy()
+        n = off[-1]
+        return Workload(self.name, off, self.t[:n].copy(), self.y[:n].copy(), self.f_min,
+                        self.f_max, self.n_f, self.unit, self.true_freq[:k].copy(),
+                        self.kind[:k].copy(), self.seed)
+
+
+def seasonal_times(u: np.ndarray) -> np.ndarray:
+    """Map u in [0, 2450) onto [0, 3650) minus the yearly gap [120, 240]."""
+    keep = YEAR_DAYS - (GAP[1] - GAP[0])  # 245 allowed days per year
+    yr = np.floor(u / keep)
+    r = u - yr * keep
+    t = np.where(r < GAP[0], yr * YEAR_DAYS + r, yr * YEAR_DAYS + GAP[1] + (r - GAP[0]))
+    return t
+
+
+def in_gap(t: np.ndarray) -> np.ndarray:
+    m = np.mod(t, YEAR_DAYS)
+    return (m >= GAP[0]) & (m <= GAP[1])
+
+
+def _draw_times(rng: np.random.Generator, n: int) -> np.ndarray:
+    keep_total = (SPAN_DAYS / YEAR_DAYS) * (YEAR_DAYS - (GAP[1] - GAP[0]))
+    t = seasonal_times(rng.random(n) * keep_total)
+    bad = in_gap(t) | (t >= SPAN_DAYS)
+    while bad.any():  # only boundary round-off can land here; redraw those points
+        t[bad] = seasonal_times(rng.random(int(bad.sum())) * keep_total)
+        bad = in_gap(t) | (t >= SPAN_DAYS)
+    return t
+
+
+def _sort_segments(t: np.ndarray, offsets: np.ndarray, chunk: int = 8192) -> np.ndarray:
+    """Sort t ascending within each CSR segment (exact; padded 2-D sorts per chunk)."""
+    out = np.empty_like(t)
+    n_obj = len(offsets) - 1
+    for c0 in range(0, n_obj, chunk):
+        c1 = min(n_obj, c0 + chunk)
+        lens = np.diff(offsets[c0:c1 + 1])
+        width = int(lens.max()) if len(lens) else 0
+        if width == 0:
+            continue
+        col = np.arange(width)
+        mask = col[None, :] < lens[:, None]
+        pad = np.full((c1 - c0, width), np.inf)
+        pad[mask] = t[offsets[c0]:offsets[c1]]
+        pad.sort(axis=1)
+        out[offsets[c0]:offsets[c1]] = pad[mask]
+    return out
+
+
+def make_workload(name: str, n_obj: int | None = None, seed: int | None = None) -> Workload:
+    """Generate a named workload (optionally only its first n_obj objects)."""
+    full_obj, (nt_lo, nt_hi), (f_min, f_max), n_f, mix, sid = WORKLOADS[name]
+    seed = SEED_BASE + sid if seed is None else int(seed)
+    k = full_obj if n_obj is None else int(n_obj)
+    ss = np.random.SeedSequence(seed)
+    r_len, r_par, r_t, r_noise = (np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(4))
+
+    n_t = r_len.integers(nt_lo, nt_hi + 1, size=full_obj)[:k].astype(np.int64)
+    # per-object parameters, drawn for the full population so prefixes agree
+    logp = r_par.uniform(np.log10(PERIOD_RANGE[0]), np.log10(PERIOD_RANGE[1]), size=full_obj)
+    phi = r_par.uniform(0.0, 2.0 * np.pi, size=full_obj)
+    u_kind = r_par.random(full_obj)
+    ratio = r_par.uniform(0.1, 0.5, size=full_obj)
+    phi2 = r_par.uniform(0.0, 2.0 * np.pi, size=full_obj)
+    period = (10.0 ** logp)[:k]
+    phi, u_kind, ratio, phi2 = phi[:k], u_kind[:k], ratio[:k], phi2[:k]
+    if mix == "lsst":
+        kind = np.where(u_kind < 0.6, KIND_SINE,
+                        np.where(u_kind < 0.9, KIND_TWO_HARMONIC, KIND_NOISE)).astype(np.int32)
+    else:
+        kind = np.full(k, KIND_SINE, dtype=np.int32)
+
+    offsets = np.zeros(k + 1, dtype=np.int64)
+    np.cumsum(n_t, out=offsets[1:])
+    n_obs = int(offsets[-1])
+    owner = np.repeat(np.arange(k, dtype=np.int64), n_t)
+    t = _sort_segments(_draw_times(r_t, n_obs), offsets)
+
+    P = period[owner]
+    y = AMP * np.sin(2.0 * np.pi * t / P + phi[owner])
+    two = kind[owner] == KIND_TWO_HARMONIC
+    y = y + np.where(two, ratio[owner] * AMP * np.sin(4.0 * np.pi * t / P + phi2[owner]), 0.0)
+    y = np.where(kind[owner] == KIND_NOISE, 0.0, y)
+    y = y + r_noise.normal(0.0, NOISE_SIGMA, size=n_obs)
+
+    true_freq = np.where(kind == KIND_NOISE, np.nan, 1.0 / period)
+    return Workload(name, offsets, t, y, float(f_min), float(f_max), int(n_f), 0, true_freq, kind,
+                    seed)
+
+
+def pack(series) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """CSR-pack a list of (t, y) pairs into (offsets, t, y)."""
+    n_t = np.array([len(s[0]) for s in series], dtype=np.int64)
+    offsets = np.zeros(len(series) + 1, dtype=np.int64)
+    np.cumsum(n_t, out=offsets[1:])
+    t = np.concatenate([np.asarray(s[0], np.float64) for s in series]) if len(series) else np.zeros(0)
+    y = np.concatenate([np.asarray(s[1], np.float64) for s in series]) if len(series) else np.zeros(0)
+    return offsets, t, y
+
+
+def sine_object(n_t: int, seed: int, period: float | None = None, sigma: float = NOISE_SIGMA,
+                amp: float = AMP):
+    """One seasonal-cadence sinusoid; returns (t, y, true frequency in cycles/day)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if period is None:
+        period = 10.0 ** rng.uniform(-1.0, 0.0)
+    phi = rng.uniform(0.0, 2.0 * np.pi)
+    t = np.sort(_draw_times(rng, n_t))
+    y = amp * np.sin(2.0 * np.pi * t / period + phi)
+    if sigma > 0:
+        y = y + rng.normal(0.0, sigma, size=n_t)
+    return t, y, 1.0 / period

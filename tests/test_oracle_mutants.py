@@ -1,0 +1,56 @@
+"""Each plausible slip planted in a copy of the oracle trips at least one pin.
+
+The mutants are built on the CPU from the oracle's source with one textual
+change each (a dropped term, a wrong sign, transposed operands, an off-by-one
+grid index, ...).  This shows that the pins in oracle_pins.py constrain every
+part of the oracle's arithmetic, not just its overall shape.
+"""
+import os
+
+import pytest
+
+import oracle
+from oracle_pins import ALL_PINS
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "lsp_oracle.c")
+
+MUTANTS = {
+    "dropped_sine_term": ("p += YS * YS / SS;", "p += 0.0;"),
+    "dropped_cosine_term": ("p += YC * YC / CC;", "p += 0.0;"),
+    "wrong_sign_shift": ("double arg = w * (t[j] - tau);", "double arg = w * (t[j] + tau);"),
+    "tau_missing_factor_two": ("/ (2.0 * w);", "/ w;"),
+    "atan2_transposed": ("atan2(ora_sum_get(&ss), ora_sum_get(&sc))",
+                         "atan2(ora_sum_get(&sc), ora_sum_get(&ss))"),
+    "grid_off_by_one": ("return f_min + df * (double)i;", "return f_min + df * (double)(i + 1);"),
+    "grid_closed_interval": ("double df = (f_max - f_min) / (double)n_f;",
+                             "double df = (f_max - f_min) / (double)(n_f - 1);"),
+    "mean_not_removed": ("ybar = ora_sum_get(&sy) / (double)n;", "ybar = 0.0;"),
+    "normalisation_missing_two": ("return 2.0 * pls / syy;", "return pls / syy;"),
+    "omega_missing_two_pi": ("return ORA_TWO_PI * f;", "return f;"),
+    "argmax_last_tie": ("if (best < 0 || p[i] > bp) {", "if (best < 0 || p[i] >= bp) {"),
+    "cos_denominator_from_sine": ("ora_sum_add(&cc, c * c);", "ora_sum_add(&cc, s * s);"),
+    "swapped_numerators": ("ora_sum_add(&yc, yp[j] * c);", "ora_sum_add(&yc, yp[j] * s);"),
+    "no_degenerate_term_rule": ("if (SS > 1e-12 * (double)n)", "if (1)"),
+    "period_missing_two_pi": ("return ORA_TWO_PI / ora_omega(f, unit);",
+                              "return 1.0 / ora_omega(f, unit);"),
+    "window_single_angle": ("ora_sum_add(&ss, sin(2.0 * w * t[j]));",
+                            "ora_sum_add(&ss, sin(w * t[j]));"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    lib = oracle.compile_source(str(path), str(tmp_path / "libmutant.so"))
+    ora = oracle.Oracle(lib)
+    caught = []
+    for pin in ALL_PINS:
+        try:
+            pin(ora)
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"no pin catches mutant {name}"
