@@ -1,0 +1,218 @@
+"""Benchmark of the Lomb-Scargle periodogram hot path on one MI355X.
+
+Default workload (single_4096): one object with N_t = 4,096 seasonal-cadence
+observations, N_f = 500,000 frequencies over [0.5, 24) cycles/day, full FP32
+periodogram (2 MB) plus the peak.  One step = one lsp_single call of the FP32
+form (prep, main kernel, FP64 fix-up check, combine, peak), inputs resident in
+HBM.  The plain FP64 form is timed on the same input for the "vs plain FP64
+kernel" comparison, and the two periodograms are compared for peak-bin
+agreement.  The oracle (CPU, FP64) is timed on a bounded sample of the same
+workload on this host's cores.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LS obs×freq evals/s and objects/s vs plain FP64 kernel at peak-bin agreement"
+# FP32 form, first-order angle-addition recurrence: per eval 4 FMA for the
+# sums (8 flops) + 2 mul + 2 FMA for the rotation (6 flops).
+FLOPS_PER_EVAL_FP32P = 14
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 2.4 GHz x 64 flops/clock/SIMD
+# (32 FMA lanes per clock), the published 157.3 TFLOP/s.
+PEAK_FP32_TFLOPS = 256 * 4 * 2.4e9 * 64 / 1e12
+# Per eval, as compiled for gfx950 with K = 16 frequencies per lane: 124 FP32
+# FMA/mul for the sums and rotations plus ~9 per-observation instructions
+# (FP64 phase, cvt, 2 transcendentals, moves) shared by the lane's 16 evals.
+VALU_OPS_PER_EVAL = 133 / 16
+K_PER_LANE = 16
+KERNEL_SOURCES = ["paper_2105_04006_amd/csrc/lsp_fp32p.hip",
+                  "paper_2105_04006_amd/csrc/lsp_common.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fp32p_single_4096_traffic.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, target_evals, threads):
+    """The oracle on every m-th bin of the same object (a bounded sample)."""
+    import oracle
+
+    stride = max(1, int(round(w.evals / target_evals)))
+    bins = np.arange(0, w.n_f, stride, dtype=np.int64)
+    objs = np.zeros(len(bins), dtype=np.int64)
+    oracle.default()
+    t0 = time.perf_counter()
+    oracle.eval_bins(w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, objs, bins, threads=threads)
+    dt = time.perf_counter() - t0
+    evals = len(bins) * w.n_obs
+    return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th of the {w.n_f} bins ({len(bins)} bins x {w.n_obs} obs, "
+                      f"{evals:.3g} evals) of the same object, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="single_4096")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-evals", type=float, default=2e8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the periodogram of "
+              "independent objects would shard by object across GPUs, which this build does "
+              "not implement.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2105_04006_amd import lsp, synth
+
+    lsp.lib()  # fails loudly if the HIP library is not built
+    dev = torch.device("cuda:0")
+    w = synth.make_workload(args.workload)
+    single = w.n_obj == 1
+    log(f"[bench] workload {w.name}: n_obj={w.n_obj} n_obs={w.n_obs} n_f={w.n_f} "
+        f"evals={w.evals:.3e}")
+    t = torch.as_tensor(w.t, device=dev)
+    y = torch.as_tensor(w.y, device=dev)
+    off = None if single else torch.as_tensor(w.offsets, device=dev)
+    kw = dict(offsets=off, pgram=single, peaks=True)
+    p32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P,
+                          schedule=lsp.SCHED_AUTO, **kw)
+    p64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, **kw)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    for _ in range(args.warmup):
+        p32()
+    p64()
+    torch.cuda.synchronize()
+    log("[bench] warm-up done")
+    ms32 = timed(p32, args.steps)
+    log(f"[bench] fp32p {ms32:.4f} ms/step")
+    steps64 = max(3, args.steps // 8)
+    ms64 = timed(p64, steps64)
+    log(f"[bench] fp64 {ms64:.4f} ms/step ({steps64} steps)")
+
+    # dominant kernel's own device time, from events the library records
+    # around the main kernel on its launch stream
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+    for a, b in pairs:
+        a.record()
+        b.record()
+    torch.cuda.synchronize()
+    for a, b in pairs:
+        lsp.set_stage_events(a.cuda_event, b.cuda_event)
+        p32()
+    lsp.set_stage_events(None, None)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in pairs]))
+    log(f"[bench] fp32p main kernel {k_ms:.4f} ms/launch")
+
+    pk32, pk64 = p32.peaks(), p64.peaks()
+    agree = np.abs(pk32["index"] - pk64["index"]) <= 1
+    if single:
+        d = (p32.pgram.double() - p64.pgram.double()).abs().max().item()
+    else:
+        d = float(np.max(np.abs(pk32["power"] - pk64["power"])))
+
+    evals = w.evals
+    value = evals / (ms32 * 1e-3)
+    achieved = FLOPS_PER_EVAL_FP32P * evals / (k_ms * 1e-3) / 1e12
+    valu_ops = VALU_OPS_PER_EVAL * evals / (k_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_obj": w.n_obj, "n_t": int(w.n_obs) if single else
+                   "U{%d..%d}" % (int(w.n_t.min()), int(w.n_t.max())), "n_obs": int(w.n_obs),
+                   "n_f": w.n_f, "f_range_cycles_per_day": [w.f_min, w.f_max],
+                   "form": "fp32 sums, fp64 phase reduction", "output": "pgram f32 + peak"
+                   if single else "peaks"},
+        "objects_per_s": w.n_obj / (ms32 * 1e-3),
+        "fp64_reference": {"evals_per_s": evals / (ms64 * 1e-3), "ms_per_step": ms64,
+                           "objects_per_s": w.n_obj / (ms64 * 1e-3)},
+        "speedup_vs_fp64": ms64 / ms32,
+        "peak_bin_agreement": float(agree.mean()),
+        "max_abs_dpower_vs_fp64": d,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": measured_traffic(),
+            "kernel": "fp32p_kernel",
+            "kernel_ms": k_ms,
+            "flops_per_eval": FLOPS_PER_EVAL_FP32P,
+            "valu_lane_ops_per_s": valu_ops,
+            "valu_issue_frac": valu_ops / (PEAK_FP32_TFLOPS * 1e12 / 2),
+            "transcendentals_per_s": 2 * evals / K_PER_LANE / (k_ms * 1e-3),
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        log(f"[bench] oracle baseline on {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_evals, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,331 @@
+// lsp_api.hip -- host side of the C ABI declared in include/lsp.h.
+//
+// Validates arguments on the host (nothing is enqueued on error), resolves the
+// launch configuration from the options and the problem shape, carves the
+// caller's workspace, and enqueues prep -> main kernel -> (combine) -> peaks on
+// the caller's stream.  No device memory is allocated and the device is never
+// synchronised, so a call can be captured into a HIP graph.
+#include <math.h>
+#include <stdint.h>
+
+#include "lsp_common.h"
+
+namespace lsp {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxGrid = ((int64_t)1 << 31) - 1;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Config {
+    int form;
+    int k;
+    int waves;
+    int split;
+    int persistent;
+    int64_t tile_freqs;
+    int64_t tiles_per_obj;
+    int64_t n_items;
+    int64_t rec_per_obj;
+};
+
+struct Layout {
+    size_t meta, tau, yp64, yp32, step, rec, ill, part, queue, total;
+};
+
+bool valid_grid(const lsp_grid* g) {
+    return g && isfinite(g->f_min) && isfinite(g->f_max) && g->f_max > g->f_min && g->n_f >= 1 &&
+           (g->unit == LSP_UNIT_CYCLES || g->unit == LSP_UNIT_ANGULAR) &&
+           isfinite((g->f_max - g->f_min) / (double)g->n_f);
+}
+
+bool is_bool(int32_t v) { return v == 0 || v == 1; }
+
+lsp_status valid_options(const lsp_options* o) {
+    if (!(o->form == LSP_FORM_FP64 || o->form == LSP_FORM_FP32P)) return LSP_EINVAL;
+    if (!is_bool(o->normalize) || !is_bool(o->subtract_mean)) return LSP_EINVAL;
+    if (!(o->pgram_dtype == LSP_PGRAM_F32 || o->pgram_dtype == LSP_PGRAM_F64)) return LSP_EINVAL;
+    if (!(o->waves_per_wg == 0 || o->waves_per_wg == 1 || o->waves_per_wg == 2 ||
+          o->waves_per_wg == 4))
+        return LSP_EINVAL;
+    if (o->form == LSP_FORM_FP64) {
+        if (!(o->k_per_lane == 0 || o->k_per_lane == 1 || o->k_per_lane == 2 ||
+              o->k_per_lane == 4))
+            return LSP_EINVAL;
+    } else if (!(o->k_per_lane == 0 || o->k_per_lane == 4 || o->k_per_lane == 8 ||
+                 o->k_per_lane == 16 || o->k_per_lane == 32)) {
+        return LSP_EINVAL;
+    }
+    if (o->t_split < 0 || o->t_split > 64) return LSP_EINVAL;
+    if (o->schedule < LSP_SCHED_AUTO || o->schedule > LSP_SCHED_PERSISTENT) return LSP_EINVAL;
+    return LSP_OK;
+}
+
+// Launch configuration: a pure function of the shape and the options, so that
+// lsp_workspace_bytes and the call agree.
+lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_options* o,
+                   Config* c) {
+    const int64_t n_f = g->n_f;
+    c->form = o->form;
+    c->persistent = 0;
+    c->split = 1;
+    if (o->form == LSP_FORM_FP64) {
+        c->k = o->k_per_lane ? o->k_per_lane : 2;
+        c->waves = o->waves_per_wg ? o->waves_per_wg : 4;
+        if (!o->waves_per_wg)
+            while ((int64_t)kWave * c->k * c->waves > n_f && c->waves > 1) c->waves /= 2;
+        if (!o->k_per_lane)
+            while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 1) c->k /= 2;
+        if (o->t_split > 1) return LSP_EUNSUPPORTED;
+        if (o->schedule == LSP_SCHED_PERSISTENT) return LSP_EUNSUPPORTED;
+    } else {
+        c->k = o->k_per_lane ? o->k_per_lane : 16;
+        c->waves = o->waves_per_wg ? o->waves_per_wg : 4;
+        if (!o->waves_per_wg)
+            while ((int64_t)kWave * c->k * c->waves > n_f && c->waves > 1) c->waves /= 2;
+        if (!o->k_per_lane)
+            while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 4) c->k /= 2;
+        c->persistent = o->schedule == LSP_SCHED_PERSISTENT ? 1 : 0;
+        if (o->t_split > 1) {
+            if (n_obj != 1) return LSP_EUNSUPPORTED;
+            c->split = o->t_split;
+        } else if (o->t_split == 0 && n_obj == 1) {
+            // Too few frequency tiles to occupy 1024 SIMDs with a few waves
+            // each: split the observation axis as well.
+            const int64_t tpw = (int64_t)kWave * c->k * c->waves;
+            const int64_t waves_total = ((n_f + tpw - 1) / tpw) * c->waves;
+            int64_t want = 4096 / (waves_total > 0 ? waves_total : 1);
+            int64_t cap = n_obs / kTile;
+            if (cap > 64) cap = 64;
+            if (want > cap) want = cap;
+            c->split = want > 1 ? (int)want : 1;
+        }
+    }
+    c->tile_freqs = (int64_t)kWave * c->k * c->waves;
+    c->tiles_per_obj = (n_f + c->tile_freqs - 1) / c->tile_freqs;
+    if (c->tiles_per_obj > kMaxGrid / n_obj / c->split) return LSP_EUNSUPPORTED;
+    c->n_items = n_obj * c->tiles_per_obj * c->split;
+    c->rec_per_obj = c->split > 1 ? (n_f + kCombineThreads - 1) / kCombineThreads : c->tiles_per_obj;
+    return LSP_OK;
+}
+
+Layout layout(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const Config& c) {
+    Layout L;
+    size_t off = 0;
+    const bool f32 = c.form == LSP_FORM_FP32P;
+    L.meta = off;
+    off += align_up((size_t)n_obj * sizeof(ObjMeta));
+    L.tau = off;
+    off += align_up((size_t)n_obs * sizeof(double));
+    L.yp64 = off;
+    off += align_up((size_t)n_obs * sizeof(double));
+    L.yp32 = off;
+    off += f32 ? align_up((size_t)n_obs * sizeof(float)) : 0;
+    L.step = off;
+    off += f32 ? align_up((size_t)n_obs * sizeof(float2)) : 0;
+    L.rec = off;
+    off += align_up((size_t)n_obj * (size_t)c.rec_per_obj * sizeof(PeakRec));
+    L.ill = off;
+    off += (f32 && c.split == 1) ? align_up((size_t)n_obj * (size_t)c.tiles_per_obj * 4) : 0;
+    L.part = off;
+    off += c.split > 1 ? align_up((size_t)c.split * 4 * (size_t)g->n_f * sizeof(float)) : 0;
+    L.queue = off;
+    off += kAlign;
+    L.total = off;
+    return L;
+}
+
+thread_local hipEvent_t t_main_begin = nullptr;
+thread_local hipEvent_t t_main_end = nullptr;
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+               const double* y, const lsp_grid* grid, const lsp_options* opt_in, void* pgram,
+               lsp_peak* peaks, void* ws, size_t ws_bytes, void* stream) {
+    if (!grid || !ws) return LSP_EINVAL;
+    if (n_obj < 1 || n_obs < 0) return LSP_EINVAL;
+    if (n_obs > 0 && (!t || !y)) return LSP_EINVAL;
+    if (!valid_grid(grid)) return LSP_EINVAL;
+    if (!pgram && !peaks) return LSP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return LSP_EINVAL;
+    const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
+    lsp_status st = valid_options(&opt);
+    if (st != LSP_OK) return st;
+    Config c;
+    st = resolve(n_obj, n_obs, grid, &opt, &c);
+    if (st != LSP_OK) return st;
+    const Layout L = layout(n_obj, n_obs, grid, c);
+    if (ws_bytes < L.total) return LSP_ENOMEM;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double df = (grid->f_max - grid->f_min) / (double)grid->n_f;
+    const double to_cyc = grid->unit == LSP_UNIT_CYCLES ? 1.0 : kInvTwoPi;
+    const bool f32 = c.form == LSP_FORM_FP32P;
+
+    PrepParams pp;
+    pp.offsets = offsets;
+    pp.t = t;
+    pp.y = y;
+    pp.n_obj = n_obj;
+    pp.n_obs = n_obs;
+    pp.subtract_mean = opt.subtract_mean;
+    pp.normalize = opt.normalize;
+    pp.step_cyc = f32 ? (double)kWave * df * to_cyc : 0.0;
+    pp.meta = at<ObjMeta>(ws, L.meta);
+    pp.tau = at<double>(ws, L.tau);
+    pp.yp64 = at<double>(ws, L.yp64);
+    pp.yp32 = f32 ? at<float>(ws, L.yp32) : nullptr;
+    pp.step = f32 ? at<float2>(ws, L.step) : nullptr;
+    if (launch_prep(pp, s) != hipSuccess) return LSP_EHIP;
+
+    MainParams mp;
+    mp.meta = pp.meta;
+    mp.tau = pp.tau;
+    mp.yp64 = pp.yp64;
+    mp.yp32 = pp.yp32;
+    mp.step = pp.step;
+    mp.f_min = grid->f_min;
+    mp.df = df;
+    mp.to_cyc = to_cyc;
+    mp.n_f = grid->n_f;
+    mp.n_obj = n_obj;
+    mp.tiles_per_obj = c.tiles_per_obj;
+    mp.n_items = c.n_items;
+    mp.n_split = c.split;
+    mp.pgram_f64 = opt.pgram_dtype == LSP_PGRAM_F64;
+    mp.pgram = pgram;
+    mp.rec = at<PeakRec>(ws, L.rec);
+    mp.ill = (f32 && c.split == 1) ? at<uint32_t>(ws, L.ill) : nullptr;
+    mp.part = c.split > 1 ? at<float>(ws, L.part) : nullptr;
+    mp.queue = at<unsigned int>(ws, L.queue);
+    mp.persistent = c.persistent;
+    mp.pad = 0;
+
+    if (f32 && c.persistent && launch_fill_u32(mp.queue, kXcds, 0u, s) != hipSuccess)
+        return LSP_EHIP;
+    if (t_main_begin && hipEventRecord(t_main_begin, s) != hipSuccess) return LSP_EHIP;
+    if (f32) {
+        if (launch_fp32p(mp, c.k, c.waves, s) != hipSuccess) return LSP_EHIP;
+    } else {
+        if (launch_fp64(mp, c.k, c.waves, s) != hipSuccess) return LSP_EHIP;
+    }
+    if (t_main_end && hipEventRecord(t_main_end, s) != hipSuccess) return LSP_EHIP;
+    if (f32) {
+        if (c.split == 1) {
+            FixupParams fp;
+            fp.meta = mp.meta;
+            fp.tau = mp.tau;
+            fp.yp64 = mp.yp64;
+            fp.ill = mp.ill;
+            fp.f_min = mp.f_min;
+            fp.df = df;
+            fp.to_cyc = to_cyc;
+            fp.n_f = mp.n_f;
+            fp.tiles_per_obj = c.tiles_per_obj;
+            fp.n_tiles = n_obj * c.tiles_per_obj;
+            fp.tile_freqs = c.tile_freqs;
+            fp.pgram_f64 = mp.pgram_f64;
+            fp.pad = 0;
+            fp.pgram = pgram;
+            fp.rec = mp.rec;
+            if (launch_fixup(fp, s) != hipSuccess) return LSP_EHIP;
+        } else {
+            CombineParams cp;
+            cp.meta = mp.meta;
+            cp.tau = mp.tau;
+            cp.yp64 = mp.yp64;
+            cp.part = mp.part;
+            cp.n_split = c.split;
+            cp.pgram_f64 = mp.pgram_f64;
+            cp.f_min = mp.f_min;
+            cp.df = df;
+            cp.to_cyc = to_cyc;
+            cp.n_f = mp.n_f;
+            cp.pgram = pgram;
+            cp.rec = mp.rec;
+            if (launch_combine(cp, s) != hipSuccess) return LSP_EHIP;
+        }
+    }
+
+    if (peaks) {
+        PeakParams kp;
+        kp.meta = mp.meta;
+        kp.rec = mp.rec;
+        kp.n_obj = n_obj;
+        kp.rec_per_obj = c.rec_per_obj;
+        kp.f_min = grid->f_min;
+        kp.df = df;
+        kp.unit = grid->unit;
+        kp.pad = 0;
+        kp.peaks = peaks;
+        if (launch_peaks(kp, s) != hipSuccess) return LSP_EHIP;
+    }
+    return LSP_OK;
+}
+
+}  // namespace
+}  // namespace lsp
+
+extern "C" {
+
+lsp_options lsp_default_options(void) {
+    lsp_options o = {};
+    o.form = LSP_FORM_FP64;
+    o.normalize = 1;
+    o.subtract_mean = 1;
+    o.pgram_dtype = LSP_PGRAM_F32;
+    return o;
+}
+
+size_t lsp_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                           const lsp_options* opt_in) {
+    if (n_obj < 1 || n_obs < 0 || !lsp::valid_grid(grid)) return 0;
+    const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
+    if (lsp::valid_options(&opt) != LSP_OK) return 0;
+    lsp::Config c;
+    if (lsp::resolve(n_obj, n_obs, grid, &opt, &c) != LSP_OK) return 0;
+    return lsp::layout(n_obj, n_obs, grid, c).total;
+}
+
+lsp_status lsp_single(const double* t, const double* y, int64_t n_t, const lsp_grid* grid,
+                      const lsp_options* opt, void* pgram, lsp_peak* peak, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+    if (n_t < 0) return LSP_EINVAL;
+    return lsp::run(nullptr, 1, n_t, t, y, grid, opt, pgram, peak, workspace, workspace_bytes,
+                    stream);
+}
+
+lsp_status lsp_batch(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                     const double* y, const lsp_grid* grid, const lsp_options* opt, void* pgram,
+                     lsp_peak* peaks, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!offsets) return LSP_EINVAL;
+    return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
+                    workspace_bytes, stream);
+}
+
+lsp_status lsp_set_stage_events(void* main_begin, void* main_end) {
+    if ((main_begin == nullptr) != (main_end == nullptr)) return LSP_EINVAL;
+    lsp::t_main_begin = static_cast<hipEvent_t>(main_begin);
+    lsp::t_main_end = static_cast<hipEvent_t>(main_end);
+    return LSP_OK;
+}
+
+const char* lsp_status_string(lsp_status status) {
+    switch (status) {
+        case LSP_OK: return "ok";
+        case LSP_EINVAL: return "invalid argument";
+        case LSP_ENOMEM: return "workspace too small";
+        case LSP_EHIP: return "HIP launch failed";
+        case LSP_EUNSUPPORTED: return "unsupported option combination";
+        default: return "unknown status";
+    }
+}
+
+int32_t lsp_version(void) { return 100; }
+
+}  // extern "C"

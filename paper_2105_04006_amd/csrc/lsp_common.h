@@ -1,0 +1,289 @@
+// lsp_common.h -- definitions shared by the library's HIP sources (device side
+// and host launchers).  Not part of the public interface (see include/lsp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lsp.h"
+
+namespace lsp {
+
+constexpr int kWave = 64;
+// Observations staged in LDS per pass of a workgroup over its object.
+constexpr int kTile = 256;
+constexpr int kPrepThreads = 256;
+constexpr int kCombineThreads = 256;
+constexpr int kXcds = 8;
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+// A term of Eq. 2 whose denominator is at most kDenEps * N_t is dropped: the
+// corresponding regressor vanishes on the data (w = 0, or every 2wt equal).
+constexpr double kDenEps = 1e-12;
+// An object whose centred magnitudes have sum of squares <= kVarEps * sum y^2
+// (or exactly 0) has no variance to explain.
+constexpr double kVarEps = 1e-20;
+// FP32 form: a bin whose smaller shifted denominator, N - |sum e^{2iwt}|, is
+// below this fraction of N is ill-conditioned in FP32 and is recomputed in FP64.
+constexpr float kIllTheta = 1.0f / 32.0f;
+
+// Per-object statistics written by the prep kernel.
+struct ObjMeta {
+    int64_t j0;      // first observation of the object in the packed arrays
+    int64_t n;       // number of observations
+    double ybar;     // mean removed from y (0 when the caller's y is used as is)
+    double syy;      // sum of squared centred magnitudes
+    double t0;       // time origin: mid-point of the object's time span
+    double scale;    // factor from P_LS to the reported power (2/S_yy or 1)
+    int32_t status;  // LSP_OBJ_*
+    int32_t pad[3];
+};
+static_assert(sizeof(ObjMeta) == 64, "ObjMeta layout");
+
+// Best (power, index) of one frequency tile; index -1 means none.
+struct PeakRec {
+    double p;
+    int64_t i;
+};
+
+// Frequency of grid index i, rounded exactly as f_min + df * i written out in
+// IEEE double (no fused multiply-add), so every path agrees on the grid.
+__device__ __forceinline__ double grid_freq(double f_min, double df, int64_t i) {
+    return __dadd_rn(f_min, __dmul_rn(df, (double)i));
+}
+
+// (p, i) ordering of the argmax: larger power wins, lower index on ties; NaN
+// never wins.
+__device__ __forceinline__ bool better(double p, int64_t i, double bp, int64_t bi) {
+    if (!(p == p)) return false;
+    if (bi < 0) return true;
+    return p > bp || (p == bp && i < bi);
+}
+
+__device__ __forceinline__ PeakRec wave_best(PeakRec r) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        PeakRec o;
+        o.p = __shfl_xor(r.p, off, kWave);
+        o.i = __shfl_xor(r.i, off, kWave);
+        if (better(o.p, o.i, r.p, r.i)) r = o;
+    }
+    return r;
+}
+
+// sin and cos of 2 pi (f_cyc * tau), with the phase reduced exactly to
+// [-1/2, 1/2] cycles in FP64 before the library call.
+__device__ __forceinline__ void sincos_cycles64(double f_cyc, double tau, double* s, double* c) {
+    double ph = f_cyc * tau;
+    ph -= rint(ph);
+    sincospi(2.0 * ph, s, c);
+}
+
+struct Sums64 {
+    double xc, xs, cc, ss, cs;  // sum y cos, y sin, cos^2, sin^2, cos sin at angle wt
+};
+
+__device__ __forceinline__ void sums64_add(Sums64& a, double yj, double s, double c) {
+    a.xc = fma(yj, c, a.xc);
+    a.xs = fma(yj, s, a.xs);
+    a.cc = fma(c, c, a.cc);
+    a.ss = fma(s, s, a.ss);
+    a.cs = fma(c, s, a.cs);
+}
+
+// Power from the single-pass sums in FP64.  Eq. 1 fixes the shift angle
+// a = w tau through the sums at angle 2wt, which are (cc - ss, 2 cs); Eq. 2's
+// shifted sums then follow from the angle-difference identities.  P_LS is
+// multiplied by `scale`.
+__device__ __forceinline__ double power64(const Sums64& s, double n, double scale) {
+    const double c2 = s.cc - s.ss;
+    const double s2 = 2.0 * s.cs;
+    const double two_a = atan2(s2, c2);
+    double sa, ca;
+    sincos(0.5 * two_a, &sa, &ca);
+    const double ycs = ca * s.xc + sa * s.xs;                 // sum y cos w(t - tau)
+    const double ysn = ca * s.xs - sa * s.xc;                 // sum y sin w(t - tau)
+    const double rot = c2 * (ca * ca - sa * sa) + s2 * (2.0 * sa * ca);  // sum cos 2w(t - tau)
+    const double tot = s.cc + s.ss;
+    const double dcos = 0.5 * (tot + rot);                    // sum cos^2 w(t - tau)
+    const double dsin = 0.5 * (tot - rot);                    // sum sin^2 w(t - tau)
+    double p = 0.0;
+    if (dcos > kDenEps * n) p += ycs * ycs / dcos;
+    if (dsin > kDenEps * n) p += ysn * ysn / dsin;
+    return 0.5 * p * scale;
+}
+
+// Power from FP32 sums (cc = sum cos^2, cs = sum cos sin; sum sin^2 = N - cc).
+// The shift needs no angle: with C2 + i S2 = sum e^{2iwt} and R = |C2 + i S2|,
+// the shifted denominators are (N + R)/2 and (N - R)/2 and the half-angle
+// formulas give cos and sin of w tau.  `ill` reports a bin whose N - R is too
+// small for FP32 to resolve.
+__device__ __forceinline__ float power32(float xc, float xs, float cc, float cs, float n,
+                                         float scale, bool& ill) {
+    const float c2 = fmaf(2.0f, cc, -n);
+    const float s2 = 2.0f * cs;
+    const float r = __builtin_amdgcn_sqrtf(fmaf(c2, c2, s2 * s2));
+    const float dp = n + r;
+    const float dm = n - r;
+    ill = !(dm > kIllTheta * n);
+    float ca = 1.0f, sa = 0.0f;
+    if (r > 0.0f) {
+        const float ir = __builtin_amdgcn_rcpf(r);
+        const float cos2a = c2 * ir, sin2a = s2 * ir;
+        if (cos2a >= 0.0f) {
+            ca = __builtin_amdgcn_sqrtf(0.5f + 0.5f * cos2a);
+            sa = 0.5f * sin2a * __builtin_amdgcn_rcpf(ca);
+        } else {
+            sa = copysignf(__builtin_amdgcn_sqrtf(0.5f - 0.5f * cos2a), sin2a);
+            ca = 0.5f * sin2a * __builtin_amdgcn_rcpf(sa);
+        }
+    }
+    const float ycs = fmaf(xc, ca, xs * sa);
+    const float ysn = fmaf(xs, ca, -(xc * sa));
+    float p = ycs * ycs * __builtin_amdgcn_rcpf(dp);
+    if (dm > 0.0f) p = fmaf(ysn * ysn, __builtin_amdgcn_rcpf(dm), p);
+    return p * scale;
+}
+
+// FP64 power of one (object, frequency) pair straight from the re-centred
+// series in global memory; used for FP32 bins flagged ill-conditioned.  Callers
+// invoke it from a single site placed after their FP32 accumulators are dead,
+// so inlining it does not raise the hot loop's register allocation.
+__device__ __forceinline__ double power64_bin(const ObjMeta& m, const double* __restrict__ tau,
+                                     const double* __restrict__ yp, double f_cyc) {
+    Sums64 a = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = m.j0; j < m.j0 + m.n; ++j) {
+        double s, c;
+        sincos_cycles64(f_cyc, tau[j], &s, &c);
+        sums64_add(a, yp[j], s, c);
+    }
+    return power64(a, (double)m.n, m.scale);
+}
+
+// Value written for every bin of an object whose status is not OK.
+__device__ __forceinline__ double fill_value(int32_t status) {
+    return status == LSP_OBJ_DEGENERATE ? 0.0 : __builtin_nan("");
+}
+
+__device__ __forceinline__ void store_pgram(void* pgram, int32_t f64, int64_t idx, double v) {
+    if (f64)
+        static_cast<double*>(pgram)[idx] = v;
+    else
+        static_cast<float*>(pgram)[idx] = (float)v;
+}
+
+// Launch grids: the dispatch packet counts work-items in 32 bits per
+// dimension, so large launches are folded into (x, y) with at most kGridX
+// blocks along x; kernels recover the linear block index and drop the excess.
+constexpr int64_t kGridX = 32768;
+
+inline dim3 grid_for(int64_t blocks) {
+    if (blocks <= kGridX) return dim3((unsigned)blocks, 1, 1);
+    return dim3((unsigned)kGridX, (unsigned)((blocks + kGridX - 1) / kGridX), 1);
+}
+
+__device__ __forceinline__ int64_t linear_block() {
+    return (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+}
+
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs,
+// so block b runs on XCD b % 8.  Remap so that each XCD receives a contiguous
+// run of items (and hence the same objects stay in one XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
+    const int64_t full = (n / kXcds) * kXcds;
+    if (b >= full) return b;
+    return (b % kXcds) * (full / kXcds) + b / kXcds;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel parameter blocks and host launchers.
+
+struct PrepParams {
+    const int64_t* offsets;  // NULL: one object spanning [0, n_obs)
+    const double* t;
+    const double* y;
+    int64_t n_obj;
+    int64_t n_obs;
+    int32_t subtract_mean;
+    int32_t normalize;
+    double step_cyc;  // lane-stride frequency step in cycles (FP32 form); 0: no step table
+    ObjMeta* meta;
+    double* tau;   // [n_obs] t - t0
+    double* yp64;  // [n_obs] y - ybar
+    float* yp32;   // [n_obs] (float)(y - ybar), or NULL
+    float2* step;  // [n_obs] (cos, sin)(2 pi step_cyc tau), or NULL
+};
+
+struct MainParams {
+    const ObjMeta* meta;
+    const double* tau;
+    const double* yp64;
+    const float* yp32;
+    const float2* step;
+    double f_min, df, to_cyc;
+    int64_t n_f;
+    int64_t n_obj;
+    int64_t tiles_per_obj;  // frequency tiles per object
+    int64_t n_items;        // n_obj * tiles_per_obj * n_split
+    int32_t n_split;        // observation-axis split (single object only)
+    int32_t pgram_f64;
+    void* pgram;             // NULL: peaks only
+    PeakRec* rec;            // [n_obj * tiles_per_obj] when n_split == 1
+    uint32_t* ill;           // [n_obj * tiles_per_obj]: tile needs the FP64 fix-up
+    float* part;             // [n_split][4][n_f] when n_split > 1
+    unsigned int* queue;     // persistent schedule: kXcds counters
+    int32_t persistent;
+    int32_t pad;
+};
+
+struct CombineParams {
+    const ObjMeta* meta;
+    const double* tau;
+    const double* yp64;
+    const float* part;
+    int32_t n_split;
+    int32_t pgram_f64;
+    double f_min, df, to_cyc;
+    int64_t n_f;
+    void* pgram;
+    PeakRec* rec;  // [ceil(n_f / kCombineThreads)]
+};
+
+struct FixupParams {
+    const ObjMeta* meta;
+    const double* tau;
+    const double* yp64;
+    const uint32_t* ill;
+    double f_min, df, to_cyc;
+    int64_t n_f;
+    int64_t tiles_per_obj;
+    int64_t n_tiles;
+    int64_t tile_freqs;
+    int32_t pgram_f64;
+    int32_t pad;
+    void* pgram;
+    PeakRec* rec;
+};
+
+struct PeakParams {
+    const ObjMeta* meta;
+    const PeakRec* rec;
+    int64_t n_obj;
+    int64_t rec_per_obj;
+    double f_min, df;
+    int32_t unit;
+    int32_t pad;
+    lsp_peak* peaks;
+};
+
+hipError_t launch_prep(const PrepParams& p, hipStream_t s);
+hipError_t launch_fp64(const MainParams& p, int kf, int waves, hipStream_t s);
+hipError_t launch_fp32p(const MainParams& p, int k, int waves, hipStream_t s);
+hipError_t launch_fixup(const FixupParams& p, hipStream_t s);
+hipError_t launch_combine(const CombineParams& p, hipStream_t s);
+hipError_t launch_peaks(const PeakParams& p, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* dst, int64_t n, unsigned int v, hipStream_t s);
+int persistent_blocks(int k, int waves, int form);
+
+}  // namespace lsp

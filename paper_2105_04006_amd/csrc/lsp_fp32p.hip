@@ -1,0 +1,295 @@
+// lsp_fp32p.hip -- the FP32 form of the periodogram with FP64 phase reduction.
+//
+// The sums of the single-pass form (Section 2) are accumulated in FP32.  Each
+// lane owns K frequencies spaced 64 bins apart, f_k = f_0 + 64 k df.  For every
+// observation the lane
+//   1. forms its first phase f_0 (t_j - t0) in cycles in FP64 and reduces it
+//      exactly to [-1/2, 1/2] (the only FP64 work per observation),
+//   2. seeds (cos, sin) of that phase with the hardware v_cos_f32 / v_sin_f32,
+//      whose argument is in revolutions,
+//   3. walks its other K-1 frequencies by angle addition with the
+//      observation's step rotation (cos, sin)(2 pi 64 df (t_j - t0)), tabulated
+//      once per observation by the prep kernel, and
+//   4. accumulates sum y cos, sum y sin, sum cos^2 and sum cos sin per frequency.
+// The recurrence restarts from an exact FP64-reduced seed at every
+// observation, so its rounding error never grows beyond K - 1 steps.  This is
+// the frequency-to-frequency recurrence Section 4.5 describes and sets aside
+// for a sequential loop over the whole grid; here each lane runs it over only
+// its own K frequencies, so every lane stays independent.
+//
+// Eq. 1 and Eq. 2 are applied to the FP32 sums without forming tau (power32).
+// A bin whose smaller shifted denominator is too small for FP32 to resolve
+// marks its tile, and the FP64 fix-up kernel (lsp_fp64.hip) recomputes that
+// whole tile from the FP64 series; the hot kernel itself carries no FP64 trig.
+//
+// Items are (object, frequency tile[, observation split]).  A workgroup of W
+// wavefronts covers 64 K W frequencies of one object, sharing the LDS-staged
+// observations.  Items are either one per workgroup (grid schedule, with an
+// XCD-aware order) or popped by resident workgroups from eight per-XCD atomic
+// queues (persistent schedule); a workgroup that drains its own XCD's queue
+// moves on to the next XCD's, and exits once every queue is empty.
+#include "lsp_common.h"
+
+namespace lsp {
+namespace {
+
+template <int K, int W>
+__device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, double* s_tau,
+                                           float4* s_obs, PeakRec* s_red) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int64_t tile_freqs = (int64_t)kWave * K * W;
+    const int64_t tile = item / P.n_split;
+    const int split = (int)(item - tile * P.n_split);
+    const int64_t obj = tile / P.tiles_per_obj;
+    const int64_t ftile = tile - obj * P.tiles_per_obj;
+    const ObjMeta m = P.meta[obj];
+    const int64_t i0 = ftile * tile_freqs + (int64_t)wave * kWave * K + lane;
+
+    if (m.status != LSP_OBJ_OK) {
+        if (P.n_split == 1) {
+            if (P.pgram) {
+                const double v = fill_value(m.status);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int64_t i = i0 + (int64_t)kWave * k;
+                    if (i < P.n_f) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
+                }
+            }
+            if (threadIdx.x == 0) {
+                P.rec[tile] = PeakRec{0.0, -1};
+                P.ill[tile] = 0u;
+            }
+        }
+        return;
+    }
+
+    const int64_t chunk = (m.n + P.n_split - 1) / P.n_split;
+    const int64_t lo = (int64_t)split * chunk < m.n ? (int64_t)split * chunk : m.n;
+    const int64_t hi = lo + chunk < m.n ? lo + chunk : m.n;
+    const int64_t js = m.j0 + lo, je = m.j0 + hi;
+    const double fl = grid_freq(P.f_min, P.df, i0) * P.to_cyc;
+
+    float xc[K], xs[K], cc[K], cs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
+
+    for (int64_t jt = js; jt < je; jt += kTile) {
+        const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += kWave * W) {
+            s_tau[q] = P.tau[jt + q];
+            const float2 st = P.step[jt + q];
+            s_obs[q] = make_float4(P.yp32[jt + q], st.x, st.y, 0.0f);
+        }
+        __syncthreads();
+        for (int q = 0; q < cnt; ++q) {
+            const double tq = s_tau[q];
+            const float4 o = s_obs[q];  // (y - ybar, cos step, sin step, -)
+            double ph = fl * tq;
+            ph -= rint(ph);
+            const float r = (float)ph;
+            float s = __builtin_amdgcn_sinf(r);
+            float c = __builtin_amdgcn_cosf(r);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                xc[k] = fmaf(o.x, c, xc[k]);
+                xs[k] = fmaf(o.x, s, xs[k]);
+                cc[k] = fmaf(c, c, cc[k]);
+                cs[k] = fmaf(c, s, cs[k]);
+                if (k + 1 < K) {
+                    const float cn = fmaf(c, o.y, -(s * o.z));
+                    s = fmaf(s, o.y, c * o.z);
+                    c = cn;
+                }
+            }
+        }
+    }
+
+    if (P.n_split > 1) {
+        const int64_t nf = P.n_f;
+        float* base = P.part + (int64_t)split * 4 * nf;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t i = i0 + (int64_t)kWave * k;
+            if (i < nf) {
+                base[i] = xc[k];
+                base[nf + i] = xs[k];
+                base[2 * nf + i] = cc[k];
+                base[3 * nf + i] = cs[k];
+            }
+        }
+        return;
+    }
+
+    PeakRec best{0.0, -1};
+    const float n = (float)m.n;
+    const float scale = (float)m.scale;
+    bool any_ill = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t i = i0 + (int64_t)kWave * k;
+        if (i < P.n_f) {
+            bool ill;
+            const double p = (double)power32(xc[k], xs[k], cc[k], cs[k], n, scale, ill);
+            any_ill |= ill;
+            if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, p);
+            if (better(p, i, best.p, best.i)) best = PeakRec{p, i};
+        }
+    }
+    // A tile holding an ill-conditioned bin is recomputed in FP64 by the
+    // fix-up kernel, which overwrites its bins and its record.
+    any_ill = __syncthreads_or(any_ill);
+    best = wave_best(best);
+    if (lane == 0) s_red[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        PeakRec b = s_red[0];
+#pragma unroll
+        for (int w = 1; w < W; ++w)
+            if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
+        P.rec[tile] = b;
+        P.ill[tile] = any_ill ? 1u : 0u;
+    }
+}
+
+template <int K, int W>
+__global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
+    __shared__ double s_tau[kTile];
+    __shared__ float4 s_obs[kTile];
+    __shared__ PeakRec s_red[W];
+    __shared__ int64_t s_item;
+
+    if (!P.persistent) {
+        const int64_t b = linear_block();
+        if (b < P.n_items) fp32p_item<K, W>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red);
+        return;
+    }
+    const int64_t per = (P.n_items + kXcds - 1) / kXcds;
+    const int x0 = (int)(blockIdx.x % kXcds);
+    for (int d = 0; d < kXcds; ++d) {
+        const int x = (x0 + d) % kXcds;
+        const int64_t lo = (int64_t)x * per;
+        const int64_t hi = lo + per < P.n_items ? lo + per : P.n_items;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = lo + (int64_t)atomicAdd(&P.queue[x], 1u);
+            __syncthreads();
+            const int64_t item = s_item;
+            __syncthreads();
+            if (item >= hi) break;
+            fp32p_item<K, W>(P, item, s_tau, s_obs, s_red);
+        }
+    }
+}
+
+// Sum the per-split partial sums of a single object in a fixed order, then
+// finalise exactly as the unsplit path does.
+__global__ __launch_bounds__(kCombineThreads) void combine_kernel(const CombineParams P) {
+    __shared__ PeakRec s_red[kCombineThreads / kWave];
+    const int64_t blk = linear_block();
+    const int64_t i = blk * kCombineThreads + threadIdx.x;
+    const ObjMeta m = P.meta[0];
+    PeakRec best{0.0, -1};
+    if (i < P.n_f) {
+        if (m.status != LSP_OBJ_OK) {
+            if (P.pgram) store_pgram(P.pgram, P.pgram_f64, i, fill_value(m.status));
+        } else {
+            const int64_t nf = P.n_f;
+            float xc = 0.0f, xs = 0.0f, cc = 0.0f, cs = 0.0f;
+            for (int s = 0; s < P.n_split; ++s) {
+                const float* b = P.part + (int64_t)s * 4 * nf;
+                xc += b[i];
+                xs += b[nf + i];
+                cc += b[2 * nf + i];
+                cs += b[3 * nf + i];
+            }
+            bool ill;
+            double p = (double)power32(xc, xs, cc, cs, (float)m.n, (float)m.scale, ill);
+            if (ill)
+                p = (double)(float)power64_bin(m, P.tau, P.yp64,
+                                               grid_freq(P.f_min, P.df, i) * P.to_cyc);
+            if (P.pgram) store_pgram(P.pgram, P.pgram_f64, i, p);
+            best = PeakRec{p, i};
+            if (!(p == p)) best = PeakRec{0.0, -1};
+        }
+    }
+    best = wave_best(best);
+    const int wave = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) s_red[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        PeakRec b = s_red[0];
+        for (int w = 1; w < kCombineThreads / kWave; ++w)
+            if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
+        P.rec[blk] = b;
+    }
+}
+
+template <int K>
+hipError_t launch_k(const MainParams& p, int waves, hipStream_t s) {
+    const dim3 grid = p.persistent ? dim3((unsigned)persistent_blocks(K, waves, LSP_FORM_FP32P))
+                                   : grid_for(p.n_items);
+    switch (waves) {
+        case 1: hipLaunchKernelGGL((fp32p_kernel<K, 1>), grid, dim3(kWave * 1), 0, s, p); break;
+        case 2: hipLaunchKernelGGL((fp32p_kernel<K, 2>), grid, dim3(kWave * 2), 0, s, p); break;
+        case 4: hipLaunchKernelGGL((fp32p_kernel<K, 4>), grid, dim3(kWave * 4), 0, s, p); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int K, int W>
+int occupancy_blocks() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fp32p_kernel<K, W>, kWave * W, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    return per_cu * cus;
+}
+
+template <int K>
+int occupancy_k(int waves) {
+    switch (waves) {
+        case 1: return occupancy_blocks<K, 1>();
+        case 2: return occupancy_blocks<K, 2>();
+        default: return occupancy_blocks<K, 4>();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fp32p(const MainParams& p, int k, int waves, hipStream_t s) {
+    if (p.n_items <= 0) return hipSuccess;
+    switch (k) {
+        case 4: return launch_k<4>(p, waves, s);
+        case 8: return launch_k<8>(p, waves, s);
+        case 16: return launch_k<16>(p, waves, s);
+        case 32: return launch_k<32>(p, waves, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int persistent_blocks(int k, int waves, int form) {
+    (void)form;
+    switch (k) {
+        case 4: return occupancy_k<4>(waves);
+        case 8: return occupancy_k<8>(waves);
+        case 16: return occupancy_k<16>(waves);
+        default: return occupancy_k<32>(waves);
+    }
+}
+
+hipError_t launch_combine(const CombineParams& p, hipStream_t s) {
+    if (p.n_f <= 0) return hipSuccess;
+    hipLaunchKernelGGL(combine_kernel, grid_for((p.n_f + kCombineThreads - 1) / kCombineThreads),
+                       dim3(kCombineThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace lsp

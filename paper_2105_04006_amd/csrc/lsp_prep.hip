@@ -1,0 +1,134 @@
+// lsp_prep.hip -- per-object preparation ahead of the periodogram kernels.
+//
+// Section 2 assumes zero-mean magnitudes; this kernel removes each object's
+// mean in FP64 and records S_yy = sum (y - ybar)^2, which normalises the power.
+// It also re-centres time on the object's mid-span t0 (the power does not
+// depend on the time origin, and |t - t0| halves the phase magnitude that the
+// FP32 form must reduce), and for the FP32 form tabulates per observation the
+// rotation (cos, sin)(2 pi * step * (t - t0)) that advances a lane's phase from
+// one of its frequencies to the next.  One workgroup per object; all reductions
+// are fixed-order trees, so results are bitwise reproducible.
+#include "lsp_common.h"
+
+namespace lsp {
+namespace {
+
+struct Red {
+    double sy, syy_raw, tmin, tmax;
+    int bad;
+};
+
+__device__ void block_reduce(Red& r, Red* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = r;
+    __syncthreads();
+    for (int w = kPrepThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            Red a = sh[tid], b = sh[tid + w];
+            a.sy += b.sy;
+            a.syy_raw += b.syy_raw;
+            a.tmin = fmin(a.tmin, b.tmin);
+            a.tmax = fmax(a.tmax, b.tmax);
+            a.bad |= b.bad;
+            sh[tid] = a;
+        }
+        __syncthreads();
+    }
+    r = sh[0];
+    __syncthreads();
+}
+
+__device__ double block_sum(double v, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int w = kPrepThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    const double out = sh[0];
+    __syncthreads();
+    return out;
+}
+
+__global__ __launch_bounds__(kPrepThreads) void prep_kernel(const PrepParams P) {
+    __shared__ Red sh_red[kPrepThreads];
+    __shared__ double sh_sum[kPrepThreads];
+    const int64_t o = linear_block();
+    const int tid = threadIdx.x;
+    if (o >= P.n_obj) return;
+
+    int64_t j0 = 0, j1 = P.n_obs;
+    if (P.offsets) {
+        j0 = P.offsets[o];
+        j1 = P.offsets[o + 1];
+    }
+    if (j0 < 0 || j1 < j0 || j1 > P.n_obs) {
+        if (tid == 0) {
+            ObjMeta m = {};
+            m.j0 = 0;
+            m.n = 0;
+            m.status = LSP_OBJ_BADRANGE;
+            P.meta[o] = m;
+        }
+        return;
+    }
+    const int64_t n = j1 - j0;
+
+    Red r = {0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0};
+    for (int64_t j = j0 + tid; j < j1; j += kPrepThreads) {
+        const double tj = P.t[j], yj = P.y[j];
+        if (!isfinite(tj) || !isfinite(yj)) r.bad = 1;
+        r.sy += yj;
+        r.syy_raw += yj * yj;
+        r.tmin = fmin(r.tmin, tj);
+        r.tmax = fmax(r.tmax, tj);
+    }
+    block_reduce(r, sh_red);
+
+    const double ybar = (P.subtract_mean && n > 0) ? r.sy / (double)n : 0.0;
+    const double t0 = (n > 0 && !r.bad) ? 0.5 * (r.tmin + r.tmax) : 0.0;
+
+    double sq = 0.0;
+    for (int64_t j = j0 + tid; j < j1; j += kPrepThreads) {
+        const double tc = P.t[j] - t0;
+        const double yc = P.y[j] - ybar;
+        sq += yc * yc;
+        P.tau[j] = tc;
+        P.yp64[j] = yc;
+        if (P.yp32) P.yp32[j] = (float)yc;
+        if (P.step) {
+            double s, c;
+            sincos_cycles64(P.step_cyc, tc, &s, &c);
+            P.step[j] = make_float2((float)c, (float)s);
+        }
+    }
+    const double syy = block_sum(sq, sh_sum);
+
+    if (tid == 0) {
+        ObjMeta m = {};
+        m.j0 = j0;
+        m.n = n;
+        m.ybar = ybar;
+        m.syy = syy;
+        m.t0 = t0;
+        int32_t st = LSP_OBJ_OK;
+        if (r.bad)
+            st = LSP_OBJ_NONFINITE;
+        else if (n < 2 || syy == 0.0 || syy <= kVarEps * r.syy_raw)
+            st = LSP_OBJ_DEGENERATE;
+        m.status = st;
+        m.scale = P.normalize ? (st == LSP_OBJ_OK ? 2.0 / syy : 0.0) : 1.0;
+        P.meta[o] = m;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_prep(const PrepParams& p, hipStream_t s) {
+    if (p.n_obj <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prep_kernel, grid_for(p.n_obj), dim3(kPrepThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace lsp

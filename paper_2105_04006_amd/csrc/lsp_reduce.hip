@@ -1,0 +1,75 @@
+// lsp_reduce.hip -- per-object peak from the per-tile (power, index) records,
+// and a small fill kernel for queue counters.
+//
+// Section 3.3 takes the argmax of the periodogram (first maximal index) and
+// converts it to a period, p = 2 pi / w; Section 3.4 keeps, per object, the best
+// (power, index) found by each thread and reduces them.  Here every frequency
+// tile has already reduced its bins to one record; one workgroup per object
+// reduces the object's records with the same (power desc, index asc) order, so
+// the result does not depend on execution order.
+#include "lsp_common.h"
+
+namespace lsp {
+namespace {
+
+constexpr int kPeakThreads = 256;
+
+__global__ __launch_bounds__(kPeakThreads) void peaks_kernel(const PeakParams P) {
+    __shared__ PeakRec s_red[kPeakThreads / kWave];
+    const int64_t o = linear_block();
+    if (o >= P.n_obj) return;
+    const ObjMeta m = P.meta[o];
+    PeakRec best{0.0, -1};
+    if (m.status == LSP_OBJ_OK) {
+        const PeakRec* r = P.rec + o * P.rec_per_obj;
+        for (int64_t q = threadIdx.x; q < P.rec_per_obj; q += kPeakThreads) {
+            const PeakRec c = r[q];
+            if (c.i >= 0 && better(c.p, c.i, best.p, best.i)) best = c;
+        }
+    }
+    best = wave_best(best);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_red[threadIdx.x / kWave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        PeakRec b = s_red[0];
+        for (int w = 1; w < kPeakThreads / kWave; ++w)
+            if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
+        lsp_peak pk;
+        pk.status = m.status;
+        pk.reserved = 0;
+        if (m.status == LSP_OBJ_OK && b.i >= 0) {
+            const double f = grid_freq(P.f_min, P.df, b.i);
+            pk.index = b.i;
+            pk.freq = f;
+            pk.period = P.unit == LSP_UNIT_ANGULAR ? kTwoPi / f : 1.0 / f;
+            pk.power = b.p;
+        } else {
+            pk.index = -1;
+            pk.freq = __builtin_nan("");
+            pk.period = __builtin_nan("");
+            pk.power = m.status == LSP_OBJ_OK ? __builtin_nan("") : fill_value(m.status);
+        }
+        P.peaks[o] = pk;
+    }
+}
+
+__global__ void fill_u32_kernel(unsigned int* dst, int64_t n, unsigned int v) {
+    const int64_t i = linear_block() * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_peaks(const PeakParams& p, hipStream_t s) {
+    if (p.n_obj <= 0) return hipSuccess;
+    hipLaunchKernelGGL(peaks_kernel, grid_for(p.n_obj), dim3(kPeakThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* dst, int64_t n, unsigned int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, grid_for((n + 255) / 256), dim3(256), 0, s, dst, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace lsp

@@ -1,0 +1,217 @@
+"""Thin Python binding of liblsp.so (include/lsp.h): argument marshalling only.
+
+Every step of the periodogram runs in the library's HIP kernels; this module
+allocates the outputs and the workspace with PyTorch on the caller's device,
+passes raw device pointers and the current HIP stream, and raises on any
+non-OK status.  There is no CPU path: a missing library or a CPU tensor is an
+error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lsp.h")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
+OBJ_OK, OBJ_DEGENERATE, OBJ_BADRANGE, OBJ_NONFINITE = 0, 1, 2, 3
+FORM_FP64, FORM_FP32P = 0, 1
+CYCLES, ANGULAR = 0, 1
+PGRAM_F32, PGRAM_F64 = 0, 1
+SCHED_AUTO, SCHED_GRID, SCHED_PERSISTENT = 0, 1, 2
+
+PEAK_DTYPE = np.dtype(
+    [("index", "<i8"), ("freq", "<f8"), ("period", "<f8"), ("power", "<f8"),
+     ("status", "<i4"), ("reserved", "<i4")]
+)
+PEAK_BYTES = 40
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("f_min", ctypes.c_double), ("f_max", ctypes.c_double), ("n_f", ctypes.c_int64),
+                ("unit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("normalize", ctypes.c_int32),
+                ("subtract_mean", ctypes.c_int32), ("pgram_dtype", ctypes.c_int32),
+                ("k_per_lane", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
+                ("t_split", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class LspError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2105_04006_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        L.lsp_default_options.restype = Options
+        L.lsp_default_options.argtypes = []
+        L.lsp_workspace_bytes.restype = sz
+        L.lsp_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid), ctypes.POINTER(Options)]
+        L.lsp_single.restype = ctypes.c_int
+        L.lsp_single.argtypes = [vp, vp, i64, ctypes.POINTER(Grid), ctypes.POINTER(Options), vp, vp,
+                                 vp, sz, vp]
+        L.lsp_batch.restype = ctypes.c_int
+        L.lsp_batch.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
+                                ctypes.POINTER(Options), vp, vp, vp, sz, vp]
+        L.lsp_status_string.restype = ctypes.c_char_p
+        L.lsp_status_string.argtypes = [ctypes.c_int]
+        L.lsp_set_stage_events.restype = ctypes.c_int
+        L.lsp_set_stage_events.argtypes = [vp, vp]
+        L.lsp_version.restype = ctypes.c_int32
+        L.lsp_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def declared_functions():
+    """Names of the functions include/lsp.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsp_[a-z_0-9]+)\s*\(", text)))
+
+
+def set_stage_events(begin, end):
+    """Record caller-owned hipEvent_t handles around the main kernel of later
+    calls from this thread (None, None to stop)."""
+    st = lib().lsp_set_stage_events(begin, end)
+    if st != OK:
+        raise LspError(st, "lsp_set_stage_events")
+
+
+def status_string(status):
+    return lib().lsp_status_string(int(status)).decode()
+
+
+def default_options():
+    return lib().lsp_default_options()
+
+
+def make_grid(f_min, f_max, n_f, unit=CYCLES):
+    return Grid(float(f_min), float(f_max), int(n_f), int(unit), 0)
+
+
+def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype=PGRAM_F32, k=0,
+                 waves=0, t_split=0, schedule=SCHED_AUTO):
+    o = Options()
+    o.form, o.normalize, o.subtract_mean, o.pgram_dtype = (int(form), int(bool(normalize)),
+                                                           int(bool(subtract_mean)),
+                                                           int(pgram_dtype))
+    o.k_per_lane, o.waves_per_wg, o.t_split, o.schedule = int(k), int(waves), int(t_split), int(
+        schedule)
+    return o
+
+
+def workspace_bytes(n_obj, n_obs, grid, opt):
+    return int(lib().lsp_workspace_bytes(int(n_obj), int(n_obs), ctypes.byref(grid),
+                                         ctypes.byref(opt)))
+
+
+def _dev_ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+def _check(x, dtype, name):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a device tensor (the library has no CPU path)")
+    if x.dtype != dtype or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Periodogram:
+    """A periodogram call with its outputs and workspace allocated once.
+
+    Calling the object enqueues the library's kernels on the stream and
+    allocates nothing, so it can be timed in a loop or captured in a graph.
+    ``offsets=None`` selects single-periodogram mode (lsp_single).
+    """
+
+    def __init__(self, t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, form=FORM_FP64,
+                 normalize=True, subtract_mean=True, pgram=True, pgram_dtype=PGRAM_F32,
+                 peaks=True, k=0, waves=0, t_split=0, schedule=SCHED_AUTO):
+        _check(t, torch.float64, "t")
+        _check(y, torch.float64, "y")
+        if t.numel() != y.numel():
+            raise ValueError("t and y differ in length")
+        if offsets is not None:
+            _check(offsets, torch.int64, "offsets")
+        self.t, self.y, self.offsets = t, y, offsets
+        self.n_obs = int(t.numel())
+        self.n_obj = 1 if offsets is None else int(offsets.numel()) - 1
+        self.grid = make_grid(f_min, f_max, n_f, unit)
+        self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, t_split,
+                                schedule)
+        dev = t.device
+        nb = workspace_bytes(self.n_obj, self.n_obs, self.grid, self.opt)
+        if nb == 0:
+            raise LspError(EINVAL, "lsp_workspace_bytes")
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+        pdt = torch.float64 if pgram_dtype == PGRAM_F64 else torch.float32
+        self.pgram = (torch.empty((self.n_obj, int(n_f)), dtype=pdt, device=dev)
+                      if pgram else None)
+        self.peaks_raw = (torch.empty(self.n_obj * PEAK_BYTES, dtype=torch.uint8, device=dev)
+                          if peaks else None)
+
+    def __call__(self, stream=None):
+        L = lib()
+        s = _stream_handle(stream)
+        ws = self.workspace
+        if self.offsets is None:
+            st = L.lsp_single(_dev_ptr(self.t), _dev_ptr(self.y), self.n_obs,
+                              ctypes.byref(self.grid), ctypes.byref(self.opt),
+                              _dev_ptr(self.pgram), _dev_ptr(self.peaks_raw), _dev_ptr(ws),
+                              ws.numel(), s)
+            what = "lsp_single"
+        else:
+            st = L.lsp_batch(_dev_ptr(self.offsets), self.n_obj, self.n_obs, _dev_ptr(self.t),
+                             _dev_ptr(self.y), ctypes.byref(self.grid), ctypes.byref(self.opt),
+                             _dev_ptr(self.pgram), _dev_ptr(self.peaks_raw), _dev_ptr(ws),
+                             ws.numel(), s)
+            what = "lsp_batch"
+        if st != OK:
+            raise LspError(st, what)
+        return self
+
+    def peaks(self):
+        """Peak records copied to the host as a numpy structured array."""
+        if self.peaks_raw is None:
+            return None
+        return self.peaks_raw.cpu().numpy().view(PEAK_DTYPE).copy()
+
+
+def single(t, y, f_min, f_max, n_f, **kw):
+    """One series (Section 3.3); returns (pgram[n_f] tensor or None, peak record)."""
+    p = Periodogram(t, y, f_min, f_max, n_f, offsets=None, **kw)()
+    pk = p.peaks()
+    return (p.pgram[0] if p.pgram is not None else None), (pk[0] if pk is not None else None)
+
+
+def batch(offsets, t, y, f_min, f_max, n_f, **kw):
+    """CSR batch (Section 3.4); returns (pgram[n_obj, n_f] tensor or None, peaks array)."""
+    p = Periodogram(t, y, f_min, f_max, n_f, offsets=offsets, **kw)()
+    return p.pgram, p.peaks()

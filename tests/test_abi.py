@@ -1,0 +1,102 @@
+"""The C ABI library loads, exports what include/lsp.h declares, and rejects bad
+arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+
+import pytest
+
+from paper_2105_04006_amd import lsp
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lsp.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = lsp.declared_functions()
+    assert {"lsp_single", "lsp_batch", "lsp_workspace_bytes", "lsp_status_string",
+            "lsp_default_options", "lsp_version"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/lsp.h but not exported"
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(lsp.Grid) == 32
+    assert ctypes.sizeof(lsp.Options) == 48
+    assert lsp.PEAK_DTYPE.itemsize == lsp.PEAK_BYTES == 40
+
+
+def test_default_options(L):
+    o = lsp.default_options()
+    assert (o.form, o.normalize, o.subtract_mean, o.pgram_dtype) == (lsp.FORM_FP64, 1, 1, 0)
+    assert L.lsp_version() == 100
+
+
+def test_status_strings():
+    assert lsp.status_string(lsp.OK) == "ok"
+    assert "workspace" in lsp.status_string(lsp.ENOMEM)
+    assert lsp.status_string(99) == "unknown status"
+
+
+def test_workspace_bytes():
+    g = lsp.make_grid(1.0, 12.0, 10_000)
+    for form in (lsp.FORM_FP64, lsp.FORM_FP32P):
+        o = lsp.make_options(form=form)
+        nb = lsp.workspace_bytes(1, 256, g, o)
+        assert nb > 0 and nb % 256 == 0
+        assert lsp.workspace_bytes(100, 50_000, g, o) > nb
+    assert lsp.workspace_bytes(0, 10, g, lsp.make_options()) == 0
+    assert lsp.workspace_bytes(1, 10, lsp.make_grid(2.0, 1.0, 10), lsp.make_options()) == 0
+    assert lsp.workspace_bytes(1, 10, g, lsp.make_options(form=7)) == 0
+
+
+FAKE = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: every call below fails validation
+
+
+def _single(L, t=FAKE, y=FAKE, n=16, grid=None, opt=None, pgram=FAKE, peak=FAKE, ws=FAKE,
+            nbytes=1 << 30):
+    grid = grid or lsp.make_grid(1.0, 2.0, 100)
+    opt = opt or lsp.make_options()
+    return L.lsp_single(t, y, n, ctypes.byref(grid), ctypes.byref(opt), pgram, peak, ws, nbytes,
+                        None)
+
+
+def test_argument_errors_are_reported_before_any_launch(L):
+    assert _single(L, t=None) == lsp.EINVAL
+    assert _single(L, ws=None) == lsp.EINVAL
+    assert _single(L, n=-1) == lsp.EINVAL
+    assert _single(L, pgram=None, peak=None) == lsp.EINVAL
+    assert _single(L, ws=ctypes.c_void_p((1 << 20) + 8)) == lsp.EINVAL  # misaligned
+    assert _single(L, nbytes=1) == lsp.ENOMEM
+    for g in (lsp.make_grid(2.0, 1.0, 10), lsp.make_grid(1.0, 2.0, 0),
+              lsp.make_grid(float("nan"), 2.0, 10), lsp.make_grid(1.0, float("inf"), 10),
+              lsp.make_grid(1.0, 2.0, 10, unit=5)):
+        assert _single(L, grid=g) == lsp.EINVAL
+    bad_norm = lsp.make_options()
+    bad_norm.normalize = 2
+    bad_mean = lsp.make_options()
+    bad_mean.subtract_mean = -1
+    for o in (lsp.make_options(form=3), lsp.make_options(pgram_dtype=2), bad_norm, bad_mean,
+              lsp.make_options(k=3), lsp.make_options(form=lsp.FORM_FP32P, k=2),
+              lsp.make_options(waves=3), lsp.make_options(t_split=65),
+              lsp.make_options(schedule=9)):
+        assert _single(L, opt=o) == lsp.EINVAL
+    assert _single(L, opt=lsp.make_options(t_split=2)) == lsp.EUNSUPPORTED
+    assert _single(L, opt=lsp.make_options(schedule=lsp.SCHED_PERSISTENT)) == lsp.EUNSUPPORTED
+    g = lsp.make_grid(1.0, 2.0, 100)
+    o = lsp.make_options(form=lsp.FORM_FP32P, t_split=2)
+    assert L.lsp_batch(FAKE, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE, FAKE, FAKE,
+                       1 << 30, None) == lsp.EUNSUPPORTED
+    o = lsp.make_options()
+    assert L.lsp_batch(None, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE, FAKE, FAKE,
+                       1 << 30, None) == lsp.EINVAL
+    assert L.lsp_batch(FAKE, 0, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE, FAKE, FAKE,
+                       1 << 30, None) == lsp.EINVAL
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+
+    t = torch.zeros(8, dtype=torch.float64)
+    with pytest.raises(TypeError):
+        lsp.Periodogram(t, t, 1.0, 2.0, 10)
