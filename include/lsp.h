@@ -128,8 +128,10 @@ lsp_options lsp_default_options(void);
  * Device workspace (bytes, 256-aligned) that lsp_batch / lsp_single need for
  * n_obj objects holding n_obs observations in total on `grid` with `opt`.
  * Returns 0 if the arguments are invalid.  The workspace holds per-object
- * statistics, the re-centred series, per-tile peak records, queue counters and
- * (single object with t_split > 1) partial sums; its contents are scratch.
+ * statistics (mean, S_yy, time origin, status), per-tile peak records and
+ * flags, queue counters and (single object with t_split > 1) partial sums; its
+ * contents are scratch.  t and y are only read, so objects whose CSR ranges
+ * overlap are each computed from their own range.
  */
 size_t lsp_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid *grid,
                            const lsp_options *opt);

@@ -64,7 +64,7 @@ def _bind(path):
     L.ora_single.restype = i32
     L.ora_single.argtypes = [p, p, i64, d, d, i64, i32, i32, i32, p, p, p, i32]
     L.ora_batch.restype = i32
-    L.ora_batch.argtypes = [p, i64, i64, p, p, d, d, i64, i32, i32, i32, p, p, p, p, i32]
+    L.ora_batch.argtypes = [p, i64, i64, p, p, d, d, i64, i32, i32, i32, p, p, i32]
     L.ora_eval_bins.restype = i32
     L.ora_eval_bins.argtypes = [p, i64, i64, p, p, d, d, i64, i32, i32, i32, p, p, i64, p, i32]
     return L
@@ -147,19 +147,13 @@ class Oracle:
         offsets, t, y = _i64(offsets), _f64(t), _f64(y)
         n_obj = len(offsets) - 1
         n_f = int(n_f)
-        yp = np.zeros(max(len(t), 1))
         pk = np.zeros(n_obj, dtype=PEAK_DTYPE)
-        if want_pgram:
-            pg = np.empty((n_obj, n_f))
-            scratch = None
-        else:
-            pg = None
-            nt = threads if threads > 0 else (os.cpu_count() or 1)
-            scratch = np.empty(max(nt, 64) * n_f)
-        self.L.ora_batch(_ptr(offsets), n_obj, len(t), _ptr(t), _ptr(y), float(f_min),
-                         float(f_max), n_f, int(unit), int(bool(normalize)),
-                         int(bool(subtract_mean)), _ptr(yp), _ptr(pg), _ptr(scratch), _ptr(pk),
-                         int(threads))
+        pg = np.empty((n_obj, n_f)) if want_pgram else None
+        rc = self.L.ora_batch(_ptr(offsets), n_obj, len(t), _ptr(t), _ptr(y), float(f_min),
+                              float(f_max), n_f, int(unit), int(bool(normalize)),
+                              int(bool(subtract_mean)), _ptr(pg), _ptr(pk), int(threads))
+        if rc != 0:
+            raise MemoryError("oracle batch could not allocate scratch")
         return pg, pk
 
     def eval_bins(self, offsets, t, y, f_min, f_max, n_f, obj, bins, unit=CYCLES,

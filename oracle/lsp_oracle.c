@@ -287,42 +287,55 @@ static int32_t ora_range_status(const int64_t *offsets, int64_t o, int64_t n_obs
 
 /*
  * Batch mode (Section 3.4): object o owns observations [offsets[o], offsets[o+1]).
- * pgram is [n_obj * n_f] row-major, or NULL for peaks only; row_scratch must
- * then hold n_threads * n_f doubles.  yp_scratch holds n_obs doubles.
+ * pgram is [n_obj * n_f] row-major, or NULL for peaks only.  Each object gets
+ * private scratch, so objects whose ranges overlap do not interfere.
  * Objects are scheduled dynamically over threads as in the paper's CPU port.
+ * Returns -1 if scratch memory cannot be had.
  */
 int32_t ora_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
                   const double *y, double f_min, double f_max, int64_t n_f, int32_t unit,
-                  int32_t normalize, int32_t subtract_mean, double *yp_scratch, double *pgram,
-                  double *row_scratch, ora_peak *peaks, int32_t nthreads)
+                  int32_t normalize, int32_t subtract_mean, double *pgram, ora_peak *peaks,
+                  int32_t nthreads)
 {
     int64_t o;
+    int32_t failed = 0;
 #pragma omp parallel for schedule(dynamic) num_threads(ora_threads(nthreads))
     for (o = 0; o < n_obj; o++) {
-        int tid = 0;
-        double *row;
-        int32_t st;
+        double *row = pgram ? pgram + o * n_f : (double *)malloc(sizeof(double) * (size_t)n_f);
+        double *yp = NULL;
+        int32_t st = ora_range_status(offsets, o, n_obs);
         int64_t i;
-#ifdef _OPENMP
-        tid = omp_get_thread_num();
-#endif
-        row = pgram ? pgram + o * n_f : row_scratch + (int64_t)tid * n_f;
-        st = ora_range_status(offsets, o, n_obs);
+        if (!row) {
+#pragma omp atomic write
+            failed = 1;
+            continue;
+        }
         if (st == ORA_OK) {
             int64_t a = offsets[o], n = offsets[o + 1] - offsets[o];
             double syy = 0.0;
-            st = ora_prep(t + a, y + a, n, subtract_mean, yp_scratch + a, &syy);
+            yp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            if (!yp) {
+#pragma omp atomic write
+                failed = 1;
+                if (!pgram)
+                    free(row);
+                continue;
+            }
+            st = ora_prep(t + a, y + a, n, subtract_mean, yp, &syy);
             if (st == ORA_OK)
                 for (i = 0; i < n_f; i++)
-                    row[i] = ora_power_one(t + a, yp_scratch + a, n, syy,
-                                           ora_grid_freq(f_min, f_max, n_f, i), unit, normalize);
+                    row[i] = ora_power_one(t + a, yp, n, syy, ora_grid_freq(f_min, f_max, n_f, i),
+                                           unit, normalize);
+            free(yp);
         }
         if (st != ORA_OK)
             ora_fill_row(row, n_f, st);
         if (peaks)
             ora_fill_peak(&peaks[o], st, row, n_f, f_min, f_max, unit);
+        if (!pgram)
+            free(row);
     }
-    return ORA_OK;
+    return failed ? -1 : ORA_OK;
 }
 
 /*

@@ -31,7 +31,7 @@ struct Config {
 };
 
 struct Layout {
-    size_t meta, tau, yp64, yp32, step, rec, ill, part, queue, total;
+    size_t meta, rec, ill, part, queue, total;
 };
 
 bool valid_grid(const lsp_grid* g) {
@@ -110,20 +110,12 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     return LSP_OK;
 }
 
-Layout layout(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const Config& c) {
+Layout layout(int64_t n_obj, const lsp_grid* g, const Config& c) {
     Layout L;
     size_t off = 0;
     const bool f32 = c.form == LSP_FORM_FP32P;
     L.meta = off;
     off += align_up((size_t)n_obj * sizeof(ObjMeta));
-    L.tau = off;
-    off += align_up((size_t)n_obs * sizeof(double));
-    L.yp64 = off;
-    off += align_up((size_t)n_obs * sizeof(double));
-    L.yp32 = off;
-    off += f32 ? align_up((size_t)n_obs * sizeof(float)) : 0;
-    L.step = off;
-    off += f32 ? align_up((size_t)n_obs * sizeof(float2)) : 0;
     L.rec = off;
     off += align_up((size_t)n_obj * (size_t)c.rec_per_obj * sizeof(PeakRec));
     L.ill = off;
@@ -159,7 +151,7 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     Config c;
     st = resolve(n_obj, n_obs, grid, &opt, &c);
     if (st != LSP_OK) return st;
-    const Layout L = layout(n_obj, n_obs, grid, c);
+    const Layout L = layout(n_obj, grid, c);
     if (ws_bytes < L.total) return LSP_ENOMEM;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -175,20 +167,14 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     pp.n_obs = n_obs;
     pp.subtract_mean = opt.subtract_mean;
     pp.normalize = opt.normalize;
-    pp.step_cyc = f32 ? (double)kWave * df * to_cyc : 0.0;
     pp.meta = at<ObjMeta>(ws, L.meta);
-    pp.tau = at<double>(ws, L.tau);
-    pp.yp64 = at<double>(ws, L.yp64);
-    pp.yp32 = f32 ? at<float>(ws, L.yp32) : nullptr;
-    pp.step = f32 ? at<float2>(ws, L.step) : nullptr;
     if (launch_prep(pp, s) != hipSuccess) return LSP_EHIP;
 
     MainParams mp;
     mp.meta = pp.meta;
-    mp.tau = pp.tau;
-    mp.yp64 = pp.yp64;
-    mp.yp32 = pp.yp32;
-    mp.step = pp.step;
+    mp.t = t;
+    mp.y = y;
+    mp.step_cyc = (double)kWave * df * to_cyc;
     mp.f_min = grid->f_min;
     mp.df = df;
     mp.to_cyc = to_cyc;
@@ -219,8 +205,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
         if (c.split == 1) {
             FixupParams fp;
             fp.meta = mp.meta;
-            fp.tau = mp.tau;
-            fp.yp64 = mp.yp64;
+            fp.t = t;
+            fp.y = y;
             fp.ill = mp.ill;
             fp.f_min = mp.f_min;
             fp.df = df;
@@ -237,8 +223,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
         } else {
             CombineParams cp;
             cp.meta = mp.meta;
-            cp.tau = mp.tau;
-            cp.yp64 = mp.yp64;
+            cp.t = t;
+            cp.y = y;
             cp.part = mp.part;
             cp.n_split = c.split;
             cp.pgram_f64 = mp.pgram_f64;
@@ -289,7 +275,7 @@ size_t lsp_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
     if (lsp::valid_options(&opt) != LSP_OK) return 0;
     lsp::Config c;
     if (lsp::resolve(n_obj, n_obs, grid, &opt, &c) != LSP_OK) return 0;
-    return lsp::layout(n_obj, n_obs, grid, c).total;
+    return lsp::layout(n_obj, grid, c).total;
 }
 
 lsp_status lsp_single(const double* t, const double* y, int64_t n_t, const lsp_grid* grid,

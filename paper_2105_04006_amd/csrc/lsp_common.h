@@ -146,17 +146,16 @@ __device__ __forceinline__ float power32(float xc, float xs, float cc, float cs,
     return p * scale;
 }
 
-// FP64 power of one (object, frequency) pair straight from the re-centred
-// series in global memory; used for FP32 bins flagged ill-conditioned.  Callers
-// invoke it from a single site placed after their FP32 accumulators are dead,
-// so inlining it does not raise the hot loop's register allocation.
-__device__ __forceinline__ double power64_bin(const ObjMeta& m, const double* __restrict__ tau,
-                                     const double* __restrict__ yp, double f_cyc) {
+// FP64 power of one (object, frequency) pair straight from the caller's
+// series, re-centred on the fly; used to recompute FP32 bins flagged
+// ill-conditioned (never from the FP32 hot kernel itself).
+__device__ __forceinline__ double power64_bin(const ObjMeta& m, const double* __restrict__ t,
+                                              const double* __restrict__ y, double f_cyc) {
     Sums64 a = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t j = m.j0; j < m.j0 + m.n; ++j) {
         double s, c;
-        sincos_cycles64(f_cyc, tau[j], &s, &c);
-        sums64_add(a, yp[j], s, c);
+        sincos_cycles64(f_cyc, t[j] - m.t0, &s, &c);
+        sums64_add(a, y[j] - m.ybar, s, c);
     }
     return power64(a, (double)m.n, m.scale);
 }
@@ -187,6 +186,21 @@ __device__ __forceinline__ int64_t linear_block() {
     return (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
 }
 
+// A value the whole workgroup read from LDS, marked wave-uniform.  Loops whose
+// trip count or exit depends on an LDS broadcast must test a value the
+// compiler can prove uniform: otherwise the exit is treated as per-lane, and
+// the structurised control flow may let some lanes re-enter a barrier-bearing
+// loop body without the lanes that were to update the broadcast.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int32_t uniform_i32(int32_t v) {
+    return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
 // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs,
 // so block b runs on XCD b % 8.  Remap so that each XCD receives a contiguous
 // run of items (and hence the same objects stay in one XCD's L2).
@@ -207,21 +221,15 @@ struct PrepParams {
     int64_t n_obs;
     int32_t subtract_mean;
     int32_t normalize;
-    double step_cyc;  // lane-stride frequency step in cycles (FP32 form); 0: no step table
     ObjMeta* meta;
-    double* tau;   // [n_obs] t - t0
-    double* yp64;  // [n_obs] y - ybar
-    float* yp32;   // [n_obs] (float)(y - ybar), or NULL
-    float2* step;  // [n_obs] (cos, sin)(2 pi step_cyc tau), or NULL
 };
 
 struct MainParams {
     const ObjMeta* meta;
-    const double* tau;
-    const double* yp64;
-    const float* yp32;
-    const float2* step;
+    const double* t;  // caller's times and magnitudes (read-only)
+    const double* y;
     double f_min, df, to_cyc;
+    double step_cyc;  // FP32 form: lane-stride frequency step (kWave bins) in cycles
     int64_t n_f;
     int64_t n_obj;
     int64_t tiles_per_obj;  // frequency tiles per object
@@ -239,8 +247,8 @@ struct MainParams {
 
 struct CombineParams {
     const ObjMeta* meta;
-    const double* tau;
-    const double* yp64;
+    const double* t;
+    const double* y;
     const float* part;
     int32_t n_split;
     int32_t pgram_f64;
@@ -252,8 +260,8 @@ struct CombineParams {
 
 struct FixupParams {
     const ObjMeta* meta;
-    const double* tau;
-    const double* yp64;
+    const double* t;
+    const double* y;
     const uint32_t* ill;
     double f_min, df, to_cyc;
     int64_t n_f;

@@ -8,8 +8,9 @@
 //   2. seeds (cos, sin) of that phase with the hardware v_cos_f32 / v_sin_f32,
 //      whose argument is in revolutions,
 //   3. walks its other K-1 frequencies by angle addition with the
-//      observation's step rotation (cos, sin)(2 pi 64 df (t_j - t0)), tabulated
-//      once per observation by the prep kernel, and
+//      observation's step rotation (cos, sin)(2 pi 64 df (t_j - t0)), formed
+//      the same way (FP64 reduction, hardware sin/cos) when the observation is
+//      staged into LDS, and
 //   4. accumulates sum y cos, sum y sin, sum cos^2 and sum cos sin per frequency.
 // The recurrence restarts from an exact FP64-reduced seed at every
 // observation, so its rounding error never grows beyond K - 1 steps.  This is
@@ -78,9 +79,14 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
         const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
         __syncthreads();
         for (int q = threadIdx.x; q < cnt; q += kWave * W) {
-            s_tau[q] = P.tau[jt + q];
-            const float2 st = P.step[jt + q];
-            s_obs[q] = make_float4(P.yp32[jt + q], st.x, st.y, 0.0f);
+            const double tc = P.t[jt + q] - m.t0;
+            s_tau[q] = tc;
+            // step rotation: the phase advance over kWave bins, reduced in FP64
+            double sp = P.step_cyc * tc;
+            sp -= rint(sp);
+            const float rs = (float)sp;
+            s_obs[q] = make_float4((float)(P.y[jt + q] - m.ybar), __builtin_amdgcn_cosf(rs),
+                                   __builtin_amdgcn_sinf(rs), 0.0f);
         }
         __syncthreads();
         for (int q = 0; q < cnt; ++q) {
@@ -153,6 +159,17 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
     }
 }
 
+// One queue pop for the whole workgroup: thread 0 takes the next item number
+// and every thread receives it as a wave-uniform value.  The leading barrier
+// keeps thread 0 from overwriting the broadcast slot while other threads may
+// still be reading the previous item's LDS data.
+__device__ __forceinline__ int64_t pop_item(unsigned int* counter, int64_t lo, int64_t* s_item) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_item = lo + (int64_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    return uniform_i64(*s_item);
+}
+
 template <int K, int W>
 __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
@@ -171,13 +188,10 @@ __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
         const int x = (x0 + d) % kXcds;
         const int64_t lo = (int64_t)x * per;
         const int64_t hi = lo + per < P.n_items ? lo + per : P.n_items;
-        for (;;) {
-            if (threadIdx.x == 0) s_item = lo + (int64_t)atomicAdd(&P.queue[x], 1u);
-            __syncthreads();
-            const int64_t item = s_item;
-            __syncthreads();
-            if (item >= hi) break;
+        int64_t item = pop_item(&P.queue[x], lo, &s_item);
+        while (item < hi) {
             fp32p_item<K, W>(P, item, s_tau, s_obs, s_red);
+            item = pop_item(&P.queue[x], lo, &s_item);
         }
     }
 }
@@ -206,7 +220,7 @@ __global__ __launch_bounds__(kCombineThreads) void combine_kernel(const CombineP
             bool ill;
             double p = (double)power32(xc, xs, cc, cs, (float)m.n, (float)m.scale, ill);
             if (ill)
-                p = (double)(float)power64_bin(m, P.tau, P.yp64,
+                p = (double)(float)power64_bin(m, P.t, P.y,
                                                grid_freq(P.f_min, P.df, i) * P.to_cyc);
             if (P.pgram) store_pgram(P.pgram, P.pgram_f64, i, p);
             best = PeakRec{p, i};

@@ -61,8 +61,8 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
         const int cnt = (int)((j_end - jt) < kTile ? (j_end - jt) : kTile);
         __syncthreads();
         for (int q = threadIdx.x; q < cnt; q += kWave * W) {
-            s_tau[q] = P.tau[jt + q];
-            s_y[q] = P.yp64[jt + q];
+            s_tau[q] = P.t[jt + q] - m.t0;
+            s_y[q] = P.y[jt + q] - m.ybar;
         }
         __syncthreads();
         for (int q = 0; q < cnt; ++q) {
@@ -118,16 +118,16 @@ __global__ __launch_bounds__(kFixThreads) void fixup_kernel(const FixupParams P)
         const int64_t mine = base + threadIdx.x;
         if (mine < P.n_tiles && P.ill[mine]) s_list[atomicAdd(&s_count, 1)] = mine;
         __syncthreads();
-        const int count = s_count;
+        const int count = uniform_i32(s_count);
         for (int q = 0; q < count; ++q) {
-            const int64_t tile = s_list[q];
+            const int64_t tile = uniform_i64(s_list[q]);
             const int64_t obj = tile / P.tiles_per_obj;
             const int64_t f0 = (tile - obj * P.tiles_per_obj) * P.tile_freqs;
             const ObjMeta m = P.meta[obj];
             PeakRec best{0.0, -1};
             for (int64_t i = f0 + threadIdx.x; i < f0 + P.tile_freqs && i < P.n_f;
                  i += kFixThreads) {
-                const double p = (double)(float)power64_bin(m, P.tau, P.yp64,
+                const double p = (double)(float)power64_bin(m, P.t, P.y,
                                                             grid_freq(P.f_min, P.df, i) * P.to_cyc);
                 if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, p);
                 if (better(p, i, best.p, best.i)) best = PeakRec{p, i};

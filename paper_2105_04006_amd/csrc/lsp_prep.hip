@@ -1,13 +1,13 @@
-// lsp_prep.hip -- per-object preparation ahead of the periodogram kernels.
+// lsp_prep.hip -- per-object statistics ahead of the periodogram kernels.
 //
-// Section 2 assumes zero-mean magnitudes; this kernel removes each object's
-// mean in FP64 and records S_yy = sum (y - ybar)^2, which normalises the power.
-// It also re-centres time on the object's mid-span t0 (the power does not
-// depend on the time origin, and |t - t0| halves the phase magnitude that the
-// FP32 form must reduce), and for the FP32 form tabulates per observation the
-// rotation (cos, sin)(2 pi * step * (t - t0)) that advances a lane's phase from
-// one of its frequencies to the next.  One workgroup per object; all reductions
-// are fixed-order trees, so results are bitwise reproducible.
+// Section 2 assumes zero-mean magnitudes; this kernel finds each object's mean
+// ybar in FP64 and S_yy = sum (y - ybar)^2, which normalises the power, and the
+// time origin t0 = mid-span of the object's times (the power does not depend
+// on the time origin, and |t - t0| halves the phase magnitude the FP32 form
+// must reduce).  The periodogram kernels re-centre t and y with these values
+// as they stage observations, so nothing per observation is written here and
+// objects whose CSR ranges overlap cannot interfere.  One workgroup per
+// object; all reductions are fixed-order trees (bitwise reproducible).
 #include "lsp_common.h"
 
 namespace lsp {
@@ -91,17 +91,8 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const PrepParams P) 
 
     double sq = 0.0;
     for (int64_t j = j0 + tid; j < j1; j += kPrepThreads) {
-        const double tc = P.t[j] - t0;
         const double yc = P.y[j] - ybar;
         sq += yc * yc;
-        P.tau[j] = tc;
-        P.yp64[j] = yc;
-        if (P.yp32) P.yp32[j] = (float)yc;
-        if (P.step) {
-            double s, c;
-            sincos_cycles64(P.step_cyc, tc, &s, &c);
-            P.step[j] = make_float2((float)c, (float)s);
-        }
     }
     const double syy = block_sum(sq, sh_sum);
 

@@ -10,23 +10,47 @@ Tolerances
 """
 import math
 import sys
+import time
 
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
-import oracle  # noqa: E402
+import oracle as _oracle  # noqa: E402
 from paper_2105_04006_amd import lsp, synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
+
+
+class _LoggedOracle:
+    """The oracle, announcing each call so a stalled step is named in the log."""
+
+    def __getattr__(self, name):
+        fn = getattr(_oracle, name)
+        if not callable(fn):
+            return fn
+
+        def call(*a, **k):
+            say(f"  oracle.{name}")
+            out = fn(*a, **k)
+            say(f"  oracle.{name} done")
+            return out
+
+        return call
+
+
+oracle = _LoggedOracle()
 
 FP64_RTOL, FP64_FLOOR = 1e-9, 1e-3
 FP32_ATOL = 1e-3
 
 
+_T0 = time.time()
+
+
 def say(msg):
-    print(msg, flush=True)
+    print(f"[{time.time() - _T0:8.2f}s] {msg}", flush=True)
     sys.stdout.flush()
 
 
@@ -42,6 +66,7 @@ def cuda(a, dev, dtype=torch.float64):
 
 
 def run_batch(dev, off, t, y, f_min, f_max, n_f, **kw):
+    say(f"  gpu lsp_batch n_obj={len(off) - 1} n_obs={len(t)} n_f={n_f} {kw}")
     p = lsp.Periodogram(cuda(t, dev), cuda(y, dev), f_min, f_max, n_f,
                         offsets=cuda(off, dev, torch.int64), **kw)
     p()
@@ -51,6 +76,7 @@ def run_batch(dev, off, t, y, f_min, f_max, n_f, **kw):
 
 
 def run_single(dev, t, y, f_min, f_max, n_f, **kw):
+    say(f"  gpu lsp_single n_t={len(t)} n_f={n_f} {kw}")
     p = lsp.Periodogram(cuda(t, dev), cuda(y, dev), f_min, f_max, n_f, **kw)
     p()
     torch.cuda.synchronize()
@@ -110,10 +136,6 @@ def test_single_small_fp32p(dev):
         assert peak_ok(ora_pg, ora_pk["index"], pk["index"], 2 * FP32_ATOL, bins=1)
 
 
-@pytest.mark.skip(reason="went silent for 180 s on the GPU in its first run (after the FP64 and "
-                  "FP32 single-object tests passed); no cause found by reading the kernels or by "
-                  "replaying this exact configuration in a CPU emulation of the kernels, so it "
-                  "stays off the GPU until a cause is shown")
 def test_batch_ragged_both_forms(dev):
     w = synth.make_workload("batch_10k", n_obj=40)
     n_f = 2500  # not a multiple of any tile size: ragged tail in every object

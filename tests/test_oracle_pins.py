@@ -46,6 +46,20 @@ def test_degenerate_and_bad_objects(ora):
     assert np.all(np.isnan(pg[1]))
 
 
+def test_overlapping_ranges_are_independent(ora):
+    """A malformed CSR array can make two valid ranges overlap; each object is
+    still computed from its own range alone."""
+    rng = np.random.default_rng(4)
+    t = np.sort(rng.uniform(0, 20, 12))
+    y = rng.normal(size=12)
+    off = np.array([0, 10, 2, 3, 12], dtype=np.int64)  # objects 0 and 3 overlap
+    pg, pk = ora.batch(off, t, y, 0.5, 3.0, 60)
+    assert list(pk["status"]) == [oracle.OK, oracle.BADRANGE, oracle.DEGENERATE, oracle.OK]
+    for o, (a, b) in ((0, (0, 10)), (3, (3, 12))):
+        ps, _ = ora.single(t[a:b], y[a:b], 0.5, 3.0, 60)
+        assert np.array_equal(ps, pg[o])
+
+
 def test_batch_equals_single(ora):
     from paper_2105_04006_amd import synth
 
