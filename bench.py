@@ -27,17 +27,21 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "LS obs×freq evals/s and objects/s vs plain FP64 kernel at peak-bin agreement"
-# FP32 form, first-order angle-addition recurrence: per eval 4 FMA for the
-# sums (8 flops) + 2 mul + 2 FMA for the rotation (6 flops).
-FLOPS_PER_EVAL_FP32P = 14
+# FP32 form, algorithmic flops per eval: 4 FMA for the sums (8 flops) plus the
+# recurrence, 2 mul + 2 FMA for a rotation (6 flops) or 2 FMA for the
+# three-term (Chebyshev) recurrence (4 flops).
+FLOPS_PER_EVAL = {"rotation": 14, "chebyshev": 12}
 # MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 2.4 GHz x 64 flops/clock/SIMD
 # (32 FMA lanes per clock), the published 157.3 TFLOP/s.
 PEAK_FP32_TFLOPS = 256 * 4 * 2.4e9 * 64 / 1e12
-# Per eval, as compiled for gfx950 with K = 16 frequencies per lane: 124 FP32
-# FMA/mul for the sums and rotations plus ~9 per-observation instructions
-# (FP64 phase, cvt, 2 transcendentals, moves) shared by the lane's 16 evals.
-VALU_OPS_PER_EVAL = 133 / 16
-K_PER_LANE = 16
+# VALU instructions per observation and lane in the compiled gfx950 loop, for
+# K frequencies per lane: 4K for the sums, the recurrence (4(K-1) for rotations;
+# 4 + 2(K-2) for Chebyshev), and 9-10 per-observation instructions (FP64
+# phase, cvt, 2 transcendentals, moves).  K = 16 compiles to 133 and 106.
+def valu_ops_per_eval(rec, k):
+    if rec == "chebyshev":
+        return (4 * k + 4 + 2 * (k - 2) + 10) / k
+    return (4 * k + 4 * (k - 1) + 9) / k
 KERNEL_SOURCES = ["paper_2105_04006_amd/csrc/lsp_fp32p.hip",
                   "paper_2105_04006_amd/csrc/lsp_common.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fp32p_single_4096_traffic.json")
@@ -92,7 +96,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="single_4096")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--recurrence", default="auto", choices=["auto", "rotation", "chebyshev"])
+    ap.add_argument("--k", type=int, default=0, help="frequencies per lane (0: library default)")
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--schedule", default="auto", choices=["auto", "grid", "persistent"])
     ap.add_argument("--cpu-evals", type=float, default=2e8)
+    ap.add_argument("--fp64-steps", type=int, default=0,
+                    help="timed steps of the FP64 reference form (default steps // 8, >= 3)")
+    ap.add_argument("--mode", default="lsp", choices=["lsp", "copy"],
+                    help="copy: time a plain device-to-device copy of --copy-bytes bytes "
+                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--copy-bytes", type=float, default=256 * 2**20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the periodogram of "
@@ -101,6 +115,22 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.mode == "copy":
+        n = int(args.copy_bytes) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "ms_per_copy": dt * 1e3, "GB_per_s": 8 * n / dt / 1e9}), flush=True)
+        return
 
     from paper_2105_04006_amd import lsp, synth
 
@@ -114,8 +144,12 @@ def main():
     y = torch.as_tensor(w.y, device=dev)
     off = None if single else torch.as_tensor(w.offsets, device=dev)
     kw = dict(offsets=off, pgram=single, peaks=True)
-    p32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P,
-                          schedule=lsp.SCHED_AUTO, **kw)
+    rec = {"auto": lsp.REC_AUTO, "rotation": lsp.REC_ROTATION,
+           "chebyshev": lsp.REC_CHEBYSHEV}[args.recurrence]
+    sched = {"auto": lsp.SCHED_AUTO, "grid": lsp.SCHED_GRID,
+             "persistent": lsp.SCHED_PERSISTENT}[args.schedule]
+    p32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, schedule=sched,
+                          recurrence=rec, k=args.k, waves=args.waves, **kw)
     p64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, **kw)
 
     def timed(fn, steps):
@@ -136,7 +170,7 @@ def main():
     log("[bench] warm-up done")
     ms32 = timed(p32, args.steps)
     log(f"[bench] fp32p {ms32:.4f} ms/step")
-    steps64 = max(3, args.steps // 8)
+    steps64 = args.fp64_steps if args.fp64_steps > 0 else max(3, args.steps // 8)
     ms64 = timed(p64, steps64)
     log(f"[bench] fp64 {ms64:.4f} ms/step ({steps64} steps)")
 
@@ -165,8 +199,10 @@ def main():
 
     evals = w.evals
     value = evals / (ms32 * 1e-3)
-    achieved = FLOPS_PER_EVAL_FP32P * evals / (k_ms * 1e-3) / 1e12
-    valu_ops = VALU_OPS_PER_EVAL * evals / (k_ms * 1e-3)
+    rec_name = "chebyshev" if args.recurrence == "chebyshev" else "rotation"
+    k_lane = args.k if args.k else 16
+    achieved = FLOPS_PER_EVAL[rec_name] * evals / (k_ms * 1e-3) / 1e12
+    valu_ops = valu_ops_per_eval(rec_name, k_lane) * evals / (k_ms * 1e-3)
     out = {
         "metric": METRIC,
         "value": value,
@@ -200,10 +236,12 @@ def main():
             "traffic": measured_traffic(),
             "kernel": "fp32p_kernel",
             "kernel_ms": k_ms,
-            "flops_per_eval": FLOPS_PER_EVAL_FP32P,
+            "flops_per_eval": FLOPS_PER_EVAL[rec_name],
+            "recurrence": rec_name,
+            "k_per_lane": k_lane,
             "valu_lane_ops_per_s": valu_ops,
             "valu_issue_frac": valu_ops / (PEAK_FP32_TFLOPS * 1e12 / 2),
-            "transcendentals_per_s": 2 * evals / K_PER_LANE / (k_ms * 1e-3),
+            "transcendentals_per_s": 2 * evals / k_lane / (k_ms * 1e-3),
         },
         "cpu_baseline": None,
     }

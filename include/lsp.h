@@ -72,6 +72,13 @@ enum {
 /* Element type of the periodogram output. */
 enum { LSP_PGRAM_F32 = 0, LSP_PGRAM_F64 = 1 };
 
+/* Frequency-to-frequency recurrence of the FP32 form (within one lane). */
+enum {
+    LSP_REC_AUTO = 0,
+    LSP_REC_ROTATION = 1,  /* (c, s) <- (c C - s S, s C + c S): 4 ops per step        */
+    LSP_REC_CHEBYSHEV = 2  /* x_{k+1} = 2C x_k - x_{k-1} for x = cos, sin: 2 ops/step */
+};
+
 /* Work scheduling of the batch path. */
 enum {
     LSP_SCHED_AUTO = 0,
@@ -108,7 +115,8 @@ typedef struct {
     int32_t waves_per_wg;  /* wavefronts per workgroup: 1, 2 or 4                       */
     int32_t t_split;       /* single object: split of the observation axis, 1..64       */
     int32_t schedule;      /* LSP_SCHED_*                                               */
-    int32_t reserved[4];
+    int32_t recurrence;    /* LSP_REC_* (FP32 form only)                                */
+    int32_t reserved[3];
 } lsp_options;
 
 /* One object's peak (40 bytes). */
@@ -167,6 +175,144 @@ lsp_status lsp_single(const double *t, const double *y, int64_t n_t, const lsp_g
 lsp_status lsp_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
                      const double *y, const lsp_grid *grid, const lsp_options *opt, void *pgram,
                      lsp_peak *peaks, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Row mode: the batch kernels of Section 3.4 applied to chosen parts of the
+ * grid, for refining proposed frequency bands or re-running chosen objects
+ * (the paper evaluates whole grids only; this is the same per-bin arithmetic
+ * on fewer bins).  A row is one object and either its whole grid (row_band ==
+ * NULL) or band b, the bins [b * band_bins, min((b + 1) * band_bins, n_f)).
+ * Consecutive runs of rows_per_group rows form a group whose peak is reduced
+ * together and written to peaks[row_obj[first row of the group]]; every row
+ * of a group must name that same object and no object may head two groups.
+ *   offsets, t, y, grid, opt : as lsp_batch (per-object statistics are taken
+ *               over the whole CSR range, whatever the rows).
+ *   row_obj   : device, n_rows int32 object indices in [0, n_obj).  Rows naming
+ *               another index, or a negative band, evaluate nothing.
+ *   row_band  : device, n_rows int32 band indices, or NULL.
+ *   band_bins : bins per band, 1..n_f (ignored when row_band is NULL).
+ *   pgram     : as lsp_batch, but only the bins of the rows are written.
+ *   peaks     : device, n_obj records of which only group heads are written;
+ *               the peak is the best bin over the group's rows (index -1 and
+ *               power NaN if they hold no bin).
+ *   workspace : >= lsp_rows_workspace_bytes(n_obj, n_obs, grid, opt, n_rows,
+ *               band_bins (0 when row_band is NULL), rows_per_group) bytes.
+ * Errors as lsp_batch, plus LSP_EINVAL for NULL row_obj, n_rows < 1,
+ * rows_per_group < 1 or not dividing n_rows, band_bins outside 1..n_f, and
+ * LSP_EUNSUPPORTED for t_split > 1.
+ */
+size_t lsp_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid *grid,
+                                const lsp_options *opt, int64_t n_rows, int64_t band_bins,
+                                int32_t rows_per_group);
+lsp_status lsp_batch_rows(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                          const double *y, const lsp_grid *grid, const lsp_options *opt,
+                          const int32_t *row_obj, const int32_t *row_band, int64_t n_rows,
+                          int64_t band_bins, int32_t rows_per_group, void *pgram,
+                          lsp_peak *peaks, void *workspace, size_t workspace_bytes,
+                          void *stream);
+
+/*
+ * Captured calls (HIP graphs).  A plan records one lsp_single (offsets ==
+ * NULL, n_obj == 1) or lsp_batch call with fixed arguments and buffers into a
+ * HIP graph; launching the plan replays every kernel of the call with one
+ * hipGraphLaunch, removing the per-kernel launch overhead of repeated calls on
+ * the same buffers (Section 3.4 notes that many small launches cost time).
+ * The buffers must stay allocated, unmoved and unaliased by other work for the
+ * plan's lifetime; their contents may change between launches.  The plan owns
+ * only host-side graph objects.  Argument errors are those of lsp_single /
+ * lsp_batch; LSP_EHIP if capture or instantiation fails.  Launches of one plan
+ * must not overlap each other (they share the workspace).
+ */
+typedef struct lsp_plan_s *lsp_plan;
+
+lsp_status lsp_plan_create(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                           const double *y, const lsp_grid *grid, const lsp_options *opt,
+                           void *pgram, lsp_peak *peaks, void *workspace, size_t workspace_bytes,
+                           lsp_plan *plan);
+lsp_status lsp_plan_launch(lsp_plan plan, void *stream);
+void lsp_plan_destroy(lsp_plan plan);
+
+/*
+ * Launch-shape autotuner for the FP32 form.  Times candidate shapes (K
+ * frequencies per lane, wavefronts per workgroup, recurrence, schedule and,
+ * for one object, the observation split) on the caller's data -- for a batch,
+ * on a prefix of its objects holding about 1e11 evaluations -- and writes the
+ * fastest candidate whose peaks agree with the FP64 form on those objects
+ * (within one bin on >= 99.9% of them, |dP| <= 1e-3 at the peaks) to *tuned
+ * (base's other fields are kept).  offsets == NULL tunes single-object mode.
+ *   peak_scratch : device, >= n_obj lsp_peak records (overwritten).
+ *   workspace    : device, >= lsp_autotune_workspace_bytes(...) bytes; smaller
+ *                  workspaces skip the candidates that do not fit.
+ *   cache_path   : host string or NULL.  When given, a JSON-lines file keyed by
+ *                  device architecture and the log2 classes of n_obj, mean N_t
+ *                  and n_f: a cached entry is returned without timing, and new
+ *                  results are appended.
+ *   repeats      : timed launches per candidate (>= 1).
+ * Synchronous (it reads results back to the host); allocates no device
+ * memory.  Errors as lsp_batch, LSP_EUNSUPPORTED if no candidate passes.
+ */
+size_t lsp_autotune_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid *grid,
+                                    const lsp_options *base);
+lsp_status lsp_autotune(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                        const double *y, const lsp_grid *grid, const lsp_options *base,
+                        lsp_options *tuned, lsp_peak *peak_scratch, void *workspace,
+                        size_t workspace_bytes, const char *cache_path, int32_t repeats,
+                        void *stream);
+
+/*
+ * Learned band proposal: building blocks of the small network that proposes
+ * which frequency bands to refine.  BF16 arrays are passed as raw 16-bit words
+ * (upper half of an IEEE single, round-to-nearest-even); all pointers are
+ * device pointers; all calls are asynchronous on `stream`.
+ *
+ * lsp_gemm_bf16: C = op(A) op(B) (+ bias) (ReLU) (masked), M x N, FP32
+ *   accumulation on the matrix cores.  A(m, k) is A[m*sam + k*sak] and B(k, n)
+ *   is B[k*sbk + n*sbn] (BF16), so X.W, dY.W^T and X^T.dY are all expressible.
+ *   bias: FP32 [N] or NULL.  relu: 0/1.  mask: BF16 [M x ldc] or NULL; where
+ *   mask <= 0 the result is set to 0 (ReLU backward).  Results go to C (FP32)
+ *   and/or C_bf16 (BF16), leading dimension ldc >= N; at least one non-NULL.
+ *   Errors: LSP_EINVAL for negative sizes, NULL operands, ldc < N;
+ *   LSP_EUNSUPPORTED if M or N exceeds 65535 tiles of 64.
+ */
+lsp_status lsp_gemm_bf16(int64_t M, int64_t N, int64_t K, const void *A, int64_t sam,
+                         int64_t sak, const void *B, int64_t sbk, int64_t sbn, const float *bias,
+                         const void *mask, int32_t relu, float *C, void *C_bf16, int64_t ldc,
+                         void *stream);
+
+/* Row-wise softmax cross-entropy of logits [n x c] against labels [n]:
+ * loss_rows[i] = log sum_j exp z_ij - z_i,label (0 for a label outside [0, c)),
+ * gradient (softmax - onehot) * scale into dlogits (FP32) and/or dlogits_bf16.
+ * Output pointers may be NULL. */
+lsp_status lsp_softmax_xent(const float *logits, const int32_t *labels, int64_t n, int32_t c,
+                            float scale, float *dlogits, void *dlogits_bf16, float *loss_rows,
+                            void *stream);
+
+/* out[j] = sum_i x[i*c + j] (FP32, fixed order): bias gradients. */
+lsp_status lsp_col_sums(const float *x, int64_t n, int32_t c, float *out, void *stream);
+
+/* Column mean and 1/standard deviation of x [n x d] (1 where a column is
+ * constant), for standardising network inputs. */
+lsp_status lsp_col_stats(const float *x, int64_t n, int32_t d, float *mean, float *inv_std,
+                         void *stream);
+
+/* out = BF16((x - mean) * inv_std) column-wise, x [n x d] FP32. */
+lsp_status lsp_standardize_bf16(const float *x, int64_t n, int32_t d, const float *mean,
+                                const float *inv_std, void *out, void *stream);
+
+/* out[i] = BF16(x[i]). */
+lsp_status lsp_cast_bf16(const float *x, int64_t count, void *out, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on FP32 parameters param[count]
+ * with moments m, v; refreshes param_bf16 (BF16 copy) when non-NULL. */
+lsp_status lsp_adam(float *param, const float *grad, float *m, float *v, int64_t count,
+                    int32_t step, float lr, float beta1, float beta2, float eps,
+                    void *param_bf16, void *stream);
+
+/* Per row of logits [n x c] (c <= 128): the k largest entries' indices in
+ * decreasing order (lowest index on ties) into idx [n x k], and the softmax
+ * probability mass of those k entries into mass [n] (may be NULL). */
+lsp_status lsp_top_k(const float *logits, int64_t n, int32_t c, int32_t k, int32_t *idx,
+                     float *mass, void *stream);
 
 /*
  * Optional instrumentation for profiling.  After a call with non-NULL

@@ -8,6 +8,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <new>
+
 #include "lsp_common.h"
 
 namespace lsp {
@@ -20,15 +22,31 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Config {
     int form;
+    int rec;
     int k;
     int waves;
     int split;
     int persistent;
     int64_t tile_freqs;
-    int64_t tiles_per_obj;
+    int64_t tiles_per_row;
     int64_t n_items;
-    int64_t rec_per_obj;
+    int64_t rec_per_group;
 };
+
+// Rows of work.  The whole-grid entry points use one row per object covering
+// every bin; lsp_batch_rows names (object, band) rows and groups of rows that
+// share a peak record.
+struct Rows {
+    const int32_t* row_obj;   // NULL: row r is object r
+    const int32_t* row_band;  // NULL: every row covers the whole grid
+    int64_t n_rows;
+    int64_t band_bins;        // bins per band (n_f when row_band is NULL)
+    int32_t rows_per_group;
+};
+
+Rows whole_grid(int64_t n_obj, const lsp_grid* g) {
+    return Rows{nullptr, nullptr, n_obj, g ? g->n_f : 0, 1};
+}
 
 struct Layout {
     size_t meta, rec, ill, part, queue, total;
@@ -59,15 +77,19 @@ lsp_status valid_options(const lsp_options* o) {
     }
     if (o->t_split < 0 || o->t_split > 64) return LSP_EINVAL;
     if (o->schedule < LSP_SCHED_AUTO || o->schedule > LSP_SCHED_PERSISTENT) return LSP_EINVAL;
+    if (o->recurrence < LSP_REC_AUTO || o->recurrence > LSP_REC_CHEBYSHEV) return LSP_EINVAL;
     return LSP_OK;
 }
 
 // Launch configuration: a pure function of the shape and the options, so that
 // lsp_workspace_bytes and the call agree.
 lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_options* o,
-                   Config* c) {
-    const int64_t n_f = g->n_f;
+                   const Rows& rows, Config* c) {
+    // Launch shapes are sized for the bins of one row.
+    const int64_t n_f = rows.row_band ? (rows.band_bins < g->n_f ? rows.band_bins : g->n_f) : g->n_f;
+    const bool whole = rows.row_obj == nullptr && rows.row_band == nullptr;
     c->form = o->form;
+    c->rec = o->recurrence == LSP_REC_CHEBYSHEV ? LSP_REC_CHEBYSHEV : LSP_REC_ROTATION;
     c->persistent = 0;
     c->split = 1;
     if (o->form == LSP_FORM_FP64) {
@@ -88,9 +110,9 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
             while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 4) c->k /= 2;
         c->persistent = o->schedule == LSP_SCHED_PERSISTENT ? 1 : 0;
         if (o->t_split > 1) {
-            if (n_obj != 1) return LSP_EUNSUPPORTED;
+            if (n_obj != 1 || !whole) return LSP_EUNSUPPORTED;
             c->split = o->t_split;
-        } else if (o->t_split == 0 && n_obj == 1) {
+        } else if (o->t_split == 0 && n_obj == 1 && whole) {
             // Too few frequency tiles to occupy 1024 SIMDs with a few waves
             // each: split the observation axis as well.
             const int64_t tpw = (int64_t)kWave * c->k * c->waves;
@@ -103,23 +125,26 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         }
     }
     c->tile_freqs = (int64_t)kWave * c->k * c->waves;
-    c->tiles_per_obj = (n_f + c->tile_freqs - 1) / c->tile_freqs;
-    if (c->tiles_per_obj > kMaxGrid / n_obj / c->split) return LSP_EUNSUPPORTED;
-    c->n_items = n_obj * c->tiles_per_obj * c->split;
-    c->rec_per_obj = c->split > 1 ? (n_f + kCombineThreads - 1) / kCombineThreads : c->tiles_per_obj;
+    c->tiles_per_row = (n_f + c->tile_freqs - 1) / c->tile_freqs;
+    if (c->tiles_per_row * rows.rows_per_group > kMaxGrid / rows.n_rows / c->split)
+        return LSP_EUNSUPPORTED;
+    c->n_items = rows.n_rows * c->tiles_per_row * c->split;
+    c->rec_per_group = c->split > 1 ? (n_f + kCombineThreads - 1) / kCombineThreads
+                                    : c->tiles_per_row * rows.rows_per_group;
     return LSP_OK;
 }
 
-Layout layout(int64_t n_obj, const lsp_grid* g, const Config& c) {
+Layout layout(int64_t n_obj, const lsp_grid* g, const Rows& rows, const Config& c) {
     Layout L;
     size_t off = 0;
     const bool f32 = c.form == LSP_FORM_FP32P;
+    const size_t n_groups = (size_t)(rows.n_rows / rows.rows_per_group);
     L.meta = off;
     off += align_up((size_t)n_obj * sizeof(ObjMeta));
     L.rec = off;
-    off += align_up((size_t)n_obj * (size_t)c.rec_per_obj * sizeof(PeakRec));
+    off += align_up(n_groups * (size_t)c.rec_per_group * sizeof(PeakRec));
     L.ill = off;
-    off += (f32 && c.split == 1) ? align_up((size_t)n_obj * (size_t)c.tiles_per_obj * 4) : 0;
+    off += (f32 && c.split == 1) ? align_up((size_t)rows.n_rows * (size_t)c.tiles_per_row * 4) : 0;
     L.part = off;
     off += c.split > 1 ? align_up((size_t)c.split * 4 * (size_t)g->n_f * sizeof(float)) : 0;
     L.queue = off;
@@ -136,9 +161,18 @@ T* at(void* ws, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
-               const double* y, const lsp_grid* grid, const lsp_options* opt_in, void* pgram,
-               lsp_peak* peaks, void* ws, size_t ws_bytes, void* stream) {
+// Host-side argument checks shared by every entry point; nothing is enqueued.
+lsp_status valid_rows(const Rows& r, const lsp_grid* grid) {
+    if (r.n_rows < 1 || r.rows_per_group < 1 || r.n_rows % r.rows_per_group) return LSP_EINVAL;
+    if (r.row_band && (r.band_bins < 1 || r.band_bins > grid->n_f)) return LSP_EINVAL;
+    return LSP_OK;
+}
+
+lsp_status validate(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                    const double* y, const lsp_grid* grid, const lsp_options* opt_in,
+                    const void* pgram, const lsp_peak* peaks, const void* ws, size_t ws_bytes,
+                    const Rows& rows) {
+    (void)offsets;
     if (!grid || !ws) return LSP_EINVAL;
     if (n_obj < 1 || n_obs < 0) return LSP_EINVAL;
     if (n_obs > 0 && (!t || !y)) return LSP_EINVAL;
@@ -148,11 +182,26 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
     lsp_status st = valid_options(&opt);
     if (st != LSP_OK) return st;
-    Config c;
-    st = resolve(n_obj, n_obs, grid, &opt, &c);
+    st = valid_rows(rows, grid);
     if (st != LSP_OK) return st;
-    const Layout L = layout(n_obj, grid, c);
-    if (ws_bytes < L.total) return LSP_ENOMEM;
+    Config c;
+    st = resolve(n_obj, n_obs, grid, &opt, rows, &c);
+    if (st != LSP_OK) return st;
+    if (ws_bytes < layout(n_obj, grid, rows, c).total) return LSP_ENOMEM;
+    return LSP_OK;
+}
+
+lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+               const double* y, const lsp_grid* grid, const lsp_options* opt_in, void* pgram,
+               lsp_peak* peaks, void* ws, size_t ws_bytes, void* stream, const Rows& rows) {
+    lsp_status st =
+        validate(offsets, n_obj, n_obs, t, y, grid, opt_in, pgram, peaks, ws, ws_bytes, rows);
+    if (st != LSP_OK) return st;
+    const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
+    Config c;
+    resolve(n_obj, n_obs, grid, &opt, rows, &c);
+    const Layout L = layout(n_obj, grid, rows, c);
+    const int64_t n_groups = rows.n_rows / rows.rows_per_group;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double df = (grid->f_max - grid->f_min) / (double)grid->n_f;
@@ -180,7 +229,10 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     mp.to_cyc = to_cyc;
     mp.n_f = grid->n_f;
     mp.n_obj = n_obj;
-    mp.tiles_per_obj = c.tiles_per_obj;
+    mp.row_obj = rows.row_obj;
+    mp.row_band = rows.row_band;
+    mp.band_bins = rows.row_band ? rows.band_bins : grid->n_f;
+    mp.tiles_per_row = c.tiles_per_row;
     mp.n_items = c.n_items;
     mp.n_split = c.split;
     mp.pgram_f64 = opt.pgram_dtype == LSP_PGRAM_F64;
@@ -196,7 +248,7 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
         return LSP_EHIP;
     if (t_main_begin && hipEventRecord(t_main_begin, s) != hipSuccess) return LSP_EHIP;
     if (f32) {
-        if (launch_fp32p(mp, c.k, c.waves, s) != hipSuccess) return LSP_EHIP;
+        if (launch_fp32p(mp, c.k, c.waves, c.rec, s) != hipSuccess) return LSP_EHIP;
     } else {
         if (launch_fp64(mp, c.k, c.waves, s) != hipSuccess) return LSP_EHIP;
     }
@@ -212,8 +264,12 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             fp.df = df;
             fp.to_cyc = to_cyc;
             fp.n_f = mp.n_f;
-            fp.tiles_per_obj = c.tiles_per_obj;
-            fp.n_tiles = n_obj * c.tiles_per_obj;
+            fp.n_obj = n_obj;
+            fp.row_obj = mp.row_obj;
+            fp.row_band = mp.row_band;
+            fp.band_bins = mp.band_bins;
+            fp.tiles_per_row = c.tiles_per_row;
+            fp.n_tiles = rows.n_rows * c.tiles_per_row;
             fp.tile_freqs = c.tile_freqs;
             fp.pgram_f64 = mp.pgram_f64;
             fp.pad = 0;
@@ -243,7 +299,11 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
         kp.meta = mp.meta;
         kp.rec = mp.rec;
         kp.n_obj = n_obj;
-        kp.rec_per_obj = c.rec_per_obj;
+        kp.n_groups = n_groups;
+        kp.row_obj = rows.row_obj;
+        kp.rows_per_group = rows.rows_per_group;
+        kp.pad2 = 0;
+        kp.rec_per_obj = c.rec_per_group;
         kp.f_min = grid->f_min;
         kp.df = df;
         kp.unit = grid->unit;
@@ -256,6 +316,11 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
 
 }  // namespace
 }  // namespace lsp
+
+struct lsp_plan_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
 
 extern "C" {
 
@@ -273,9 +338,26 @@ size_t lsp_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
     if (n_obj < 1 || n_obs < 0 || !lsp::valid_grid(grid)) return 0;
     const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
     if (lsp::valid_options(&opt) != LSP_OK) return 0;
+    const lsp::Rows rows = lsp::whole_grid(n_obj, grid);
     lsp::Config c;
-    if (lsp::resolve(n_obj, n_obs, grid, &opt, &c) != LSP_OK) return 0;
-    return lsp::layout(n_obj, grid, c).total;
+    if (lsp::resolve(n_obj, n_obs, grid, &opt, rows, &c) != LSP_OK) return 0;
+    return lsp::layout(n_obj, grid, rows, c).total;
+}
+
+size_t lsp_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                                const lsp_options* opt_in, int64_t n_rows, int64_t band_bins,
+                                int32_t rows_per_group) {
+    if (n_obj < 1 || n_obs < 0 || !lsp::valid_grid(grid)) return 0;
+    const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
+    if (lsp::valid_options(&opt) != LSP_OK) return 0;
+    // Any non-null band pointer stands for "banded" when sizing.
+    static const int32_t kBanded = 0;
+    const lsp::Rows rows{&kBanded, band_bins > 0 ? &kBanded : nullptr, n_rows, band_bins,
+                         rows_per_group};
+    if (lsp::valid_rows(rows, grid) != LSP_OK) return 0;
+    lsp::Config c;
+    if (lsp::resolve(n_obj, n_obs, grid, &opt, rows, &c) != LSP_OK) return 0;
+    return lsp::layout(n_obj, grid, rows, c).total;
 }
 
 lsp_status lsp_single(const double* t, const double* y, int64_t n_t, const lsp_grid* grid,
@@ -283,7 +365,7 @@ lsp_status lsp_single(const double* t, const double* y, int64_t n_t, const lsp_g
                       size_t workspace_bytes, void* stream) {
     if (n_t < 0) return LSP_EINVAL;
     return lsp::run(nullptr, 1, n_t, t, y, grid, opt, pgram, peak, workspace, workspace_bytes,
-                    stream);
+                    stream, lsp::whole_grid(1, grid));
 }
 
 lsp_status lsp_batch(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
@@ -291,7 +373,78 @@ lsp_status lsp_batch(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const
                      lsp_peak* peaks, void* workspace, size_t workspace_bytes, void* stream) {
     if (!offsets) return LSP_EINVAL;
     return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
-                    workspace_bytes, stream);
+                    workspace_bytes, stream, lsp::whole_grid(n_obj, grid));
+}
+
+lsp_status lsp_batch_rows(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                          const double* y, const lsp_grid* grid, const lsp_options* opt,
+                          const int32_t* row_obj, const int32_t* row_band, int64_t n_rows,
+                          int64_t band_bins, int32_t rows_per_group, void* pgram,
+                          lsp_peak* peaks, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+    if (!offsets || !row_obj) return LSP_EINVAL;
+    if (!row_band) band_bins = grid ? grid->n_f : 0;
+    const lsp::Rows rows{row_obj, row_band, n_rows, band_bins, rows_per_group};
+    return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
+                    workspace_bytes, stream, rows);
+}
+
+lsp_status lsp_plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                           const double* y, const lsp_grid* grid, const lsp_options* opt,
+                           void* pgram, lsp_peak* peaks, void* workspace, size_t workspace_bytes,
+                           lsp_plan* plan) {
+    if (!plan) return LSP_EINVAL;
+    *plan = nullptr;
+    if (!offsets && n_obj != 1) return LSP_EINVAL;
+    // Validate first, on the host, so that an argument error never leaves a
+    // half-open capture behind.
+    {
+        lsp_status st = lsp::validate(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks,
+                                      workspace, workspace_bytes, lsp::whole_grid(n_obj, grid));
+        if (st != LSP_OK) return st;
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LSP_EHIP;
+    hipGraph_t graph = nullptr;
+    lsp_status st = LSP_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = LSP_EHIP;
+    } else {
+        st = lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
+                      workspace_bytes, cs, lsp::whole_grid(n_obj, grid));
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess && st == LSP_OK) st = LSP_EHIP;
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != LSP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return LSP_EHIP;
+    }
+    lsp_plan p = new (std::nothrow) lsp_plan_s{graph, exec};
+    if (!p) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return LSP_EHIP;
+    }
+    *plan = p;
+    return LSP_OK;
+}
+
+lsp_status lsp_plan_launch(lsp_plan plan, void* stream) {
+    if (!plan) return LSP_EINVAL;
+    return hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? LSP_OK
+                                                                                       : LSP_EHIP;
+}
+
+void lsp_plan_destroy(lsp_plan plan) {
+    if (!plan) return;
+    (void)hipGraphExecDestroy(plan->exec);
+    (void)hipGraphDestroy(plan->graph);
+    delete plan;
 }
 
 lsp_status lsp_set_stage_events(void* main_begin, void* main_end) {

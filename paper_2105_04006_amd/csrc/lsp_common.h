@@ -201,6 +201,38 @@ __device__ __forceinline__ int32_t uniform_i32(int32_t v) {
     return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
 }
 
+// A row of work: one object's whole grid, or one band of it.
+struct RowRange {
+    int64_t obj;
+    int64_t f_lo, f_hi;  // frequency indices [f_lo, f_hi); empty if the row is invalid
+};
+
+__device__ __forceinline__ RowRange decode_row(const int32_t* row_obj, const int32_t* row_band,
+                                               int64_t band_bins, int64_t n_obj, int64_t n_f,
+                                               int64_t row) {
+    RowRange r;
+    r.obj = row_obj ? (int64_t)row_obj[row] : row;
+    r.f_lo = 0;
+    r.f_hi = n_f;
+    if (row_band) {
+        const int64_t b = row_band[row];
+        r.f_lo = b * band_bins;
+        r.f_hi = r.f_lo + band_bins < n_f ? r.f_lo + band_bins : n_f;
+        if (b < 0) r.f_lo = r.f_hi = 0;
+    }
+    if (r.obj < 0 || r.obj >= n_obj) {
+        r.obj = -1;
+        r.f_lo = r.f_hi = 0;
+    }
+    // The row index is wave-uniform, so these are too; say so to the compiler,
+    // since they bound loops that hold barriers.
+    r.obj = uniform_i64(r.obj);
+    r.f_lo = uniform_i64(r.f_lo);
+    r.f_hi = uniform_i64(r.f_hi);
+    return r;
+}
+
+
 // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs,
 // so block b runs on XCD b % 8.  Remap so that each XCD receives a contiguous
 // run of items (and hence the same objects stay in one XCD's L2).
@@ -232,13 +264,16 @@ struct MainParams {
     double step_cyc;  // FP32 form: lane-stride frequency step (kWave bins) in cycles
     int64_t n_f;
     int64_t n_obj;
-    int64_t tiles_per_obj;  // frequency tiles per object
-    int64_t n_items;        // n_obj * tiles_per_obj * n_split
+    const int32_t* row_obj;   // object of each row, or NULL: row r is object r
+    const int32_t* row_band;  // band of each row ([b*band_bins, (b+1)*band_bins)), or NULL
+    int64_t band_bins;
+    int64_t tiles_per_row;  // frequency tiles per row
+    int64_t n_items;        // n_rows * tiles_per_row * n_split
     int32_t n_split;        // observation-axis split (single object only)
     int32_t pgram_f64;
     void* pgram;             // NULL: peaks only
-    PeakRec* rec;            // [n_obj * tiles_per_obj] when n_split == 1
-    uint32_t* ill;           // [n_obj * tiles_per_obj]: tile needs the FP64 fix-up
+    PeakRec* rec;            // [n_rows * tiles_per_row] when n_split == 1
+    uint32_t* ill;           // [n_rows * tiles_per_row]: tile needs the FP64 fix-up
     float* part;             // [n_split][4][n_f] when n_split > 1
     unsigned int* queue;     // persistent schedule: kXcds counters
     int32_t persistent;
@@ -265,7 +300,11 @@ struct FixupParams {
     const uint32_t* ill;
     double f_min, df, to_cyc;
     int64_t n_f;
-    int64_t tiles_per_obj;
+    int64_t n_obj;
+    const int32_t* row_obj;
+    const int32_t* row_band;
+    int64_t band_bins;
+    int64_t tiles_per_row;
     int64_t n_tiles;
     int64_t tile_freqs;
     int32_t pgram_f64;
@@ -278,7 +317,11 @@ struct PeakParams {
     const ObjMeta* meta;
     const PeakRec* rec;
     int64_t n_obj;
-    int64_t rec_per_obj;
+    int64_t n_groups;        // groups of rows; group g covers rows [g R, (g+1) R)
+    const int32_t* row_obj;  // object of each row, or NULL (group g is object g)
+    int32_t rows_per_group;  // R
+    int32_t pad2;
+    int64_t rec_per_obj;     // records per group
     double f_min, df;
     int32_t unit;
     int32_t pad;
@@ -287,11 +330,11 @@ struct PeakParams {
 
 hipError_t launch_prep(const PrepParams& p, hipStream_t s);
 hipError_t launch_fp64(const MainParams& p, int kf, int waves, hipStream_t s);
-hipError_t launch_fp32p(const MainParams& p, int k, int waves, hipStream_t s);
+hipError_t launch_fp32p(const MainParams& p, int k, int waves, int rec, hipStream_t s);
 hipError_t launch_fixup(const FixupParams& p, hipStream_t s);
 hipError_t launch_combine(const CombineParams& p, hipStream_t s);
 hipError_t launch_peaks(const PeakParams& p, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* dst, int64_t n, unsigned int v, hipStream_t s);
-int persistent_blocks(int k, int waves, int form);
+
 
 }  // namespace lsp

@@ -34,7 +34,7 @@
 namespace lsp {
 namespace {
 
-template <int K, int W>
+template <int K, int W, bool CHEB>
 __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, double* s_tau,
                                            float4* s_obs, PeakRec* s_red) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -42,10 +42,20 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
     const int64_t tile_freqs = (int64_t)kWave * K * W;
     const int64_t tile = item / P.n_split;
     const int split = (int)(item - tile * P.n_split);
-    const int64_t obj = tile / P.tiles_per_obj;
-    const int64_t ftile = tile - obj * P.tiles_per_obj;
+    const int64_t row = tile / P.tiles_per_row;
+    const int64_t ftile = tile - row * P.tiles_per_row;
+    const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.n_obj, P.n_f, row);
+    const int64_t obj = rr.obj;
+    const int64_t i0 = rr.f_lo + ftile * tile_freqs + (int64_t)wave * kWave * K + lane;
+    const int64_t f_hi = rr.f_hi;
+    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) {  // invalid row or empty tile
+        if (threadIdx.x == 0 && P.n_split == 1) {
+            P.rec[tile] = PeakRec{0.0, -1};
+            P.ill[tile] = 0u;
+        }
+        return;
+    }
     const ObjMeta m = P.meta[obj];
-    const int64_t i0 = ftile * tile_freqs + (int64_t)wave * kWave * K + lane;
 
     if (m.status != LSP_OBJ_OK) {
         if (P.n_split == 1) {
@@ -54,7 +64,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int64_t i = i0 + (int64_t)kWave * k;
-                    if (i < P.n_f) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
+                    if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
                 }
             }
             if (threadIdx.x == 0) {
@@ -97,16 +107,45 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
             const float r = (float)ph;
             float s = __builtin_amdgcn_sinf(r);
             float c = __builtin_amdgcn_cosf(r);
+            if (!CHEB) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                xc[k] = fmaf(o.x, c, xc[k]);
-                xs[k] = fmaf(o.x, s, xs[k]);
-                cc[k] = fmaf(c, c, cc[k]);
-                cs[k] = fmaf(c, s, cs[k]);
-                if (k + 1 < K) {
-                    const float cn = fmaf(c, o.y, -(s * o.z));
-                    s = fmaf(s, o.y, c * o.z);
-                    c = cn;
+                for (int k = 0; k < K; ++k) {
+                    xc[k] = fmaf(o.x, c, xc[k]);
+                    xs[k] = fmaf(o.x, s, xs[k]);
+                    cc[k] = fmaf(c, c, cc[k]);
+                    cs[k] = fmaf(c, s, cs[k]);
+                    if (k + 1 < K) {
+                        const float cn = fmaf(c, o.y, -(s * o.z));
+                        s = fmaf(s, o.y, c * o.z);
+                        c = cn;
+                    }
+                }
+            } else {
+                // One rotation to reach the second frequency, then the
+                // three-term recurrence x_{k+1} = 2C x_k - x_{k-1}, which
+                // cos and sin of an arithmetic progression of angles obey.
+                const float two_c = o.y + o.y;
+                float cp = c, sp = s;
+                c = fmaf(cp, o.y, -(sp * o.z));
+                s = fmaf(sp, o.y, cp * o.z);
+                xc[0] = fmaf(o.x, cp, xc[0]);
+                xs[0] = fmaf(o.x, sp, xs[0]);
+                cc[0] = fmaf(cp, cp, cc[0]);
+                cs[0] = fmaf(cp, sp, cs[0]);
+#pragma unroll
+                for (int k = 1; k < K; ++k) {
+                    xc[k] = fmaf(o.x, c, xc[k]);
+                    xs[k] = fmaf(o.x, s, xs[k]);
+                    cc[k] = fmaf(c, c, cc[k]);
+                    cs[k] = fmaf(c, s, cs[k]);
+                    if (k + 1 < K) {
+                        const float cn = fmaf(two_c, c, -cp);
+                        const float sn = fmaf(two_c, s, -sp);
+                        cp = c;
+                        sp = s;
+                        c = cn;
+                        s = sn;
+                    }
                 }
             }
         }
@@ -118,7 +157,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int64_t i = i0 + (int64_t)kWave * k;
-            if (i < nf) {
+            if (i < f_hi) {
                 base[i] = xc[k];
                 base[nf + i] = xs[k];
                 base[2 * nf + i] = cc[k];
@@ -135,7 +174,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t i = i0 + (int64_t)kWave * k;
-        if (i < P.n_f) {
+        if (i < f_hi) {
             bool ill;
             const double p = (double)power32(xc[k], xs[k], cc[k], cs[k], n, scale, ill);
             any_ill |= ill;
@@ -170,7 +209,7 @@ __device__ __forceinline__ int64_t pop_item(unsigned int* counter, int64_t lo, i
     return uniform_i64(*s_item);
 }
 
-template <int K, int W>
+template <int K, int W, bool CHEB>
 __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
     __shared__ float4 s_obs[kTile];
@@ -179,7 +218,7 @@ __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
 
     if (!P.persistent) {
         const int64_t b = linear_block();
-        if (b < P.n_items) fp32p_item<K, W>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red);
+        if (b < P.n_items) fp32p_item<K, W, CHEB>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red);
         return;
     }
     const int64_t per = (P.n_items + kXcds - 1) / kXcds;
@@ -190,7 +229,7 @@ __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
         const int64_t hi = lo + per < P.n_items ? lo + per : P.n_items;
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
-            fp32p_item<K, W>(P, item, s_tau, s_obs, s_red);
+            fp32p_item<K, W, CHEB>(P, item, s_tau, s_obs, s_red);
             item = pop_item(&P.queue[x], lo, &s_item);
         }
     }
@@ -239,24 +278,11 @@ __global__ __launch_bounds__(kCombineThreads) void combine_kernel(const CombineP
     }
 }
 
-template <int K>
-hipError_t launch_k(const MainParams& p, int waves, hipStream_t s) {
-    const dim3 grid = p.persistent ? dim3((unsigned)persistent_blocks(K, waves, LSP_FORM_FP32P))
-                                   : grid_for(p.n_items);
-    switch (waves) {
-        case 1: hipLaunchKernelGGL((fp32p_kernel<K, 1>), grid, dim3(kWave * 1), 0, s, p); break;
-        case 2: hipLaunchKernelGGL((fp32p_kernel<K, 2>), grid, dim3(kWave * 2), 0, s, p); break;
-        case 4: hipLaunchKernelGGL((fp32p_kernel<K, 4>), grid, dim3(kWave * 4), 0, s, p); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int K, int W>
+template <int K, int W, bool CHEB>
 int occupancy_blocks() {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fp32p_kernel<K, W>, kWave * W, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fp32p_kernel<K, W, CHEB>, kWave * W,
+                                                     0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int dev = 0, cus = 0;
@@ -267,36 +293,41 @@ int occupancy_blocks() {
     return per_cu * cus;
 }
 
-template <int K>
-int occupancy_k(int waves) {
+template <int K, int W, bool CHEB>
+hipError_t launch_kwc(const MainParams& p, hipStream_t s) {
+    const dim3 grid = p.persistent ? dim3((unsigned)occupancy_blocks<K, W, CHEB>())
+                                   : grid_for(p.n_items);
+    hipLaunchKernelGGL((fp32p_kernel<K, W, CHEB>), grid, dim3(kWave * W), 0, s, p);
+    return hipGetLastError();
+}
+
+template <int K, bool CHEB>
+hipError_t launch_kc(const MainParams& p, int waves, hipStream_t s) {
     switch (waves) {
-        case 1: return occupancy_blocks<K, 1>();
-        case 2: return occupancy_blocks<K, 2>();
-        default: return occupancy_blocks<K, 4>();
+        case 1: return launch_kwc<K, 1, CHEB>(p, s);
+        case 2: return launch_kwc<K, 2, CHEB>(p, s);
+        case 4: return launch_kwc<K, 4, CHEB>(p, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool CHEB>
+hipError_t launch_c(const MainParams& p, int k, int waves, hipStream_t s) {
+    switch (k) {
+        case 4: return launch_kc<4, CHEB>(p, waves, s);
+        case 8: return launch_kc<8, CHEB>(p, waves, s);
+        case 16: return launch_kc<16, CHEB>(p, waves, s);
+        case 32: return launch_kc<32, CHEB>(p, waves, s);
+        default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_fp32p(const MainParams& p, int k, int waves, hipStream_t s) {
+hipError_t launch_fp32p(const MainParams& p, int k, int waves, int rec, hipStream_t s) {
     if (p.n_items <= 0) return hipSuccess;
-    switch (k) {
-        case 4: return launch_k<4>(p, waves, s);
-        case 8: return launch_k<8>(p, waves, s);
-        case 16: return launch_k<16>(p, waves, s);
-        case 32: return launch_k<32>(p, waves, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-int persistent_blocks(int k, int waves, int form) {
-    (void)form;
-    switch (k) {
-        case 4: return occupancy_k<4>(waves);
-        case 8: return occupancy_k<8>(waves);
-        case 16: return occupancy_k<16>(waves);
-        default: return occupancy_k<32>(waves);
-    }
+    return rec == LSP_REC_CHEBYSHEV ? launch_c<true>(p, k, waves, s)
+                                    : launch_c<false>(p, k, waves, s);
 }
 
 hipError_t launch_combine(const CombineParams& p, hipStream_t s) {

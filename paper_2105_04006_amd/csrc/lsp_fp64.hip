@@ -30,10 +30,17 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
     const int64_t b = linear_block();
     if (b >= P.n_items) return;
     const int64_t item = xcd_remap(b, P.n_items);
-    const int64_t obj = item / P.tiles_per_obj;
-    const int64_t ftile = item - obj * P.tiles_per_obj;
+    const int64_t row = item / P.tiles_per_row;
+    const int64_t ftile = item - row * P.tiles_per_row;
+    const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.n_obj, P.n_f, row);
+    const int64_t obj = rr.obj;
+    const int64_t i0 = rr.f_lo + ftile * tile_freqs + (int64_t)wave * kWave * KF + lane;
+    const int64_t f_hi = rr.f_hi;
+    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) {
+        if (threadIdx.x == 0) P.rec[item] = PeakRec{0.0, -1};
+        return;
+    }
     const ObjMeta m = P.meta[obj];
-    const int64_t i0 = ftile * tile_freqs + (int64_t)wave * kWave * KF + lane;
 
     if (m.status != LSP_OBJ_OK) {
         if (P.pgram) {
@@ -41,7 +48,7 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
                 const int64_t i = i0 + (int64_t)kWave * k;
-                if (i < P.n_f) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
+                if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
             }
         }
         if (threadIdx.x == 0) P.rec[item] = PeakRec{0.0, -1};
@@ -82,7 +89,7 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
 #pragma unroll
     for (int k = 0; k < KF; ++k) {
         const int64_t i = i0 + (int64_t)kWave * k;
-        if (i < P.n_f) {
+        if (i < f_hi) {
             const double p = power64(acc[k], n, m.scale);
             if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, p);
             if (better(p, i, best.p, best.i)) best = PeakRec{p, i};
@@ -121,11 +128,14 @@ __global__ __launch_bounds__(kFixThreads) void fixup_kernel(const FixupParams P)
         const int count = uniform_i32(s_count);
         for (int q = 0; q < count; ++q) {
             const int64_t tile = uniform_i64(s_list[q]);
-            const int64_t obj = tile / P.tiles_per_obj;
-            const int64_t f0 = (tile - obj * P.tiles_per_obj) * P.tile_freqs;
+            const int64_t row = tile / P.tiles_per_row;
+            const RowRange rr =
+                decode_row(P.row_obj, P.row_band, P.band_bins, P.n_obj, P.n_f, row);
+            const int64_t obj = rr.obj < 0 ? 0 : rr.obj;
+            const int64_t f0 = rr.f_lo + (tile - row * P.tiles_per_row) * P.tile_freqs;
             const ObjMeta m = P.meta[obj];
             PeakRec best{0.0, -1};
-            for (int64_t i = f0 + threadIdx.x; i < f0 + P.tile_freqs && i < P.n_f;
+            for (int64_t i = f0 + threadIdx.x; i < f0 + P.tile_freqs && i < rr.f_hi;
                  i += kFixThreads) {
                 const double p = (double)(float)power64_bin(m, P.t, P.y,
                                                             grid_freq(P.f_min, P.df, i) * P.to_cyc);

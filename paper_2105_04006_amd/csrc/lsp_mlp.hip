@@ -1,0 +1,359 @@
+// lsp_mlp.hip -- kernels of the learned band proposal: a BF16 matrix-core GEMM
+// with FP32 accumulation (forward X.W, backward-data dY.W^T and
+// backward-weight X^T.dY all use it through strides), and the small element
+// kernels around it (softmax cross-entropy, column sums, Adam, feature
+// standardisation, top-k bands, FP32 -> BF16).
+//
+// GEMM tiling: a 256-thread workgroup (4 wavefronts) owns a 64 x 64 tile of C
+// and walks K in steps of 32.  Each step stages a 64 x 32 slice of A and a
+// 32 x 64 slice of B into LDS with K contiguous (whatever the source strides),
+// then each wavefront issues 2 x 2 v_mfma_f32_16x16x32_bf16 for its 32 x 32
+// quarter.  A lane supplies row (lane % 16) of A and column (lane % 16) of B
+// with eight consecutive k; both operands use the same k assignment, so the
+// product does not depend on how the instruction orders k internally.  The
+// 16 x 16 result is held as rows 4 (lane / 16) + r, column lane % 16.
+#include <math.h>
+#include <stdint.h>
+
+#include "lsp_common.h"
+
+namespace lsp {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBM = 64, kBN = 64, kBK = 32;
+constexpr int kLdsK = kBK + 8;  // padded row: 80 bytes, keeps 16-byte fragment reads aligned
+constexpr int kGemmThreads = 256;
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+struct GemmArgs {
+    int64_t M, N, K;
+    const uint16_t* A;
+    int64_t sam, sak;
+    const uint16_t* B;
+    int64_t sbk, sbn;
+    const float* bias;     // [N] or NULL
+    const uint16_t* mask;  // BF16 [M x N], leading dimension ldc: keep C where mask > 0
+    int32_t relu;
+    int32_t pad;
+    float* Cf;             // FP32 output or NULL
+    uint16_t* Cb;          // BF16 output or NULL
+    int64_t ldc;
+};
+
+__global__ __launch_bounds__(kGemmThreads) void gemm_bf16_kernel(const GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLdsK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLdsK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.y * kBM, n0 = (int64_t)blockIdx.x * kBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // staging assignment: thread -> (row of the tile, 8 consecutive k)
+    const int srow = tid >> 2, sk = (tid & 3) * 8;
+    for (int64_t k0 = 0; k0 < g.K; k0 += kBK) {
+        {
+            const int64_t m = m0 + srow;
+            uint16_t v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t k = k0 + sk + e;
+                v[e] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) As[srow * kLdsK + sk + e] = v[e];
+            const int64_t n = n0 + srow;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t k = k0 + sk + e;
+                v[e] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Bs[srow * kLdsK + sk + e] = v[e];
+        }
+        __syncthreads();
+        const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 a =
+                *reinterpret_cast<const bf16x8*>(&As[(wm + 16 * i + fr) * kLdsK + fk]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 b =
+                    *reinterpret_cast<const bf16x8*>(&Bs[(wn + 16 * j + fr) * kLdsK + fk]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int64_t n = n0 + wn + 16 * j + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][r];
+                if (g.bias) v += g.bias[n];
+                if (g.relu) v = v > 0.f ? v : 0.f;
+                if (g.mask && !(bf16_bits_to_f32(g.mask[m * g.ldc + n]) > 0.f)) v = 0.f;
+                if (g.Cf) g.Cf[m * g.ldc + n] = v;
+                if (g.Cb) g.Cb[m * g.ldc + n] = f32_to_bf16_bits(v);
+            }
+}
+
+// One wavefront per row: softmax of the row's logits, cross-entropy against
+// the label, and the gradient (softmax - onehot) * scale.
+__global__ __launch_bounds__(256) void softmax_xent_kernel(const float* __restrict__ logits,
+                                                           const int32_t* __restrict__ labels,
+                                                           int64_t n, int32_t c, float scale,
+                                                           float* dlogits, uint16_t* dlogits_bf16,
+                                                           float* loss_rows) {
+    const int64_t row = linear_block() * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const float* z = logits + row * c;
+    float mx = -INFINITY;
+    for (int j = lane; j < c; j += 64) mx = fmaxf(mx, z[j]);
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    float se = 0.f;
+    for (int j = lane; j < c; j += 64) se += expf(z[j] - mx);
+    for (int off = 32; off >= 1; off >>= 1) se += __shfl_xor(se, off, 64);
+    const int32_t lab = labels[row];
+    for (int j = lane; j < c; j += 64) {
+        const float p = expf(z[j] - mx) / se;
+        const float d = (p - (j == lab ? 1.f : 0.f)) * scale;
+        if (dlogits) dlogits[row * c + j] = d;
+        if (dlogits_bf16) dlogits_bf16[row * c + j] = f32_to_bf16_bits(d);
+    }
+    if (lane == 0 && loss_rows)
+        loss_rows[row] = (lab >= 0 && lab < c) ? (logf(se) + mx - z[lab]) : 0.f;
+}
+
+// Column sums of an n x c FP32 matrix, one thread per column, fixed order.
+__global__ void col_sums_kernel(const float* __restrict__ x, int64_t n, int32_t c, float* out) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= c) return;
+    float s = 0.f;
+    for (int64_t i = 0; i < n; ++i) s += x[i * c + j];
+    out[j] = s;
+}
+
+// Column mean and 1/std (population) of an n x d FP32 matrix; a column with no
+// spread gets 1/std = 1.  One thread per column, fixed order, FP64 sums.
+__global__ void col_stats_kernel(const float* __restrict__ x, int64_t n, int32_t d, float* mean,
+                                 float* inv_std) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (double)x[i * d + j];
+    const double mu = n > 0 ? s / (double)n : 0.0;
+    double q = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double e = (double)x[i * d + j] - mu;
+        q += e * e;
+    }
+    const double sd = n > 0 ? sqrt(q / (double)n) : 0.0;
+    mean[j] = (float)mu;
+    inv_std[j] = sd > 1e-12 ? (float)(1.0 / sd) : 1.0f;
+}
+
+__global__ void standardize_kernel(const float* __restrict__ x, int64_t n, int32_t d,
+                                   const float* __restrict__ mean,
+                                   const float* __restrict__ inv_std, uint16_t* out) {
+    const int64_t i = linear_block() * blockDim.x + threadIdx.x;
+    if (i >= n * d) return;
+    const int32_t j = (int32_t)(i % d);
+    out[i] = f32_to_bf16_bits((x[i] - mean[j]) * inv_std[j]);
+}
+
+__global__ void cast_bf16_kernel(const float* __restrict__ x, int64_t count, uint16_t* out) {
+    const int64_t i = linear_block() * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = f32_to_bf16_bits(x[i]);
+}
+
+// Adam with bias correction on FP32 master parameters; optionally refreshes
+// the BF16 copy the GEMMs read.
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ grad,
+                            float* __restrict__ m, float* __restrict__ v, int64_t count,
+                            float lr, float b1, float b2, float eps, float c1, float c2,
+                            uint16_t* p_bf16) {
+    const int64_t i = linear_block() * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = grad[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (p_bf16) p_bf16[i] = f32_to_bf16_bits(pi);
+}
+
+// One wavefront per row: the k largest of c logits (lowest index on ties), in
+// decreasing order, and the softmax probability mass they carry.
+__global__ __launch_bounds__(256) void top_k_kernel(const float* __restrict__ logits, int64_t n,
+                                                    int32_t c, int32_t k, int32_t* idx,
+                                                    float* mass) {
+    const int64_t row = linear_block() * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const float* z = logits + row * c;
+    // each lane holds up to two logits (c <= 128)
+    float v0 = lane < c ? z[lane] : -INFINITY;
+    float v1 = lane + 64 < c ? z[lane + 64] : -INFINITY;
+    float mx = fmaxf(v0, v1);
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    float se = (lane < c ? expf(v0 - mx) : 0.f) + (lane + 64 < c ? expf(v1 - mx) : 0.f);
+    for (int off = 32; off >= 1; off >>= 1) se += __shfl_xor(se, off, 64);
+    float taken = 0.f;
+    for (int r = 0; r < k; ++r) {
+        float bv = v0;
+        int bi = lane < c ? lane : 1 << 30;
+        if (v1 > bv || (v1 == bv && lane + 64 < c && lane + 64 < bi)) {
+            bv = v1;
+            bi = lane + 64 < c ? lane + 64 : 1 << 30;
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float ov = __shfl_xor(bv, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) idx[row * k + r] = bi < c ? bi : -1;
+        if (bi < c) taken += expf(bv - mx);
+        if (bi == lane) v0 = -INFINITY;
+        if (bi == lane + 64) v1 = -INFINITY;
+    }
+    if (lane == 0 && mass) mass[row] = taken / se;
+}
+
+}  // namespace
+}  // namespace lsp
+
+extern "C" {
+
+lsp_status lsp_gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t sam, int64_t sak,
+                         const void* B, int64_t sbk, int64_t sbn, const float* bias,
+                         const void* mask, int32_t relu, float* C, void* C_bf16, int64_t ldc,
+                         void* stream) {
+    if (M < 0 || N < 0 || K < 0 || (M > 0 && N > 0 && (!A || !B)) || (!C && !C_bf16) ||
+        ldc < N || (relu != 0 && relu != 1))
+        return LSP_EINVAL;
+    if ((M + lsp::kBM - 1) / lsp::kBM > 65535 || (N + lsp::kBN - 1) / lsp::kBN > 65535)
+        return LSP_EUNSUPPORTED;
+    if (M == 0 || N == 0) return LSP_OK;
+    lsp::GemmArgs g;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.A = static_cast<const uint16_t*>(A);
+    g.sam = sam;
+    g.sak = sak;
+    g.B = static_cast<const uint16_t*>(B);
+    g.sbk = sbk;
+    g.sbn = sbn;
+    g.bias = bias;
+    g.mask = static_cast<const uint16_t*>(mask);
+    g.relu = relu;
+    g.pad = 0;
+    g.Cf = C;
+    g.Cb = static_cast<uint16_t*>(C_bf16);
+    g.ldc = ldc;
+    const dim3 grid((unsigned)((N + lsp::kBN - 1) / lsp::kBN),
+                    (unsigned)((M + lsp::kBM - 1) / lsp::kBM));
+    hipLaunchKernelGGL(lsp::gemm_bf16_kernel, grid, dim3(lsp::kGemmThreads), 0,
+                       static_cast<hipStream_t>(stream), g);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_softmax_xent(const float* logits, const int32_t* labels, int64_t n, int32_t c,
+                            float scale, float* dlogits, void* dlogits_bf16, float* loss_rows,
+                            void* stream) {
+    if (n < 0 || c < 1 || (n > 0 && (!logits || !labels))) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::softmax_xent_kernel, lsp::grid_for((n + 3) / 4), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), logits, labels, n, c, scale, dlogits,
+                       static_cast<uint16_t*>(dlogits_bf16), loss_rows);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_col_sums(const float* x, int64_t n, int32_t c, float* out, void* stream) {
+    if (n < 0 || c < 1 || !out || (n > 0 && !x)) return LSP_EINVAL;
+    hipLaunchKernelGGL(lsp::col_sums_kernel, dim3((c + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), x, n, c, out);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_col_stats(const float* x, int64_t n, int32_t d, float* mean, float* inv_std,
+                         void* stream) {
+    if (n < 0 || d < 1 || !mean || !inv_std || (n > 0 && !x)) return LSP_EINVAL;
+    hipLaunchKernelGGL(lsp::col_stats_kernel, dim3((d + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), x, n, d, mean, inv_std);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_standardize_bf16(const float* x, int64_t n, int32_t d, const float* mean,
+                                const float* inv_std, void* out, void* stream) {
+    if (n < 0 || d < 1 || !mean || !inv_std || (n > 0 && (!x || !out))) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::standardize_kernel, lsp::grid_for((n * d + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), x, n, d, mean, inv_std,
+                       static_cast<uint16_t*>(out));
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_cast_bf16(const float* x, int64_t count, void* out, void* stream) {
+    if (count < 0 || (count > 0 && (!x || !out))) return LSP_EINVAL;
+    if (count == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::cast_bf16_kernel, lsp::grid_for((count + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), x, count, static_cast<uint16_t*>(out));
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_adam(float* param, const float* grad, float* m, float* v, int64_t count,
+                    int32_t step, float lr, float beta1, float beta2, float eps, void* param_bf16,
+                    void* stream) {
+    if (count < 0 || step < 1 || (count > 0 && (!param || !grad || !m || !v))) return LSP_EINVAL;
+    if (count == 0) return LSP_OK;
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(lsp::adam_kernel, lsp::grid_for((count + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), param, grad, m, v, count, lr, beta1,
+                       beta2, eps, c1, c2, static_cast<uint16_t*>(param_bf16));
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_top_k(const float* logits, int64_t n, int32_t c, int32_t k, int32_t* idx,
+                     float* mass, void* stream) {
+    if (n < 0 || c < 1 || c > 128 || k < 1 || k > c || (n > 0 && (!logits || !idx)))
+        return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::top_k_kernel, lsp::grid_for((n + 3) / 4), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), logits, n, c, k, idx, mass);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+}  // extern "C"

@@ -16,12 +16,15 @@ constexpr int kPeakThreads = 256;
 
 __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(const PeakParams P) {
     __shared__ PeakRec s_red[kPeakThreads / kWave];
-    const int64_t o = linear_block();
-    if (o >= P.n_obj) return;
+    const int64_t grp = linear_block();
+    if (grp >= P.n_groups) return;
+    const int64_t o =
+        P.row_obj ? (int64_t)P.row_obj[grp * P.rows_per_group] : grp;  // uniform per group
+    if (o < 0 || o >= P.n_obj) return;
     const ObjMeta m = P.meta[o];
     PeakRec best{0.0, -1};
     if (m.status == LSP_OBJ_OK) {
-        const PeakRec* r = P.rec + o * P.rec_per_obj;
+        const PeakRec* r = P.rec + grp * P.rec_per_obj;
         for (int64_t q = threadIdx.x; q < P.rec_per_obj; q += kPeakThreads) {
             const PeakRec c = r[q];
             if (c.i >= 0 && better(c.p, c.i, best.p, best.i)) best = c;
@@ -61,8 +64,8 @@ __global__ void fill_u32_kernel(unsigned int* dst, int64_t n, unsigned int v) {
 }  // namespace
 
 hipError_t launch_peaks(const PeakParams& p, hipStream_t s) {
-    if (p.n_obj <= 0) return hipSuccess;
-    hipLaunchKernelGGL(peaks_kernel, grid_for(p.n_obj), dim3(kPeakThreads), 0, s, p);
+    if (p.n_groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(peaks_kernel, grid_for(p.n_groups), dim3(kPeakThreads), 0, s, p);
     return hipGetLastError();
 }
 

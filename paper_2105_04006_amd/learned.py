@@ -1,0 +1,173 @@
+"""Learned band proposal: the network, its training step and its inference.
+
+The network takes a per-object feature vector (a 1,024-bin coarse periodogram
+and 64 sampling-window features, standardised) and proposes which of 64
+equal-width frequency bands hold the periodogram's peak.  Every arithmetic step
+runs in the library's kernels (BF16 matrix-core GEMMs with FP32 accumulation,
+softmax cross-entropy, Adam); this module owns the device buffers and calls
+the kernels in order.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import lsp
+
+DIMS = (1088, 512, 256, 64)
+
+
+def _p(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+def _s(stream=None):
+    return lsp._stream_handle(stream)
+
+
+def _ok(st, what):
+    if st != lsp.OK:
+        raise lsp.LspError(st, what)
+
+
+def gemm(A, B, M, N, K, sam, sak, sbk, sbn, C=None, C_bf16=None, bias=None, mask=None,
+         relu=False, ldc=None, stream=None):
+    """C = A.B through lsp_gemm_bf16 (A, B: int16 tensors holding BF16 bits)."""
+    _ok(lsp.lib().lsp_gemm_bf16(int(M), int(N), int(K), _p(A), int(sam), int(sak), _p(B),
+                                int(sbk), int(sbn), _p(bias), _p(mask), int(bool(relu)), _p(C),
+                                _p(C_bf16), int(ldc if ldc is not None else N), _s(stream)),
+        "lsp_gemm_bf16")
+
+
+def to_bf16(x, out=None, stream=None):
+    """FP32 device tensor -> BF16 bits (int16 tensor) via lsp_cast_bf16."""
+    out = torch.empty(x.shape, dtype=torch.int16, device=x.device) if out is None else out
+    _ok(lsp.lib().lsp_cast_bf16(_p(x), x.numel(), _p(out), _s(stream)), "lsp_cast_bf16")
+    return out
+
+
+def bf16_to_f32(h):
+    """BF16 bits (int16 tensor) -> float32 tensor (exact widening)."""
+    return (h.to(torch.int32) << 16).view(torch.float32)
+
+
+class BandNet:
+    """1088 -> 512 -> 256 -> 64 ReLU network with FP32 master weights, BF16 copies
+    for the GEMMs, and Adam state, all on one device."""
+
+    def __init__(self, device, seed=0, dims=DIMS, params=None):
+        self.dims = tuple(dims)
+        self.device = device
+        if params is None:
+            rng = np.random.default_rng(seed)
+            params = []
+            for a, b in zip(self.dims[:-1], self.dims[1:]):
+                params.append(rng.normal(0.0, np.sqrt(2.0 / a), size=(a, b)))
+                params.append(np.zeros(b))
+        self.master = [torch.as_tensor(np.asarray(p, np.float32), device=device).contiguous()
+                       for p in params]
+        self.w_bf16 = [to_bf16(self.master[2 * l]) for l in range(3)]
+        self.m = [torch.zeros_like(p) for p in self.master]
+        self.v = [torch.zeros_like(p) for p in self.master]
+        self.step = 0
+        self.mean = None
+        self.inv_std = None
+        self._bufs = {}
+
+    # ------------------------------------------------------------- buffers
+    def _buf(self, name, shape, dtype):
+        b = self._bufs.get(name)
+        if b is None or tuple(b.shape) != tuple(shape) or b.dtype != dtype:
+            b = torch.empty(shape, dtype=dtype, device=self.device)
+            self._bufs[name] = b
+        return b
+
+    # ------------------------------------------------------- standardising
+    def fit_standardizer(self, feats, stream=None):
+        n, d = feats.shape
+        self.mean = torch.empty(d, dtype=torch.float32, device=self.device)
+        self.inv_std = torch.empty(d, dtype=torch.float32, device=self.device)
+        _ok(lsp.lib().lsp_col_stats(_p(feats), n, d, _p(self.mean), _p(self.inv_std),
+                                    _s(stream)), "lsp_col_stats")
+
+    def standardize(self, feats, out=None, stream=None):
+        n, d = feats.shape
+        out = torch.empty((n, d), dtype=torch.int16, device=self.device) if out is None else out
+        _ok(lsp.lib().lsp_standardize_bf16(_p(feats), n, d, _p(self.mean), _p(self.inv_std),
+                                           _p(out), _s(stream)), "lsp_standardize_bf16")
+        return out
+
+    # ------------------------------------------------------------ forward
+    def forward(self, x_bf16, logits=None, stream=None, keep=False):
+        """x_bf16: [n, 1088] int16 (BF16 bits).  Returns FP32 logits [n, 64]."""
+        n = x_bf16.shape[0]
+        d0, d1, d2, d3 = self.dims
+        h1 = self._buf("h1", (n, d1), torch.int16)
+        h2 = self._buf("h2", (n, d2), torch.int16)
+        logits = torch.empty((n, d3), dtype=torch.float32, device=self.device) \
+            if logits is None else logits
+        W1, W2, W3 = self.w_bf16
+        b1, b2, b3 = self.master[1], self.master[3], self.master[5]
+        gemm(x_bf16, W1, n, d1, d0, d0, 1, d1, 1, C_bf16=h1, bias=b1, relu=True, stream=stream)
+        gemm(h1, W2, n, d2, d1, d1, 1, d2, 1, C_bf16=h2, bias=b2, relu=True, stream=stream)
+        gemm(h2, W3, n, d3, d2, d2, 1, d3, 1, C=logits, bias=b3, stream=stream)
+        return logits
+
+    # ----------------------------------------------------------- training
+    def gradients(self, x_bf16, labels, stream=None):
+        """Forward + backward on one batch; returns (loss rows, [dW1, db1, ...])."""
+        n = x_bf16.shape[0]
+        d0, d1, d2, d3 = self.dims
+        logits = self.forward(x_bf16, stream=stream)
+        h1, h2 = self._bufs["h1"], self._bufs["h2"]
+        W1, W2, W3 = self.w_bf16
+        g3 = self._buf("g3", (n, d3), torch.float32)
+        g3b = self._buf("g3b", (n, d3), torch.int16)
+        loss_rows = self._buf("loss", (n,), torch.float32)
+        _ok(lsp.lib().lsp_softmax_xent(_p(logits), _p(labels), n, d3, ctypes.c_float(1.0 / n),
+                                       _p(g3), _p(g3b), _p(loss_rows), _s(stream)),
+            "lsp_softmax_xent")
+        grads = [self._buf(f"g{i}", tuple(p.shape), torch.float32)
+                 for i, p in enumerate(self.master)]
+        dW1, db1, dW2, db2, dW3, db3 = grads
+        # layer 3: dW3 = h2^T g3, db3 = sum g3, dz2 = (g3 W3^T) * (h2 > 0)
+        gemm(h2, g3b, d2, d3, n, 1, d2, d3, 1, C=dW3, stream=stream)
+        _ok(lsp.lib().lsp_col_sums(_p(g3), n, d3, _p(db3), _s(stream)), "lsp_col_sums")
+        dz2 = self._buf("dz2", (n, d2), torch.float32)
+        dz2b = self._buf("dz2b", (n, d2), torch.int16)
+        gemm(g3b, W3, n, d2, d3, d3, 1, 1, d3, C=dz2, C_bf16=dz2b, mask=h2, stream=stream)
+        # layer 2
+        gemm(h1, dz2b, d1, d2, n, 1, d1, d2, 1, C=dW2, stream=stream)
+        _ok(lsp.lib().lsp_col_sums(_p(dz2), n, d2, _p(db2), _s(stream)), "lsp_col_sums")
+        dz1 = self._buf("dz1", (n, d1), torch.float32)
+        dz1b = self._buf("dz1b", (n, d1), torch.int16)
+        gemm(dz2b, W2, n, d1, d2, d2, 1, 1, d2, C=dz1, C_bf16=dz1b, mask=h1, stream=stream)
+        # layer 1
+        gemm(x_bf16, dz1b, d0, d1, n, 1, d0, d1, 1, C=dW1, stream=stream)
+        _ok(lsp.lib().lsp_col_sums(_p(dz1), n, d1, _p(db1), _s(stream)), "lsp_col_sums")
+        return loss_rows, grads
+
+    def train_step(self, x_bf16, labels, lr=1e-3, stream=None):
+        loss_rows, grads = self.gradients(x_bf16, labels, stream=stream)
+        self.step += 1
+        for i, (p, g) in enumerate(zip(self.master, grads)):
+            wb = self.w_bf16[i // 2] if i % 2 == 0 else None
+            _ok(lsp.lib().lsp_adam(_p(p), _p(g), _p(self.m[i]), _p(self.v[i]), p.numel(),
+                                   self.step, ctypes.c_float(lr), ctypes.c_float(0.9),
+                                   ctypes.c_float(0.999), ctypes.c_float(1e-8), _p(wb),
+                                   _s(stream)), "lsp_adam")
+        return loss_rows
+
+    def params_numpy(self):
+        return [p.detach().cpu().numpy().astype(np.float64) for p in self.master]
+
+
+def top_bands(logits, k=8, stream=None):
+    """Indices of the k highest logits per row (decreasing) and their softmax mass."""
+    n, c = logits.shape
+    idx = torch.empty((n, k), dtype=torch.int32, device=logits.device)
+    mass = torch.empty(n, dtype=torch.float32, device=logits.device)
+    _ok(lsp.lib().lsp_top_k(_p(logits), n, c, k, _p(idx), _p(mass), _s(stream)), "lsp_top_k")
+    return idx, mass

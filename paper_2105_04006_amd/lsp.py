@@ -25,6 +25,7 @@ FORM_FP64, FORM_FP32P = 0, 1
 CYCLES, ANGULAR = 0, 1
 PGRAM_F32, PGRAM_F64 = 0, 1
 SCHED_AUTO, SCHED_GRID, SCHED_PERSISTENT = 0, 1, 2
+REC_AUTO, REC_ROTATION, REC_CHEBYSHEV = 0, 1, 2
 
 PEAK_DTYPE = np.dtype(
     [("index", "<i8"), ("freq", "<f8"), ("period", "<f8"), ("power", "<f8"),
@@ -43,7 +44,7 @@ class Options(ctypes.Structure):
                 ("subtract_mean", ctypes.c_int32), ("pgram_dtype", ctypes.c_int32),
                 ("k_per_lane", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
                 ("t_split", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("recurrence", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class LspError(RuntimeError):
@@ -74,8 +75,48 @@ def lib():
         L.lsp_batch.restype = ctypes.c_int
         L.lsp_batch.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
                                 ctypes.POINTER(Options), vp, vp, vp, sz, vp]
+        L.lsp_rows_workspace_bytes.restype = sz
+        L.lsp_rows_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
+                                               ctypes.POINTER(Options), i64, i64, ctypes.c_int32]
+        L.lsp_batch_rows.restype = ctypes.c_int
+        L.lsp_batch_rows.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
+                                     ctypes.POINTER(Options), vp, vp, i64, i64, ctypes.c_int32,
+                                     vp, vp, vp, sz, vp]
         L.lsp_status_string.restype = ctypes.c_char_p
         L.lsp_status_string.argtypes = [ctypes.c_int]
+        L.lsp_plan_create.restype = ctypes.c_int
+        L.lsp_plan_create.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
+                                      ctypes.POINTER(Options), vp, vp, vp, sz,
+                                      ctypes.POINTER(vp)]
+        L.lsp_plan_launch.restype = ctypes.c_int
+        L.lsp_plan_launch.argtypes = [vp, vp]
+        L.lsp_plan_destroy.restype = None
+        L.lsp_plan_destroy.argtypes = [vp]
+        L.lsp_autotune_workspace_bytes.restype = sz
+        L.lsp_autotune_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
+                                                   ctypes.POINTER(Options)]
+        L.lsp_autotune.restype = ctypes.c_int
+        L.lsp_autotune.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
+                                   ctypes.POINTER(Options), ctypes.POINTER(Options), vp, vp, sz,
+                                   ctypes.c_char_p, ctypes.c_int32, vp]
+        i32, f32 = ctypes.c_int32, ctypes.c_float
+        L.lsp_gemm_bf16.restype = ctypes.c_int
+        L.lsp_gemm_bf16.argtypes = [i64, i64, i64, vp, i64, i64, vp, i64, i64, vp, vp, i32, vp,
+                                    vp, i64, vp]
+        L.lsp_softmax_xent.restype = ctypes.c_int
+        L.lsp_softmax_xent.argtypes = [vp, vp, i64, i32, f32, vp, vp, vp, vp]
+        L.lsp_col_sums.restype = ctypes.c_int
+        L.lsp_col_sums.argtypes = [vp, i64, i32, vp, vp]
+        L.lsp_col_stats.restype = ctypes.c_int
+        L.lsp_col_stats.argtypes = [vp, i64, i32, vp, vp, vp]
+        L.lsp_standardize_bf16.restype = ctypes.c_int
+        L.lsp_standardize_bf16.argtypes = [vp, i64, i32, vp, vp, vp, vp]
+        L.lsp_cast_bf16.restype = ctypes.c_int
+        L.lsp_cast_bf16.argtypes = [vp, i64, vp, vp]
+        L.lsp_adam.restype = ctypes.c_int
+        L.lsp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp, vp]
+        L.lsp_top_k.restype = ctypes.c_int
+        L.lsp_top_k.argtypes = [vp, i64, i32, i32, vp, vp, vp]
         L.lsp_set_stage_events.restype = ctypes.c_int
         L.lsp_set_stage_events.argtypes = [vp, vp]
         L.lsp_version.restype = ctypes.c_int32
@@ -112,13 +153,14 @@ def make_grid(f_min, f_max, n_f, unit=CYCLES):
 
 
 def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype=PGRAM_F32, k=0,
-                 waves=0, t_split=0, schedule=SCHED_AUTO):
+                 waves=0, t_split=0, schedule=SCHED_AUTO, recurrence=REC_AUTO):
     o = Options()
     o.form, o.normalize, o.subtract_mean, o.pgram_dtype = (int(form), int(bool(normalize)),
                                                            int(bool(subtract_mean)),
                                                            int(pgram_dtype))
     o.k_per_lane, o.waves_per_wg, o.t_split, o.schedule = int(k), int(waves), int(t_split), int(
         schedule)
+    o.recurrence = int(recurrence)
     return o
 
 
@@ -153,7 +195,8 @@ class Periodogram:
 
     def __init__(self, t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, form=FORM_FP64,
                  normalize=True, subtract_mean=True, pgram=True, pgram_dtype=PGRAM_F32,
-                 peaks=True, k=0, waves=0, t_split=0, schedule=SCHED_AUTO):
+                 peaks=True, k=0, waves=0, t_split=0, schedule=SCHED_AUTO,
+                 recurrence=REC_AUTO):
         _check(t, torch.float64, "t")
         _check(y, torch.float64, "y")
         if t.numel() != y.numel():
@@ -165,7 +208,7 @@ class Periodogram:
         self.n_obj = 1 if offsets is None else int(offsets.numel()) - 1
         self.grid = make_grid(f_min, f_max, n_f, unit)
         self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, t_split,
-                                schedule)
+                                schedule, recurrence)
         dev = t.device
         nb = workspace_bytes(self.n_obj, self.n_obs, self.grid, self.opt)
         if nb == 0:
@@ -197,11 +240,139 @@ class Periodogram:
             raise LspError(st, what)
         return self
 
+    def capture(self):
+        """Record this call into a HIP graph (lsp_plan_create); returns a Plan."""
+        return Plan(self)
+
     def peaks(self):
         """Peak records copied to the host as a numpy structured array."""
         if self.peaks_raw is None:
             return None
         return self.peaks_raw.cpu().numpy().view(PEAK_DTYPE).copy()
+
+
+class Plan:
+    """A captured call (lsp_plan_*): launching it replays all of the call's
+    kernels as one HIP graph on the given stream."""
+
+    def __init__(self, call):
+        self.call = call
+        h = ctypes.c_void_p()
+        st = lib().lsp_plan_create(_dev_ptr(call.offsets), call.n_obj, call.n_obs,
+                                   _dev_ptr(call.t), _dev_ptr(call.y), ctypes.byref(call.grid),
+                                   ctypes.byref(call.opt), _dev_ptr(call.pgram),
+                                   _dev_ptr(call.peaks_raw), _dev_ptr(call.workspace),
+                                   call.workspace.numel(), ctypes.byref(h))
+        if st != OK:
+            raise LspError(st, "lsp_plan_create")
+        self.handle = h
+
+    def __call__(self, stream=None):
+        st = lib().lsp_plan_launch(self.handle, _stream_handle(stream))
+        if st != OK:
+            raise LspError(st, "lsp_plan_launch")
+        return self.call
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().lsp_plan_destroy(h)
+            self.handle = None
+
+
+class Rows:
+    """A row-mode call (lsp_batch_rows) with its workspace allocated once.
+
+    ``row_obj`` (int32 device tensor) names the object of each row;
+    ``row_band`` (int32 device tensor or None) its band of ``band_bins`` bins.
+    Groups of ``rows_per_group`` consecutive rows share one peak record, written
+    at the group's object in ``peaks`` (an n_obj-record tensor the caller may
+    pass in so that several calls fill one array).  ``pgram`` likewise may be
+    passed in; only the rows' bins are written.
+    """
+
+    def __init__(self, offsets, t, y, f_min, f_max, n_f, row_obj, row_band=None, band_bins=0,
+                 rows_per_group=1, unit=CYCLES, form=FORM_FP32P, normalize=True,
+                 subtract_mean=True, pgram=None, pgram_dtype=PGRAM_F32, peaks=None, k=0,
+                 waves=0, schedule=SCHED_AUTO, recurrence=REC_AUTO, max_rows=None):
+        for x, dt, nm in ((t, torch.float64, "t"), (y, torch.float64, "y"),
+                          (offsets, torch.int64, "offsets"), (row_obj, torch.int32, "row_obj")):
+            _check(x, dt, nm)
+        if row_band is not None:
+            _check(row_band, torch.int32, "row_band")
+            if row_band.numel() != row_obj.numel():
+                raise ValueError("row_obj and row_band differ in length")
+        self.t, self.y, self.offsets = t, y, offsets
+        self.n_obs = int(t.numel())
+        self.n_obj = int(offsets.numel()) - 1
+        self.grid = make_grid(f_min, f_max, n_f, unit)
+        self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, 0,
+                                schedule, recurrence)
+        self.band_bins = int(band_bins) if row_band is not None else 0
+        self.rows_per_group = int(rows_per_group)
+        cap = int(max_rows if max_rows is not None else row_obj.numel())
+        nb = int(lib().lsp_rows_workspace_bytes(self.n_obj, self.n_obs, ctypes.byref(self.grid),
+                                                ctypes.byref(self.opt), max(cap, 1),
+                                                self.band_bins, self.rows_per_group))
+        if nb == 0:
+            raise LspError(EINVAL, "lsp_rows_workspace_bytes")
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=t.device)
+        self.pgram = pgram
+        self.peaks_raw = (torch.empty(self.n_obj * PEAK_BYTES, dtype=torch.uint8,
+                                      device=t.device) if peaks is None else peaks)
+        self.set_rows(row_obj, row_band)
+
+    def set_rows(self, row_obj, row_band=None):
+        """Point the call at new row arrays (no larger than the sized maximum)."""
+        self.row_obj, self.row_band = row_obj, row_band
+        self.n_rows = int(row_obj.numel())
+        return self
+
+    def __call__(self, stream=None):
+        if self.n_rows == 0:
+            return self
+        st = lib().lsp_batch_rows(_dev_ptr(self.offsets), self.n_obj, self.n_obs,
+                                  _dev_ptr(self.t), _dev_ptr(self.y), ctypes.byref(self.grid),
+                                  ctypes.byref(self.opt), _dev_ptr(self.row_obj),
+                                  _dev_ptr(self.row_band), self.n_rows, self.band_bins,
+                                  self.rows_per_group, _dev_ptr(self.pgram),
+                                  _dev_ptr(self.peaks_raw), _dev_ptr(self.workspace),
+                                  self.workspace.numel(), _stream_handle(stream))
+        if st != OK:
+            raise LspError(st, "lsp_batch_rows")
+        return self
+
+    def peaks(self):
+        return self.peaks_raw.cpu().numpy().view(PEAK_DTYPE).copy()
+
+
+def autotune(t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, normalize=True,
+             subtract_mean=True, cache_path=None, repeats=3, stream=None):
+    """Run lsp_autotune on device data; returns the tuned keyword options
+    (k, waves, recurrence, schedule, t_split) for Periodogram(form=FORM_FP32P)."""
+    _check(t, torch.float64, "t")
+    _check(y, torch.float64, "y")
+    if offsets is not None:
+        _check(offsets, torch.int64, "offsets")
+    n_obj = 1 if offsets is None else int(offsets.numel()) - 1
+    grid = make_grid(f_min, f_max, n_f, unit)
+    base = make_options(FORM_FP32P, normalize, subtract_mean)
+    nb = int(lib().lsp_autotune_workspace_bytes(n_obj, int(t.numel()), ctypes.byref(grid),
+                                                ctypes.byref(base)))
+    if nb == 0:
+        raise LspError(EINVAL, "lsp_autotune_workspace_bytes")
+    ws = torch.empty(nb, dtype=torch.uint8, device=t.device)
+    scratch = torch.empty(n_obj * PEAK_BYTES, dtype=torch.uint8, device=t.device)
+    tuned = Options()
+    st = lib().lsp_autotune(_dev_ptr(offsets), n_obj, int(t.numel()), _dev_ptr(t), _dev_ptr(y),
+                            ctypes.byref(grid), ctypes.byref(base), ctypes.byref(tuned),
+                            _dev_ptr(scratch), _dev_ptr(ws), nb,
+                            cache_path.encode() if cache_path else None, int(repeats),
+                            _stream_handle(stream))
+    if st != OK:
+        raise LspError(st, "lsp_autotune")
+    return dict(k=tuned.k_per_lane, waves=tuned.waves_per_wg, recurrence=tuned.recurrence,
+                schedule=tuned.schedule, t_split=tuned.t_split)
 
 
 def single(t, y, f_min, f_max, n_f, **kw):

@@ -94,6 +94,56 @@ def test_argument_errors_are_reported_before_any_launch(L):
                        1 << 30, None) == lsp.EINVAL
 
 
+def test_plan_and_autotune_argument_errors(L):
+    g = lsp.make_grid(1.0, 2.0, 100)
+    o = lsp.make_options()
+    h = ctypes.c_void_p()
+    assert L.lsp_plan_create(FAKE, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE,
+                             FAKE, FAKE, 1 << 30, None) == lsp.EINVAL  # no plan pointer
+    assert L.lsp_plan_create(None, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE,
+                             FAKE, FAKE, 1 << 30, ctypes.byref(h)) == lsp.EINVAL  # batch w/o CSR
+    assert L.lsp_plan_create(FAKE, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE,
+                             FAKE, FAKE, 1, ctypes.byref(h)) == lsp.ENOMEM
+    assert not h.value
+    assert L.lsp_plan_launch(None, None) == lsp.EINVAL
+    L.lsp_plan_destroy(None)
+    tuned = lsp.Options()
+    assert L.lsp_autotune(FAKE, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), None, FAKE,
+                          FAKE, 1 << 30, None, 1, None) == lsp.EINVAL
+    assert L.lsp_autotune(FAKE, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o),
+                          ctypes.byref(tuned), FAKE, FAKE, 1 << 30, None, 0, None) == lsp.EINVAL
+    assert lsp.lib().lsp_autotune_workspace_bytes(3, 30, ctypes.byref(g), ctypes.byref(o)) > 0
+
+
+def test_rows_argument_errors(L):
+    g = lsp.make_grid(1.0, 2.0, 100)
+    o = lsp.make_options(form=lsp.FORM_FP32P)
+
+    def call(offsets=FAKE, row_obj=FAKE, row_band=FAKE, n_rows=8, band_bins=10, rpg=4, opt=o,
+             ws_bytes=1 << 30):
+        return L.lsp_batch_rows(offsets, 3, 30, FAKE, FAKE, ctypes.byref(g), ctypes.byref(opt),
+                                row_obj, row_band, n_rows, band_bins, rpg, FAKE, FAKE, FAKE,
+                                ws_bytes, None)
+
+    assert call(offsets=None) == lsp.EINVAL
+    assert call(row_obj=None) == lsp.EINVAL
+    assert call(n_rows=0) == lsp.EINVAL
+    assert call(rpg=0) == lsp.EINVAL
+    assert call(rpg=3) == lsp.EINVAL        # 3 does not divide 8 rows
+    assert call(band_bins=0) == lsp.EINVAL
+    assert call(band_bins=101) == lsp.EINVAL
+    assert call(ws_bytes=1) == lsp.ENOMEM
+    assert call(opt=lsp.make_options(form=lsp.FORM_FP32P, t_split=2)) == lsp.EUNSUPPORTED
+    ws = L.lsp_rows_workspace_bytes
+    assert ws(3, 30, ctypes.byref(g), ctypes.byref(o), 8, 10, 4) > 0
+    assert ws(3, 30, ctypes.byref(g), ctypes.byref(o), 8, 0, 1) > 0       # whole-grid rows
+    assert ws(3, 30, ctypes.byref(g), ctypes.byref(o), 8, 10, 3) == 0
+    assert ws(3, 30, ctypes.byref(g), ctypes.byref(o), 0, 10, 1) == 0
+    # records grow with rows, not with objects
+    assert (ws(3, 30, ctypes.byref(g), ctypes.byref(o), 800, 10, 4) >
+            ws(3, 30, ctypes.byref(g), ctypes.byref(o), 8, 10, 4))
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
 

@@ -1,0 +1,140 @@
+"""Band-proposal network kernels vs the CPU reference (needs an MI355X)."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp_ref  # noqa: E402
+from paper_2105_04006_amd import learned, lsp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def bits(a, dev):
+    return torch.as_tensor(mlp_ref.bf16_bits(a).view(np.int16), device=dev)
+
+
+@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (200, 130, 100), (37, 70, 1088), (1, 5, 3)])
+def test_gemm_plain_and_transposed(dev, M, N, K):
+    rng = np.random.default_rng(M * 1000 + N)
+    A = mlp_ref.bf16_round(rng.normal(size=(M, K)))
+    B = mlp_ref.bf16_round(rng.normal(size=(K, N)))
+    ref = A @ B
+    tol = 1e-5 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() + 1e-6
+    C = torch.empty((M, N), dtype=torch.float32, device=dev)
+    say(f"gemm {M}x{N}x{K}")
+    learned.gemm(bits(A, dev), bits(B, dev), M, N, K, K, 1, N, 1, C=C)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(C.cpu().numpy() - ref)) <= tol
+    # the same product from transposed storage of both operands
+    At, Bt = bits(np.ascontiguousarray(A.T), dev), bits(np.ascontiguousarray(B.T), dev)
+    C2 = torch.empty((M, N), dtype=torch.float32, device=dev)
+    learned.gemm(At, Bt, M, N, K, 1, M, 1, K, C=C2)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(C2.cpu().numpy() - ref)) <= tol
+
+
+def test_gemm_epilogues(dev):
+    rng = np.random.default_rng(7)
+    M, N, K = 150, 96, 64
+    A = mlp_ref.bf16_round(rng.normal(size=(M, K)))
+    B = mlp_ref.bf16_round(rng.normal(size=(K, N)))
+    bias = rng.normal(size=N).astype(np.float32)
+    mask = mlp_ref.bf16_round(rng.normal(size=(M, N)))
+    Cf = torch.empty((M, N), dtype=torch.float32, device=dev)
+    Cb = torch.empty((M, N), dtype=torch.int16, device=dev)
+    learned.gemm(bits(A, dev), bits(B, dev), M, N, K, K, 1, N, 1, C=Cf, C_bf16=Cb,
+                 bias=torch.as_tensor(bias, device=dev), relu=True)
+    torch.cuda.synchronize()
+    ref = np.maximum(A @ B + bias, 0.0)
+    assert np.max(np.abs(Cf.cpu().numpy() - ref)) <= 1e-4
+    cb = mlp_ref.from_bf16_bits(Cb.cpu().numpy().view(np.uint16))
+    assert np.array_equal(cb, mlp_ref.bf16_round(Cf.cpu().numpy()))
+    learned.gemm(bits(A, dev), bits(B, dev), M, N, K, K, 1, N, 1, C=Cf, mask=bits(mask, dev))
+    torch.cuda.synchronize()
+    ref = (A @ B) * (mask > 0)
+    assert np.max(np.abs(Cf.cpu().numpy() - ref)) <= 1e-4
+
+
+def test_small_kernels(dev):
+    rng = np.random.default_rng(11)
+    n, c = 37, 64
+    z = rng.normal(size=(n, c)).astype(np.float32) * 3
+    lab = rng.integers(0, c, size=n).astype(np.int32)
+    zt = torch.as_tensor(z, device=dev)
+    g = torch.empty_like(zt)
+    loss = torch.empty(n, dtype=torch.float32, device=dev)
+    L = lsp.lib()
+    p = learned._p
+    assert L.lsp_softmax_xent(p(zt), p(torch.as_tensor(lab, device=dev)), n, c,
+                              ctypes.c_float(1.0 / n), p(g), None, p(loss), None) == 0
+    ref_loss, ref_g = mlp_ref.softmax_xent(z.astype(np.float64), lab)
+    torch.cuda.synchronize()
+    assert abs(loss.cpu().numpy().mean() - ref_loss) <= 1e-5
+    assert np.max(np.abs(g.cpu().numpy() - ref_g)) <= 1e-6
+    cs = torch.empty(c, dtype=torch.float32, device=dev)
+    assert L.lsp_col_sums(p(zt), n, c, p(cs), None) == 0
+    torch.cuda.synchronize()
+    assert np.allclose(cs.cpu().numpy(), z.astype(np.float64).sum(axis=0), atol=1e-4)
+    mean = torch.empty(c, dtype=torch.float32, device=dev)
+    inv = torch.empty(c, dtype=torch.float32, device=dev)
+    assert L.lsp_col_stats(p(zt), n, c, p(mean), p(inv), None) == 0
+    torch.cuda.synchronize()
+    assert np.allclose(mean.cpu().numpy(), z.mean(axis=0), atol=1e-5)
+    assert np.allclose(inv.cpu().numpy(), 1.0 / z.astype(np.float64).std(axis=0), rtol=1e-5)
+    idx, mass = learned.top_bands(zt, k=8)
+    torch.cuda.synchronize()
+    order = np.argsort(-z, axis=1, kind="stable")[:, :8]
+    assert np.array_equal(idx.cpu().numpy(), order)
+    e = np.exp(z - z.max(axis=1, keepdims=True))
+    pm = e / e.sum(axis=1, keepdims=True)
+    assert np.allclose(mass.cpu().numpy(), np.take_along_axis(pm, order, 1).sum(1), atol=1e-5)
+
+
+def test_training_step_matches_reference(dev):
+    """One forward/backward/Adam step of the full-size network on the GPU vs the
+    BF16-emulated FP64 reference of the same arithmetic."""
+    rng = np.random.default_rng(5)
+    n = 96
+    params = mlp_ref.init_params(9)
+    for pp in params[1::2]:
+        pp += rng.normal(0, 0.05, size=pp.shape)
+    x = mlp_ref.bf16_round(rng.normal(size=(n, 1088)))
+    labels = rng.integers(0, 64, size=n).astype(np.int32)
+    net = learned.BandNet(dev, params=params)
+    xb = bits(x, dev)
+    lab = torch.as_tensor(labels, device=dev)
+    loss_rows, grads = net.gradients(xb, lab)
+    torch.cuda.synchronize()
+    bparams = [mlp_ref.bf16_round(p) if i % 2 == 0 else p.astype(np.float32).astype(np.float64)
+               for i, p in enumerate(params)]
+    logits, cache = mlp_ref.forward(bparams, x, bf16=True)
+    ref_loss, dl = mlp_ref.softmax_xent(logits, labels)
+    ref_grads = mlp_ref.backward(bparams, cache, dl, bf16=True)
+    assert abs(loss_rows.cpu().numpy().mean() - ref_loss) <= 2e-3 * max(1.0, ref_loss)
+    for name, g, r in zip(["dW1", "db1", "dW2", "db2", "dW3", "db3"], grads, ref_grads):
+        g = g.cpu().numpy()
+        err = np.max(np.abs(g - r)) / (np.max(np.abs(r)) + 1e-12)
+        say(f"  {name}: max rel err {err:.3g}")
+        assert err <= 2e-2, name
+    before = [p.clone() for p in net.master]
+    net.train_step(xb, lab, lr=1e-3)
+    torch.cuda.synchronize()
+    for b, a in zip(before, net.master):
+        d = (a - b).abs().max().item()
+        assert 0.0 < d <= 1.01e-3  # the first Adam step moves each parameter by <= lr

@@ -128,12 +128,14 @@ def test_single_small_fp64(dev):
 def test_single_small_fp32p(dev):
     w = synth.make_workload("single_256")
     ora_pg, ora_pk = oracle.single(w.t, w.y, w.f_min, w.f_max, w.n_f)
-    for k in (4, 8, 16, 32):
-        say(f"single_256 fp32p k={k}")
-        pg, pk = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, k=k)
-        err = assert_fp32_close(pg, ora_pg, f"single_256 fp32p k={k}")
-        assert err < 1e-4, f"k={k}: max |dP| {err:.3g} is far above the expected FP32 level"
-        assert peak_ok(ora_pg, ora_pk["index"], pk["index"], 2 * FP32_ATOL, bins=1)
+    for rec in (lsp.REC_ROTATION, lsp.REC_CHEBYSHEV):
+        for k in (4, 8, 16, 32):
+            pg, pk = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, k=k,
+                                recurrence=rec)
+            err = assert_fp32_close(pg, ora_pg, f"single_256 fp32p k={k} rec={rec}")
+            say(f"    max |dP| = {err:.3g}")
+            assert err < 1e-4, f"k={k}: max |dP| {err:.3g} is far above the expected FP32 level"
+            assert peak_ok(ora_pg, ora_pk["index"], pk["index"], 2 * FP32_ATOL, bins=1)
 
 
 def test_batch_ragged_both_forms(dev):
@@ -328,6 +330,12 @@ def test_full_single_4096(dev):
     pg64, pk64 = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64,
                             pgram_dtype=lsp.PGRAM_F64)
     pg32, pk32 = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P)
+    pgc, pkc = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P,
+                          recurrence=lsp.REC_CHEBYSHEV)
+    say(f"    rotation max |dP| vs fp64 {np.max(np.abs(pg32 - pg64)):.3g}, "
+        f"chebyshev {np.max(np.abs(pgc - pg64)):.3g}")
+    assert_fp32_close(pgc, pg64, "single_4096 chebyshev vs fp64 (all bins)")
+    assert abs(int(pkc["index"]) - int(pk64["index"])) <= 1
     rng = np.random.default_rng(0)
     top = np.argsort(pg64)[-64:]
     bins = np.unique(np.concatenate([rng.integers(0, w.n_f, 3000), top,
@@ -359,6 +367,14 @@ def test_full_batch_10k_peaks(dev):
     agree = np.abs(pk32["index"] - pk64["index"]) <= 1
     assert agree.mean() >= 0.999, f"peak agreement {agree.mean():.4%}"
     assert np.all(np.abs(pk32["power"] - pk64["power"]) <= FP32_ATOL)
+    _, pkc = run_batch(dev, w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P,
+                       pgram=False, recurrence=lsp.REC_CHEBYSHEV)
+    agree_c = np.abs(pkc["index"] - pk64["index"]) <= 1
+    say(f"    peak agreement rotation {agree.mean():.5f} chebyshev {agree_c.mean():.5f}; max dP "
+        f"{np.max(np.abs(pk32['power'] - pk64['power'])):.3g} / "
+        f"{np.max(np.abs(pkc['power'] - pk64['power'])):.3g}")
+    assert agree_c.mean() >= 0.999
+    assert np.all(np.abs(pkc["power"] - pk64["power"]) <= FP32_ATOL)
     sub = w.subset(8)
     ora_pg, ora_pk = oracle.batch(sub.offsets, sub.t, sub.y, w.f_min, w.f_max, w.n_f,
                                   want_pgram=True)

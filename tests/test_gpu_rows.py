@@ -1,0 +1,132 @@
+"""Row mode (lsp_batch_rows) vs the CPU oracle and vs whole-grid calls (needs an MI355X).
+
+Row mode runs the same per-bin kernels as lsp_batch on chosen bands of chosen
+objects, so:
+  * FP64 form: every written bin within 1e-9 relative of the oracle; the group
+    peak is the oracle's argmax over the union of the group's bands.
+  * FP32 form: |dP| <= 1e-3; group peak within one bin or a near-tie.
+  * Whole-grid rows of a subset of objects give the same records, hence
+    bit-identical peaks, as lsp_batch on all objects with the same options.
+  * Bins outside every row, and peaks of objects that head no group, are left
+    as they were.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2105_04006_amd import lsp, synth  # noqa: E402
+from test_gpu_parity import (FP32_ATOL, assert_fp32_close, assert_fp64_close, cuda,  # noqa: E402
+                             dev, oracle, run_batch, say)
+
+pytestmark = pytest.mark.gpu
+
+SENTINEL = -7.0
+
+
+def _rows_call(dev, w, n_f, row_obj, row_band, band_bins, rpg, form, **kw):
+    say(f"  gpu lsp_batch_rows n_rows={len(row_obj)} band_bins={band_bins} rpg={rpg} form={form}")
+    pgram = torch.full((w.n_obj, n_f), SENTINEL, dtype=torch.float64, device=dev)
+    peaks = torch.zeros(w.n_obj * lsp.PEAK_BYTES, dtype=torch.uint8, device=dev)
+    rb = cuda(row_band, dev, torch.int32) if row_band is not None else None
+    r = lsp.Rows(cuda(w.offsets, dev, torch.int64), cuda(w.t, dev), cuda(w.y, dev), w.f_min,
+                 w.f_max, n_f, cuda(row_obj, dev, torch.int32), rb, band_bins, rpg, form=form,
+                 pgram=pgram, pgram_dtype=lsp.PGRAM_F64, peaks=peaks, **kw)
+    r()
+    torch.cuda.synchronize()
+    return pgram.cpu().numpy(), r.peaks()
+
+
+def _band_bins_of(bands, band_bins, n_f):
+    out = []
+    for b in bands:
+        if b >= 0:
+            out.extend(range(b * band_bins, min((b + 1) * band_bins, n_f)))
+    return np.array(sorted(set(out)), dtype=np.int64)
+
+
+@pytest.mark.parametrize("form", [lsp.FORM_FP64, lsp.FORM_FP32P])
+def test_banded_rows_match_oracle(dev, form):
+    w = synth.make_workload("batch_10k", n_obj=24)
+    n_f, n_bands, rpg = 6400, 64, 8
+    band_bins = n_f // n_bands
+    rng = np.random.default_rng(5)
+    heads = rng.permutation(w.n_obj)[:16]      # 8 objects head no group
+    row_obj, row_band = [], []
+    for g, o in enumerate(heads):
+        bands = rng.choice(n_bands, size=rpg, replace=False)
+        if g == 3:
+            bands[2] = -1                       # a row that evaluates nothing
+        if g == 5:
+            bands[:] = bands[0]                 # the same band eight times
+        row_obj += [o] * rpg
+        row_band += list(bands)
+    row_obj = np.array(row_obj, np.int32)
+    row_band = np.array(row_band, np.int32)
+    ora_pg, _ = oracle.batch(w.offsets, w.t, w.y, w.f_min, w.f_max, n_f)
+    pg, pk = _rows_call(dev, w, n_f, row_obj, row_band, band_bins, rpg, form)
+    for g, o in enumerate(heads):
+        bins = _band_bins_of(row_band[g * rpg:(g + 1) * rpg], band_bins, n_f)
+        if form == lsp.FORM_FP64:
+            assert_fp64_close(pg[o, bins], ora_pg[o, bins], f"object {o} bands")
+        else:
+            assert_fp32_close(pg[o, bins], ora_pg[o, bins], f"object {o} bands")
+        untouched = np.setdiff1d(np.arange(n_f), bins)
+        assert np.all(pg[o, untouched] == SENTINEL)
+        sub = ora_pg[o, bins]
+        best = bins[int(np.argmax(sub))]
+        got = int(pk["index"][o])
+        assert got in set(bins.tolist())
+        if form == lsp.FORM_FP64:
+            assert got == best or ora_pg[o, got] >= ora_pg[o, best] - 1e-9
+        else:
+            assert abs(got - best) <= 1 or ora_pg[o, got] >= ora_pg[o, best] - 2 * FP32_ATOL
+    others = np.setdiff1d(np.arange(w.n_obj), heads)
+    assert np.all(pg[others] == SENTINEL)
+    assert np.all(pk["index"][others] == 0) and np.all(pk["status"][others] == 0)
+
+
+def test_whole_grid_rows_equal_batch(dev):
+    w = synth.make_workload("batch_10k", n_obj=60)
+    n_f = 5000
+    sub = np.array([3, 17, 42, 59, 0, 8], np.int32)
+    for form in (lsp.FORM_FP64, lsp.FORM_FP32P):
+        _, ref = run_batch(dev, w.offsets, w.t, w.y, w.f_min, w.f_max, n_f, form=form,
+                           pgram=False)
+        pg, pk = _rows_call(dev, w, n_f, sub, None, 0, 1, form)
+        for o in sub:
+            assert pk[o].tobytes() == ref[o].tobytes(), f"object {o} form {form}"
+        mask = np.ones(w.n_obj, bool)
+        mask[sub] = False
+        assert np.all(pg[mask] == SENTINEL)
+
+
+def test_band_edges_and_degenerate_objects(dev):
+    """Bands smaller than a tile, a ragged last band, degenerate objects, a
+    group whose every row is invalid."""
+    t2, y2, _ = synth.sine_object(150, 3)
+    series = [(t2, y2), (np.array([1.0]), np.array([2.0])), (t2[:40], y2[:40]),
+              (t2, np.full(len(t2), 3.0))]
+    off, t, y = synth.pack(series)
+    w = synth.Workload("edges", off, t, y, 0.5, 6.0, 0)
+    n_f, band_bins = 1000, 37                   # 28 bands, the last holds 1000 - 27*37 = 1 bin
+    rows = [(0, 27), (0, 0), (0, 13), (1, 4), (1, 5), (1, 6), (2, 27), (2, 26), (2, -1),
+            (3, 1), (3, 2), (3, 3)]
+    row_obj = np.array([r[0] for r in rows], np.int32)
+    row_band = np.array([r[1] for r in rows], np.int32)
+    ora_pg, ora_pk = oracle.batch(off, t, y, 0.5, 6.0, n_f)
+    for form in (lsp.FORM_FP64, lsp.FORM_FP32P):
+        pg, pk = _rows_call(dev, w, n_f, row_obj, row_band, band_bins, 3, form)
+        for g in range(4):
+            o = g
+            assert pk["status"][o] == ora_pk["status"][o]
+            bins = _band_bins_of(row_band[3 * g:3 * g + 3], band_bins, n_f)
+            if ora_pk["status"][o] != 0:
+                assert pk["index"][o] == -1
+                assert np.all(pg[o, bins] == ora_pg[o, bins])
+                continue
+            tol_fn = assert_fp64_close if form == lsp.FORM_FP64 else assert_fp32_close
+            tol_fn(pg[o, bins], ora_pg[o, bins], f"edge object {o}")
+            best = bins[int(np.argmax(ora_pg[o, bins]))]
+            assert abs(int(pk["index"][o]) - best) <= (0 if form == lsp.FORM_FP64 else 1) or \
+                ora_pg[o, pk["index"][o]] >= ora_pg[o, best] - 2 * FP32_ATOL

@@ -1,0 +1,105 @@
+"""HIP-graph plans and the autotuner, through the C ABI (needs an MI355X)."""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2105_04006_amd import lsp, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _snapshot(p):
+    torch.cuda.synchronize()
+    pg = p.pgram.clone() if p.pgram is not None else None
+    return pg, p.peaks()
+
+
+@pytest.mark.parametrize("form", [lsp.FORM_FP64, lsp.FORM_FP32P])
+@pytest.mark.parametrize("mode", ["single", "batch"])
+def test_graph_replays_match_eager(dev, form, mode):
+    if mode == "single":
+        w = synth.make_workload("single_256")
+        off = None
+    else:
+        w = synth.make_workload("batch_10k", n_obj=48)
+        off = torch.as_tensor(w.offsets, device=dev)
+    say(f"graph {mode} form={form}")
+    t = torch.as_tensor(w.t, device=dev)
+    y = torch.as_tensor(w.y, device=dev)
+    kw = dict(offsets=off, form=form, pgram_dtype=lsp.PGRAM_F64)
+    if form == lsp.FORM_FP32P and mode == "batch":
+        kw["schedule"] = lsp.SCHED_PERSISTENT
+    p = lsp.Periodogram(t, y, w.f_min, w.f_max, 3000, **kw)
+    p()
+    ref_pg, ref_pk = _snapshot(p)
+    plan = p.capture()
+    other = lsp.Periodogram(t, y, w.f_min, w.f_max, 777, offsets=off, form=lsp.FORM_FP32P)
+    for rep in range(4):
+        p.pgram.fill_(-1.0)  # eager work between replays, on the same stream
+        other()
+        _ = (t * 2.0).sum().item()
+        torch.cuda.synchronize()
+        plan()
+        pg, pk = _snapshot(p)
+        assert torch.equal(pg, ref_pg), f"replay {rep} differs from the eager call"
+        assert np.array_equal(pk, ref_pk)
+    # the plan reads its buffers at launch time: new data gives new results
+    y.mul_(-1.5).add_(0.25)
+    p()
+    new_pg, new_pk = _snapshot(p)
+    p.pgram.fill_(-1.0)
+    torch.cuda.synchronize()
+    plan()
+    pg, pk = _snapshot(p)
+    assert torch.equal(pg, new_pg) and np.array_equal(pk, new_pk)
+    del plan
+
+
+def test_autotune_single_and_batch(dev, tmp_path):
+    cache = str(tmp_path / "tune.jsonl")
+    for mode in ("single", "batch"):
+        if mode == "single":
+            w = synth.make_workload("single_256")
+            off_d, n_f = None, 20000
+        else:
+            w = synth.make_workload("batch_10k", n_obj=300)
+            off_d, n_f = torch.as_tensor(w.offsets, device=dev), 20000
+        t = torch.as_tensor(w.t, device=dev)
+        y = torch.as_tensor(w.y, device=dev)
+        say(f"autotune {mode}")
+        tuned = lsp.autotune(t, y, w.f_min, w.f_max, n_f, offsets=off_d, cache_path=cache,
+                             repeats=2)
+        say(f"  tuned {tuned}")
+        assert tuned["k"] in (8, 16, 32) and tuned["waves"] in (1, 2, 4)
+        assert tuned["recurrence"] in (lsp.REC_ROTATION, lsp.REC_CHEBYSHEV)
+        again = lsp.autotune(t, y, w.f_min, w.f_max, n_f, offsets=off_d, cache_path=cache)
+        assert again == tuned  # served from the cache
+        p = lsp.Periodogram(t, y, w.f_min, w.f_max, n_f, offsets=off_d, form=lsp.FORM_FP32P,
+                            pgram_dtype=lsp.PGRAM_F64, **tuned)()
+        torch.cuda.synchronize()
+        pg = p.pgram.cpu().numpy()
+        rows = [0] if mode == "single" else [0, 7, 150, 299]
+        for o in rows:
+            tt, yy = w.obj(o)
+            ora, _ = oracle.single(tt, yy, w.f_min, w.f_max, n_f)
+            assert np.max(np.abs(pg[o] - ora)) <= 1e-3
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 2 and all('"key"' in l for l in lines)
