@@ -74,7 +74,7 @@ enum { LSP_PGRAM_F32 = 0, LSP_PGRAM_F64 = 1 };
 
 /* Frequency-to-frequency recurrence of the FP32 form (within one lane). */
 enum {
-    LSP_REC_AUTO = 0,
+    LSP_REC_AUTO = 0,      /* the library's choice (currently LSP_REC_CHEBYSHEV)    */
     LSP_REC_ROTATION = 1,  /* (c, s) <- (c C - s S, s C + c S): 4 ops per step        */
     LSP_REC_CHEBYSHEV = 2  /* x_{k+1} = 2C x_k - x_{k-1} for x = cos, sin: 2 ops/step */
 };
@@ -187,8 +187,10 @@ lsp_status lsp_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const
  * of a group must name that same object and no object may head two groups.
  *   offsets, t, y, grid, opt : as lsp_batch (per-object statistics are taken
  *               over the whole CSR range, whatever the rows).
- *   row_obj   : device, n_rows int32 object indices in [0, n_obj).  Rows naming
- *               another index, or a negative band, evaluate nothing.
+ *   row_obj   : device, n_rows int32 object indices in [0, n_obj), or NULL
+ *               when n_rows == n_obj * rows_per_group and row r belongs to object
+ *               r / rows_per_group.  Rows naming an index outside [0, n_obj), or
+ *               a negative band, evaluate nothing.
  *   row_band  : device, n_rows int32 band indices, or NULL.
  *   band_bins : bins per band, 1..n_f (ignored when row_band is NULL).
  *   pgram     : as lsp_batch, but only the bins of the rows are written.
@@ -197,7 +199,8 @@ lsp_status lsp_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const
  *               power NaN if they hold no bin).
  *   workspace : >= lsp_rows_workspace_bytes(n_obj, n_obs, grid, opt, n_rows,
  *               band_bins (0 when row_band is NULL), rows_per_group) bytes.
- * Errors as lsp_batch, plus LSP_EINVAL for NULL row_obj, n_rows < 1,
+ * Errors as lsp_batch, plus LSP_EINVAL for NULL row_obj with n_rows other than
+ * n_obj * rows_per_group, n_rows < 1,
  * rows_per_group < 1 or not dividing n_rows, band_bins outside 1..n_f, and
  * LSP_EUNSUPPORTED for t_split > 1.
  */
@@ -260,6 +263,53 @@ lsp_status lsp_autotune(const int64_t *offsets, int64_t n_obj, int64_t n_obs, co
                         void *stream);
 
 /*
+ * Band-proposal features.  The paper evaluates every bin; the learned path
+ * evaluates only bands proposed from these per-object features (1,088 FP32
+ * values per object, row-major [n_obj][LSP_FEAT_DIM]):
+ *   [0, 1024)    coarse spectrum: the series is cut into seasons (a new season
+ *                at every gap longer than season_gap); each season with at least
+ *                min_season_obs observations gets the normalised power of
+ *                Section 2 (Eq. 1-2, season mean removed) on 8,192 bins over
+ *                [grid->f_min, grid->f_max) in the grid's unit; bins are
+ *                max-pooled in runs of 8 and averaged over those seasons (0 if
+ *                none).  FP32 arithmetic as in LSP_FORM_FP32P, no FP64 fix-up;
+ *                each value is clamped to [0, 1].
+ *   [1024, 1088) sampling and magnitude statistics in FP64: log10 N_t,
+ *                log10 max(span, 1e-3), number of seasons, number with >=
+ *                min_season_obs points, log10 max(mean within-season spacing,
+ *                1e-6), standard deviation of log10 max(spacing, 1e-6), fraction
+ *                of points in qualifying seasons, log10 sigma_y, skewness,
+ *                excess kurtosis, max |y - ybar| / sigma_y, then the spectral
+ *                window |sum_j exp(2 pi i f_p t_j)|^2 / N_t^2 at the 53
+ *                frequencies f_p = 10^(-3 + p (log10 30 + 3) / 52), p = 0..52,
+ *                in cycles per time unit.
+ * Observations are taken in the order given (time order for sorted input).
+ * Objects whose status would not be LSP_OBJ_OK get an all-zero row.
+ *   grid      : f_min, f_max and unit are used; n_f is ignored.
+ *   features  : device, n_obj * LSP_FEAT_DIM floats.
+ *   workspace : device, >= lsp_features_workspace_bytes(n_obj) bytes, 256-aligned.
+ * Errors: LSP_EINVAL for NULL offsets/features/workspace/grid, n_obj < 1, a
+ * bad grid range or unit, season_gap negative or non-finite, min_season_obs < 1;
+ * LSP_ENOMEM for a short workspace.
+ */
+#define LSP_FEAT_COARSE 1024
+#define LSP_FEAT_POOL 8
+#define LSP_FEAT_WINDOW 64
+#define LSP_FEAT_DIM (LSP_FEAT_COARSE + LSP_FEAT_WINDOW)
+
+typedef struct {
+    double season_gap;      /* time units; default 60                         */
+    int32_t min_season_obs; /* default 8                                      */
+    int32_t reserved;
+} lsp_feature_options;
+
+lsp_feature_options lsp_default_feature_options(void);
+size_t lsp_features_workspace_bytes(int64_t n_obj);
+lsp_status lsp_features(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                        const double *y, const lsp_grid *grid, const lsp_feature_options *fopt,
+                        float *features, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Learned band proposal: building blocks of the small network that proposes
  * which frequency bands to refine.  BF16 arrays are passed as raw 16-bit words
  * (upper half of an IEEE single, round-to-nearest-even); all pointers are
@@ -280,9 +330,10 @@ lsp_status lsp_gemm_bf16(int64_t M, int64_t N, int64_t K, const void *A, int64_t
                          void *stream);
 
 /* Row-wise softmax cross-entropy of logits [n x c] against labels [n]:
- * loss_rows[i] = log sum_j exp z_ij - z_i,label (0 for a label outside [0, c)),
- * gradient (softmax - onehot) * scale into dlogits (FP32) and/or dlogits_bf16.
- * Output pointers may be NULL. */
+ * loss_rows[i] = log sum_j exp z_ij - z_i,label, gradient (softmax - onehot) *
+ * scale into dlogits (FP32) and/or dlogits_bf16.  A row whose label lies
+ * outside [0, c) is ignored: zero loss and zero gradient.  Output pointers may
+ * be NULL. */
 lsp_status lsp_softmax_xent(const float *logits, const int32_t *labels, int64_t n, int32_t c,
                             float scale, float *dlogits, void *dlogits_bf16, float *loss_rows,
                             void *stream);
@@ -313,6 +364,22 @@ lsp_status lsp_adam(float *param, const float *grad, float *m, float *v, int64_t
  * probability mass of those k entries into mass [n] (may be NULL). */
 lsp_status lsp_top_k(const float *logits, int64_t n, int32_t c, int32_t k, int32_t *idx,
                      float *mass, void *stream);
+
+/* Training labels for the proposal: labels[i] = peaks[i].index / band_bins for
+ * an object with status OK and a peak in bands [0, n_bands), else -1 (ignored
+ * by lsp_softmax_xent). */
+lsp_status lsp_peak_bands(const lsp_peak *peaks, int64_t n, int64_t band_bins, int32_t n_bands,
+                          int32_t *labels, void *stream);
+
+/* Fallback selection after refining proposed bands: writes to objects[] the
+ * indices, in increasing order, of the objects with status OK whose refined
+ * peak is missing, has power below power_min (or NaN), or whose proposal mass
+ * (mass[i], the softmax mass of the refined bands; mass may be NULL) is below
+ * mass_min, and their number to *count (device int32).  objects must hold n
+ * entries.  One workgroup; n <= INT32_MAX. */
+lsp_status lsp_select_fallback(const lsp_peak *peaks, const float *mass, int64_t n,
+                               float mass_min, float power_min, int32_t *objects, int32_t *count,
+                               void *stream);
 
 /*
  * Optional instrumentation for profiling.  After a call with non-NULL

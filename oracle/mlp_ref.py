@@ -50,14 +50,20 @@ def forward(params, x, bf16=False):
 
 
 def softmax_xent(logits, labels):
-    """Mean cross-entropy and its gradient with respect to the logits."""
+    """Cross-entropy averaged over all n rows, and its gradient with respect to
+    the logits.  A row whose label is outside [0, c) is ignored: it adds 0 to
+    the loss sum and gets a zero gradient (the divisor stays n)."""
     z = logits - logits.max(axis=1, keepdims=True)
     p = np.exp(z)
     p /= p.sum(axis=1, keepdims=True)
-    n = logits.shape[0]
-    loss = -np.log(p[np.arange(n), labels]).mean()
+    n, c = logits.shape
+    labels = np.asarray(labels)
+    keep = (labels >= 0) & (labels < c)
+    rows = np.arange(n)[keep]
+    loss = -np.log(p[rows, labels[keep]]).sum() / n
     g = p.copy()
-    g[np.arange(n), labels] -= 1.0
+    g[rows, labels[keep]] -= 1.0
+    g[~keep] = 0.0
     return loss, g / n
 
 

@@ -42,10 +42,11 @@ struct Rows {
     int64_t n_rows;
     int64_t band_bins;        // bins per band (n_f when row_band is NULL)
     int32_t rows_per_group;
+    bool whole;               // lsp_single / lsp_batch: one whole-grid row per object
 };
 
 Rows whole_grid(int64_t n_obj, const lsp_grid* g) {
-    return Rows{nullptr, nullptr, n_obj, g ? g->n_f : 0, 1};
+    return Rows{nullptr, nullptr, n_obj, g ? g->n_f : 0, 1, true};
 }
 
 struct Layout {
@@ -87,9 +88,11 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
                    const Rows& rows, Config* c) {
     // Launch shapes are sized for the bins of one row.
     const int64_t n_f = rows.row_band ? (rows.band_bins < g->n_f ? rows.band_bins : g->n_f) : g->n_f;
-    const bool whole = rows.row_obj == nullptr && rows.row_band == nullptr;
+    const bool whole = rows.whole;
     c->form = o->form;
-    c->rec = o->recurrence == LSP_REC_CHEBYSHEV ? LSP_REC_CHEBYSHEV : LSP_REC_ROTATION;
+    // The three-term recurrence needs fewer operations per bin and measured as
+    // accurate as the rotation, so it is the default.
+    c->rec = o->recurrence == LSP_REC_ROTATION ? LSP_REC_ROTATION : LSP_REC_CHEBYSHEV;
     c->persistent = 0;
     c->split = 1;
     if (o->form == LSP_FORM_FP64) {
@@ -232,6 +235,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     mp.row_obj = rows.row_obj;
     mp.row_band = rows.row_band;
     mp.band_bins = rows.row_band ? rows.band_bins : grid->n_f;
+    mp.rows_per_group = rows.rows_per_group;
+    mp.pad_rows = 0;
     mp.tiles_per_row = c.tiles_per_row;
     mp.n_items = c.n_items;
     mp.n_split = c.split;
@@ -268,6 +273,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             fp.row_obj = mp.row_obj;
             fp.row_band = mp.row_band;
             fp.band_bins = mp.band_bins;
+            fp.rows_per_group = mp.rows_per_group;
+            fp.pad_rows = 0;
             fp.tiles_per_row = c.tiles_per_row;
             fp.n_tiles = rows.n_rows * c.tiles_per_row;
             fp.tile_freqs = c.tile_freqs;
@@ -352,8 +359,8 @@ size_t lsp_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* gr
     if (lsp::valid_options(&opt) != LSP_OK) return 0;
     // Any non-null band pointer stands for "banded" when sizing.
     static const int32_t kBanded = 0;
-    const lsp::Rows rows{&kBanded, band_bins > 0 ? &kBanded : nullptr, n_rows, band_bins,
-                         rows_per_group};
+    const lsp::Rows rows{nullptr, band_bins > 0 ? &kBanded : nullptr, n_rows, band_bins,
+                         rows_per_group, false};
     if (lsp::valid_rows(rows, grid) != LSP_OK) return 0;
     lsp::Config c;
     if (lsp::resolve(n_obj, n_obs, grid, &opt, rows, &c) != LSP_OK) return 0;
@@ -382,9 +389,10 @@ lsp_status lsp_batch_rows(const int64_t* offsets, int64_t n_obj, int64_t n_obs, 
                           int64_t band_bins, int32_t rows_per_group, void* pgram,
                           lsp_peak* peaks, void* workspace, size_t workspace_bytes,
                           void* stream) {
-    if (!offsets || !row_obj) return LSP_EINVAL;
+    if (!offsets) return LSP_EINVAL;
+    if (!row_obj && n_rows != n_obj * (int64_t)rows_per_group) return LSP_EINVAL;
     if (!row_band) band_bins = grid ? grid->n_f : 0;
-    const lsp::Rows rows{row_obj, row_band, n_rows, band_bins, rows_per_group};
+    const lsp::Rows rows{row_obj, row_band, n_rows, band_bins, rows_per_group, false};
     return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
                     workspace_bytes, stream, rows);
 }

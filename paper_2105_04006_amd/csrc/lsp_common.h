@@ -208,10 +208,10 @@ struct RowRange {
 };
 
 __device__ __forceinline__ RowRange decode_row(const int32_t* row_obj, const int32_t* row_band,
-                                               int64_t band_bins, int64_t n_obj, int64_t n_f,
-                                               int64_t row) {
+                                               int64_t band_bins, int32_t rows_per_group,
+                                               int64_t n_obj, int64_t n_f, int64_t row) {
     RowRange r;
-    r.obj = row_obj ? (int64_t)row_obj[row] : row;
+    r.obj = row_obj ? (int64_t)row_obj[row] : row / rows_per_group;
     r.f_lo = 0;
     r.f_hi = n_f;
     if (row_band) {
@@ -264,9 +264,11 @@ struct MainParams {
     double step_cyc;  // FP32 form: lane-stride frequency step (kWave bins) in cycles
     int64_t n_f;
     int64_t n_obj;
-    const int32_t* row_obj;   // object of each row, or NULL: row r is object r
+    const int32_t* row_obj;   // object of each row, or NULL: row r is object r / rows_per_group
     const int32_t* row_band;  // band of each row ([b*band_bins, (b+1)*band_bins)), or NULL
     int64_t band_bins;
+    int32_t rows_per_group;
+    int32_t pad_rows;
     int64_t tiles_per_row;  // frequency tiles per row
     int64_t n_items;        // n_rows * tiles_per_row * n_split
     int32_t n_split;        // observation-axis split (single object only)
@@ -304,6 +306,8 @@ struct FixupParams {
     const int32_t* row_obj;
     const int32_t* row_band;
     int64_t band_bins;
+    int32_t rows_per_group;
+    int32_t pad_rows;
     int64_t tiles_per_row;
     int64_t n_tiles;
     int64_t tile_freqs;

@@ -1,0 +1,397 @@
+// lsp_features.hip -- per-object features for the learned band proposal.
+//
+// The paper evaluates every bin of every object.  The learned path first
+// computes, per object, 1,088 cheap features and lets a small network propose
+// the few frequency bands worth evaluating.  Two kernels fill one feature row
+// per object:
+//
+//   coarse_kernel : the object is cut into seasons (a new season at every gap
+//     longer than `season_gap`).  For each season with at least
+//     `min_season_obs` observations, the normalised Lomb-Scargle power of
+//     Section 2 (season mean removed, Eq. 1-2 in the tau-free form) is
+//     evaluated on 8,192 bins over [f_min, f_max), max-pooled over runs of 8
+//     bins and averaged over the seasons -> features [0, 1024).  This is the
+//     FP32 hot loop of the main kernel (FP64 phase reduction, hardware sin/cos
+//     per observation, rotation across a lane's frequencies) with two extra
+//     sums (sum cos, sum sin) so that each season's own mean can be removed
+//     after the fact: sum (y - m) c = sum y c - m sum c.
+//   window_kernel : one wavefront per object computes sampling and magnitude
+//     statistics and the spectral window at 53 probe frequencies in FP64
+//     -> features [1024, 1088).
+//
+// Objects whose status is not OK get an all-zero row.
+#include <math.h>
+
+#include <cmath>
+
+#include "lsp_common.h"
+
+namespace lsp {
+namespace {
+
+constexpr int kCoarseK = 8;      // frequencies per lane
+constexpr int kCoarseW = 4;      // wavefronts per workgroup
+constexpr int kCoarseTile = kWave * kCoarseK * kCoarseW;  // 2,048 bins
+constexpr int kTilesPerObj = LSP_FEAT_COARSE * LSP_FEAT_POOL / kCoarseTile;
+constexpr float kDenEps32 = 1e-5f;  // drop a term whose denominator is below this * N
+constexpr int kProbes = LSP_FEAT_WINDOW - 11;
+
+static_assert(LSP_FEAT_POOL == 8, "pooling uses three lane-exchange steps");
+static_assert(kTilesPerObj * kCoarseTile == LSP_FEAT_COARSE * LSP_FEAT_POOL, "tile split");
+
+struct FeatParams {
+    const ObjMeta* meta;
+    const double* t;
+    const double* y;
+    double f_min, df, to_cyc;  // coarse grid: df = (f_max - f_min) / 8192
+    double step_cyc;           // phase advance over kWave coarse bins, in cycles
+    double gap;
+    int64_t n_obj;
+    int32_t min_obs;
+    int32_t pad;
+    float* out;  // [n_obj][LSP_FEAT_DIM]
+};
+
+__device__ __forceinline__ float pool8_max(float v) {
+    v = fmaxf(v, __shfl_xor(v, 1, kWave));
+    v = fmaxf(v, __shfl_xor(v, 2, kWave));
+    v = fmaxf(v, __shfl_xor(v, 4, kWave));
+    return v;
+}
+
+__global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParams P) {
+    __shared__ double s_tau[kTile];
+    __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, new-season flag)
+    constexpr int K = kCoarseK;
+    const int64_t item = xcd_remap(linear_block(), P.n_obj * kTilesPerObj);
+    if (item >= P.n_obj * kTilesPerObj) return;
+    const int64_t obj = item / kTilesPerObj;
+    const int tile = (int)(item - obj * kTilesPerObj);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int64_t i0 = (int64_t)tile * kCoarseTile + (int64_t)wave * kWave * K + lane;
+    float* out = P.out + obj * LSP_FEAT_DIM;
+    const ObjMeta m = P.meta[obj];
+
+    float feat[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) feat[k] = 0.0f;
+    int n_good = 0;
+
+    if (m.status == LSP_OBJ_OK) {
+        const double fl = grid_freq(P.f_min, P.df, i0) * P.to_cyc;
+        float xc[K], xs[K], sc[K], ss[K], cc[K], cs[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) xc[k] = xs[k] = sc[k] = ss[k] = cc[k] = cs[k] = 0.0f;
+        // season statistics (wave-uniform): count, sum and sum of squares of y - ybar
+        int64_t ns = 0;
+        double sy = 0.0, syy = 0.0;
+
+        // Close the current season: add its pooled power to the features if it
+        // has enough observations.
+        auto close_season = [&]() {
+            if (ns >= P.min_obs) {
+                const double mean = sy / (double)ns;
+                const double svar = syy - (double)ns * mean * mean;
+                const double raw = syy + 2.0 * m.ybar * sy + (double)ns * m.ybar * m.ybar;
+                const bool flat = !(svar > 0.0) || svar <= kVarEps * raw;
+                const float N = (float)ns;
+                const float mf = (float)mean;
+                const float inv_s = flat ? 0.0f : (float)(1.0 / svar);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float XC = fmaf(-mf, sc[k], xc[k]);
+                    const float XS = fmaf(-mf, ss[k], xs[k]);
+                    const float C2 = 2.0f * cc[k] - N;
+                    const float S2 = 2.0f * cs[k];
+                    const float R = sqrtf(C2 * C2 + S2 * S2);
+                    const float A = XC * XC + XS * XS;
+                    const float B = R > 0.0f ? ((XC * XC - XS * XS) * C2 + 2.0f * XC * XS * S2) / R
+                                             : 0.0f;
+                    const float dp = N + R, dm = N - R;
+                    float p = 0.0f;
+                    if (dp > kDenEps32 * N) p += (A + B) / dp;
+                    if (dm > kDenEps32 * N) p += (A - B) / dm;
+                    p = fminf(fmaxf(p * inv_s, 0.0f), 1.0f);
+                    feat[k] += pool8_max(p);
+                }
+                ++n_good;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) xc[k] = xs[k] = sc[k] = ss[k] = cc[k] = cs[k] = 0.0f;
+            ns = 0;
+            sy = syy = 0.0;
+        };
+
+        const int64_t j_end = m.j0 + m.n;
+        for (int64_t jt = m.j0; jt < j_end; jt += kTile) {
+            const int cnt = (int)((j_end - jt) < kTile ? (j_end - jt) : kTile);
+            __syncthreads();
+            for (int q = threadIdx.x; q < cnt; q += kWave * kCoarseW) {
+                const int64_t j = jt + q;
+                const double tj = P.t[j];
+                const double tc = tj - m.t0;
+                s_tau[q] = tc;
+                double sp = P.step_cyc * tc;
+                sp -= rint(sp);
+                const float rs = (float)sp;
+                const bool starts = j > m.j0 && tj - P.t[j - 1] > P.gap;
+                s_obs[q] = make_float4((float)(P.y[j] - m.ybar), __builtin_amdgcn_cosf(rs),
+                                       __builtin_amdgcn_sinf(rs), starts ? 1.0f : 0.0f);
+            }
+            __syncthreads();
+            for (int q = 0; q < cnt; ++q) {
+                const float4 o = s_obs[q];
+                // every lane reads the same slot, so the flag is wave-uniform
+                if (uniform_i32(o.w != 0.0f ? 1 : 0)) close_season();
+                const double ph0 = fl * s_tau[q];
+                const float r = (float)(ph0 - rint(ph0));
+                float s = __builtin_amdgcn_sinf(r);
+                float c = __builtin_amdgcn_cosf(r);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    xc[k] = fmaf(o.x, c, xc[k]);
+                    xs[k] = fmaf(o.x, s, xs[k]);
+                    sc[k] += c;
+                    ss[k] += s;
+                    cc[k] = fmaf(c, c, cc[k]);
+                    cs[k] = fmaf(c, s, cs[k]);
+                    if (k + 1 < K) {
+                        const float cn = fmaf(c, o.y, -(s * o.z));
+                        s = fmaf(s, o.y, c * o.z);
+                        c = cn;
+                    }
+                }
+                const double yq = (double)o.x;
+                ++ns;
+                sy += yq;
+                syy += yq * yq;
+            }
+        }
+        close_season();
+    }
+
+    const float inv = n_good > 0 ? 1.0f / (float)n_good : 0.0f;
+    if ((lane & (LSP_FEAT_POOL - 1)) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t q = (i0 + (int64_t)kWave * k) / LSP_FEAT_POOL;
+            out[q] = feat[k] * inv;
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// One wavefront per object.
+__global__ __launch_bounds__(kWave) void window_kernel(const FeatParams P) {
+    const int64_t obj = linear_block();
+    if (obj >= P.n_obj) return;
+    const int lane = threadIdx.x;
+    float* out = P.out + obj * LSP_FEAT_DIM + LSP_FEAT_COARSE;
+    const ObjMeta m = P.meta[obj];
+    if (m.status != LSP_OBJ_OK) {
+        out[lane] = 0.0f;
+        return;
+    }
+    const int64_t j0 = m.j0, n = m.n, j1 = j0 + n;
+
+    // Pass 1: time span, moments of y - ybar, within-season spacings.
+    double tmin = __builtin_inf(), tmax = -__builtin_inf();
+    double m3 = 0.0, m4 = 0.0, amax = 0.0;
+    double dsum = 0.0, lsum = 0.0, lsq = 0.0, dcnt = 0.0;
+    for (int64_t j = j0 + lane; j < j1; j += kWave) {
+        const double tj = P.t[j];
+        const double yc = P.y[j] - m.ybar;
+        tmin = fmin(tmin, tj);
+        tmax = fmax(tmax, tj);
+        const double y2 = yc * yc;
+        m3 += y2 * yc;
+        m4 += y2 * y2;
+        amax = fmax(amax, fabs(yc));
+        if (j > j0) {
+            const double d = tj - P.t[j - 1];
+            if (d <= P.gap) {
+                const double l = log10(fmax(d, 1e-6));
+                dsum += d;
+                lsum += l;
+                lsq += l * l;
+                dcnt += 1.0;
+            }
+        }
+    }
+    tmin = wave_min(tmin);
+    tmax = wave_max(tmax);
+    m3 = wave_sum(m3);
+    m4 = wave_sum(m4);
+    amax = wave_max(amax);
+    dsum = wave_sum(dsum);
+    lsum = wave_sum(lsum);
+    lsq = wave_sum(lsq);
+    dcnt = wave_sum(dcnt);
+
+    // Pass 2: seasons, 64 observations per step.  The ballot of season starts
+    // is wave-uniform, so the loop over its set bits is too.
+    int64_t n_seasons = 0, n_good = 0, good_obs = 0, start = j0;
+    for (int64_t jb = j0; jb < j1; jb += kWave) {
+        const int64_t j = jb + lane;
+        const bool st = j < j1 && j > j0 && P.t[j] - P.t[j - 1] > P.gap;
+        uint64_t mask = __ballot(st);
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int64_t s = jb + b;
+            ++n_seasons;
+            if (s - start >= P.min_obs) {
+                ++n_good;
+                good_obs += s - start;
+            }
+            start = s;
+        }
+    }
+    if (n > 0) {
+        ++n_seasons;
+        if (j1 - start >= P.min_obs) {
+            ++n_good;
+            good_obs += j1 - start;
+        }
+    }
+
+    const double nd = (double)n;
+    const double var = m.syy / nd;
+    const double sigma = sqrt(var);
+    double w = 0.0;
+    switch (lane) {
+        case 0: w = log10(nd); break;
+        case 1: w = log10(fmax(tmax - tmin, 1e-3)); break;
+        case 2: w = (double)n_seasons; break;
+        case 3: w = (double)n_good; break;
+        case 4: w = dcnt > 0.0 ? log10(fmax(dsum / dcnt, 1e-6)) : 0.0; break;
+        case 5: {
+            if (dcnt > 0.0) {
+                const double mu = lsum / dcnt;
+                w = sqrt(fmax(lsq / dcnt - mu * mu, 0.0));
+            }
+            break;
+        }
+        case 6: w = (double)good_obs / nd; break;
+        case 7: w = sigma > 0.0 ? log10(sigma) : -30.0; break;
+        case 8: w = sigma > 0.0 ? (m3 / nd) / (var * sigma) : 0.0; break;
+        case 9: w = sigma > 0.0 ? (m4 / nd) / (var * var) - 3.0 : 0.0; break;
+        case 10: w = sigma > 0.0 ? amax / sigma : 0.0; break;
+        default: break;
+    }
+
+    // Pass 3: spectral window |sum_j exp(2 pi i f_p t_j)|^2 / N^2, phases
+    // taken from the object's mid-span origin (the modulus does not depend on
+    // it), reduced to [-1/2, 1/2] cycles in FP64.
+    const double lstep = (log10(30.0) + 3.0) / (double)(kProbes - 1);
+    for (int p = 0; p < kProbes; ++p) {
+        const double f = pow(10.0, -3.0 + (double)p * lstep);
+        double sc = 0.0, ss = 0.0;
+        for (int64_t j = j0 + lane; j < j1; j += kWave) {
+            double ph = f * (P.t[j] - m.t0);
+            ph -= rint(ph);
+            double sn, cn;
+            sincospi(2.0 * ph, &sn, &cn);
+            sc += cn;
+            ss += sn;
+        }
+        sc = wave_sum(sc);
+        ss = wave_sum(ss);
+        if (lane == 11 + p) w = (sc * sc + ss * ss) / (nd * nd);
+    }
+    out[lane] = (float)w;
+}
+
+}  // namespace
+
+static hipError_t launch_features(const ObjMeta* meta, const double* t, const double* y, double f_min,
+                           double f_max, int unit, double gap, int min_obs, int64_t n_obj,
+                           float* out, hipStream_t s) {
+    if (n_obj <= 0) return hipSuccess;
+    FeatParams p;
+    p.meta = meta;
+    p.t = t;
+    p.y = y;
+    p.f_min = f_min;
+    p.df = (f_max - f_min) / (double)(LSP_FEAT_COARSE * LSP_FEAT_POOL);
+    p.to_cyc = unit == LSP_UNIT_CYCLES ? 1.0 : kInvTwoPi;
+    p.step_cyc = (double)kWave * p.df * p.to_cyc;
+    p.gap = gap;
+    p.n_obj = n_obj;
+    p.min_obs = min_obs;
+    p.pad = 0;
+    p.out = out;
+    hipLaunchKernelGGL(coarse_kernel, grid_for(n_obj * kTilesPerObj), dim3(kWave * kCoarseW), 0,
+                       s, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(window_kernel, grid_for(n_obj), dim3(kWave), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace lsp
+
+extern "C" {
+
+lsp_feature_options lsp_default_feature_options(void) {
+    lsp_feature_options o = {};
+    o.season_gap = 60.0;
+    o.min_season_obs = 8;
+    return o;
+}
+
+size_t lsp_features_workspace_bytes(int64_t n_obj) {
+    if (n_obj < 1) return 0;
+    return ((size_t)n_obj * sizeof(lsp::ObjMeta) + 255) / 256 * 256;
+}
+
+lsp_status lsp_features(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                        const double* y, const lsp_grid* grid, const lsp_feature_options* fopt_in,
+                        float* features, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!offsets || !grid || !features || !workspace) return LSP_EINVAL;
+    if (n_obj < 1 || n_obs < 0 || (n_obs > 0 && (!t || !y))) return LSP_EINVAL;
+    if (!(std::isfinite(grid->f_min) && std::isfinite(grid->f_max) && grid->f_max > grid->f_min) ||
+        !(grid->unit == LSP_UNIT_CYCLES || grid->unit == LSP_UNIT_ANGULAR))
+        return LSP_EINVAL;
+    const lsp_feature_options fo = fopt_in ? *fopt_in : lsp_default_feature_options();
+    if (!(std::isfinite(fo.season_gap) && fo.season_gap >= 0.0) || fo.min_season_obs < 1)
+        return LSP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return LSP_EINVAL;
+    if (workspace_bytes < lsp_features_workspace_bytes(n_obj)) return LSP_ENOMEM;
+    if (n_obj > (((int64_t)1 << 31) - 1) / lsp::kTilesPerObj) return LSP_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    lsp::PrepParams pp;
+    pp.offsets = offsets;
+    pp.t = t;
+    pp.y = y;
+    pp.n_obj = n_obj;
+    pp.n_obs = n_obs;
+    pp.subtract_mean = 1;
+    pp.normalize = 1;
+    pp.meta = static_cast<lsp::ObjMeta*>(workspace);
+    if (lsp::launch_prep(pp, s) != hipSuccess) return LSP_EHIP;
+    if (lsp::launch_features(pp.meta, t, y, grid->f_min, grid->f_max, grid->unit, fo.season_gap,
+                             fo.min_season_obs, n_obj, features, s) != hipSuccess)
+        return LSP_EHIP;
+    return LSP_OK;
+}
+
+}  // extern "C"

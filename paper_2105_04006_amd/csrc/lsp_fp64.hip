@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
     const int64_t item = xcd_remap(b, P.n_items);
     const int64_t row = item / P.tiles_per_row;
     const int64_t ftile = item - row * P.tiles_per_row;
-    const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.n_obj, P.n_f, row);
+    const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;
     const int64_t i0 = rr.f_lo + ftile * tile_freqs + (int64_t)wave * kWave * KF + lane;
     const int64_t f_hi = rr.f_hi;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kFixThreads) void fixup_kernel(const FixupParams P)
             const int64_t tile = uniform_i64(s_list[q]);
             const int64_t row = tile / P.tiles_per_row;
             const RowRange rr =
-                decode_row(P.row_obj, P.row_band, P.band_bins, P.n_obj, P.n_f, row);
+                decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
             const int64_t obj = rr.obj < 0 ? 0 : rr.obj;
             const int64_t f0 = rr.f_lo + (tile - row * P.tiles_per_row) * P.tile_freqs;
             const ObjMeta m = P.meta[obj];

@@ -141,14 +141,73 @@ __global__ __launch_bounds__(256) void softmax_xent_kernel(const float* __restri
     for (int j = lane; j < c; j += 64) se += expf(z[j] - mx);
     for (int off = 32; off >= 1; off >>= 1) se += __shfl_xor(se, off, 64);
     const int32_t lab = labels[row];
+    const bool keep = lab >= 0 && lab < c;  // other labels mark rows to ignore
     for (int j = lane; j < c; j += 64) {
         const float p = expf(z[j] - mx) / se;
-        const float d = (p - (j == lab ? 1.f : 0.f)) * scale;
+        const float d = keep ? (p - (j == lab ? 1.f : 0.f)) * scale : 0.f;
         if (dlogits) dlogits[row * c + j] = d;
         if (dlogits_bf16) dlogits_bf16[row * c + j] = f32_to_bf16_bits(d);
     }
     if (lane == 0 && loss_rows)
-        loss_rows[row] = (lab >= 0 && lab < c) ? (logf(se) + mx - z[lab]) : 0.f;
+        loss_rows[row] = keep ? (logf(se) + mx - z[lab]) : 0.f;
+}
+
+// Training labels from full-grid peaks: the band holding each peak, or -1 for
+// an object without a peak.
+__global__ void peak_bands_kernel(const lsp_peak* __restrict__ peaks, int64_t n,
+                                  int64_t band_bins, int32_t n_bands, int32_t* labels) {
+    const int64_t i = linear_block() * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const lsp_peak pk = peaks[i];
+    int32_t b = -1;
+    if (pk.status == LSP_OBJ_OK && pk.index >= 0) {
+        const int64_t q = pk.index / band_bins;
+        b = q < n_bands ? (int32_t)q : -1;
+    }
+    labels[i] = b;
+}
+
+// Objects whose refined peak must be confirmed on the whole grid, listed in
+// increasing order: status OK and (proposal mass below mass_min, or refined
+// power below power_min or not a number, or no peak found).  One workgroup
+// walks the objects 1,024 at a time; each wave compacts its flags with a
+// ballot and the waves' counts are prefix-summed in LDS.
+constexpr int kSelThreads = 1024;
+
+__global__ __launch_bounds__(kSelThreads) void select_kernel(const lsp_peak* __restrict__ peaks,
+                                                           const float* __restrict__ mass,
+                                                           int64_t n, float mass_min,
+                                                           float power_min, int32_t* out,
+                                                           int32_t* count) {
+    __shared__ int32_t s_cnt[kSelThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t done = 0;
+    for (int64_t base = 0; base < n; base += kSelThreads) {
+        const int64_t i = base + threadIdx.x;
+        bool need = false;
+        if (i < n) {
+            const lsp_peak pk = peaks[i];
+            if (pk.status == LSP_OBJ_OK)
+                need = !(pk.index >= 0) || !(pk.power >= (double)power_min) ||
+                       (mass && !(mass[i] >= mass_min));
+        }
+        const uint64_t m = __ballot(need);
+        if (lane == 0) s_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int64_t off = done;
+        int32_t total = 0;
+        for (int w = 0; w < kSelThreads / 64; ++w) {
+            if (w < wave) off += s_cnt[w];
+            total += s_cnt[w];
+        }
+        if (need) {
+            const uint64_t below = lane ? (m & ((~0ull) >> (64 - lane))) : 0ull;
+            out[off + __popcll(below)] = (int32_t)i;
+        }
+        done += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = (int32_t)done;
 }
 
 // Column sums of an n x c FP32 matrix, one thread per column, fixed order.
@@ -353,6 +412,25 @@ lsp_status lsp_top_k(const float* logits, int64_t n, int32_t c, int32_t k, int32
     if (n == 0) return LSP_OK;
     hipLaunchKernelGGL(lsp::top_k_kernel, lsp::grid_for((n + 3) / 4), dim3(256), 0,
                        static_cast<hipStream_t>(stream), logits, n, c, k, idx, mass);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_peak_bands(const lsp_peak* peaks, int64_t n, int64_t band_bins, int32_t n_bands,
+                          int32_t* labels, void* stream) {
+    if (n < 0 || band_bins < 1 || n_bands < 1 || (n > 0 && (!peaks || !labels))) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::peak_bands_kernel, lsp::grid_for((n + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), peaks, n, band_bins, n_bands, labels);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_select_fallback(const lsp_peak* peaks, const float* mass, int64_t n,
+                               float mass_min, float power_min, int32_t* objects, int32_t* count,
+                               void* stream) {
+    if (n < 0 || n > INT32_MAX || !count || (n > 0 && (!peaks || !objects))) return LSP_EINVAL;
+    hipLaunchKernelGGL(lsp::select_kernel, dim3(1), dim3(lsp::kSelThreads), 0,
+                       static_cast<hipStream_t>(stream), peaks, mass, n, mass_min, power_min,
+                       objects, count);
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
 

@@ -20,6 +20,7 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(const PeakParams P)
     if (grp >= P.n_groups) return;
     const int64_t o =
         P.row_obj ? (int64_t)P.row_obj[grp * P.rows_per_group] : grp;  // uniform per group
+    // (without row_obj, row r belongs to object r / rows_per_group, so group g is object g)
     if (o < 0 || o >= P.n_obj) return;
     const ObjMeta m = P.meta[o];
     PeakRec best{0.0, -1};

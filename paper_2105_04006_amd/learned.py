@@ -171,3 +171,142 @@ def top_bands(logits, k=8, stream=None):
     mass = torch.empty(n, dtype=torch.float32, device=logits.device)
     _ok(lsp.lib().lsp_top_k(_p(logits), n, c, k, _p(idx), _p(mass), _s(stream)), "lsp_top_k")
     return idx, mass
+
+
+def peak_bands(peaks_raw, n, band_bins, n_bands, out=None, stream=None):
+    """Training labels (band of each full-grid peak, -1 if none) via lsp_peak_bands."""
+    out = torch.empty(n, dtype=torch.int32, device=peaks_raw.device) if out is None else out
+    _ok(lsp.lib().lsp_peak_bands(_p(peaks_raw), int(n), int(band_bins), int(n_bands), _p(out),
+                                 _s(stream)), "lsp_peak_bands")
+    return out
+
+
+def select_fallback(peaks_raw, mass, n, mass_min, power_min, objects, count, stream=None):
+    """Objects to re-run on the whole grid (lsp_select_fallback); fills objects[:count]."""
+    _ok(lsp.lib().lsp_select_fallback(_p(peaks_raw), _p(mass), int(n), ctypes.c_float(mass_min),
+                                      ctypes.c_float(power_min), _p(objects), _p(count),
+                                      _s(stream)), "lsp_select_fallback")
+
+
+class BandGeometry:
+    """n_bands equal bands of ceil(n_f / n_bands) bins (the last one may be shorter)."""
+
+    def __init__(self, n_f, n_bands=64):
+        self.n_f = int(n_f)
+        self.n_bands = int(n_bands)
+        self.band_bins = -(-self.n_f // self.n_bands)
+
+
+class LearnedPeriodogram:
+    """Peaks of a CSR batch from proposed bands (Section 3.4's batch peaks,
+    computed on a fraction of the grid).
+
+    For each object: features -> standardise -> network -> the `top` most
+    probable bands -> the FP32 batch kernels on those bands only (row mode)
+    -> objects whose proposal is uncertain (softmax mass of the refined bands
+    below mass_min) or whose refined peak is weak (power below power_min) are
+    re-run on the whole grid.  Every step is a library kernel; the host only
+    reads the number of fallback objects to size the last launch.
+    """
+
+    def __init__(self, net, geometry, offsets, t, y, f_min, f_max, unit=lsp.CYCLES, top=8,
+                 mass_min=0.0, power_min=0.0, k=0, waves=0):
+        self.net, self.geo, self.top = net, geometry, int(top)
+        self.offsets, self.t, self.y = offsets, t, y
+        self.n_obj = int(offsets.numel()) - 1
+        self.mass_min, self.power_min = float(mass_min), float(power_min)
+        dev = t.device
+        self.feat = lsp.Features(offsets, t, y, f_min, f_max, unit=unit)
+        self.x = torch.empty((self.n_obj, net.dims[0]), dtype=torch.int16, device=dev)
+        self.logits = torch.empty((self.n_obj, net.dims[-1]), dtype=torch.float32, device=dev)
+        self.idx = torch.empty((self.n_obj, self.top), dtype=torch.int32, device=dev)
+        self.mass = torch.empty(self.n_obj, dtype=torch.float32, device=dev)
+        self.peaks_raw = torch.empty(self.n_obj * lsp.PEAK_BYTES, dtype=torch.uint8, device=dev)
+        self.objects = torch.empty(self.n_obj, dtype=torch.int32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.refine = lsp.Rows(offsets, t, y, f_min, f_max, geometry.n_f, None,
+                               self.idx.view(-1), geometry.band_bins, self.top, unit=unit,
+                               form=lsp.FORM_FP32P, peaks=self.peaks_raw, k=k, waves=waves)
+        self.full = lsp.Rows(offsets, t, y, f_min, f_max, geometry.n_f, self.objects, None, 0, 1,
+                             unit=unit, form=lsp.FORM_FP32P, peaks=self.peaks_raw, k=k,
+                             waves=waves, max_rows=self.n_obj)
+        self.n_fallback = 0
+
+    def propose(self, stream=None):
+        """Features, network and top bands; fills self.idx and self.mass."""
+        feats = self.feat(stream)
+        self.net.standardize(feats, out=self.x, stream=stream)
+        self.net.forward(self.x, logits=self.logits, stream=stream)
+        _ok(lsp.lib().lsp_top_k(_p(self.logits), self.n_obj, self.logits.shape[1], self.top,
+                                _p(self.idx), _p(self.mass), _s(stream)), "lsp_top_k")
+
+    def refine_only(self, stream=None):
+        self.propose(stream)
+        self.refine(stream)
+        return self
+
+    def __call__(self, stream=None):
+        self.refine_only(stream)
+        select_fallback(self.peaks_raw, self.mass, self.n_obj, self.mass_min, self.power_min,
+                        self.objects, self.count, stream)
+        n = int(self.count.item())  # synchronises: sizes the fallback launch
+        self.n_fallback = n
+        if n:
+            self.full.set_rows(self.objects[:n])
+            self.full(stream)
+        return self
+
+    def peaks(self):
+        return self.peaks_raw.cpu().numpy().view(lsp.PEAK_DTYPE).copy()
+
+
+def train_proposer(net, feats, labels, epochs=20, batch=1024, lr=1e-3, lr_final=1e-4,
+                   log=None, stream=None):
+    """Adam on softmax cross-entropy over contiguous minibatches (the synthetic
+    training objects are drawn independently, so their order is already random);
+    the learning rate decays geometrically from lr to lr_final.  Fits the
+    standardiser first.  Returns the mean loss of each epoch."""
+    n = feats.shape[0]
+    net.fit_standardizer(feats, stream=stream)
+    x = net.standardize(feats, stream=stream)
+    steps = max(1, (n // batch)) * epochs
+    decay = (lr_final / lr) ** (1.0 / max(1, steps - 1))
+    rate = lr
+    hist = []
+    for ep in range(epochs):
+        tot = torch.zeros((), dtype=torch.float32, device=feats.device)
+        nb = 0
+        for b0 in range(0, n - batch + 1, batch):
+            loss_rows = net.train_step(x[b0:b0 + batch], labels[b0:b0 + batch], lr=rate,
+                                       stream=stream)
+            tot += loss_rows.sum()
+            nb += 1
+            rate *= decay
+        hist.append(float(tot.item()) / max(1, nb * batch))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.4f}")
+    return hist
+
+
+def calibrate(refined, full, mass, target=0.999):
+    """Thresholds (mass_min, power_min) that keep the recovery rate on a
+    validation set at or above `target` with the fewest fallbacks.
+
+    refined, full: peak arrays (refine only, whole grid); mass: proposal mass.
+    An object is recovered if its refined peak is within one bin of the
+    whole-grid peak; a fallback object is recovered by construction."""
+    ok = full["status"] == 0
+    hit = ok & (np.abs(refined["index"] - full["index"]) <= 1)
+    n = int(ok.sum())
+    allowed = int(np.floor((1.0 - target) * n))
+    pw = np.where(np.isfinite(refined["power"]), refined["power"], -1.0)
+    m_grid = np.unique(np.concatenate([[0.0], np.quantile(mass[ok], np.linspace(0, 0.5, 51))]))
+    p_grid = np.unique(np.concatenate([[0.0], np.quantile(pw[ok], np.linspace(0, 0.5, 51))]))
+    best = (2.0, 2.0, n + 1)
+    for mm in m_grid:
+        for pm in p_grid:
+            fb = ok & ((mass < mm) | (pw < pm) | (refined["index"] < 0))
+            miss = int((ok & ~hit & ~fb).sum())
+            if miss <= allowed and int(fb.sum()) < best[2]:
+                best = (float(mm), float(pm), int(fb.sum()))
+    return best

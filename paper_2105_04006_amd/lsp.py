@@ -47,6 +47,15 @@ class Options(ctypes.Structure):
                 ("recurrence", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
+class FeatureOptions(ctypes.Structure):
+    _fields_ = [("season_gap", ctypes.c_double), ("min_season_obs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+FEAT_COARSE, FEAT_POOL, FEAT_WINDOW = 1024, 8, 64
+FEAT_DIM = FEAT_COARSE + FEAT_WINDOW
+
+
 class LspError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
@@ -117,6 +126,17 @@ def lib():
         L.lsp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp, vp]
         L.lsp_top_k.restype = ctypes.c_int
         L.lsp_top_k.argtypes = [vp, i64, i32, i32, vp, vp, vp]
+        L.lsp_peak_bands.restype = ctypes.c_int
+        L.lsp_peak_bands.argtypes = [vp, i64, i64, i32, vp, vp]
+        L.lsp_select_fallback.restype = ctypes.c_int
+        L.lsp_select_fallback.argtypes = [vp, vp, i64, f32, f32, vp, vp, vp]
+        L.lsp_default_feature_options.restype = FeatureOptions
+        L.lsp_default_feature_options.argtypes = []
+        L.lsp_features_workspace_bytes.restype = sz
+        L.lsp_features_workspace_bytes.argtypes = [i64]
+        L.lsp_features.restype = ctypes.c_int
+        L.lsp_features.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
+                                   ctypes.POINTER(FeatureOptions), vp, vp, sz, vp]
         L.lsp_set_stage_events.restype = ctypes.c_int
         L.lsp_set_stage_events.argtypes = [vp, vp]
         L.lsp_version.restype = ctypes.c_int32
@@ -296,12 +316,14 @@ class Rows:
                  subtract_mean=True, pgram=None, pgram_dtype=PGRAM_F32, peaks=None, k=0,
                  waves=0, schedule=SCHED_AUTO, recurrence=REC_AUTO, max_rows=None):
         for x, dt, nm in ((t, torch.float64, "t"), (y, torch.float64, "y"),
-                          (offsets, torch.int64, "offsets"), (row_obj, torch.int32, "row_obj")):
+                          (offsets, torch.int64, "offsets")):
             _check(x, dt, nm)
+        if row_obj is not None:
+            _check(row_obj, torch.int32, "row_obj")
         if row_band is not None:
             _check(row_band, torch.int32, "row_band")
-            if row_band.numel() != row_obj.numel():
-                raise ValueError("row_obj and row_band differ in length")
+        if row_obj is None and row_band is None:
+            raise ValueError("row mode needs row_obj, row_band or both")
         self.t, self.y, self.offsets = t, y, offsets
         self.n_obs = int(t.numel())
         self.n_obj = int(offsets.numel()) - 1
@@ -310,7 +332,8 @@ class Rows:
                                 schedule, recurrence)
         self.band_bins = int(band_bins) if row_band is not None else 0
         self.rows_per_group = int(rows_per_group)
-        cap = int(max_rows if max_rows is not None else row_obj.numel())
+        named = row_obj if row_obj is not None else row_band
+        cap = int(max_rows if max_rows is not None else named.numel())
         nb = int(lib().lsp_rows_workspace_bytes(self.n_obj, self.n_obs, ctypes.byref(self.grid),
                                                 ctypes.byref(self.opt), max(cap, 1),
                                                 self.band_bins, self.rows_per_group))
@@ -323,9 +346,12 @@ class Rows:
         self.set_rows(row_obj, row_band)
 
     def set_rows(self, row_obj, row_band=None):
-        """Point the call at new row arrays (no larger than the sized maximum)."""
+        """Point the call at new row arrays (no more rows than the sized maximum).
+        With row_obj None, row r belongs to object r // rows_per_group."""
+        if row_obj is not None and row_band is not None and row_band.numel() != row_obj.numel():
+            raise ValueError("row_obj and row_band differ in length")
         self.row_obj, self.row_band = row_obj, row_band
-        self.n_rows = int(row_obj.numel())
+        self.n_rows = int((row_obj if row_obj is not None else row_band).numel())
         return self
 
     def __call__(self, stream=None):
@@ -344,6 +370,44 @@ class Rows:
 
     def peaks(self):
         return self.peaks_raw.cpu().numpy().view(PEAK_DTYPE).copy()
+
+
+class Features:
+    """Band-proposal features (lsp_features) with the workspace allocated once:
+    calling it fills ``out`` ([n_obj, FEAT_DIM] float32) for the CSR batch."""
+
+    def __init__(self, offsets, t, y, f_min, f_max, unit=CYCLES, season_gap=60.0,
+                 min_season_obs=8, out=None):
+        for x, dt, nm in ((t, torch.float64, "t"), (y, torch.float64, "y"),
+                          (offsets, torch.int64, "offsets")):
+            _check(x, dt, nm)
+        self.offsets, self.t, self.y = offsets, t, y
+        self.n_obj = int(offsets.numel()) - 1
+        self.n_obs = int(t.numel())
+        self.grid = make_grid(f_min, f_max, 1, unit)
+        self.fopt = FeatureOptions()
+        self.fopt.season_gap = float(season_gap)
+        self.fopt.min_season_obs = int(min_season_obs)
+        nb = int(lib().lsp_features_workspace_bytes(self.n_obj))
+        if nb == 0:
+            raise LspError(EINVAL, "lsp_features_workspace_bytes")
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=t.device)
+        if out is None:
+            out = torch.empty((self.n_obj, FEAT_DIM), dtype=torch.float32, device=t.device)
+        _check(out, torch.float32, "out")
+        if out.numel() != self.n_obj * FEAT_DIM:
+            raise ValueError("out must hold n_obj * FEAT_DIM floats")
+        self.out = out
+
+    def __call__(self, stream=None):
+        st = lib().lsp_features(_dev_ptr(self.offsets), self.n_obj, self.n_obs, _dev_ptr(self.t),
+                                _dev_ptr(self.y), ctypes.byref(self.grid),
+                                ctypes.byref(self.fopt), _dev_ptr(self.out),
+                                _dev_ptr(self.workspace), self.workspace.numel(),
+                                _stream_handle(stream))
+        if st != OK:
+            raise LspError(st, "lsp_features")
+        return self.out
 
 
 def autotune(t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, normalize=True,

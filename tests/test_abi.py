@@ -24,6 +24,47 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(lsp.Grid) == 32
     assert ctypes.sizeof(lsp.Options) == 48
     assert lsp.PEAK_DTYPE.itemsize == lsp.PEAK_BYTES == 40
+    assert ctypes.sizeof(lsp.FeatureOptions) == 16
+
+
+def test_feature_constants_match_header():
+    import re
+    text = open(lsp.HEADER).read()
+    for name, val in (("LSP_FEAT_COARSE", lsp.FEAT_COARSE), ("LSP_FEAT_POOL", lsp.FEAT_POOL),
+                      ("LSP_FEAT_WINDOW", lsp.FEAT_WINDOW)):
+        assert int(re.search(rf"#define {name} (\d+)", text).group(1)) == val
+    from oracle import features_ref
+    assert (features_ref.COARSE, features_ref.POOL, features_ref.WINDOW) == (
+        lsp.FEAT_COARSE, lsp.FEAT_POOL, lsp.FEAT_WINDOW)
+
+
+def test_feature_argument_errors(L):
+    g = lsp.make_grid(1.0, 12.0, 1)
+    fo = L.lsp_default_feature_options()
+    assert (fo.season_gap, fo.min_season_obs) == (60.0, 8)
+    nb = L.lsp_features_workspace_bytes(10)
+    assert nb >= 10 * 64 and nb % 256 == 0
+    assert L.lsp_features_workspace_bytes(0) == 0
+
+    def call(offsets=FAKE, n_obj=10, grid=g, fopt=fo, out=FAKE, ws=FAKE, ws_bytes=nb):
+        return L.lsp_features(offsets, n_obj, 100, FAKE, FAKE, ctypes.byref(grid),
+                              ctypes.byref(fopt), out, ws, ws_bytes, None)
+
+    assert call(offsets=None) == lsp.EINVAL
+    assert call(out=None) == lsp.EINVAL
+    assert call(ws=None) == lsp.EINVAL
+    assert call(n_obj=0) == lsp.EINVAL
+    assert call(grid=lsp.make_grid(2.0, 1.0, 1)) == lsp.EINVAL
+    assert call(ws=ctypes.c_void_p((1 << 20) + 8)) == lsp.EINVAL
+    assert call(ws_bytes=nb - 1) == lsp.ENOMEM
+    bad = lsp.FeatureOptions()
+    bad.season_gap, bad.min_season_obs = -1.0, 8
+    assert call(fopt=bad) == lsp.EINVAL
+    bad.season_gap, bad.min_season_obs = 60.0, 0
+    assert call(fopt=bad) == lsp.EINVAL
+    bad.season_gap = float("nan")
+    bad.min_season_obs = 8
+    assert call(fopt=bad) == lsp.EINVAL
 
 
 def test_default_options(L):
@@ -126,7 +167,8 @@ def test_rows_argument_errors(L):
                                 ws_bytes, None)
 
     assert call(offsets=None) == lsp.EINVAL
-    assert call(row_obj=None) == lsp.EINVAL
+    assert call(row_obj=None) == lsp.EINVAL           # 8 rows != 3 objects * 4
+    assert call(row_obj=None, n_rows=12, ws_bytes=1) == lsp.ENOMEM  # 12 == 3 * 4: accepted
     assert call(n_rows=0) == lsp.EINVAL
     assert call(rpg=0) == lsp.EINVAL
     assert call(rpg=3) == lsp.EINVAL        # 3 does not divide 8 rows

@@ -76,6 +76,8 @@ def test_small_kernels(dev):
     n, c = 37, 64
     z = rng.normal(size=(n, c)).astype(np.float32) * 3
     lab = rng.integers(0, c, size=n).astype(np.int32)
+    lab[[3, 17]] = -1      # ignored rows
+    lab[30] = c
     zt = torch.as_tensor(z, device=dev)
     g = torch.empty_like(zt)
     loss = torch.empty(n, dtype=torch.float32, device=dev)
@@ -138,3 +140,41 @@ def test_training_step_matches_reference(dev):
     for b, a in zip(before, net.master):
         d = (a - b).abs().max().item()
         assert 0.0 < d <= 1.01e-3  # the first Adam step moves each parameter by <= lr
+
+
+def test_peak_bands_and_fallback_selection(dev):
+    rng = np.random.default_rng(12)
+    n = 5000
+    pk = np.zeros(n, lsp.PEAK_DTYPE)
+    pk["index"] = rng.integers(0, 6400, n)
+    pk["power"] = rng.uniform(0, 1, n)
+    pk["status"] = 0
+    pk["status"][[5, 77, 4000]] = [1, 2, 3]
+    pk["index"][[5, 77, 4000]] = -1
+    pk["index"][[9, 11]] = -1          # no peak found although status OK
+    pk["power"][13] = np.nan
+    mass = rng.uniform(0, 1, n).astype(np.float32)
+    raw = torch.as_tensor(pk.view(np.uint8), device=dev)
+    mt = torch.as_tensor(mass, device=dev)
+    L = lsp.lib()
+    p = learned._p
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    assert L.lsp_peak_bands(p(raw), n, 100, 64, p(labels), None) == 0
+    want = np.where((pk["status"] == 0) & (pk["index"] >= 0), pk["index"] // 100, -1)
+    torch.cuda.synchronize()
+    assert np.array_equal(labels.cpu().numpy(), want)
+    objs = torch.full((n,), -5, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    for mmin, pmin, use_mass in ((0.6, 0.3, True), (0.0, 0.0, False), (2.0, 0.0, True)):
+        assert L.lsp_select_fallback(p(raw), p(mt) if use_mass else None, n,
+                                     ctypes.c_float(mmin), ctypes.c_float(pmin), p(objs), p(cnt),
+                                     None) == 0
+        torch.cuda.synchronize()
+        ok = pk["status"] == 0
+        need = ok & ((pk["index"] < 0) | ~(pk["power"] >= np.float32(pmin)))
+        if use_mass:
+            need |= ok & ~(mass >= np.float32(mmin))
+        sel = np.nonzero(need)[0]
+        k = int(cnt.item())
+        assert k == len(sel)
+        assert np.array_equal(objs.cpu().numpy()[:k], sel)

@@ -130,3 +130,25 @@ def test_band_edges_and_degenerate_objects(dev):
             best = bins[int(np.argmax(ora_pg[o, bins]))]
             assert abs(int(pk["index"][o]) - best) <= (0 if form == lsp.FORM_FP64 else 1) or \
                 ora_pg[o, pk["index"][o]] >= ora_pg[o, best] - 2 * FP32_ATOL
+
+
+def test_implicit_row_objects(dev):
+    """row_obj = NULL with n_rows = n_obj * R (row r -> object r // R) matches
+    the same rows named explicitly, bit for bit."""
+    w = synth.make_workload("batch_10k", n_obj=30)
+    n_f, n_bands, rpg = 8000, 64, 8
+    band_bins = n_f // n_bands
+    rng = np.random.default_rng(11)
+    row_band = np.concatenate([rng.choice(n_bands, rpg, replace=False)
+                               for _ in range(w.n_obj)]).astype(np.int32)
+    row_obj = np.repeat(np.arange(w.n_obj), rpg).astype(np.int32)
+    pg1, pk1 = _rows_call(dev, w, n_f, row_obj, row_band, band_bins, rpg, lsp.FORM_FP32P)
+    say("  gpu lsp_batch_rows implicit row_obj")
+    pgram = torch.full((w.n_obj, n_f), SENTINEL, dtype=torch.float64, device=dev)
+    r = lsp.Rows(cuda(w.offsets, dev, torch.int64), cuda(w.t, dev), cuda(w.y, dev), w.f_min,
+                 w.f_max, n_f, None, cuda(row_band, dev, torch.int32), band_bins, rpg,
+                 form=lsp.FORM_FP32P, pgram=pgram, pgram_dtype=lsp.PGRAM_F64)
+    r()
+    torch.cuda.synchronize()
+    assert np.array_equal(pgram.cpu().numpy(), pg1)
+    assert r.peaks().tobytes() == pk1.tobytes()

@@ -26,6 +26,18 @@ def test_softmax_xent_closed_forms():
     assert loss < 1e-40
 
 
+def test_softmax_xent_ignores_rows_without_label():
+    rng = np.random.default_rng(2)
+    z = rng.normal(size=(6, 64))
+    lab = np.array([3, -1, 10, 64, 0, -7])
+    loss, g = mlp_ref.softmax_xent(z, lab)
+    keep = [0, 2, 4]
+    l2, g2 = mlp_ref.softmax_xent(z[keep], lab[keep])
+    assert abs(loss - l2 * 3 / 6) < 1e-12            # same sum, divisor 6
+    assert np.allclose(g[keep], g2 * 3 / 6, atol=1e-15)
+    assert np.all(g[[1, 3, 5]] == 0.0)
+
+
 def test_gradients_match_finite_differences():
     """Back-propagation against central differences of the loss (FP64)."""
     dims = (7, 6, 5, 4)
