@@ -267,12 +267,13 @@ lsp_status lsp_autotune(const int64_t *offsets, int64_t n_obj, int64_t n_obs, co
  * evaluates only bands proposed from these per-object features (1,088 FP32
  * values per object, row-major [n_obj][LSP_FEAT_DIM]):
  *   [0, 1024)    coarse spectrum: the series is cut into seasons (a new season
- *                at every gap longer than season_gap); each season with at least
- *                min_season_obs observations gets the normalised power of
- *                Section 2 (Eq. 1-2, season mean removed) on 8,192 bins over
- *                [grid->f_min, grid->f_max) in the grid's unit; bins are
- *                max-pooled in runs of 8 and averaged over those seasons (0 if
- *                none).  FP32 arithmetic as in LSP_FORM_FP32P, no FP64 fix-up;
+ *                at every gap longer than season_gap) and consecutive seasons
+ *                are grouped until a group holds min_season_obs observations (a
+ *                trailing group with fewer is dropped); each group gets the
+ *                normalised power of Section 2 (Eq. 1-2, group mean removed) on
+ *                8,192 bins over [grid->f_min, grid->f_max) in the grid's unit;
+ *                bins are max-pooled in runs of 8 and averaged over the groups
+ *                (0 if none).  FP32 arithmetic as in LSP_FORM_FP32P, no FP64 fix-up;
  *                each value is clamped to [0, 1].
  *   [1024, 1088) sampling and magnitude statistics in FP64: log10 N_t,
  *                log10 max(span, 1e-3), number of seasons, number with >=
@@ -341,8 +342,8 @@ lsp_status lsp_softmax_xent(const float *logits, const int32_t *labels, int64_t 
 /* out[j] = sum_i x[i*c + j] (FP32, fixed order): bias gradients. */
 lsp_status lsp_col_sums(const float *x, int64_t n, int32_t c, float *out, void *stream);
 
-/* Column mean and 1/standard deviation of x [n x d] (1 where a column is
- * constant), for standardising network inputs. */
+/* Column mean and 1/standard deviation of x [n x d] (0 where a column is
+ * constant, so that it standardises to 0), for standardising network inputs. */
 lsp_status lsp_col_stats(const float *x, int64_t n, int32_t d, float *mean, float *inv_std,
                          void *stream);
 
@@ -364,6 +365,21 @@ lsp_status lsp_adam(float *param, const float *grad, float *m, float *v, int64_t
  * probability mass of those k entries into mass [n] (may be NULL). */
 lsp_status lsp_top_k(const float *logits, int64_t n, int32_t c, int32_t k, int32_t *idx,
                      float *mass, void *stream);
+
+/* Pool the statistics of columns [start, start + count) (as produced by
+ * lsp_col_stats) into one mean and 1/std for the whole block, so that columns
+ * that are shifted copies of each other share one scale. */
+lsp_status lsp_pool_stats(float *mean, float *inv_std, int32_t start, int32_t count,
+                          void *stream);
+
+/* Training-time shift augmentation of BF16 rows x [n x d]: the first n_coarse
+ * = group * n_bands columns move by shifts[i] groups of `group` columns
+ * (vacated columns get `fill`), other columns are copied, and labels[i] moves
+ * by shifts[i] (-1 if it leaves [0, n_bands) or was -1).  Shifts are supplied
+ * by the caller (its random draws). */
+lsp_status lsp_shift_bands(const void *x_bf16, const int32_t *labels, const int32_t *shifts,
+                           int64_t n, int32_t d, int32_t n_coarse, int32_t group, int32_t n_bands,
+                           float fill, void *out_bf16, int32_t *out_labels, void *stream);
 
 /* Training labels for the proposal: labels[i] = peaks[i].index / band_bins for
  * an object with status OK and a peak in bands [0, n_bands), else -1 (ignored

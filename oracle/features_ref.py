@@ -9,14 +9,17 @@ evaluates only those.  The features of one object are 1,088 numbers:
 Coarse part (1,024 values).  The series is cut into seasons: a new season
 starts at every observation that follows the previous one by more than
 ``gap`` time units (observations are taken in the order given, which is time
-order for sorted input).  Each season with at least ``min_obs`` observations
-gets its own Lomb-Scargle periodogram -- exactly the normalised power of
-Section 2 (Eq. 1 for tau, Eq. 2 for the power, mean removed per season) -- on
-the half-open grid of 8,192 bins over [f_min, f_max).  Bins are max-pooled in
-runs of 8, giving 1,024 values, and the pooled values are averaged over the
-qualifying seasons (all zero if there is none).  A season spans far less
-time than the whole baseline, so its peaks are wide enough to be resolved by
-8,192 bins, and averaging over seasons reinforces a period that persists.
+order for sorted input).  Consecutive seasons are grouped: a group ends at the
+first season boundary reached once it holds at least ``min_obs``
+observations, so sparse seasons merge with their neighbours; a trailing group
+with fewer observations is dropped.  Each group gets its own Lomb-Scargle
+periodogram -- exactly the normalised power of Section 2 (Eq. 1 for tau, Eq. 2
+for the power, mean removed per group) -- on the half-open grid of 8,192 bins
+over [f_min, f_max).  Bins are max-pooled in runs of 8, giving 1,024 values,
+and the pooled values are averaged over the groups (all zero if there is
+none).  A group spans far less time than the whole baseline, so its peaks are
+wide enough to be resolved by 8,192 bins, and averaging over groups
+reinforces a period that persists.
 
 Window part (64 values).  Sampling and magnitude statistics of the whole
 series: w0 = log10 N_t; w1 = log10 max(T, 1e-3) with T the time span; w2 =
@@ -61,13 +64,24 @@ def seasons(t, gap=SEASON_GAP):
     return list(zip(starts.tolist(), ends.tolist()))
 
 
+def season_groups(t, gap=SEASON_GAP, min_obs=MIN_SEASON_OBS):
+    """[(start, end)) ranges of the season groups that get a periodogram."""
+    out = []
+    start = None
+    for a, b in seasons(t, gap):
+        if start is None:
+            start = a
+        if b - start >= min_obs:
+            out.append((start, b))
+            start = None
+    return out
+
+
 def coarse(t, y, f_min, f_max, unit=oracle.CYCLES, gap=SEASON_GAP, min_obs=MIN_SEASON_OBS):
-    """Season-averaged, max-pooled coarse periodogram (1,024 values)."""
+    """Group-averaged, max-pooled coarse periodogram (1,024 values)."""
     acc = np.zeros(COARSE)
     count = 0
-    for a, b in seasons(t, gap):
-        if b - a < min_obs:
-            continue
+    for a, b in season_groups(t, gap, min_obs):
         pg, _ = oracle.single(t[a:b], y[a:b], f_min, f_max, COARSE_BINS, unit=unit)
         acc += pg.reshape(COARSE, POOL).max(axis=1)
         count += 1

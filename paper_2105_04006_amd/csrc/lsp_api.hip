@@ -105,13 +105,18 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         if (o->t_split > 1) return LSP_EUNSUPPORTED;
         if (o->schedule == LSP_SCHED_PERSISTENT) return LSP_EUNSUPPORTED;
     } else {
+        // Measured defaults: one object on the whole grid runs best with four
+        // waves per workgroup sharing its staged observations; many rows run
+        // best as single-wave workgroups fed from the per-XCD queues.
+        const bool one_row = whole && n_obj == 1;
         c->k = o->k_per_lane ? o->k_per_lane : 16;
-        c->waves = o->waves_per_wg ? o->waves_per_wg : 4;
+        c->waves = o->waves_per_wg ? o->waves_per_wg : (one_row ? 4 : 1);
         if (!o->waves_per_wg)
             while ((int64_t)kWave * c->k * c->waves > n_f && c->waves > 1) c->waves /= 2;
         if (!o->k_per_lane)
             while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 4) c->k /= 2;
-        c->persistent = o->schedule == LSP_SCHED_PERSISTENT ? 1 : 0;
+        c->persistent = o->schedule == LSP_SCHED_PERSISTENT ||
+                        (o->schedule == LSP_SCHED_AUTO && !one_row);
         if (o->t_split > 1) {
             if (n_obj != 1 || !whole) return LSP_EUNSUPPORTED;
             c->split = o->t_split;

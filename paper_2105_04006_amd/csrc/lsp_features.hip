@@ -6,13 +6,14 @@
 // per object:
 //
 //   coarse_kernel : the object is cut into seasons (a new season at every gap
-//     longer than `season_gap`).  For each season with at least
-//     `min_season_obs` observations, the normalised Lomb-Scargle power of
-//     Section 2 (season mean removed, Eq. 1-2 in the tau-free form) is
-//     evaluated on 8,192 bins over [f_min, f_max), max-pooled over runs of 8
-//     bins and averaged over the seasons -> features [0, 1024).  This is the
+//     longer than `season_gap`), and consecutive seasons are grouped until a
+//     group holds at least `min_season_obs` observations (a trailing group
+//     with fewer is dropped).  For each group, the normalised Lomb-Scargle
+//     power of Section 2 (group mean removed, Eq. 1-2 in the tau-free form)
+//     is evaluated on 8,192 bins over [f_min, f_max), max-pooled over runs of
+//     8 bins and averaged over the groups -> features [0, 1024).  This is the
 //     FP32 hot loop of the main kernel (FP64 phase reduction, hardware sin/cos
-//     per observation, rotation across a lane's frequencies) with two extra
+//     per observation, three-term recurrence across a lane's frequencies) with two extra
 //     sums (sum cos, sum sin) so that each season's own mean can be removed
 //     after the fact: sum (y - m) c = sum y c - m sum c.
 //   window_kernel : one wavefront per object computes sampling and magnitude
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
         int64_t ns = 0;
         double sy = 0.0, syy = 0.0;
 
-        // Close the current season: add its pooled power to the features if it
+        // Close the current group: add its pooled power to the features if it
         // has enough observations.
         auto close_season = [&]() {
             if (ns >= P.min_obs) {
@@ -142,14 +143,27 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
             __syncthreads();
             for (int q = 0; q < cnt; ++q) {
                 const float4 o = s_obs[q];
-                // every lane reads the same slot, so the flag is wave-uniform
-                if (uniform_i32(o.w != 0.0f ? 1 : 0)) close_season();
+                // A season boundary closes the current group once it holds
+                // min_obs observations; sparser seasons merge with the next.
+                // Every lane reads the same slot, so the flag is wave-uniform.
+                if (uniform_i32(o.w != 0.0f ? 1 : 0) && ns >= P.min_obs) close_season();
                 const double ph0 = fl * s_tau[q];
                 const float r = (float)(ph0 - rint(ph0));
-                float s = __builtin_amdgcn_sinf(r);
-                float c = __builtin_amdgcn_cosf(r);
+                // Lane frequencies f, f + 64 df, ...: one rotation by the step
+                // angle, then the three-term recurrence x_{k+1} = 2C x_k - x_{k-1}.
+                float sp = __builtin_amdgcn_sinf(r);
+                float cp = __builtin_amdgcn_cosf(r);
+                float c = fmaf(cp, o.y, -(sp * o.z));
+                float s = fmaf(sp, o.y, cp * o.z);
+                const float two_c = o.y + o.y;
+                xc[0] = fmaf(o.x, cp, xc[0]);
+                xs[0] = fmaf(o.x, sp, xs[0]);
+                sc[0] += cp;
+                ss[0] += sp;
+                cc[0] = fmaf(cp, cp, cc[0]);
+                cs[0] = fmaf(cp, sp, cs[0]);
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
+                for (int k = 1; k < K; ++k) {
                     xc[k] = fmaf(o.x, c, xc[k]);
                     xs[k] = fmaf(o.x, s, xs[k]);
                     sc[k] += c;
@@ -157,9 +171,12 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
                     cc[k] = fmaf(c, c, cc[k]);
                     cs[k] = fmaf(c, s, cs[k]);
                     if (k + 1 < K) {
-                        const float cn = fmaf(c, o.y, -(s * o.z));
-                        s = fmaf(s, o.y, c * o.z);
+                        const float cn = fmaf(two_c, c, -cp);
+                        const float sn = fmaf(two_c, s, -sp);
+                        cp = c;
+                        sp = s;
                         c = cn;
+                        s = sn;
                     }
                 }
                 const double yq = (double)o.x;

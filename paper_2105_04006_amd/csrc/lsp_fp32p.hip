@@ -99,32 +99,14 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
                                    __builtin_amdgcn_sinf(rs), 0.0f);
         }
         __syncthreads();
-        // Software pipeline over observations: the seed (FP64 phase
-        // reduction, conversion, hardware sin/cos) of observation q + 1 is
-        // computed while the bins of observation q accumulate, so its latency
-        // chain overlaps independent FMAs instead of stalling the wave.
-        float4 o_nx = s_obs[0];
-        float s_nx, c_nx;
-        {
-            double ph = fl * s_tau[0];
+        for (int q = 0; q < cnt; ++q) {
+            const double tq = s_tau[q];
+            const float4 o = s_obs[q];  // (y - ybar, cos step, sin step, -)
+            double ph = fl * tq;
             ph -= rint(ph);
             const float r = (float)ph;
-            s_nx = __builtin_amdgcn_sinf(r);
-            c_nx = __builtin_amdgcn_cosf(r);
-        }
-        for (int q = 0; q < cnt; ++q) {
-            const float4 o = o_nx;  // (y - ybar, cos step, sin step, -)
-            float s = s_nx;
-            float c = c_nx;
-            {
-                const int qn = q + 1 < cnt ? q + 1 : q;  // last turn: recompute, unused
-                o_nx = s_obs[qn];
-                double ph = fl * s_tau[qn];
-                ph -= rint(ph);
-                const float r = (float)ph;
-                s_nx = __builtin_amdgcn_sinf(r);
-                c_nx = __builtin_amdgcn_cosf(r);
-            }
+            float s = __builtin_amdgcn_sinf(r);
+            float c = __builtin_amdgcn_cosf(r);
             if (!CHEB) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {

@@ -14,6 +14,7 @@
 // 16 x 16 result is held as rows 4 (lane / 16) + r, column lane % 16.
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "lsp_common.h"
 
@@ -27,8 +28,9 @@ constexpr int kBM = 64, kBN = 64, kBK = 32;
 constexpr int kLdsK = kBK + 8;  // padded row: 80 bytes, keeps 16-byte fragment reads aligned
 constexpr int kGemmThreads = 256;
 
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
+__host__ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
     if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
     u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
     return (uint16_t)(u >> 16);
@@ -235,7 +237,72 @@ __global__ void col_stats_kernel(const float* __restrict__ x, int64_t n, int32_t
     }
     const double sd = n > 0 ? sqrt(q / (double)n) : 0.0;
     mean[j] = (float)mu;
-    inv_std[j] = sd > 1e-12 ? (float)(1.0 / sd) : 1.0f;
+    inv_std[j] = sd > 1e-12 ? (float)(1.0 / sd) : 0.0f;  // a constant column carries nothing
+}
+
+// Replace the statistics of columns [start, start + count) by those of the
+// pooled block (every entry of those columns taken together):
+// mean = mean_j m_j, var = mean_j (var_j + m_j^2) - mean^2.  One workgroup,
+// fixed-order sums.
+__global__ __launch_bounds__(256) void pool_stats_kernel(float* mean, float* inv_std,
+                                                         int32_t start, int32_t count) {
+    __shared__ double s_m[256], s_q[256];
+    double m = 0.0, q = 0.0;
+    for (int32_t j = threadIdx.x; j < count; j += 256) {
+        const double mj = mean[start + j];
+        const double is = inv_std[start + j];
+        m += mj;
+        q += (is > 0.0 ? 1.0 / (is * is) : 0.0) + mj * mj;
+    }
+    s_m[threadIdx.x] = m;
+    s_q[threadIdx.x] = q;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_m[threadIdx.x] += s_m[threadIdx.x + w];
+            s_q[threadIdx.x] += s_q[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    const double mu = s_m[0] / (double)count;
+    const double var = s_q[0] / (double)count - mu * mu;
+    const float is = var > 1e-24 ? (float)(1.0 / sqrt(var)) : 0.0f;
+    for (int32_t j = threadIdx.x; j < count; j += 256) {
+        mean[start + j] = (float)mu;
+        inv_std[start + j] = is;
+    }
+}
+
+// Training-time shift augmentation.  Row i's first n_coarse columns hold
+// n_bands groups of `group` columns, one group per frequency band; they move
+// by shift[i] groups (vacated columns get `fill`), the other columns are
+// copied, and the label moves with them (-1 if it leaves [0, n_bands) or was
+// already -1).  A signal whose frequency moves by one band width moves its
+// coarse spectrum by one group, so this multiplies the labelled examples.
+__global__ void shift_bands_kernel(const uint16_t* __restrict__ x,
+                                   const int32_t* __restrict__ labels,
+                                   const int32_t* __restrict__ shifts, int64_t n, int32_t d,
+                                   int32_t n_coarse, int32_t group, int32_t n_bands,
+                                   uint16_t fill, uint16_t* __restrict__ out,
+                                   int32_t* __restrict__ out_labels) {
+    const int64_t e = linear_block() * blockDim.x + threadIdx.x;
+    if (e >= n * d) return;
+    const int64_t i = e / d;
+    const int32_t j = (int32_t)(e - i * d);
+    const int32_t sh = shifts[i];
+    uint16_t v;
+    if (j < n_coarse) {
+        const int64_t src = (int64_t)j - (int64_t)sh * group;
+        v = (src >= 0 && src < n_coarse) ? x[i * d + src] : fill;
+    } else {
+        v = x[e];
+    }
+    out[e] = v;
+    if (j == 0) {
+        const int32_t lab = labels[i];
+        const int32_t nl = lab + sh;
+        out_labels[i] = (lab >= 0 && nl >= 0 && nl < n_bands) ? nl : -1;
+    }
 }
 
 __global__ void standardize_kernel(const float* __restrict__ x, int64_t n, int32_t d,
@@ -412,6 +479,29 @@ lsp_status lsp_top_k(const float* logits, int64_t n, int32_t c, int32_t k, int32
     if (n == 0) return LSP_OK;
     hipLaunchKernelGGL(lsp::top_k_kernel, lsp::grid_for((n + 3) / 4), dim3(256), 0,
                        static_cast<hipStream_t>(stream), logits, n, c, k, idx, mass);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_pool_stats(float* mean, float* inv_std, int32_t start, int32_t count,
+                          void* stream) {
+    if (!mean || !inv_std || start < 0 || count < 1) return LSP_EINVAL;
+    hipLaunchKernelGGL(lsp::pool_stats_kernel, dim3(1), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), mean, inv_std, start, count);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_shift_bands(const void* x_bf16, const int32_t* labels, const int32_t* shifts,
+                           int64_t n, int32_t d, int32_t n_coarse, int32_t group, int32_t n_bands,
+                           float fill, void* out_bf16, int32_t* out_labels, void* stream) {
+    if (n < 0 || d < 1 || n_coarse < 0 || n_coarse > d || group < 1 || n_bands < 1 ||
+        (int64_t)group * n_bands != n_coarse)
+        return LSP_EINVAL;
+    if (n > 0 && (!x_bf16 || !labels || !shifts || !out_bf16 || !out_labels)) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::shift_bands_kernel, lsp::grid_for((n * d + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const uint16_t*>(x_bf16),
+                       labels, shifts, n, d, n_coarse, group, n_bands, lsp::f32_to_bf16_bits(fill),
+                       static_cast<uint16_t*>(out_bf16), out_labels);
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
 

@@ -7,7 +7,7 @@
 // must reduce).  The periodogram kernels re-centre t and y with these values
 // as they stage observations, so nothing per observation is written here and
 // objects whose CSR ranges overlap cannot interfere.  One workgroup per
-// object; all reductions are fixed-order trees (bitwise reproducible).
+// object; all reductions are in a fixed order (bitwise reproducible).
 #include "lsp_common.h"
 
 namespace lsp {
@@ -18,42 +18,52 @@ struct Red {
     int bad;
 };
 
-__device__ void block_reduce(Red& r, Red* sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = r;
-    __syncthreads();
-    for (int w = kPrepThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            Red a = sh[tid], b = sh[tid + w];
-            a.sy += b.sy;
-            a.syy_raw += b.syy_raw;
-            a.tmin = fmin(a.tmin, b.tmin);
-            a.tmax = fmax(a.tmax, b.tmax);
-            a.bad |= b.bad;
-            sh[tid] = a;
-        }
-        __syncthreads();
+__device__ __forceinline__ Red combine(Red a, const Red& b) {
+    a.sy += b.sy;
+    a.syy_raw += b.syy_raw;
+    a.tmin = fmin(a.tmin, b.tmin);
+    a.tmax = fmax(a.tmax, b.tmax);
+    a.bad |= b.bad;
+    return a;
+}
+
+// Fixed-order reduction: butterfly within each wavefront, then the wave
+// results in wave order (bitwise reproducible, one barrier pair).
+__device__ Red block_reduce(Red r, Red* sh) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        Red b;
+        b.sy = __shfl_xor(r.sy, o, kWave);
+        b.syy_raw = __shfl_xor(r.syy_raw, o, kWave);
+        b.tmin = __shfl_xor(r.tmin, o, kWave);
+        b.tmax = __shfl_xor(r.tmax, o, kWave);
+        b.bad = __shfl_xor(r.bad, o, kWave);
+        r = combine(r, b);
     }
-    r = sh[0];
+    const int wave = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[wave] = r;
     __syncthreads();
+    Red out = sh[0];
+    for (int w = 1; w < kPrepThreads / kWave; ++w) out = combine(out, sh[w]);
+    __syncthreads();
+    return out;
 }
 
 __device__ double block_sum(double v, double* sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    const int wave = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[wave] = v;
     __syncthreads();
-    for (int w = kPrepThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) sh[tid] += sh[tid + w];
-        __syncthreads();
-    }
-    const double out = sh[0];
+    double out = sh[0];
+    for (int w = 1; w < kPrepThreads / kWave; ++w) out += sh[w];
     __syncthreads();
     return out;
 }
 
 __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const PrepParams P) {
-    __shared__ Red sh_red[kPrepThreads];
-    __shared__ double sh_sum[kPrepThreads];
+    __shared__ Red sh_red[kPrepThreads / kWave];
+    __shared__ double sh_sum[kPrepThreads / kWave];
     const int64_t o = linear_block();
     const int tid = threadIdx.x;
     if (o >= P.n_obj) return;
@@ -84,7 +94,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const PrepParams P) 
         r.tmin = fmin(r.tmin, tj);
         r.tmax = fmax(r.tmax, tj);
     }
-    block_reduce(r, sh_red);
+    r = block_reduce(r, sh_red);
 
     const double ybar = (P.subtract_mean && n > 0) ? r.sy / (double)n : 0.0;
     const double t0 = (n > 0 && !r.bad) ? 0.5 * (r.tmin + r.tmax) : 0.0;

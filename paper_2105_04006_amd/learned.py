@@ -85,12 +85,18 @@ class BandNet:
         return b
 
     # ------------------------------------------------------- standardising
-    def fit_standardizer(self, feats, stream=None):
+    def fit_standardizer(self, feats, pool=lsp.FEAT_COARSE, stream=None):
+        """Column means and scales from a training set; the first `pool`
+        columns (the coarse spectrum, whose columns are shifted copies of each
+        other) share one mean and scale."""
         n, d = feats.shape
         self.mean = torch.empty(d, dtype=torch.float32, device=self.device)
         self.inv_std = torch.empty(d, dtype=torch.float32, device=self.device)
         _ok(lsp.lib().lsp_col_stats(_p(feats), n, d, _p(self.mean), _p(self.inv_std),
                                     _s(stream)), "lsp_col_stats")
+        if pool:
+            _ok(lsp.lib().lsp_pool_stats(_p(self.mean), _p(self.inv_std), 0, int(pool),
+                                         _s(stream)), "lsp_pool_stats")
 
     def standardize(self, feats, out=None, stream=None):
         n, d = feats.shape
@@ -260,25 +266,56 @@ class LearnedPeriodogram:
         return self.peaks_raw.cpu().numpy().view(lsp.PEAK_DTYPE).copy()
 
 
+def shift_bands(x, labels, shifts, n_bands, out=None, out_labels=None, stream=None):
+    """lsp_shift_bands on BF16 rows: move the coarse spectrum by shifts[i] bands."""
+    n, d = x.shape
+    out = torch.empty_like(x) if out is None else out
+    out_labels = torch.empty_like(labels) if out_labels is None else out_labels
+    group = lsp.FEAT_COARSE // n_bands
+    _ok(lsp.lib().lsp_shift_bands(_p(x), _p(labels), _p(shifts), n, d, lsp.FEAT_COARSE, group,
+                                  n_bands, ctypes.c_float(0.0), _p(out), _p(out_labels),
+                                  _s(stream)), "lsp_shift_bands")
+    return out, out_labels
+
+
 def train_proposer(net, feats, labels, epochs=20, batch=1024, lr=1e-3, lr_final=1e-4,
-                   log=None, stream=None):
+                   augment=0.5, seed=0, log=None, stream=None):
     """Adam on softmax cross-entropy over contiguous minibatches (the synthetic
     training objects are drawn independently, so their order is already random);
     the learning rate decays geometrically from lr to lr_final.  Fits the
-    standardiser first.  Returns the mean loss of each epoch."""
+    standardiser first (the coarse spectrum pooled to one scale, which is
+    what makes shifted copies comparable).
+
+    With augment > 0, that fraction of each minibatch has its coarse spectrum
+    moved so that its label becomes a band drawn uniformly (lsp_shift_bands;
+    the draws come from a seeded host generator).  Returns the mean loss of
+    each epoch."""
     n = feats.shape[0]
+    n_bands = net.dims[-1]
     net.fit_standardizer(feats, stream=stream)
     x = net.standardize(feats, stream=stream)
     steps = max(1, (n // batch)) * epochs
     decay = (lr_final / lr) ** (1.0 / max(1, steps - 1))
     rate = lr
+    rng = np.random.default_rng(seed)
+    lab_host = labels.cpu().numpy()
+    xa = torch.empty((batch, x.shape[1]), dtype=x.dtype, device=x.device)
+    la = torch.empty(batch, dtype=torch.int32, device=x.device)
     hist = []
     for ep in range(epochs):
         tot = torch.zeros((), dtype=torch.float32, device=feats.device)
         nb = 0
         for b0 in range(0, n - batch + 1, batch):
-            loss_rows = net.train_step(x[b0:b0 + batch], labels[b0:b0 + batch], lr=rate,
-                                       stream=stream)
+            xb, lb = x[b0:b0 + batch], labels[b0:b0 + batch]
+            if augment > 0:
+                lab = lab_host[b0:b0 + batch]
+                target = rng.integers(0, n_bands, batch)
+                move = (rng.random(batch) < augment) & (lab >= 0)
+                sh = np.where(move, target - lab, 0).astype(np.int32)
+                shifts = torch.as_tensor(sh, device=x.device)
+                xb, lb = shift_bands(xb, lb, shifts, n_bands, out=xa, out_labels=la,
+                                     stream=stream)
+            loss_rows = net.train_step(xb, lb, lr=rate, stream=stream)
             tot += loss_rows.sum()
             nb += 1
             rate *= decay
@@ -300,8 +337,11 @@ def calibrate(refined, full, mass, target=0.999):
     n = int(ok.sum())
     allowed = int(np.floor((1.0 - target) * n))
     pw = np.where(np.isfinite(refined["power"]), refined["power"], -1.0)
-    m_grid = np.unique(np.concatenate([[0.0], np.quantile(mass[ok], np.linspace(0, 0.5, 51))]))
-    p_grid = np.unique(np.concatenate([[0.0], np.quantile(pw[ok], np.linspace(0, 0.5, 51))]))
+    if n == 0:
+        return 0.0, 0.0, 0
+    q = np.linspace(0.0, 1.0, 101)
+    m_grid = np.unique(np.concatenate([[0.0], np.quantile(mass[ok], q), [2.0]]))
+    p_grid = np.unique(np.concatenate([[0.0], np.quantile(pw[ok], q), [2.0]]))
     best = (2.0, 2.0, n + 1)
     for mm in m_grid:
         for pm in p_grid:

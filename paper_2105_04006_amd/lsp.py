@@ -126,6 +126,10 @@ def lib():
         L.lsp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp, vp]
         L.lsp_top_k.restype = ctypes.c_int
         L.lsp_top_k.argtypes = [vp, i64, i32, i32, vp, vp, vp]
+        L.lsp_pool_stats.restype = ctypes.c_int
+        L.lsp_pool_stats.argtypes = [vp, vp, i32, i32, vp]
+        L.lsp_shift_bands.restype = ctypes.c_int
+        L.lsp_shift_bands.argtypes = [vp, vp, vp, i64, i32, i32, i32, i32, f32, vp, vp, vp]
         L.lsp_peak_bands.restype = ctypes.c_int
         L.lsp_peak_bands.argtypes = [vp, i64, i64, i32, vp, vp]
         L.lsp_select_fallback.restype = ctypes.c_int

@@ -52,13 +52,32 @@ def test_coarse_average_over_seasons_and_min_obs():
     t2, y2 = _even_season(n, dt, f0, t_start=500.0)
     two = fr.coarse(np.concatenate([t1, t2]), np.concatenate([y1, y2]), 0.0, 40.0)
     assert np.allclose(two, one, atol=1e-9)
-    # a short season (fewer than 8 points) is ignored
+    # a short trailing season (fewer than 8 points) is dropped
     t3 = np.array([900.0, 901.0, 902.5])
     y3 = np.array([1.0, -2.0, 0.5])
     three = fr.coarse(np.concatenate([t1, t3]), np.concatenate([y1, y3]), 0.0, 40.0)
     assert np.array_equal(three, one)
-    # with no qualifying season the coarse part is zero
+    # with no group of 8 points the coarse part is zero
     assert np.array_equal(fr.coarse(t3, y3, 0.0, 40.0), np.zeros(fr.COARSE))
+
+
+def test_short_seasons_merge_into_groups():
+    # seasons of 5, 5 and 12 points: the first two form one group of 10, the
+    # third is a group of its own
+    rng = np.random.default_rng(8)
+    ta = np.sort(rng.uniform(0, 30, 5))
+    tb = np.sort(rng.uniform(200, 230, 5))
+    tc = np.sort(rng.uniform(400, 440, 12))
+    t = np.concatenate([ta, tb, tc])
+    y = rng.normal(size=len(t))
+    assert fr.seasons(t) == [(0, 5), (5, 10), (10, 22)]
+    assert fr.season_groups(t) == [(0, 10), (10, 22)]
+    pg1, _ = oracle.single(t[:10], y[:10], 1.0, 5.0, fr.COARSE_BINS)
+    pg2, _ = oracle.single(t[10:], y[10:], 1.0, 5.0, fr.COARSE_BINS)
+    want = (pg1.reshape(-1, 8).max(1) + pg2.reshape(-1, 8).max(1)) / 2
+    assert np.allclose(fr.coarse(t, y, 1.0, 5.0), want, rtol=0, atol=1e-15)
+    # a short season at the end joins nothing and is dropped
+    assert fr.season_groups(np.concatenate([t, [700.0, 701.0]])) == [(0, 10), (10, 22)]
 
 
 def test_coarse_pooling_matches_per_bin_maxima():

@@ -1,8 +1,9 @@
 """Learned band proposal end to end (needs an MI355X).
 
-Small-scale version of the learned path: N_f = 20,480 bins in 64 bands of 320,
-a network trained on a few thousand synthetic objects, then on held-out
-objects:
+Reduced version of the learned path: the learned_100k grid (N_f = 200,000
+bins over [1, 12) cycles/day, 64 bands of 3,125 bins; fine enough that the
+whole-grid peak sits on the signal's main lobe, so band labels are clean), a
+network trained on a few thousand synthetic objects, then on held-out objects:
   * forcing every object to fall back reproduces the whole-grid batch peaks
     bit for bit (same kernels, same tiles);
   * refined peaks are checked against the FP64 oracle at the reported bin;
@@ -20,7 +21,7 @@ from test_gpu_parity import cuda, dev, oracle, say  # noqa: E402,F401
 
 pytestmark = pytest.mark.gpu
 
-N_F = 20480
+N_F = 200_000
 N_BANDS = 64
 
 
