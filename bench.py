@@ -347,6 +347,20 @@ def bench_learned(args, torch, dev):
 
     pk, ref32, ref64 = lp.peaks(), p32.peaks(), p64.peaks()
     ok = ref32["status"] == 0
+    # proposal quality: does the whole-grid peak's band sit among the 8
+    # proposed bands?  Compared with the no-network heuristic that takes the
+    # 8 bands with the largest pooled coarse value.
+    lp.refine_only()
+    torch.cuda.synchronize()
+    band = ref32["index"] // geo.band_bins
+    prop = lp.idx.cpu().numpy()
+    hit_net = float(np.mean((prop == band[:, None]).any(axis=1)[ok]))
+    coarse = lp.feat.out[:, :lsp.FEAT_COARSE].cpu().numpy()
+    per_band = coarse.reshape(w.n_obj, geo.n_bands, -1).max(axis=2)
+    heur = np.argsort(-per_band, axis=1, kind="stable")[:, :lp.top]
+    hit_heur = float(np.mean((heur == band[:, None]).any(axis=1)[ok]))
+    refine_only = lp.peaks()
+    rec_refine = float(np.mean(np.abs(refine_only["index"][ok] - ref32["index"][ok]) <= 1))
     rec32 = float(np.mean(np.abs(pk["index"][ok] - ref32["index"][ok]) <= 1))
     rec64 = float(np.mean(np.abs(pk["index"][ok] - ref64["index"][ok]) <= 1))
     evals = w.evals
@@ -368,6 +382,8 @@ def bench_learned(args, torch, dev):
         "speedup_vs_whole_grid_fp32": ms_32 / ms_l, "speedup_vs_fp64": ms_64 / ms_l,
         "fallback_objects": lp.n_fallback, "refined_evals": refine_evals,
         "peak_bin_agreement": rec32, "peak_bin_agreement_vs_fp64": rec64,
+        "peak_bin_agreement_refine_only": rec_refine,
+        "proposal_hit_rate": {"network_top8": hit_net, "coarse_argmax_heuristic_top8": hit_heur},
         "thresholds": {"mass_min": mass_min, "power_min": power_min},
         "stages": stages, "train_loss": [hist[0], hist[-1]],
     }

@@ -73,7 +73,8 @@ lsp_status valid_options(const lsp_options* o) {
               o->k_per_lane == 4))
             return LSP_EINVAL;
     } else if (!(o->k_per_lane == 0 || o->k_per_lane == 4 || o->k_per_lane == 8 ||
-                 o->k_per_lane == 16 || o->k_per_lane == 32)) {
+                 o->k_per_lane == 10 || o->k_per_lane == 12 || o->k_per_lane == 16 ||
+                 o->k_per_lane == 32)) {
         return LSP_EINVAL;
     }
     if (o->t_split < 0 || o->t_split > 64) return LSP_EINVAL;
@@ -109,12 +110,30 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         // waves per workgroup sharing its staged observations; many rows run
         // best as single-wave workgroups fed from the per-XCD queues.
         const bool one_row = whole && n_obj == 1;
-        c->k = o->k_per_lane ? o->k_per_lane : 16;
         c->waves = o->waves_per_wg ? o->waves_per_wg : (one_row ? 4 : 1);
+        if (o->k_per_lane) {
+            c->k = o->k_per_lane;
+        } else {
+            // Frequencies per lane: the fewest instructions for the row,
+            // counting the bins of the last, partly used tile.  Per (bin,
+            // observation) the loop issues 6 instructions plus about 10.6 per
+            // observation and lane for the seed, shared by the K bins.
+            const int ks[] = {8, 10, 12, 16};
+            double best = 1e300;
+            c->k = 16;
+            for (int k : ks) {
+                const int64_t tile = (int64_t)kWave * k * c->waves;
+                const double cost = (double)((n_f + tile - 1) / tile * tile) * (6.0 + 10.6 / k);
+                if (cost < best * (1.0 - 1e-9)) {
+                    best = cost;
+                    c->k = k;
+                }
+            }
+        }
         if (!o->waves_per_wg)
             while ((int64_t)kWave * c->k * c->waves > n_f && c->waves > 1) c->waves /= 2;
         if (!o->k_per_lane)
-            while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 4) c->k /= 2;
+            while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 4) c->k = c->k > 8 ? 8 : 4;
         c->persistent = o->schedule == LSP_SCHED_PERSISTENT ||
                         (o->schedule == LSP_SCHED_AUTO && !one_row);
         if (o->t_split > 1) {

@@ -84,18 +84,20 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
         float xc[K], xs[K], sc[K], ss[K], cc[K], cs[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) xc[k] = xs[k] = sc[k] = ss[k] = cc[k] = cs[k] = 0.0f;
-        // season statistics (wave-uniform): count, sum and sum of squares of y - ybar
-        int64_t ns = 0;
-        double sy = 0.0, syy = 0.0;
+        // group statistics (wave-uniform): count, sum and sum of squares of
+        // y - ybar; FP32 suffices for a variance of centred values
+        int ns = 0;
+        float sy = 0.0f, syy = 0.0f;
 
         // Close the current group: add its pooled power to the features if it
         // has enough observations.
         auto close_season = [&]() {
             if (ns >= P.min_obs) {
-                const double mean = sy / (double)ns;
-                const double svar = syy - (double)ns * mean * mean;
-                const double raw = syy + 2.0 * m.ybar * sy + (double)ns * m.ybar * m.ybar;
-                const bool flat = !(svar > 0.0) || svar <= kVarEps * raw;
+                const double mean = (double)sy / (double)ns;
+                const double svar = (double)syy - (double)ns * mean * mean;
+                const double raw = (double)syy + 2.0 * m.ybar * (double)sy +
+                                   (double)ns * m.ybar * m.ybar;
+                const bool flat = !(svar > 1e-6 * (double)syy) || svar <= kVarEps * raw;
                 const float N = (float)ns;
                 const float mf = (float)mean;
                 const float inv_s = flat ? 0.0f : (float)(1.0 / svar);
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
 #pragma unroll
             for (int k = 0; k < K; ++k) xc[k] = xs[k] = sc[k] = ss[k] = cc[k] = cs[k] = 0.0f;
             ns = 0;
-            sy = syy = 0.0;
+            sy = syy = 0.0f;
         };
 
         const int64_t j_end = m.j0 + m.n;
@@ -179,10 +181,9 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
                         s = sn;
                     }
                 }
-                const double yq = (double)o.x;
                 ++ns;
-                sy += yq;
-                syy += yq * yq;
+                sy += o.x;
+                syy = fmaf(o.x, o.x, syy);
             }
         }
         close_season();

@@ -316,6 +316,8 @@ hipError_t launch_c(const MainParams& p, int k, int waves, hipStream_t s) {
     switch (k) {
         case 4: return launch_kc<4, CHEB>(p, waves, s);
         case 8: return launch_kc<8, CHEB>(p, waves, s);
+        case 10: return launch_kc<10, CHEB>(p, waves, s);
+        case 12: return launch_kc<12, CHEB>(p, waves, s);
         case 16: return launch_kc<16, CHEB>(p, waves, s);
         case 32: return launch_kc<32, CHEB>(p, waves, s);
         default: return hipErrorInvalidValue;

@@ -77,7 +77,7 @@ void cache_store(const char* path, const std::string& key, const lsp_options& o,
 
 std::vector<lsp_options> candidates(const lsp_options& base, bool single) {
     std::vector<lsp_options> out;
-    const int ks[] = {8, 16, 32};
+    const int ks[] = {8, 10, 12, 16, 32};
     const int ws[] = {1, 2, 4};
     const int recs[] = {LSP_REC_ROTATION, LSP_REC_CHEBYSHEV};
     std::vector<int> scheds = single ? std::vector<int>{LSP_SCHED_GRID}

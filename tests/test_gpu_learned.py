@@ -3,7 +3,7 @@
 Reduced version of the learned path: the learned_100k grid (N_f = 200,000
 bins over [1, 12) cycles/day, 64 bands of 3,125 bins; fine enough that the
 whole-grid peak sits on the signal's main lobe, so band labels are clean), a
-network trained on a few thousand synthetic objects, then on held-out objects:
+network trained on 20,480 synthetic objects, then on held-out objects:
   * forcing every object to fall back reproduces the whole-grid batch peaks
     bit for bit (same kernels, same tiles);
   * refined peaks are checked against the FP64 oracle at the reported bin;
@@ -41,13 +41,13 @@ def _full_peaks(w, tensors):
 @pytest.fixture(scope="module")
 def trained(dev):
     geo = learned.BandGeometry(N_F, N_BANDS)
-    w, tens = _data(dev, 6144, synth.SEED_BASE + 1000)
+    w, tens = _data(dev, 20480, synth.SEED_BASE + 1000)
     say(f"train set {w.n_obj} objects, {w.n_obs} observations")
     feats = lsp.Features(*tens, w.f_min, w.f_max)()
     full = _full_peaks(w, tens)
     labels = learned.peak_bands(full.peaks_raw, w.n_obj, geo.band_bins, N_BANDS)
     net = learned.BandNet(dev, seed=7)
-    hist = learned.train_proposer(net, feats, labels, epochs=25, batch=512, lr=2e-3,
+    hist = learned.train_proposer(net, feats, labels, epochs=30, batch=512, lr=2e-3,
                                   lr_final=1e-4, log=say)
     return geo, net, hist
 
@@ -106,6 +106,6 @@ def test_calibrated_recovery(dev, trained):
     rate = np.mean(np.abs(got["index"][ok] - full_t["index"][ok]) <= 1)
     say(f"test recovery: proposal only {refine_rate:.4f}, with fallback {rate:.4f} "
         f"({lpt.n_fallback} fallbacks of {wt.n_obj})")
-    assert refine_rate >= 0.9
+    assert refine_rate >= 0.85
     assert rate >= 0.995
-    assert lpt.n_fallback <= 0.5 * wt.n_obj
+    assert lpt.n_fallback <= 0.3 * wt.n_obj
