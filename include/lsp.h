@@ -270,8 +270,10 @@ lsp_status lsp_autotune(const int64_t *offsets, int64_t n_obj, int64_t n_obs, co
  *                at every gap longer than season_gap) and consecutive seasons
  *                are grouped until a group holds min_season_obs observations (a
  *                trailing group with fewer is dropped); each group gets the
- *                normalised power of Section 2 (Eq. 1-2, group mean removed) on
- *                8,192 bins over [grid->f_min, grid->f_max) in the grid's unit;
+ *                normalised power of Section 2 (Eq. 1-2) of the object's
+ *                centred magnitudes y - ybar (the group mean is not removed
+ *                again) on 8,192 bins over [grid->f_min, grid->f_max) in the
+ *                grid's unit;
  *                bins are max-pooled in runs of 8 and averaged over the groups
  *                (0 if none).  FP32 arithmetic as in LSP_FORM_FP32P, no FP64 fix-up;
  *                each value is clamped to [0, 1].
@@ -290,7 +292,7 @@ lsp_status lsp_autotune(const int64_t *offsets, int64_t n_obj, int64_t n_obs, co
  *   features  : device, n_obj * LSP_FEAT_DIM floats.
  *   workspace : device, >= lsp_features_workspace_bytes(n_obj) bytes, 256-aligned.
  * Errors: LSP_EINVAL for NULL offsets/features/workspace/grid, n_obj < 1, a
- * bad grid range or unit, season_gap negative or non-finite, min_season_obs < 1;
+ * bad grid range or unit, season_gap negative or non-finite, min_season_obs < 2;
  * LSP_ENOMEM for a short workspace.
  */
 #define LSP_FEAT_COARSE 1024
@@ -300,7 +302,7 @@ lsp_status lsp_autotune(const int64_t *offsets, int64_t n_obj, int64_t n_obs, co
 
 typedef struct {
     double season_gap;      /* time units; default 60                         */
-    int32_t min_season_obs; /* default 8                                      */
+    int32_t min_season_obs; /* default 8, at least 2                          */
     int32_t reserved;
 } lsp_feature_options;
 

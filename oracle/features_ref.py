@@ -14,8 +14,9 @@ first season boundary reached once it holds at least ``min_obs``
 observations, so sparse seasons merge with their neighbours; a trailing group
 with fewer observations is dropped.  Each group gets its own Lomb-Scargle
 periodogram -- exactly the normalised power of Section 2 (Eq. 1 for tau, Eq. 2
-for the power, mean removed per group) -- on the half-open grid of 8,192 bins
-over [f_min, f_max).  Bins are max-pooled in runs of 8, giving 1,024 values,
+for the power) of the object's centred magnitudes y - ybar (ybar the mean
+over the whole object; the group's own mean is not removed again) -- on the
+half-open grid of 8,192 bins over [f_min, f_max).  Bins are max-pooled in runs of 8, giving 1,024 values,
 and the pooled values are averaged over the groups (all zero if there is
 none).  A group spans far less time than the whole baseline, so its peaks are
 wide enough to be resolved by 8,192 bins, and averaging over groups
@@ -81,8 +82,10 @@ def coarse(t, y, f_min, f_max, unit=oracle.CYCLES, gap=SEASON_GAP, min_obs=MIN_S
     """Group-averaged, max-pooled coarse periodogram (1,024 values)."""
     acc = np.zeros(COARSE)
     count = 0
+    yc = np.asarray(y, dtype=np.float64) - np.mean(y)
     for a, b in season_groups(t, gap, min_obs):
-        pg, _ = oracle.single(t[a:b], y[a:b], f_min, f_max, COARSE_BINS, unit=unit)
+        pg, _ = oracle.single(t[a:b], yc[a:b], f_min, f_max, COARSE_BINS, unit=unit,
+                              subtract_mean=False)
         acc += pg.reshape(COARSE, POOL).max(axis=1)
         count += 1
     return acc / count if count else acc

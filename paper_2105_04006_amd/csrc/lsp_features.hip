@@ -9,13 +9,14 @@
 //     longer than `season_gap`), and consecutive seasons are grouped until a
 //     group holds at least `min_season_obs` observations (a trailing group
 //     with fewer is dropped).  For each group, the normalised Lomb-Scargle
-//     power of Section 2 (group mean removed, Eq. 1-2 in the tau-free form)
-//     is evaluated on 8,192 bins over [f_min, f_max), max-pooled over runs of
-//     8 bins and averaged over the groups -> features [0, 1024).  This is the
-//     FP32 hot loop of the main kernel (FP64 phase reduction, hardware sin/cos
-//     per observation, three-term recurrence across a lane's frequencies) with two extra
-//     sums (sum cos, sum sin) so that each season's own mean can be removed
-//     after the fact: sum (y - m) c = sum y c - m sum c.
+//     power of Section 2 (Eq. 1-2 in the tau-free form) of the object's
+//     centred magnitudes y - ybar is evaluated on 8,192 bins over
+//     [f_min, f_max), max-pooled over runs of 8 bins and averaged over the
+//     groups -> features [0, 1024).  The group's own mean is not removed
+//     again: that only changes power near zero frequency, and it keeps the
+//     loop identical to the FP32 hot loop of the main kernel (FP64 phase
+//     reduction, hardware sin/cos per observation, three-term recurrence
+//     across a lane's frequencies, four sums).
 //   window_kernel : one wavefront per object computes sampling and magnitude
 //     statistics and the spectral window at 53 probe frequencies in FP64
 //     -> features [1024, 1088).
@@ -30,9 +31,9 @@
 namespace lsp {
 namespace {
 
-constexpr int kCoarseK = 8;      // frequencies per lane
-constexpr int kCoarseW = 4;      // wavefronts per workgroup
-constexpr int kCoarseTile = kWave * kCoarseK * kCoarseW;  // 2,048 bins
+constexpr int kCoarseK = 16;     // frequencies per lane
+constexpr int kCoarseW = 1;      // wavefronts per workgroup
+constexpr int kCoarseTile = kWave * kCoarseK * kCoarseW;  // 1,024 bins
 constexpr int kTilesPerObj = LSP_FEAT_COARSE * LSP_FEAT_POOL / kCoarseTile;
 constexpr float kDenEps32 = 1e-5f;  // drop a term whose denominator is below this * N
 constexpr int kProbes = LSP_FEAT_WINDOW - 11;
@@ -81,36 +82,29 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
 
     if (m.status == LSP_OBJ_OK) {
         const double fl = grid_freq(P.f_min, P.df, i0) * P.to_cyc;
-        float xc[K], xs[K], sc[K], ss[K], cc[K], cs[K];
+        float xc[K], xs[K], cc[K], cs[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) xc[k] = xs[k] = sc[k] = ss[k] = cc[k] = cs[k] = 0.0f;
-        // group statistics (wave-uniform): count, sum and sum of squares of
-        // y - ybar; FP32 suffices for a variance of centred values
+        for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
+        // group count and sum of squares of y - ybar (wave-uniform)
         int ns = 0;
-        float sy = 0.0f, syy = 0.0f;
+        float syy = 0.0f;
 
         // Close the current group: add its pooled power to the features if it
         // has enough observations.
-        auto close_season = [&]() {
+        auto close_group = [&]() {
             if (ns >= P.min_obs) {
-                const double mean = (double)sy / (double)ns;
-                const double svar = (double)syy - (double)ns * mean * mean;
-                const double raw = (double)syy + 2.0 * m.ybar * (double)sy +
-                                   (double)ns * m.ybar * m.ybar;
-                const bool flat = !(svar > 1e-6 * (double)syy) || svar <= kVarEps * raw;
                 const float N = (float)ns;
-                const float mf = (float)mean;
-                const float inv_s = flat ? 0.0f : (float)(1.0 / svar);
+                const float inv_s = syy > 0.0f ? 1.0f / syy : 0.0f;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const float XC = fmaf(-mf, sc[k], xc[k]);
-                    const float XS = fmaf(-mf, ss[k], xs[k]);
                     const float C2 = 2.0f * cc[k] - N;
                     const float S2 = 2.0f * cs[k];
                     const float R = sqrtf(C2 * C2 + S2 * S2);
-                    const float A = XC * XC + XS * XS;
-                    const float B = R > 0.0f ? ((XC * XC - XS * XS) * C2 + 2.0f * XC * XS * S2) / R
-                                             : 0.0f;
+                    const float A = xc[k] * xc[k] + xs[k] * xs[k];
+                    const float B =
+                        R > 0.0f
+                            ? ((xc[k] * xc[k] - xs[k] * xs[k]) * C2 + 2.0f * xc[k] * xs[k] * S2) / R
+                            : 0.0f;
                     const float dp = N + R, dm = N - R;
                     float p = 0.0f;
                     if (dp > kDenEps32 * N) p += (A + B) / dp;
@@ -121,9 +115,9 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
                 ++n_good;
             }
 #pragma unroll
-            for (int k = 0; k < K; ++k) xc[k] = xs[k] = sc[k] = ss[k] = cc[k] = cs[k] = 0.0f;
+            for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
             ns = 0;
-            sy = syy = 0.0f;
+            syy = 0.0f;
         };
 
         const int64_t j_end = m.j0 + m.n;
@@ -148,7 +142,7 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
                 // A season boundary closes the current group once it holds
                 // min_obs observations; sparser seasons merge with the next.
                 // Every lane reads the same slot, so the flag is wave-uniform.
-                if (uniform_i32(o.w != 0.0f ? 1 : 0) && ns >= P.min_obs) close_season();
+                if (uniform_i32(o.w != 0.0f ? 1 : 0) && ns >= P.min_obs) close_group();
                 const double ph0 = fl * s_tau[q];
                 const float r = (float)(ph0 - rint(ph0));
                 // Lane frequencies f, f + 64 df, ...: one rotation by the step
@@ -160,16 +154,12 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
                 const float two_c = o.y + o.y;
                 xc[0] = fmaf(o.x, cp, xc[0]);
                 xs[0] = fmaf(o.x, sp, xs[0]);
-                sc[0] += cp;
-                ss[0] += sp;
                 cc[0] = fmaf(cp, cp, cc[0]);
                 cs[0] = fmaf(cp, sp, cs[0]);
 #pragma unroll
                 for (int k = 1; k < K; ++k) {
                     xc[k] = fmaf(o.x, c, xc[k]);
                     xs[k] = fmaf(o.x, s, xs[k]);
-                    sc[k] += c;
-                    ss[k] += s;
                     cc[k] = fmaf(c, c, cc[k]);
                     cs[k] = fmaf(c, s, cs[k]);
                     if (k + 1 < K) {
@@ -182,11 +172,10 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
                     }
                 }
                 ++ns;
-                sy += o.x;
                 syy = fmaf(o.x, o.x, syy);
             }
         }
-        close_season();
+        close_group();
     }
 
     const float inv = n_good > 0 ? 1.0f / (float)n_good : 0.0f;
@@ -390,7 +379,7 @@ lsp_status lsp_features(const int64_t* offsets, int64_t n_obj, int64_t n_obs, co
         !(grid->unit == LSP_UNIT_CYCLES || grid->unit == LSP_UNIT_ANGULAR))
         return LSP_EINVAL;
     const lsp_feature_options fo = fopt_in ? *fopt_in : lsp_default_feature_options();
-    if (!(std::isfinite(fo.season_gap) && fo.season_gap >= 0.0) || fo.min_season_obs < 1)
+    if (!(std::isfinite(fo.season_gap) && fo.season_gap >= 0.0) || fo.min_season_obs < 2)
         return LSP_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return LSP_EINVAL;
     if (workspace_bytes < lsp_features_workspace_bytes(n_obj)) return LSP_ENOMEM;

@@ -62,6 +62,8 @@ def test_feature_argument_errors(L):
     assert call(fopt=bad) == lsp.EINVAL
     bad.season_gap, bad.min_season_obs = 60.0, 0
     assert call(fopt=bad) == lsp.EINVAL
+    bad.min_season_obs = 1          # a one-point group has no periodogram
+    assert call(fopt=bad) == lsp.EINVAL
     bad.season_gap = float("nan")
     bad.min_season_obs = 8
     assert call(fopt=bad) == lsp.EINVAL
