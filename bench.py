@@ -294,8 +294,8 @@ def bench_learned(args, torch, dev):
     labels = learned.peak_bands(ptr.peaks_raw, wtr.n_obj, geo.band_bins, geo.n_bands)
     net = learned.BandNet(dev, seed=7)
     t0 = time.perf_counter()
-    hist = learned.train_proposer(net, feats, labels, epochs=20, batch=1024, lr=2e-3,
-                                  lr_final=1e-4)
+    hist = learned.train_proposer(net, feats, labels, epochs=30, batch=512, lr=1e-3,
+                                  lr_final=3e-5, augment=0.9)
     log(f"[bench] trained in {time.perf_counter() - t0:.1f} s, loss {hist[0]:.3f} -> "
         f"{hist[-1]:.3f}")
     del feats, ptr, ttr
@@ -351,14 +351,15 @@ def bench_learned(args, torch, dev):
     # proposed bands?  Compared with the no-network heuristic that takes the
     # 8 bands with the largest pooled coarse value.
     lp.refine_only()
+    net8, _ = learned.top_bands(lp.logits, lp.top)
     torch.cuda.synchronize()
     band = ref32["index"] // geo.band_bins
-    prop = lp.idx.cpu().numpy()
-    hit_net = float(np.mean((prop == band[:, None]).any(axis=1)[ok]))
-    coarse = lp.feat.out[:, :lsp.FEAT_COARSE].cpu().numpy()
-    per_band = coarse.reshape(w.n_obj, geo.n_bands, -1).max(axis=2)
-    heur = np.argsort(-per_band, axis=1, kind="stable")[:, :lp.top]
-    hit_heur = float(np.mean((heur == band[:, None]).any(axis=1)[ok]))
+
+    def hit(idx):
+        return float(np.mean((idx.cpu().numpy() == band[:, None]).any(axis=1)[ok]))
+
+    hit_used, hit_net = hit(lp.idx), hit(net8)
+    hit_heur = hit(lp.idx_coarse) if lp.proposal == "hybrid" else None
     refine_only = lp.peaks()
     rec_refine = float(np.mean(np.abs(refine_only["index"][ok] - ref32["index"][ok]) <= 1))
     rec32 = float(np.mean(np.abs(pk["index"][ok] - ref32["index"][ok]) <= 1))
@@ -383,7 +384,9 @@ def bench_learned(args, torch, dev):
         "fallback_objects": lp.n_fallback, "refined_evals": refine_evals,
         "peak_bin_agreement": rec32, "peak_bin_agreement_vs_fp64": rec64,
         "peak_bin_agreement_refine_only": rec_refine,
-        "proposal_hit_rate": {"network_top8": hit_net, "coarse_argmax_heuristic_top8": hit_heur},
+        "proposal": lp.proposal, "top_network": lp.top_net,
+        "proposal_hit_rate": {"used": hit_used, "network_top8": hit_net,
+                              "coarse_power_top8": hit_heur},
         "thresholds": {"mass_min": mass_min, "power_min": power_min},
         "stages": stages, "train_loss": [hist[0], hist[-1]],
     }

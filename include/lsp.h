@@ -368,6 +368,27 @@ lsp_status lsp_adam(float *param, const float *grad, float *m, float *v, int64_t
 lsp_status lsp_top_k(const float *logits, int64_t n, int32_t c, int32_t k, int32_t *idx,
                      float *mass, void *stream);
 
+/* Band strength from the coarse spectrum: out[i][b] = max of row i's columns
+ * [start + b*group, start + (b+1)*group), b < n_bands (FP32 in, FP32 out
+ * [n x n_bands]).  With lsp_top_k it gives the bands whose coarse power peaks
+ * highest, proposals that need no training. */
+lsp_status lsp_band_max(const float *x, int64_t n, int32_t d, int32_t start, int32_t n_bands,
+                        int32_t group, float *out, void *stream);
+
+/* Per row, merge two band lists: the entries of a [n x ka] in order, then
+ * those of b [n x kb] not already taken, until k_out (<= 128) distinct
+ * non-negative bands are in out [n x k_out]; -1 fills the rest (a row with
+ * band -1 evaluates nothing in lsp_batch_rows). */
+lsp_status lsp_merge_bands(const int32_t *a, int32_t ka, const int32_t *b, int32_t kb, int64_t n,
+                           int32_t k_out, int32_t *out, void *stream);
+
+/* In place, for each row of x [n x d] (FP32): columns [start, start + count)
+ * become (x - row mean) / row standard deviation over those columns (0 for a
+ * constant row).  Applied to the coarse spectrum so that the network sees its
+ * shape rather than its level. */
+lsp_status lsp_row_normalize(float *x, int64_t n, int32_t d, int32_t start, int32_t count,
+                             void *stream);
+
 /* Pool the statistics of columns [start, start + count) (as produced by
  * lsp_col_stats) into one mean and 1/std for the whole block, so that columns
  * that are shifted copies of each other share one scale. */

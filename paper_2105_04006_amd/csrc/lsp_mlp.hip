@@ -273,6 +273,71 @@ __global__ __launch_bounds__(256) void pool_stats_kernel(float* mean, float* inv
     }
 }
 
+// Row standardisation of a column block: in each row of x [n x d], the
+// columns [start, start + count) become (x - row mean) / row std over those
+// columns (0 where the row is constant).  One wavefront per row, FP64 sums,
+// fixed order.  Makes the coarse spectrum's shape, not its overall level,
+// what the network sees: a short series has a much higher noise floor than a
+// long one, while the band that holds the peak is a property of the shape.
+__global__ __launch_bounds__(256) void row_norm_kernel(float* x, int64_t n, int32_t d,
+                                                       int32_t start, int32_t count) {
+    const int64_t row = linear_block() * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    float* r = x + row * d + start;
+    double s = 0.0, q = 0.0;
+    for (int32_t j = lane; j < count; j += 64) {
+        const double v = r[j];
+        s += v;
+        q += v * v;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        q += __shfl_xor(q, off, 64);
+    }
+    const double mu = s / (double)count;
+    const double var = q / (double)count - mu * mu;
+    const double inv = var > 1e-24 ? 1.0 / sqrt(var) : 0.0;
+    for (int32_t j = lane; j < count; j += 64) r[j] = (float)(((double)r[j] - mu) * inv);
+}
+
+// Largest value of each band's columns: row i's columns [start + b*group,
+// start + (b+1)*group) for b < n_bands.  One thread per (row, band).
+__global__ void band_max_kernel(const float* __restrict__ x, int64_t n, int32_t d, int32_t start,
+                                int32_t n_bands, int32_t group, float* __restrict__ out) {
+    const int64_t e = linear_block() * blockDim.x + threadIdx.x;
+    if (e >= n * n_bands) return;
+    const int64_t i = e / n_bands;
+    const int32_t b = (int32_t)(e - i * n_bands);
+    const float* r = x + i * d + start + (int64_t)b * group;
+    float m = r[0];
+    for (int32_t j = 1; j < group; ++j) m = fmaxf(m, r[j]);
+    out[e] = m;
+}
+
+// Per row: the entries of a (in order), then those of b not already taken,
+// until k_out distinct non-negative bands; -1 fills what is left.
+__global__ void merge_bands_kernel(const int32_t* __restrict__ a, int32_t ka,
+                                   const int32_t* __restrict__ b, int32_t kb, int64_t n,
+                                   int32_t k_out, int32_t* __restrict__ out) {
+    const int64_t i = linear_block() * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t* o = out + i * k_out;
+    int32_t m = 0;
+    for (int32_t src = 0; src < 2; ++src) {
+        const int32_t* v = src == 0 ? a + i * ka : b + i * kb;
+        const int32_t kv = src == 0 ? ka : kb;
+        for (int32_t j = 0; j < kv && m < k_out; ++j) {
+            const int32_t band = v[j];
+            if (band < 0) continue;
+            bool seen = false;
+            for (int32_t q = 0; q < m; ++q) seen |= o[q] == band;
+            if (!seen) o[m++] = band;
+        }
+    }
+    for (; m < k_out; ++m) o[m] = -1;
+}
+
 // Training-time shift augmentation.  Row i's first n_coarse columns hold
 // n_bands groups of `group` columns, one group per frequency band; they move
 // by shift[i] groups (vacated columns get `fill`), the other columns are
@@ -479,6 +544,38 @@ lsp_status lsp_top_k(const float* logits, int64_t n, int32_t c, int32_t k, int32
     if (n == 0) return LSP_OK;
     hipLaunchKernelGGL(lsp::top_k_kernel, lsp::grid_for((n + 3) / 4), dim3(256), 0,
                        static_cast<hipStream_t>(stream), logits, n, c, k, idx, mass);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_row_normalize(float* x, int64_t n, int32_t d, int32_t start, int32_t count,
+                             void* stream) {
+    if (n < 0 || d < 1 || start < 0 || count < 1 || (int64_t)start + count > d) return LSP_EINVAL;
+    if (n > 0 && !x) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::row_norm_kernel, lsp::grid_for((n + 3) / 4), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), x, n, d, start, count);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_band_max(const float* x, int64_t n, int32_t d, int32_t start, int32_t n_bands,
+                        int32_t group, float* out, void* stream) {
+    if (n < 0 || d < 1 || start < 0 || n_bands < 1 || group < 1 ||
+        (int64_t)start + (int64_t)n_bands * group > d)
+        return LSP_EINVAL;
+    if (n > 0 && (!x || !out)) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::band_max_kernel, lsp::grid_for((n * n_bands + 255) / 256), dim3(256),
+                       0, static_cast<hipStream_t>(stream), x, n, d, start, n_bands, group, out);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_merge_bands(const int32_t* a, int32_t ka, const int32_t* b, int32_t kb, int64_t n,
+                           int32_t k_out, int32_t* out, void* stream) {
+    if (n < 0 || ka < 0 || kb < 0 || k_out < 1 || k_out > 128) return LSP_EINVAL;
+    if (n > 0 && (!out || (ka > 0 && !a) || (kb > 0 && !b))) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::merge_bands_kernel, lsp::grid_for((n + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), a, ka, b, kb, n, k_out, out);
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
 

@@ -53,19 +53,61 @@ def bf16_to_f32(h):
     return (h.to(torch.int32) << 16).view(torch.float32)
 
 
+def he_init(seed, dims=DIMS):
+    """He-normal weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        params.append(rng.normal(0.0, np.sqrt(2.0 / a), size=(a, b)))
+        params.append(np.zeros(b))
+    return params
+
+
+def banded_init(seed, dims=DIMS, coarse=lsp.FEAT_COARSE, per_band=4,
+                thresholds=(-0.5, 0.5, 1.5, 3.0), noise=0.05):
+    """He initialisation with a band-detector path written into part of it.
+
+    The coarse features come in n_bands groups of coarse / n_bands columns,
+    one group per output band.  Hidden layer 1 gets `per_band` units per band
+    that average their group's standardised columns and subtract a threshold
+    (a piecewise-linear, increasing response to the band's strength), hidden
+    layer 2 one unit per band that adds them, and the output layer reads that
+    unit into the band's logit.  The initial network therefore ranks bands by
+    their coarse power; training adjusts every weight from there, including
+    the remaining randomly initialised units.
+    """
+    rng = np.random.default_rng(seed)
+    d0, d1, d2, d3 = dims
+    n_bands = d3
+    group = coarse // n_bands
+    W1, b1, W2, b2, W3, b3 = he_init(seed, dims)
+    k1 = n_bands * per_band
+    assert k1 <= d1 and n_bands <= d2 and len(thresholds) == per_band
+    W1[:, :k1] *= noise
+    W2[:k1, :] *= noise
+    W2[:, :n_bands] *= noise
+    W3 *= noise
+    for b in range(n_bands):
+        for s_, th in enumerate(thresholds):
+            u = b * per_band + s_
+            W1[b * group:(b + 1) * group, u] += 1.0 / group
+            b1[u] = -th
+            W2[u, b] += 1.0
+        W3[b, b] += 1.0
+    return [W1, b1, W2, b2, W3, b3]
+
+
 class BandNet:
     """1088 -> 512 -> 256 -> 64 ReLU network with FP32 master weights, BF16 copies
     for the GEMMs, and Adam state, all on one device."""
 
-    def __init__(self, device, seed=0, dims=DIMS, params=None):
+    def __init__(self, device, seed=0, dims=DIMS, params=None, init="banded", row_norm=True):
         self.dims = tuple(dims)
         self.device = device
+        self.row_norm = bool(row_norm)
         if params is None:
-            rng = np.random.default_rng(seed)
-            params = []
-            for a, b in zip(self.dims[:-1], self.dims[1:]):
-                params.append(rng.normal(0.0, np.sqrt(2.0 / a), size=(a, b)))
-                params.append(np.zeros(b))
+            params = (banded_init(seed, self.dims) if init == "banded"
+                      else he_init(seed, self.dims))
         self.master = [torch.as_tensor(np.asarray(p, np.float32), device=device).contiguous()
                        for p in params]
         self.w_bf16 = [to_bf16(self.master[2 * l]) for l in range(3)]
@@ -85,6 +127,16 @@ class BandNet:
         return b
 
     # ------------------------------------------------------- standardising
+    def normalize_rows(self, feats, stream=None):
+        """In place: standardise each row's coarse block (lsp_row_normalize),
+        if this network was built with row_norm.  Applied to every feature
+        matrix before the column standardiser, in training and inference."""
+        if self.row_norm:
+            n, d = feats.shape
+            _ok(lsp.lib().lsp_row_normalize(_p(feats), n, d, 0, lsp.FEAT_COARSE, _s(stream)),
+                "lsp_row_normalize")
+        return feats
+
     def fit_standardizer(self, feats, pool=lsp.FEAT_COARSE, stream=None):
         """Column means and scales from a training set; the first `pool`
         columns (the coarse spectrum, whose columns are shifted copies of each
@@ -207,8 +259,8 @@ class LearnedPeriodogram:
     """Peaks of a CSR batch from proposed bands (Section 3.4's batch peaks,
     computed on a fraction of the grid).
 
-    For each object: features -> standardise -> network -> the `top` most
-    probable bands -> the FP32 batch kernels on those bands only (row mode)
+    For each object: features -> standardise -> network -> the `top` bands to
+    refine (see propose) -> the FP32 batch kernels on those bands only (row mode)
     -> objects whose proposal is uncertain (softmax mass of the refined bands
     below mass_min) or whose refined peak is weak (power below power_min) are
     re-run on the whole grid.  Every step is a library kernel; the host only
@@ -216,8 +268,12 @@ class LearnedPeriodogram:
     """
 
     def __init__(self, net, geometry, offsets, t, y, f_min, f_max, unit=lsp.CYCLES, top=8,
-                 mass_min=0.0, power_min=0.0, k=0, waves=0):
+                 mass_min=0.0, power_min=0.0, k=0, waves=0, proposal="hybrid", top_net=4):
+        if proposal not in ("network", "coarse", "hybrid"):
+            raise ValueError("proposal must be 'network', 'coarse' or 'hybrid'")
         self.net, self.geo, self.top = net, geometry, int(top)
+        self.proposal = proposal
+        self.top_net = int(top) if proposal == "network" else int(top_net)
         self.offsets, self.t, self.y = offsets, t, y
         self.n_obj = int(offsets.numel()) - 1
         self.mass_min, self.power_min = float(mass_min), float(power_min)
@@ -226,6 +282,10 @@ class LearnedPeriodogram:
         self.x = torch.empty((self.n_obj, net.dims[0]), dtype=torch.int16, device=dev)
         self.logits = torch.empty((self.n_obj, net.dims[-1]), dtype=torch.float32, device=dev)
         self.idx = torch.empty((self.n_obj, self.top), dtype=torch.int32, device=dev)
+        self.idx_net = torch.empty((self.n_obj, self.top_net), dtype=torch.int32, device=dev)
+        self.idx_coarse = torch.empty((self.n_obj, self.top), dtype=torch.int32, device=dev)
+        self.band_score = torch.empty((self.n_obj, geometry.n_bands), dtype=torch.float32,
+                                      device=dev)
         self.mass = torch.empty(self.n_obj, dtype=torch.float32, device=dev)
         self.peaks_raw = torch.empty(self.n_obj * lsp.PEAK_BYTES, dtype=torch.uint8, device=dev)
         self.objects = torch.empty(self.n_obj, dtype=torch.int32, device=dev)
@@ -239,12 +299,33 @@ class LearnedPeriodogram:
         self.n_fallback = 0
 
     def propose(self, stream=None):
-        """Features, network and top bands; fills self.idx and self.mass."""
-        feats = self.feat(stream)
+        """Features, network and top bands; fills self.idx (the bands to
+        refine) and self.mass (the network's softmax mass on its own picks).
+
+        proposal="network": the network's `top` most probable bands.
+        proposal="coarse": the `top` bands whose pooled coarse power peaks
+        highest (no network).  proposal="hybrid": the network's `top_net`
+        bands, then coarse-power bands not already taken, up to `top`."""
+        L = lsp.lib()
+        n, nb = self.n_obj, self.geo.n_bands
+        feats = self.net.normalize_rows(self.feat(stream), stream=stream)
         self.net.standardize(feats, out=self.x, stream=stream)
         self.net.forward(self.x, logits=self.logits, stream=stream)
-        _ok(lsp.lib().lsp_top_k(_p(self.logits), self.n_obj, self.logits.shape[1], self.top,
-                                _p(self.idx), _p(self.mass), _s(stream)), "lsp_top_k")
+        first = self.idx if self.proposal == "network" else self.idx_net
+        _ok(L.lsp_top_k(_p(self.logits), n, nb, self.top_net, _p(first), _p(self.mass),
+                        _s(stream)), "lsp_top_k")
+        if self.proposal == "network":
+            return
+        # row normalisation is increasing within a row, so band maxima of the
+        # normalised coarse block rank bands as the raw power does
+        _ok(L.lsp_band_max(_p(feats), n, feats.shape[1], 0, nb, lsp.FEAT_COARSE // nb,
+                           _p(self.band_score), _s(stream)), "lsp_band_max")
+        target = self.idx if self.proposal == "coarse" else self.idx_coarse
+        _ok(L.lsp_top_k(_p(self.band_score), n, nb, self.top, _p(target), None, _s(stream)),
+            "lsp_top_k")
+        if self.proposal == "hybrid":
+            _ok(L.lsp_merge_bands(_p(self.idx_net), self.top_net, _p(self.idx_coarse), self.top,
+                                  n, self.top, _p(self.idx), _s(stream)), "lsp_merge_bands")
 
     def refine_only(self, stream=None):
         self.propose(stream)
@@ -288,10 +369,12 @@ def train_proposer(net, feats, labels, epochs=20, batch=1024, lr=1e-3, lr_final=
 
     With augment > 0, that fraction of each minibatch has its coarse spectrum
     moved so that its label becomes a band drawn uniformly (lsp_shift_bands;
-    the draws come from a seeded host generator).  Returns the mean loss of
+    the draws come from a seeded host generator).  `feats` is row-normalised
+    in place first when the network uses row normalisation.  Returns the mean loss of
     each epoch."""
     n = feats.shape[0]
     n_bands = net.dims[-1]
+    net.normalize_rows(feats, stream=stream)  # in place
     net.fit_standardizer(feats, stream=stream)
     x = net.standardize(feats, stream=stream)
     steps = max(1, (n // batch)) * epochs

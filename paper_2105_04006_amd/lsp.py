@@ -126,6 +126,12 @@ def lib():
         L.lsp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp, vp]
         L.lsp_top_k.restype = ctypes.c_int
         L.lsp_top_k.argtypes = [vp, i64, i32, i32, vp, vp, vp]
+        L.lsp_band_max.restype = ctypes.c_int
+        L.lsp_band_max.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp]
+        L.lsp_merge_bands.restype = ctypes.c_int
+        L.lsp_merge_bands.argtypes = [vp, i32, vp, i32, i64, i32, vp, vp]
+        L.lsp_row_normalize.restype = ctypes.c_int
+        L.lsp_row_normalize.argtypes = [vp, i64, i32, i32, i32, vp]
         L.lsp_pool_stats.restype = ctypes.c_int
         L.lsp_pool_stats.argtypes = [vp, vp, i32, i32, vp]
         L.lsp_shift_bands.restype = ctypes.c_int

@@ -47,8 +47,8 @@ def trained(dev):
     full = _full_peaks(w, tens)
     labels = learned.peak_bands(full.peaks_raw, w.n_obj, geo.band_bins, N_BANDS)
     net = learned.BandNet(dev, seed=7)
-    hist = learned.train_proposer(net, feats, labels, epochs=30, batch=512, lr=2e-3,
-                                  lr_final=1e-4, log=say)
+    hist = learned.train_proposer(net, feats, labels, epochs=30, batch=512, lr=1e-3,
+                                  lr_final=3e-5, augment=0.9, log=say)
     return geo, net, hist
 
 

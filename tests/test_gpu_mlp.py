@@ -178,3 +178,79 @@ def test_peak_bands_and_fallback_selection(dev):
         k = int(cnt.item())
         assert k == len(sel)
         assert np.array_equal(objs.cpu().numpy()[:k], sel)
+
+
+def test_row_normalize_pool_stats_and_shift(dev):
+    rng = np.random.default_rng(13)
+    n, d = 300, 1088
+    x = rng.gamma(2.0, 0.1, size=(n, d)).astype(np.float32)
+    x[7, :1024] = 0.25  # a constant coarse block
+    xt = torch.as_tensor(x, device=dev)
+    L = lsp.lib()
+    p = learned._p
+    assert L.lsp_row_normalize(p(xt), n, d, 0, 1024, None) == 0
+    torch.cuda.synchronize()
+    c = x[:, :1024].astype(np.float64)
+    sd = c.std(axis=1, keepdims=True)
+    want = np.where(sd > 0, (c - c.mean(axis=1, keepdims=True)) / np.where(sd > 0, sd, 1), 0.0)
+    got = xt.cpu().numpy()
+    assert np.max(np.abs(got[:, :1024] - want)) <= 1e-5
+    assert np.array_equal(got[:, 1024:], x[:, 1024:])
+    # pooled column statistics over the coarse block
+    mean = torch.empty(d, dtype=torch.float32, device=dev)
+    inv = torch.empty(d, dtype=torch.float32, device=dev)
+    assert L.lsp_col_stats(p(xt), n, d, p(mean), p(inv), None) == 0
+    assert L.lsp_pool_stats(p(mean), p(inv), 0, 1024, None) == 0
+    torch.cuda.synchronize()
+    blk = got[:, :1024].astype(np.float64)
+    assert np.allclose(mean.cpu().numpy()[:1024], blk.mean(), atol=1e-6)
+    assert np.allclose(inv.cpu().numpy()[:1024], 1.0 / blk.std(), rtol=1e-5)
+    assert np.allclose(inv.cpu().numpy()[1024:], 1.0 / got[:, 1024:].astype(np.float64).std(0),
+                       rtol=1e-5)
+    # shift augmentation on BF16 rows
+    xb = torch.as_tensor(rng.integers(-2000, 2000, size=(n, d)).astype(np.int16), device=dev)
+    lab = rng.integers(-1, 64, n).astype(np.int32)
+    sh = rng.integers(-70, 70, n).astype(np.int32)
+    out, out_lab = learned.shift_bands(xb, torch.as_tensor(lab, device=dev),
+                                       torch.as_tensor(sh, device=dev), 64)
+    torch.cuda.synchronize()
+    xh, oh = xb.cpu().numpy(), out.cpu().numpy()
+    for i in (0, 5, 77, 299):
+        for j in (0, 15, 16, 500, 1023, 1024, 1087):
+            src = j - 16 * sh[i]
+            if j < 1024:
+                want = xh[i, src] if 0 <= src < 1024 else 0
+            else:
+                want = xh[i, j]
+            assert oh[i, j] == want, (i, j)
+    nl = lab + sh
+    want_lab = np.where((lab >= 0) & (nl >= 0) & (nl < 64), nl, -1)
+    assert np.array_equal(out_lab.cpu().numpy(), want_lab)
+
+
+def test_band_max_and_merge(dev):
+    rng = np.random.default_rng(21)
+    n, d = 257, 1088
+    x = rng.normal(size=(n, d)).astype(np.float32)
+    xt = torch.as_tensor(x, device=dev)
+    out = torch.empty((n, 64), dtype=torch.float32, device=dev)
+    L = lsp.lib()
+    p = learned._p
+    assert L.lsp_band_max(p(xt), n, d, 0, 64, 16, p(out), None) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), x[:, :1024].reshape(n, 64, 16).max(axis=2))
+    a = rng.integers(-1, 64, size=(n, 4)).astype(np.int32)
+    b = rng.integers(0, 64, size=(n, 8)).astype(np.int32)
+    b[3] = a[3, 0]          # every entry of b already taken or repeated
+    m = torch.empty((n, 8), dtype=torch.int32, device=dev)
+    assert L.lsp_merge_bands(p(torch.as_tensor(a, device=dev)), 4,
+                             p(torch.as_tensor(b, device=dev)), 8, n, 8, p(m), None) == 0
+    torch.cuda.synchronize()
+    got = m.cpu().numpy()
+    for i in range(n):
+        want = []
+        for v in list(a[i]) + list(b[i]):
+            if v >= 0 and v not in want and len(want) < 8:
+                want.append(int(v))
+        want += [-1] * (8 - len(want))
+        assert list(got[i]) == want, i
