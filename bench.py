@@ -107,6 +107,9 @@ def main():
                     help="copy: time a plain device-to-device copy of --copy-bytes bytes "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--copy-bytes", type=float, default=256 * 2**20)
+    ap.add_argument("--learned", action="store_true",
+                    help="time the learned band-proposal path on --workload (always on for "
+                         "learned_100k)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the periodogram of "
@@ -136,7 +139,7 @@ def main():
 
     lsp.lib()  # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
-    if args.workload == "learned_100k":
+    if args.workload == "learned_100k" or args.learned:
         return bench_learned(args, torch, dev)
     w = synth.make_workload(args.workload)
     single = w.n_obj == 1
@@ -255,8 +258,9 @@ def main():
 
 
 def bench_learned(args, torch, dev):
-    """Learned band proposal on 1e5 objects (N_t 50..500, N_f 2e5 over [1, 12)
-    cycles/day, 64 bands of 3,125 bins, top 8 refined).
+    """Learned band proposal on a batch workload (learned_100k: 1e5 objects,
+    N_t 50..500, N_f 2e5 over [1, 12) cycles/day, 64 bands of 3,125 bins, top 8
+    refined; lsst_200k with --learned: 2e5 objects with harmonics and noise).
 
     Untimed set-up: train the proposal network on 40,000 independent objects
     (labels: whole-grid FP32 peaks), calibrate the fallback thresholds on
@@ -282,11 +286,12 @@ def bench_learned(args, torch, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
-    w = synth.make_workload("learned_100k")
+    name = args.workload
+    w = synth.make_workload(name)
     geo = learned.BandGeometry(w.n_f, 64)
     log(f"[bench] learned: n_obj={w.n_obj} n_obs={w.n_obs} n_f={w.n_f} "
         f"bands of {geo.band_bins}")
-    wtr = synth.make_workload("learned_100k", n_obj=40000, seed=synth.SEED_BASE + 1000)
+    wtr = synth.make_workload(name, n_obj=40000, seed=synth.SEED_BASE + 1000)
     ttr = tens(wtr)
     feats = lsp.Features(*ttr, wtr.f_min, wtr.f_max)()
     ptr = full(wtr, ttr)
@@ -299,7 +304,7 @@ def bench_learned(args, torch, dev):
     log(f"[bench] trained in {time.perf_counter() - t0:.1f} s, loss {hist[0]:.3f} -> "
         f"{hist[-1]:.3f}")
     del feats, ptr, ttr
-    wva = synth.make_workload("learned_100k", n_obj=20000, seed=synth.SEED_BASE + 1001)
+    wva = synth.make_workload(name, n_obj=20000, seed=synth.SEED_BASE + 1001)
     tva = tens(wva)
     lpv = learned.LearnedPeriodogram(net, geo, *tva, wva.f_min, wva.f_max)
     lpv.refine_only()
@@ -371,7 +376,8 @@ def bench_learned(args, torch, dev):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_l,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_obj": w.n_obj, "n_t": "U{50..500}",
+        "config": {"workload": w.name, "n_obj": w.n_obj,
+                   "n_t": "U{%d..%d}" % (int(np.diff(w.offsets).min()), int(np.diff(w.offsets).max())),
                    "n_obs": int(w.n_obs), "n_f": w.n_f, "f_range_cycles_per_day": [w.f_min, w.f_max],
                    "bands": geo.n_bands, "band_bins": geo.band_bins, "top": lp.top,
                    "network": "1088-512-256-64 BF16 MFMA", "output": "peaks"},

@@ -79,6 +79,14 @@ enum {
     LSP_REC_CHEBYSHEV = 2  /* x_{k+1} = 2C x_k - x_{k-1} for x = cos, sin: 2 ops/step */
 };
 
+/* How the waves of a workgroup share a frequency tile (FP32 form). */
+enum {
+    LSP_WSPLIT_AUTO = 0, /* the library's choice (currently off)                      */
+    LSP_WSPLIT_OFF = 1,  /* each wave owns 64 K of the tile's bins                   */
+    LSP_WSPLIT_ON = 2    /* all waves cover the same 64 K bins and split the
+                            observations; sums are added in LDS in wave order        */
+};
+
 /* Work scheduling of the batch path. */
 enum {
     LSP_SCHED_AUTO = 0,
@@ -116,7 +124,8 @@ typedef struct {
     int32_t t_split;       /* single object: split of the observation axis, 1..64       */
     int32_t schedule;      /* LSP_SCHED_*                                               */
     int32_t recurrence;    /* LSP_REC_* (FP32 form only)                                */
-    int32_t reserved[3];
+    int32_t wave_split;    /* LSP_WSPLIT_* (FP32 form only)                             */
+    int32_t reserved[2];
 } lsp_options;
 
 /* One object's peak (40 bytes). */

@@ -27,6 +27,7 @@ struct Config {
     int waves;
     int split;
     int persistent;
+    int ws;
     int64_t tile_freqs;
     int64_t tiles_per_row;
     int64_t n_items;
@@ -80,6 +81,7 @@ lsp_status valid_options(const lsp_options* o) {
     if (o->t_split < 0 || o->t_split > 64) return LSP_EINVAL;
     if (o->schedule < LSP_SCHED_AUTO || o->schedule > LSP_SCHED_PERSISTENT) return LSP_EINVAL;
     if (o->recurrence < LSP_REC_AUTO || o->recurrence > LSP_REC_CHEBYSHEV) return LSP_EINVAL;
+    if (o->wave_split < LSP_WSPLIT_AUTO || o->wave_split > LSP_WSPLIT_ON) return LSP_EINVAL;
     return LSP_OK;
 }
 
@@ -96,6 +98,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     c->rec = o->recurrence == LSP_REC_ROTATION ? LSP_REC_ROTATION : LSP_REC_CHEBYSHEV;
     c->persistent = 0;
     c->split = 1;
+    c->ws = 0;
     if (o->form == LSP_FORM_FP64) {
         c->k = o->k_per_lane ? o->k_per_lane : 2;
         c->waves = o->waves_per_wg ? o->waves_per_wg : 4;
@@ -136,13 +139,18 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
             while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 4) c->k = c->k > 8 ? 8 : 4;
         c->persistent = o->schedule == LSP_SCHED_PERSISTENT ||
                         (o->schedule == LSP_SCHED_AUTO && !one_row);
+        // Measured on one 4,096-point object: sharing the waves' bins and
+        // splitting observations inside the workgroup is within a few per
+        // cent of the default (the extra registers cost a wave per SIMD), so
+        // it is used only on request.
+        c->ws = c->waves > 1 && o->wave_split == LSP_WSPLIT_ON;
         if (o->t_split > 1) {
             if (n_obj != 1 || !whole) return LSP_EUNSUPPORTED;
             c->split = o->t_split;
         } else if (o->t_split == 0 && n_obj == 1 && whole) {
             // Too few frequency tiles to occupy 1024 SIMDs with a few waves
             // each: split the observation axis as well.
-            const int64_t tpw = (int64_t)kWave * c->k * c->waves;
+            const int64_t tpw = (int64_t)kWave * c->k * (c->ws ? 1 : c->waves);
             const int64_t waves_total = ((n_f + tpw - 1) / tpw) * c->waves;
             int64_t want = 4096 / (waves_total > 0 ? waves_total : 1);
             int64_t cap = n_obs / kTile;
@@ -151,7 +159,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
             c->split = want > 1 ? (int)want : 1;
         }
     }
-    c->tile_freqs = (int64_t)kWave * c->k * c->waves;
+    c->tile_freqs = (int64_t)kWave * c->k * (c->ws ? 1 : c->waves);
     c->tiles_per_row = (n_f + c->tile_freqs - 1) / c->tile_freqs;
     if (c->tiles_per_row * rows.rows_per_group > kMaxGrid / rows.n_rows / c->split)
         return LSP_EUNSUPPORTED;
@@ -271,7 +279,7 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     mp.part = c.split > 1 ? at<float>(ws, L.part) : nullptr;
     mp.queue = at<unsigned int>(ws, L.queue);
     mp.persistent = c.persistent;
-    mp.pad = 0;
+    mp.wave_split = c.ws;
 
     if (f32 && c.persistent && launch_fill_u32(mp.queue, kXcds, 0u, s) != hipSuccess)
         return LSP_EHIP;

@@ -279,7 +279,7 @@ struct MainParams {
     float* part;             // [n_split][4][n_f] when n_split > 1
     unsigned int* queue;     // persistent schedule: kXcds counters
     int32_t persistent;
-    int32_t pad;
+    int32_t wave_split;      // the waves of a workgroup split observations, not bins
 };
 
 struct CombineParams {

@@ -34,20 +34,28 @@
 namespace lsp {
 namespace {
 
-template <int K, int W, bool CHEB>
+// WS (wave split): the W waves of a workgroup share the same 64 K bins and
+// each takes every W-th staged observation; their sums are added in LDS, in
+// wave order, before the finish.  This multiplies the waves working on one
+// object without the per-split partial sums in HBM that the observation split
+// across workgroups needs.
+template <int K, int W, bool CHEB, bool WS>
 __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, double* s_tau,
-                                           float4* s_obs, PeakRec* s_red) {
+                                           float4* s_obs, PeakRec* s_red, float* s_part) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    const int64_t tile_freqs = (int64_t)kWave * K * W;
+    constexpr int WT = WS ? 1 : W;  // waves across the tile's frequencies
+    const int64_t tile_freqs = (int64_t)kWave * K * WT;
     const int64_t tile = item / P.n_split;
     const int split = (int)(item - tile * P.n_split);
     const int64_t row = tile / P.tiles_per_row;
     const int64_t ftile = tile - row * P.tiles_per_row;
     const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;
-    const int64_t i0 = rr.f_lo + ftile * tile_freqs + (int64_t)wave * kWave * K + lane;
+    const int64_t i0 =
+        rr.f_lo + ftile * tile_freqs + (WS ? 0 : (int64_t)wave * kWave * K) + lane;
     const int64_t f_hi = rr.f_hi;
+    const bool owner = !WS || wave == 0;  // the wave that finishes the tile's bins
     if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) {  // invalid row or empty tile
         if (threadIdx.x == 0 && P.n_split == 1) {
             P.rec[tile] = PeakRec{0.0, -1};
@@ -59,7 +67,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 
     if (m.status != LSP_OBJ_OK) {
         if (P.n_split == 1) {
-            if (P.pgram) {
+            if (P.pgram && owner) {
                 const double v = fill_value(m.status);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -99,7 +107,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
                                    __builtin_amdgcn_sinf(rs), 0.0f);
         }
         __syncthreads();
-        for (int q = 0; q < cnt; ++q) {
+        for (int q = WS ? wave : 0; q < cnt; q += WS ? W : 1) {
             const double tq = s_tau[q];
             const float4 o = s_obs[q];  // (y - ybar, cos step, sin step, -)
             double ph = fl * tq;
@@ -151,13 +159,35 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
         }
     }
 
+    if (WS) {
+        // add the other waves' sums into wave 0's, one array at a time
+        auto gather = [&](float(&v)[K]) {
+            __syncthreads();
+            if (wave > 0) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) s_part[((wave - 1) * K + k) * kWave + lane] = v[k];
+            }
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int w = 1; w < W; ++w)
+#pragma unroll
+                    for (int k = 0; k < K; ++k) v[k] += s_part[((w - 1) * K + k) * kWave + lane];
+            }
+        };
+        gather(xc);
+        gather(xs);
+        gather(cc);
+        gather(cs);
+    }
+
     if (P.n_split > 1) {
         const int64_t nf = P.n_f;
         float* base = P.part + (int64_t)split * 4 * nf;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int64_t i = i0 + (int64_t)kWave * k;
-            if (i < f_hi) {
+            if (owner && i < f_hi) {
                 base[i] = xc[k];
                 base[nf + i] = xs[k];
                 base[2 * nf + i] = cc[k];
@@ -174,7 +204,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t i = i0 + (int64_t)kWave * k;
-        if (i < f_hi) {
+        if (owner && i < f_hi) {
             bool ill;
             const double p = (double)power32(xc[k], xs[k], cc[k], cs[k], n, scale, ill);
             any_ill |= ill;
@@ -209,16 +239,18 @@ __device__ __forceinline__ int64_t pop_item(unsigned int* counter, int64_t lo, i
     return uniform_i64(*s_item);
 }
 
-template <int K, int W, bool CHEB>
+template <int K, int W, bool CHEB, bool WS>
 __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
     __shared__ float4 s_obs[kTile];
     __shared__ PeakRec s_red[W];
     __shared__ int64_t s_item;
+    __shared__ float s_part[WS ? (W - 1) * K * kWave : 1];
 
     if (!P.persistent) {
         const int64_t b = linear_block();
-        if (b < P.n_items) fp32p_item<K, W, CHEB>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red);
+        if (b < P.n_items)
+            fp32p_item<K, W, CHEB, WS>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red, s_part);
         return;
     }
     const int64_t per = (P.n_items + kXcds - 1) / kXcds;
@@ -229,7 +261,7 @@ __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
         const int64_t hi = lo + per < P.n_items ? lo + per : P.n_items;
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
-            fp32p_item<K, W, CHEB>(P, item, s_tau, s_obs, s_red);
+            fp32p_item<K, W, CHEB, WS>(P, item, s_tau, s_obs, s_red, s_part);
             item = pop_item(&P.queue[x], lo, &s_item);
         }
     }
@@ -278,11 +310,11 @@ __global__ __launch_bounds__(kCombineThreads) void combine_kernel(const CombineP
     }
 }
 
-template <int K, int W, bool CHEB>
+template <int K, int W, bool CHEB, bool WS>
 int occupancy_blocks() {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fp32p_kernel<K, W, CHEB>, kWave * W,
-                                                     0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fp32p_kernel<K, W, CHEB, WS>,
+                                                     kWave * W, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int dev = 0, cus = 0;
@@ -293,20 +325,21 @@ int occupancy_blocks() {
     return per_cu * cus;
 }
 
-template <int K, int W, bool CHEB>
+template <int K, int W, bool CHEB, bool WS>
 hipError_t launch_kwc(const MainParams& p, hipStream_t s) {
-    const dim3 grid = p.persistent ? dim3((unsigned)occupancy_blocks<K, W, CHEB>())
+    const dim3 grid = p.persistent ? dim3((unsigned)occupancy_blocks<K, W, CHEB, WS>())
                                    : grid_for(p.n_items);
-    hipLaunchKernelGGL((fp32p_kernel<K, W, CHEB>), grid, dim3(kWave * W), 0, s, p);
+    hipLaunchKernelGGL((fp32p_kernel<K, W, CHEB, WS>), grid, dim3(kWave * W), 0, s, p);
     return hipGetLastError();
 }
 
 template <int K, bool CHEB>
 hipError_t launch_kc(const MainParams& p, int waves, hipStream_t s) {
+    const bool ws = p.wave_split != 0;
     switch (waves) {
-        case 1: return launch_kwc<K, 1, CHEB>(p, s);
-        case 2: return launch_kwc<K, 2, CHEB>(p, s);
-        case 4: return launch_kwc<K, 4, CHEB>(p, s);
+        case 1: return launch_kwc<K, 1, CHEB, false>(p, s);
+        case 2: return ws ? launch_kwc<K, 2, CHEB, true>(p, s) : launch_kwc<K, 2, CHEB, false>(p, s);
+        case 4: return ws ? launch_kwc<K, 4, CHEB, true>(p, s) : launch_kwc<K, 4, CHEB, false>(p, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -45,17 +45,19 @@ bool cache_lookup(const char* path, const std::string& key, lsp_options* o) {
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[256];
-        int kk, w, rec, sched, split;
+        int kk, w, rec, sched, split, wsp;
         if (sscanf(line,
                    "{\"key\": \"%255[^\"]\", \"k_per_lane\": %d, \"waves_per_wg\": %d, "
-                   "\"recurrence\": %d, \"schedule\": %d, \"t_split\": %d",
-                   k, &kk, &w, &rec, &sched, &split) == 6 &&
+                   "\"recurrence\": %d, \"schedule\": %d, \"t_split\": %d, "
+                   "\"wave_split\": %d",
+                   k, &kk, &w, &rec, &sched, &split, &wsp) == 7 &&
             key == k) {
             o->k_per_lane = kk;
             o->waves_per_wg = w;
             o->recurrence = rec;
             o->schedule = sched;
             o->t_split = split;
+            o->wave_split = wsp;
             found = true;  // the last entry for a key wins
         }
     }
@@ -70,8 +72,9 @@ void cache_store(const char* path, const std::string& key, const lsp_options& o,
     if (!f) return;
     fprintf(f,
             "{\"key\": \"%s\", \"k_per_lane\": %d, \"waves_per_wg\": %d, \"recurrence\": %d, "
-            "\"schedule\": %d, \"t_split\": %d, \"ms\": %.6f}\n",
-            key.c_str(), o.k_per_lane, o.waves_per_wg, o.recurrence, o.schedule, o.t_split, ms);
+            "\"schedule\": %d, \"t_split\": %d, \"wave_split\": %d, \"ms\": %.6f}\n",
+            key.c_str(), o.k_per_lane, o.waves_per_wg, o.recurrence, o.schedule, o.t_split,
+            o.wave_split, ms);
     fclose(f);
 }
 
@@ -79,7 +82,10 @@ std::vector<lsp_options> candidates(const lsp_options& base, bool single) {
     std::vector<lsp_options> out;
     const int ks[] = {8, 10, 12, 16, 32};
     const int ws[] = {1, 2, 4};
-    const int recs[] = {LSP_REC_ROTATION, LSP_REC_CHEBYSHEV};
+    // One object: the recurrence is fixed to the three-term form (as accurate
+    // and cheaper) and the search covers how the object is split instead.
+    std::vector<int> recs = single ? std::vector<int>{LSP_REC_CHEBYSHEV}
+                                   : std::vector<int>{LSP_REC_ROTATION, LSP_REC_CHEBYSHEV};
     std::vector<int> scheds = single ? std::vector<int>{LSP_SCHED_GRID}
                                      : std::vector<int>{LSP_SCHED_GRID, LSP_SCHED_PERSISTENT};
     std::vector<int> splits = single ? std::vector<int>{0, 1, 2, 4, 8, 16} : std::vector<int>{1};
@@ -87,16 +93,18 @@ std::vector<lsp_options> candidates(const lsp_options& base, bool single) {
         for (int w : ws)
             for (int r : recs)
                 for (int sc : scheds)
-                    for (int sp : splits) {
-                        lsp_options o = base;
-                        o.form = LSP_FORM_FP32P;
-                        o.k_per_lane = k;
-                        o.waves_per_wg = w;
-                        o.recurrence = r;
-                        o.schedule = sc;
-                        o.t_split = sp;
-                        out.push_back(o);
-                    }
+                    for (int sp : splits)
+                        for (int wsp = 0; wsp < (single && w > 1 ? 2 : 1); ++wsp) {
+                            lsp_options o = base;
+                            o.form = LSP_FORM_FP32P;
+                            o.k_per_lane = k;
+                            o.waves_per_wg = w;
+                            o.recurrence = r;
+                            o.schedule = sc;
+                            o.t_split = sp;
+                            o.wave_split = wsp ? LSP_WSPLIT_ON : LSP_WSPLIT_OFF;
+                            out.push_back(o);
+                        }
     return out;
 }
 

@@ -26,6 +26,7 @@ CYCLES, ANGULAR = 0, 1
 PGRAM_F32, PGRAM_F64 = 0, 1
 SCHED_AUTO, SCHED_GRID, SCHED_PERSISTENT = 0, 1, 2
 REC_AUTO, REC_ROTATION, REC_CHEBYSHEV = 0, 1, 2
+WSPLIT_AUTO, WSPLIT_OFF, WSPLIT_ON = 0, 1, 2
 
 PEAK_DTYPE = np.dtype(
     [("index", "<i8"), ("freq", "<f8"), ("period", "<f8"), ("power", "<f8"),
@@ -44,7 +45,8 @@ class Options(ctypes.Structure):
                 ("subtract_mean", ctypes.c_int32), ("pgram_dtype", ctypes.c_int32),
                 ("k_per_lane", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
                 ("t_split", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("recurrence", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("recurrence", ctypes.c_int32), ("wave_split", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class FeatureOptions(ctypes.Structure):
@@ -183,7 +185,8 @@ def make_grid(f_min, f_max, n_f, unit=CYCLES):
 
 
 def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype=PGRAM_F32, k=0,
-                 waves=0, t_split=0, schedule=SCHED_AUTO, recurrence=REC_AUTO):
+                 waves=0, t_split=0, schedule=SCHED_AUTO, recurrence=REC_AUTO,
+                 wave_split=WSPLIT_AUTO):
     o = Options()
     o.form, o.normalize, o.subtract_mean, o.pgram_dtype = (int(form), int(bool(normalize)),
                                                            int(bool(subtract_mean)),
@@ -191,6 +194,7 @@ def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype
     o.k_per_lane, o.waves_per_wg, o.t_split, o.schedule = int(k), int(waves), int(t_split), int(
         schedule)
     o.recurrence = int(recurrence)
+    o.wave_split = int(wave_split)
     return o
 
 
@@ -226,7 +230,7 @@ class Periodogram:
     def __init__(self, t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, form=FORM_FP64,
                  normalize=True, subtract_mean=True, pgram=True, pgram_dtype=PGRAM_F32,
                  peaks=True, k=0, waves=0, t_split=0, schedule=SCHED_AUTO,
-                 recurrence=REC_AUTO):
+                 recurrence=REC_AUTO, wave_split=WSPLIT_AUTO):
         _check(t, torch.float64, "t")
         _check(y, torch.float64, "y")
         if t.numel() != y.numel():
@@ -238,7 +242,7 @@ class Periodogram:
         self.n_obj = 1 if offsets is None else int(offsets.numel()) - 1
         self.grid = make_grid(f_min, f_max, n_f, unit)
         self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, t_split,
-                                schedule, recurrence)
+                                schedule, recurrence, wave_split)
         dev = t.device
         nb = workspace_bytes(self.n_obj, self.n_obs, self.grid, self.opt)
         if nb == 0:
@@ -423,7 +427,7 @@ class Features:
 def autotune(t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, normalize=True,
              subtract_mean=True, cache_path=None, repeats=3, stream=None):
     """Run lsp_autotune on device data; returns the tuned keyword options
-    (k, waves, recurrence, schedule, t_split) for Periodogram(form=FORM_FP32P)."""
+    (k, waves, recurrence, schedule, t_split, wave_split) for Periodogram(form=FORM_FP32P)."""
     _check(t, torch.float64, "t")
     _check(y, torch.float64, "y")
     if offsets is not None:
@@ -446,7 +450,7 @@ def autotune(t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, normalize=True,
     if st != OK:
         raise LspError(st, "lsp_autotune")
     return dict(k=tuned.k_per_lane, waves=tuned.waves_per_wg, recurrence=tuned.recurrence,
-                schedule=tuned.schedule, t_split=tuned.t_split)
+                schedule=tuned.schedule, t_split=tuned.t_split, wave_split=tuned.wave_split)
 
 
 def single(t, y, f_min, f_max, n_f, **kw):

@@ -299,13 +299,17 @@ def test_peaks_only_and_determinism(dev, form):
 
 
 def test_batch_row_equals_single(dev):
+    # Same launch shape on both sides (frequencies per lane, no splitting of
+    # the observations): a batch row is then bit-identical to the single call.
     w = synth.make_workload("batch_10k", n_obj=5)
-    for form in (lsp.FORM_FP64, lsp.FORM_FP32P):
-        pgb, pkb = run_batch(dev, w.offsets, w.t, w.y, w.f_min, w.f_max, 4000, form=form,
-                             t_split=1)
+    for form, k in ((lsp.FORM_FP64, 2), (lsp.FORM_FP32P, 16)):
+        kw = dict(form=form, t_split=1, k=k)
+        if form == lsp.FORM_FP32P:
+            kw["wave_split"] = lsp.WSPLIT_OFF
+        pgb, pkb = run_batch(dev, w.offsets, w.t, w.y, w.f_min, w.f_max, 4000, **kw)
         for o in range(w.n_obj):
             t, y = w.obj(o)
-            pgs, pks = run_single(dev, t, y, w.f_min, w.f_max, 4000, form=form, t_split=1)
+            pgs, pks = run_single(dev, t, y, w.f_min, w.f_max, 4000, **kw)
             assert np.array_equal(pgs, pgb[o])
             assert pks["index"] == pkb["index"][o]
 
