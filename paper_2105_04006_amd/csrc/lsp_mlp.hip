@@ -212,13 +212,27 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const lsp_peak* __r
     if (threadIdx.x == 0) *count = (int32_t)done;
 }
 
-// Column sums of an n x c FP32 matrix, one thread per column, fixed order.
-__global__ void col_sums_kernel(const float* __restrict__ x, int64_t n, int32_t c, float* out) {
-    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= c) return;
+// Column sums of an n x c FP32 matrix.  A workgroup covers 64 columns with 16
+// row phases (row i goes to phase i mod 16); each thread sums its phase in row
+// order and the 16 phase sums are added in phase order, so the result does not
+// depend on scheduling.
+constexpr int kSumCols = 64, kSumPhases = 16;
+
+__global__ __launch_bounds__(kSumCols* kSumPhases) void col_sums_kernel(
+    const float* __restrict__ x, int64_t n, int32_t c, float* out) {
+    __shared__ float s_part[kSumPhases][kSumCols];
+    const int tx = threadIdx.x % kSumCols, ph = threadIdx.x / kSumCols;
+    const int32_t j = blockIdx.x * kSumCols + tx;
     float s = 0.f;
-    for (int64_t i = 0; i < n; ++i) s += x[i * c + j];
-    out[j] = s;
+    if (j < c)
+        for (int64_t i = ph; i < n; i += kSumPhases) s += x[i * c + j];
+    s_part[ph][tx] = s;
+    __syncthreads();
+    if (ph == 0 && j < c) {
+        float t = s_part[0][tx];
+        for (int q = 1; q < kSumPhases; ++q) t += s_part[q][tx];
+        out[j] = t;
+    }
 }
 
 // Column mean and 1/std (population) of an n x d FP32 matrix; a column with no
@@ -494,8 +508,9 @@ lsp_status lsp_softmax_xent(const float* logits, const int32_t* labels, int64_t 
 
 lsp_status lsp_col_sums(const float* x, int64_t n, int32_t c, float* out, void* stream) {
     if (n < 0 || c < 1 || !out || (n > 0 && !x)) return LSP_EINVAL;
-    hipLaunchKernelGGL(lsp::col_sums_kernel, dim3((c + 255) / 256), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), x, n, c, out);
+    hipLaunchKernelGGL(lsp::col_sums_kernel, dim3((c + lsp::kSumCols - 1) / lsp::kSumCols),
+                       dim3(lsp::kSumCols * lsp::kSumPhases), 0, static_cast<hipStream_t>(stream),
+                       x, n, c, out);
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
 

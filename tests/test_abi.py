@@ -7,6 +7,20 @@ import pytest
 from paper_2105_04006_amd import lsp
 
 
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+# Several tests pass a fake device address that every call must reject during
+# host-side validation; a mistake in such a test would launch a kernel on it.
+# They run only where no GPU is visible.
+cpu_only = pytest.mark.skipif(_gpu_visible(), reason="fake device pointers: CPU-only check")
+
+
 @pytest.fixture(scope="module")
 def L():
     return lsp.lib()
@@ -38,6 +52,7 @@ def test_feature_constants_match_header():
         lsp.FEAT_COARSE, lsp.FEAT_POOL, lsp.FEAT_WINDOW)
 
 
+@cpu_only
 def test_feature_argument_errors(L):
     g = lsp.make_grid(1.0, 12.0, 1)
     fo = L.lsp_default_feature_options()
@@ -104,6 +119,7 @@ def _single(L, t=FAKE, y=FAKE, n=16, grid=None, opt=None, pgram=FAKE, peak=FAKE,
                         None)
 
 
+@cpu_only
 def test_argument_errors_are_reported_before_any_launch(L):
     assert _single(L, t=None) == lsp.EINVAL
     assert _single(L, ws=None) == lsp.EINVAL
@@ -137,6 +153,7 @@ def test_argument_errors_are_reported_before_any_launch(L):
                        1 << 30, None) == lsp.EINVAL
 
 
+@cpu_only
 def test_plan_and_autotune_argument_errors(L):
     g = lsp.make_grid(1.0, 2.0, 100)
     o = lsp.make_options()
@@ -158,6 +175,7 @@ def test_plan_and_autotune_argument_errors(L):
     assert lsp.lib().lsp_autotune_workspace_bytes(3, 30, ctypes.byref(g), ctypes.byref(o)) > 0
 
 
+@cpu_only
 def test_rows_argument_errors(L):
     g = lsp.make_grid(1.0, 2.0, 100)
     o = lsp.make_options(form=lsp.FORM_FP32P)
@@ -194,3 +212,31 @@ def test_binding_refuses_cpu_tensors():
     t = torch.zeros(8, dtype=torch.float64)
     with pytest.raises(TypeError):
         lsp.Periodogram(t, t, 1.0, 2.0, 10)
+
+
+@cpu_only
+def test_network_helper_argument_errors(L):
+    f32 = ctypes.c_float
+    assert L.lsp_band_max(FAKE, 4, 1088, 0, 64, 18, FAKE, None) == lsp.EINVAL   # past d
+    assert L.lsp_band_max(None, 4, 1088, 0, 64, 16, FAKE, None) == lsp.EINVAL
+    assert L.lsp_band_max(FAKE, 0, 1088, 0, 64, 16, None, None) == lsp.OK       # nothing to do
+    assert L.lsp_merge_bands(FAKE, 4, FAKE, 8, 10, 0, FAKE, None) == lsp.EINVAL
+    assert L.lsp_merge_bands(FAKE, 4, FAKE, 8, 10, 129, FAKE, None) == lsp.EINVAL
+    assert L.lsp_merge_bands(None, 4, FAKE, 8, 10, 8, FAKE, None) == lsp.EINVAL
+    assert L.lsp_row_normalize(FAKE, 4, 1088, 100, 1000, None) == lsp.EINVAL    # past d
+    assert L.lsp_row_normalize(FAKE, 4, 1088, 0, 0, None) == lsp.EINVAL
+    assert L.lsp_pool_stats(None, FAKE, 0, 16, None) == lsp.EINVAL
+    assert L.lsp_pool_stats(FAKE, FAKE, 0, 0, None) == lsp.EINVAL
+    # group * n_bands must equal n_coarse
+    assert L.lsp_shift_bands(FAKE, FAKE, FAKE, 8, 1088, 1024, 15, 64, f32(0), FAKE, FAKE,
+                             None) == lsp.EINVAL
+    assert L.lsp_shift_bands(FAKE, FAKE, FAKE, 8, 1000, 1024, 16, 64, f32(0), FAKE, FAKE,
+                             None) == lsp.EINVAL
+    assert L.lsp_peak_bands(FAKE, 8, 0, 64, FAKE, None) == lsp.EINVAL
+    assert L.lsp_select_fallback(FAKE, None, 8, f32(0), f32(0), FAKE, None, None) == lsp.EINVAL
+    assert L.lsp_select_fallback(FAKE, None, 1 << 40, f32(0), f32(0), FAKE, FAKE,
+                                 None) == lsp.EINVAL
+    assert L.lsp_top_k(FAKE, 8, 129, 8, FAKE, None, None) == lsp.EINVAL
+    assert L.lsp_top_k(FAKE, 8, 64, 65, FAKE, None, None) == lsp.EINVAL
+    assert L.lsp_gemm_bf16(-1, 4, 4, FAKE, 4, 1, FAKE, 4, 1, None, None, 0, FAKE, None, 4,
+                           None) == lsp.EINVAL
