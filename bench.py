@@ -107,6 +107,9 @@ def main():
                     help="copy: time a plain device-to-device copy of --copy-bytes bytes "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--copy-bytes", type=float, default=256 * 2**20)
+    ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
+                    help="graph: each timed FP32 step replays the call captured once as a HIP "
+                         "graph (lsp_plan_*)")
     ap.add_argument("--learned", action="store_true",
                     help="time the learned band-proposal path on --workload (always on for "
                          "learned_100k)")
@@ -168,13 +171,14 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
+    step32 = p32.capture() if args.launch == "graph" else p32
     for _ in range(args.warmup):
-        p32()
+        step32()
     p64()
     torch.cuda.synchronize()
     log("[bench] warm-up done")
-    ms32 = timed(p32, args.steps)
-    log(f"[bench] fp32p {ms32:.4f} ms/step")
+    ms32 = timed(step32, args.steps)
+    log(f"[bench] fp32p {ms32:.4f} ms/step ({args.launch})")
     steps64 = args.fp64_steps if args.fp64_steps > 0 else max(3, args.steps // 8)
     ms64 = timed(p64, steps64)
     log(f"[bench] fp64 {ms64:.4f} ms/step ({steps64} steps)")
@@ -225,8 +229,10 @@ def main():
                    "U{%d..%d}" % (int(w.n_t.min()), int(w.n_t.max())), "n_obs": int(w.n_obs),
                    "n_f": w.n_f, "f_range_cycles_per_day": [w.f_min, w.f_max],
                    "form": "fp32 sums, fp64 phase reduction", "output": "pgram f32 + peak"
-                   if single else "peaks"},
+                   if single else "peaks", "launch": args.launch},
         "objects_per_s": w.n_obj / (ms32 * 1e-3),
+        "pgram_bytes_per_step": (4 * w.n_f * w.n_obj) if single else 0,
+        "pgram_write_GBps": (4 * w.n_f * w.n_obj / (ms32 * 1e-3) / 1e9) if single else 0.0,
         "fp64_reference": {"evals_per_s": evals / (ms64 * 1e-3), "ms_per_step": ms64,
                            "objects_per_s": w.n_obj / (ms64 * 1e-3)},
         "speedup_vs_fp64": ms64 / ms32,

@@ -1,11 +1,14 @@
 """Learned band proposal: the network, its training step and its inference.
 
 The network takes a per-object feature vector (a 1,024-bin coarse periodogram
-and 64 sampling-window features, standardised) and proposes which of 64
-equal-width frequency bands hold the periodogram's peak.  Every arithmetic step
-runs in the library's kernels (BF16 matrix-core GEMMs with FP32 accumulation,
-softmax cross-entropy, Adam); this module owns the device buffers and calls
-the kernels in order.
+and 64 sampling-window features, scaled) and proposes which of 64 equal-width
+frequency bands hold the periodogram's peak.  The bands refined per object
+are the network's most probable ones followed by the bands whose coarse power
+peaks highest; objects whose proposal or refined peak is weak are re-run on
+the whole grid.  Every arithmetic step runs in the library's kernels (BF16
+matrix-core GEMMs with FP32 accumulation, softmax cross-entropy, Adam, the
+feature, selection and periodogram kernels); this module owns the device
+buffers and calls the kernels in order.
 """
 from __future__ import annotations
 
@@ -158,7 +161,7 @@ class BandNet:
         return out
 
     # ------------------------------------------------------------ forward
-    def forward(self, x_bf16, logits=None, stream=None, keep=False):
+    def forward(self, x_bf16, logits=None, stream=None):
         """x_bf16: [n, 1088] int16 (BF16 bits).  Returns FP32 logits [n, 64]."""
         n = x_bf16.shape[0]
         d0, d1, d2, d3 = self.dims
