@@ -286,7 +286,8 @@ lsp_status lsp_autotune(const int64_t *offsets, int64_t n_obj, int64_t n_obs, co
  *                bins are max-pooled in runs of 8 and averaged over the groups
  *                (0 if none).  FP32 arithmetic as in LSP_FORM_FP32P, no FP64 fix-up;
  *                each value is clamped to [0, 1].
- *   [1024, 1088) sampling and magnitude statistics in FP64: log10 N_t,
+ *   [1024, 1088) sampling and magnitude statistics (FP64; the spectral window
+ *                below takes FP64-reduced phases into FP32 sin/cos): log10 N_t,
  *                log10 max(span, 1e-3), number of seasons, number with >=
  *                min_season_obs points, log10 max(mean within-season spacing,
  *                1e-6), standard deviation of log10 max(spacing, 1e-6), fraction

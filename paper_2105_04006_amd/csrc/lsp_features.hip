@@ -18,8 +18,8 @@
 //     reduction, hardware sin/cos per observation, three-term recurrence
 //     across a lane's frequencies, four sums).
 //   window_kernel : one wavefront per object computes sampling and magnitude
-//     statistics and the spectral window at 53 probe frequencies in FP64
-//     -> features [1024, 1088).
+//     statistics in FP64 and the spectral window at 53 probe frequencies
+//     (FP64 phases, hardware FP32 sin/cos, FP64 sums) -> features [1024, 1088).
 //
 // Objects whose status is not OK get an all-zero row.
 #include <math.h>
@@ -307,7 +307,9 @@ __global__ __launch_bounds__(kWave) void window_kernel(const FeatParams P) {
 
     // Pass 3: spectral window |sum_j exp(2 pi i f_p t_j)|^2 / N^2, phases
     // taken from the object's mid-span origin (the modulus does not depend on
-    // it), reduced to [-1/2, 1/2] cycles in FP64.
+    // it) and reduced to [-1/2, 1/2] cycles in FP64, then the hardware FP32
+    // sin/cos (argument in revolutions) as in the periodogram kernels, summed
+    // in FP64.
     const double lstep = (log10(30.0) + 3.0) / (double)(kProbes - 1);
     for (int p = 0; p < kProbes; ++p) {
         const double f = pow(10.0, -3.0 + (double)p * lstep);
@@ -315,10 +317,9 @@ __global__ __launch_bounds__(kWave) void window_kernel(const FeatParams P) {
         for (int64_t j = j0 + lane; j < j1; j += kWave) {
             double ph = f * (P.t[j] - m.t0);
             ph -= rint(ph);
-            double sn, cn;
-            sincospi(2.0 * ph, &sn, &cn);
-            sc += cn;
-            ss += sn;
+            const float r = (float)ph;
+            sc += (double)__builtin_amdgcn_cosf(r);
+            ss += (double)__builtin_amdgcn_sinf(r);
         }
         sc = wave_sum(sc);
         ss = wave_sum(ss);

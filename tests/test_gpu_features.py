@@ -7,8 +7,8 @@ Tolerances
                          have many near-degenerate bins (N - |sum exp(2iwt)|
                          small) where FP32 sums lose digits and the features
                          have no FP64 fix-up: |d| <= 1e-2 there.
-  window part [1024, 1088): FP64 arithmetic stored as FP32,
-                         |d| <= 1e-6 * max(1, |ref|)
+  window part [1024, 1088): FP64 statistics and FP32 sin/cos of FP64-reduced
+                         phases, stored as FP32: |d| <= 1e-6 * max(1, |ref|)
 """
 import numpy as np
 import pytest

@@ -31,6 +31,11 @@ def _data(dev, n_obj, seed):
     return w, (cuda(w.offsets, dev, torch.int64), cuda(w.t, dev), cuda(w.y, dev))
 
 
+def _data_named(dev, name, n_obj, seed):
+    w = synth.make_workload(name, n_obj=n_obj, seed=seed)
+    return w, (cuda(w.offsets, dev, torch.int64), cuda(w.t, dev), cuda(w.y, dev))
+
+
 def _full_peaks(w, tensors):
     off, t, y = tensors
     p = lsp.Periodogram(t, y, w.f_min, w.f_max, N_F, offsets=off, form=lsp.FORM_FP32P,
@@ -120,3 +125,57 @@ def test_calibrated_recovery(dev, trained):
     assert refine_rate >= 0.99
     assert rate >= 0.999
     assert frac <= 0.2
+
+
+def test_lsst_full_size_learned_path(dev):
+    """The learned path at the full lsst_200k size (2e5 objects, two-harmonic
+    and pure-noise objects included, N_f = 250,000), in the bench's launch
+    configuration: peaks match the whole-grid FP32 batch on >= 99.9% of
+    objects, and sampled objects match the FP64 oracle's whole-grid peak."""
+    name = "lsst_200k"
+    w = synth.make_workload(name)
+    geo = learned.BandGeometry(w.n_f, N_BANDS)
+    say(f"{name}: {w.n_obj} objects, {w.n_obs} observations, bands of {geo.band_bins}")
+    wtr, ttr = _data_named(dev, name, 40000, synth.SEED_BASE + 1000)
+    feats = lsp.Features(*ttr, wtr.f_min, wtr.f_max)()
+    ptr = lsp.Periodogram(ttr[1], ttr[2], wtr.f_min, wtr.f_max, w.n_f, offsets=ttr[0],
+                          form=lsp.FORM_FP32P, pgram=False)
+    ptr()
+    labels = learned.peak_bands(ptr.peaks_raw, wtr.n_obj, geo.band_bins, N_BANDS)
+    net = learned.BandNet(dev, seed=7)
+    learned.train_proposer(net, feats, labels, epochs=30, batch=512, lr=1e-3, lr_final=3e-5,
+                           augment=0.9)
+    del feats, ptr, ttr
+    wva, tva = _data_named(dev, name, 20000, synth.SEED_BASE + 1001)
+    lpv = learned.LearnedPeriodogram(net, geo, *tva, wva.f_min, wva.f_max)
+    lpv.refine_only()
+    pva = lsp.Periodogram(tva[1], tva[2], wva.f_min, wva.f_max, w.n_f, offsets=tva[0],
+                          form=lsp.FORM_FP32P, pgram=False)
+    pva()
+    mass_min, power_min, _ = learned.calibrate(lpv.peaks(), pva.peaks(), lpv.mass.cpu().numpy())
+    del lpv, pva, tva
+    tt = (cuda(w.offsets, dev, torch.int64), cuda(w.t, dev), cuda(w.y, dev))
+    lp = learned.LearnedPeriodogram(net, geo, *tt, w.f_min, w.f_max, mass_min=mass_min,
+                                    power_min=power_min)
+    lp()
+    got = lp.peaks()
+    full = lsp.Periodogram(tt[1], tt[2], w.f_min, w.f_max, w.n_f, offsets=tt[0],
+                           form=lsp.FORM_FP32P, pgram=False)
+    full()
+    ref = full.peaks()
+    ok = ref["status"] == 0
+    assert np.array_equal(got["status"], ref["status"])
+    rate = float(np.mean(np.abs(got["index"][ok] - ref["index"][ok]) <= 1))
+    say(f"  recovery {rate:.5f} with {lp.n_fallback} fallbacks")
+    assert rate >= 0.999
+    # sampled objects against the oracle's whole-grid periodogram
+    rng = np.random.default_rng(3)
+    for o in rng.choice(w.n_obj, 12, replace=False):
+        t, y = w.obj(int(o))
+        ora_pg, ora_pk = oracle.single(t, y, w.f_min, w.f_max, w.n_f)
+        if ora_pk["status"] != 0:
+            assert got["status"][o] == ora_pk["status"]
+            continue
+        i = int(got["index"][o])
+        assert abs(i - int(ora_pk["index"])) <= 1 or ora_pg[i] >= ora_pg[ora_pk["index"]] - 2e-3
+        assert abs(got["power"][o] - ora_pg[i]) <= 1e-3
