@@ -51,7 +51,8 @@ struct FeatParams {
     int64_t n_obj;
     int32_t min_obs;
     int32_t pad;
-    float* out;  // [n_obj][LSP_FEAT_DIM]
+    float* out;            // [n_obj][LSP_FEAT_DIM]
+    unsigned int* queue;   // kXcds item counters (zeroed before the launch)
 };
 
 __device__ __forceinline__ float pool8_max(float v) {
@@ -61,12 +62,10 @@ __device__ __forceinline__ float pool8_max(float v) {
     return v;
 }
 
-__global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParams P) {
-    __shared__ double s_tau[kTile];
-    __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, new-season flag)
+// One (object, 1,024-bin tile) item; called by every thread of the workgroup.
+__device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, double* s_tau,
+                                            float4* s_obs) {
     constexpr int K = kCoarseK;
-    const int64_t item = xcd_remap(linear_block(), P.n_obj * kTilesPerObj);
-    if (item >= P.n_obj * kTilesPerObj) return;
     const int64_t obj = item / kTilesPerObj;
     const int tile = (int)(item - obj * kTilesPerObj);
     const int lane = threadIdx.x & (kWave - 1);
@@ -95,6 +94,8 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
             if (ns >= P.min_obs) {
                 const float N = (float)ns;
                 const float inv_s = syy > 0.0f ? 1.0f / syy : 0.0f;
+                // hardware reciprocals (about 1 ulp): the features are inputs
+                // to a ranking, not reported powers
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const float C2 = 2.0f * cc[k] - N;
@@ -102,13 +103,13 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
                     const float R = sqrtf(C2 * C2 + S2 * S2);
                     const float A = xc[k] * xc[k] + xs[k] * xs[k];
                     const float B =
-                        R > 0.0f
-                            ? ((xc[k] * xc[k] - xs[k] * xs[k]) * C2 + 2.0f * xc[k] * xs[k] * S2) / R
-                            : 0.0f;
+                        R > 0.0f ? ((xc[k] * xc[k] - xs[k] * xs[k]) * C2 + 2.0f * xc[k] * xs[k] * S2) *
+                                       __builtin_amdgcn_rcpf(R)
+                                 : 0.0f;
                     const float dp = N + R, dm = N - R;
                     float p = 0.0f;
-                    if (dp > kDenEps32 * N) p += (A + B) / dp;
-                    if (dm > kDenEps32 * N) p += (A - B) / dm;
+                    if (dp > kDenEps32 * N) p += (A + B) * __builtin_amdgcn_rcpf(dp);
+                    if (dm > kDenEps32 * N) p += (A - B) * __builtin_amdgcn_rcpf(dm);
                     p = fminf(fmaxf(p * inv_s, 0.0f), 1.0f);
                     feat[k] += pool8_max(p);
                 }
@@ -184,6 +185,38 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
         for (int k = 0; k < K; ++k) {
             const int64_t q = (i0 + (int64_t)kWave * k) / LSP_FEAT_POOL;
             out[q] = feat[k] * inv;
+        }
+    }
+}
+
+// One queue pop for the workgroup: thread 0 takes the next item number and
+// every thread receives it as a wave-uniform value (the leading barrier keeps
+// the broadcast slot from being overwritten while it may still be read).
+__device__ __forceinline__ int64_t pop_coarse(unsigned int* counter, int64_t lo, int64_t* s_item) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_item = lo + (int64_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    return uniform_i64(*s_item);
+}
+
+// Resident workgroups take (object, tile) items from eight per-XCD queues, as
+// the batch periodogram does; a workgroup that drains its own XCD's queue
+// moves on to the next one and exits once every queue is empty.
+__global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParams P) {
+    __shared__ double s_tau[kTile];
+    __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, new-season flag)
+    __shared__ int64_t s_item;
+    const int64_t n_items = P.n_obj * kTilesPerObj;
+    const int64_t per = (n_items + kXcds - 1) / kXcds;
+    const int x0 = (int)(blockIdx.x % kXcds);
+    for (int d = 0; d < kXcds; ++d) {
+        const int x = (x0 + d) % kXcds;
+        const int64_t lo = (int64_t)x * per;
+        const int64_t hi = lo + per < n_items ? lo + per : n_items;
+        int64_t item = pop_coarse(&P.queue[x], lo, &s_item);
+        while (item < hi) {
+            coarse_item(P, item, s_tau, s_obs);
+            item = pop_coarse(&P.queue[x], lo, &s_item);
         }
     }
 }
@@ -330,7 +363,8 @@ __global__ __launch_bounds__(kWave) void window_kernel(const FeatParams P) {
 
 }  // namespace
 
-static hipError_t launch_features(const ObjMeta* meta, const double* t, const double* y, double f_min,
+static hipError_t launch_features(const ObjMeta* meta, unsigned int* queue, const double* t,
+                                  const double* y, double f_min,
                            double f_max, int unit, double gap, int min_obs, int64_t n_obj,
                            float* out, hipStream_t s) {
     if (n_obj <= 0) return hipSuccess;
@@ -347,8 +381,20 @@ static hipError_t launch_features(const ObjMeta* meta, const double* t, const do
     p.min_obs = min_obs;
     p.pad = 0;
     p.out = out;
-    hipLaunchKernelGGL(coarse_kernel, grid_for(n_obj * kTilesPerObj), dim3(kWave * kCoarseW), 0,
-                       s, p);
+    p.queue = queue;
+    hipError_t e0 = launch_fill_u32(queue, kXcds, 0u, s);
+    if (e0 != hipSuccess) return e0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, coarse_kernel, kWave * kCoarseW, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    hipLaunchKernelGGL(coarse_kernel, dim3((unsigned)(per_cu * cus)), dim3(kWave * kCoarseW), 0, s,
+                       p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(window_kernel, grid_for(n_obj), dim3(kWave), 0, s, p);
@@ -368,7 +414,8 @@ lsp_feature_options lsp_default_feature_options(void) {
 
 size_t lsp_features_workspace_bytes(int64_t n_obj) {
     if (n_obj < 1) return 0;
-    return ((size_t)n_obj * sizeof(lsp::ObjMeta) + 255) / 256 * 256;
+    // per-object statistics, then 256 bytes of queue counters
+    return ((size_t)n_obj * sizeof(lsp::ObjMeta) + 255) / 256 * 256 + 256;
 }
 
 lsp_status lsp_features(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
@@ -396,7 +443,10 @@ lsp_status lsp_features(const int64_t* offsets, int64_t n_obj, int64_t n_obs, co
     pp.normalize = 1;
     pp.meta = static_cast<lsp::ObjMeta*>(workspace);
     if (lsp::launch_prep(pp, s) != hipSuccess) return LSP_EHIP;
-    if (lsp::launch_features(pp.meta, t, y, grid->f_min, grid->f_max, grid->unit, fo.season_gap,
+    unsigned int* queue = reinterpret_cast<unsigned int*>(
+        static_cast<char*>(workspace) + lsp_features_workspace_bytes(n_obj) - 256);
+    if (lsp::launch_features(pp.meta, queue, t, y, grid->f_min, grid->f_max, grid->unit,
+                             fo.season_gap,
                              fo.min_season_obs, n_obj, features, s) != hipSuccess)
         return LSP_EHIP;
     return LSP_OK;
