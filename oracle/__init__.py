@@ -5,7 +5,8 @@ baseline leg may import this package; the product library never does.  It
 shares no code with the GPU path.  The arithmetic lives in ``lsp_oracle.c``
 (Section 2 of Gowanlock et al., arXiv 2105.04006: Eq. 1 for tau, Eq. 2 for the
 power, the uniform half-open frequency grid; Section 3.3 for the argmax and
-the period).  This file only marshals numpy arrays.
+the period; Section 4.11 for the generalized periodogram with errors and a
+floating mean, ``gen_*``).  This file only marshals numpy arrays.
 """
 from __future__ import annotations
 
@@ -67,6 +68,18 @@ def _bind(path):
     L.ora_batch.argtypes = [p, i64, i64, p, p, d, d, i64, i32, i32, i32, p, p, i32]
     L.ora_eval_bins.restype = i32
     L.ora_eval_bins.argtypes = [p, i64, i64, p, p, d, d, i64, i32, i32, i32, p, p, i64, p, i32]
+    L.ora_gen_prep.restype = i32
+    L.ora_gen_prep.argtypes = [p, p, p, i64, p, p, p, p]
+    L.ora_gen_tau.restype = d
+    L.ora_gen_tau.argtypes = [p, p, i64, d, d]
+    L.ora_gen_pls.restype = d
+    L.ora_gen_pls.argtypes = [p, p, p, i64, d, d, d, p]
+    L.ora_gen_single.restype = i32
+    L.ora_gen_single.argtypes = [p, p, p, i64, d, d, i64, i32, i32, p, p, p, p, i32]
+    L.ora_gen_batch.restype = i32
+    L.ora_gen_batch.argtypes = [p, i64, i64, p, p, p, d, d, i64, i32, i32, p, p, i32]
+    L.ora_gen_eval_bins.restype = i32
+    L.ora_gen_eval_bins.argtypes = [p, i64, i64, p, p, p, d, d, i64, i32, i32, p, p, i64, p, i32]
     return L
 
 
@@ -170,6 +183,76 @@ class Oracle:
             raise MemoryError("oracle eval_bins could not allocate scratch")
         return out
 
+    # -- generalized periodogram (Section 4.11): errors dy (None: unit errors)
+    # and a floating mean.
+
+    def gen_prep(self, t, y, dy=None):
+        """Weights, weighted-mean-centred magnitudes, YY and W; returns (status, w, yw, yy, W)."""
+        t, y = _f64(t), _f64(y)
+        dy = None if dy is None else _f64(dy)
+        n = len(t)
+        w, yw = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        yy, ws = np.zeros(1), np.zeros(1)
+        st = self.L.ora_gen_prep(_ptr(t), _ptr(y), _ptr(dy), n, _ptr(w), _ptr(yw), _ptr(yy),
+                                 _ptr(ws))
+        return st, w[:n], yw[:n], float(yy[0]), float(ws[0])
+
+    def gen_tau(self, t, w, wsum, om):
+        t, w = _f64(t), _f64(w)
+        return self.L.ora_gen_tau(_ptr(t), _ptr(w), len(t), float(wsum), float(om))
+
+    def gen_pls(self, t, yw, w, wsum, om, tau_value):
+        """Half the chi^2 reduction at om and tau; returns (P, [YC, YS, CC, SS])."""
+        t, yw, w = _f64(t), _f64(yw), _f64(w)
+        sums = np.zeros(4)
+        v = self.L.ora_gen_pls(_ptr(t), _ptr(yw), _ptr(w), len(t), float(wsum), float(om),
+                               float(tau_value), _ptr(sums))
+        return v, sums
+
+    def gen_single(self, t, y, dy, f_min, f_max, n_f, unit=CYCLES, normalize=True, threads=0):
+        """Whole generalized periodogram of one object; returns (pgram[n_f], peak record)."""
+        t, y = _f64(t), _f64(y)
+        dy = None if dy is None else _f64(dy)
+        n = len(t)
+        w, yw = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        pg = np.empty(int(n_f))
+        pk = np.zeros(1, dtype=PEAK_DTYPE)
+        self.L.ora_gen_single(_ptr(t), _ptr(y), _ptr(dy), n, float(f_min), float(f_max),
+                              int(n_f), int(unit), int(bool(normalize)), _ptr(w), _ptr(yw),
+                              _ptr(pg), _ptr(pk), int(threads))
+        return pg, pk[0]
+
+    def gen_batch(self, offsets, t, y, dy, f_min, f_max, n_f, unit=CYCLES, normalize=True,
+                  want_pgram=True, threads=0):
+        """Generalized batch over CSR objects; returns (pgram or None, peaks)."""
+        offsets, t, y = _i64(offsets), _f64(t), _f64(y)
+        dy = None if dy is None else _f64(dy)
+        n_obj = len(offsets) - 1
+        n_f = int(n_f)
+        pk = np.zeros(n_obj, dtype=PEAK_DTYPE)
+        pg = np.empty((n_obj, n_f)) if want_pgram else None
+        rc = self.L.ora_gen_batch(_ptr(offsets), n_obj, len(t), _ptr(t), _ptr(y), _ptr(dy),
+                                  float(f_min), float(f_max), n_f, int(unit),
+                                  int(bool(normalize)), _ptr(pg), _ptr(pk), int(threads))
+        if rc != 0:
+            raise MemoryError("oracle gen_batch could not allocate scratch")
+        return pg, pk
+
+    def gen_eval_bins(self, offsets, t, y, dy, f_min, f_max, n_f, obj, bins, unit=CYCLES,
+                      normalize=True, threads=0):
+        """Generalized power at chosen (object, grid index) pairs."""
+        offsets, t, y = _i64(offsets), _f64(t), _f64(y)
+        dy = None if dy is None else _f64(dy)
+        obj, bins = _i64(obj), _i64(bins)
+        out = np.empty(len(obj))
+        rc = self.L.ora_gen_eval_bins(_ptr(offsets), len(offsets) - 1, len(t), _ptr(t), _ptr(y),
+                                      _ptr(dy), float(f_min), float(f_max), int(n_f), int(unit),
+                                      int(bool(normalize)), _ptr(obj), _ptr(bins), len(obj),
+                                      _ptr(out), int(threads))
+        if rc != 0:
+            raise MemoryError("oracle gen_eval_bins could not allocate scratch")
+        return out
+
 
 _default = None
 
@@ -184,6 +267,7 @@ def default() -> Oracle:
 def __getattr__(name):
     # module-level shortcuts: oracle.single(...), oracle.batch(...), ...
     if name in ("grid_freq", "omega", "period", "prep", "tau", "pls_at", "argmax", "single",
-                "batch", "eval_bins"):
+                "batch", "eval_bins", "gen_prep", "gen_tau", "gen_pls", "gen_single", "gen_batch",
+                "gen_eval_bins"):
         return getattr(default(), name)
     raise AttributeError(name)

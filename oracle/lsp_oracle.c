@@ -378,3 +378,273 @@ int32_t ora_eval_bins(const int64_t *offsets, int64_t n_obj, int64_t n_obs, cons
     }
     return failed ? -1 : ORA_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Generalized periodogram with photometric errors and a floating mean
+ * (Section 4.11 of the paper, which follows the generalized Lomb-Scargle
+ * method of Zechmeister & Kuerster 2009 as implemented in Astropy).
+ *
+ * Each observation carries an error dy_j and the weight w_j = 1 / dy_j^2.  At
+ * angular frequency w the model y = a cos wt + b sin wt + c is fitted by
+ * weighted least squares; the power is the fraction of the weighted variance
+ * about the weighted mean that the two trigonometric terms explain.  The
+ * steps are those of the published method, in its order:
+ *   - weighted mean ybar_w = sum w y / W (W = sum w), centred yw = y - ybar_w,
+ *     YY = sum w yw^2;
+ *   - tau from the weighted, mean-removed second moments of cos wt and sin wt:
+ *     tan(2 w tau) = 2 CS / (CC - SS) with CC = sum w (cos wt - C/W)^2,
+ *     SS = sum w (sin wt - S/W)^2, CS = sum w (cos wt - C/W)(sin wt - S/W),
+ *     C = sum w cos wt, S = sum w sin wt;
+ *   - at the shifted phase th_j = w (t_j - tau), with the weighted means of
+ *     cos th and sin th removed again, YC = sum w yw cos~, YS = sum w yw sin~,
+ *     CC = sum w cos~^2, SS = sum w sin~^2;
+ *   - half the reduction in chi^2, P = 1/2 (YC^2 / CC + YS^2 / SS); the
+ *     normalised power is 2 P / YY, which lies in [0, 1].
+ * Every mean-removed quantity is formed from explicitly centred terms (one
+ * more pass over the series) rather than by subtracting C^2 / W.
+ *
+ * Readings (listed with the other readings in the design notes):
+ *   - dy == NULL means unit errors (floating-mean periodogram without errors);
+ *   - an error that is not finite or not > 0 makes the object NONFINITE;
+ *   - a term whose denominator is <= 1e-12 * W is dropped, as for Eq. 2
+ *     (with unit errors W = N_t, the same rule);
+ *   - N_t < 2, or YY <= 1e-20 * sum w y^2 (or 0), is DEGENERATE.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Weights, weighted mean and YY.  Writes w[n] and the centred magnitudes
+ * yw[n]; returns the object's status.
+ */
+int32_t ora_gen_prep(const double *t, const double *y, const double *dy, int64_t n, double *w,
+                     double *yw, double *yy, double *wsum)
+{
+    int64_t j;
+    ora_sum sw = {0.0, 0.0}, swy = {0.0, 0.0}, sq = {0.0, 0.0}, sraw = {0.0, 0.0};
+    double ybar;
+    *yy = 0.0;
+    *wsum = 0.0;
+    for (j = 0; j < n; j++) {
+        if (!isfinite(t[j]) || !isfinite(y[j]))
+            return ORA_NONFINITE;
+        if (dy && !(isfinite(dy[j]) && dy[j] > 0.0))
+            return ORA_NONFINITE;
+    }
+    for (j = 0; j < n; j++) {
+        w[j] = dy ? 1.0 / (dy[j] * dy[j]) : 1.0;
+        yw[j] = 0.0;
+    }
+    if (n < 2)
+        return ORA_DEGENERATE;
+    for (j = 0; j < n; j++) {
+        ora_sum_add(&sw, w[j]);
+        ora_sum_add(&swy, w[j] * y[j]);
+    }
+    *wsum = ora_sum_get(&sw);
+    ybar = ora_sum_get(&swy) / *wsum;
+    for (j = 0; j < n; j++) {
+        yw[j] = y[j] - ybar;
+        ora_sum_add(&sq, w[j] * yw[j] * yw[j]);
+        ora_sum_add(&sraw, w[j] * y[j] * y[j]);
+    }
+    *yy = ora_sum_get(&sq);
+    if (*yy <= 1e-20 * ora_sum_get(&sraw) || *yy == 0.0)
+        return ORA_DEGENERATE;
+    return ORA_OK;
+}
+
+/* Weighted means of cos(w (t - shift)) and sin(w (t - shift)). */
+static void ora_gen_means(const double *t, const double *w, int64_t n, double wsum, double om,
+                          double shift, double *mc, double *ms)
+{
+    int64_t j;
+    ora_sum c = {0.0, 0.0}, s = {0.0, 0.0};
+    for (j = 0; j < n; j++) {
+        double arg = om * (t[j] - shift);
+        ora_sum_add(&c, w[j] * cos(arg));
+        ora_sum_add(&s, w[j] * sin(arg));
+    }
+    *mc = ora_sum_get(&c) / wsum;
+    *ms = ora_sum_get(&s) / wsum;
+}
+
+/* tau of the generalized method: tan(2 w tau) = 2 CS / (CC - SS); 0 at w = 0. */
+double ora_gen_tau(const double *t, const double *w, int64_t n, double wsum, double om)
+{
+    int64_t j;
+    double mc, ms;
+    ora_sum cc = {0.0, 0.0}, ss = {0.0, 0.0}, cs = {0.0, 0.0};
+    if (om == 0.0)
+        return 0.0;
+    ora_gen_means(t, w, n, wsum, om, 0.0, &mc, &ms);
+    for (j = 0; j < n; j++) {
+        double dc = cos(om * t[j]) - mc;
+        double ds = sin(om * t[j]) - ms;
+        ora_sum_add(&cc, w[j] * dc * dc);
+        ora_sum_add(&ss, w[j] * ds * ds);
+        ora_sum_add(&cs, w[j] * dc * ds);
+    }
+    return atan2(2.0 * ora_sum_get(&cs), ora_sum_get(&cc) - ora_sum_get(&ss)) / (2.0 * om);
+}
+
+/*
+ * Half the chi^2 reduction at angular frequency om and a given tau.  When
+ * sums != NULL, stores {YC, YS, CC, SS} of the shifted, mean-removed terms.
+ */
+double ora_gen_pls(const double *t, const double *yw, const double *w, int64_t n, double wsum,
+                   double om, double tau, double *sums)
+{
+    int64_t j;
+    double mc, ms, gc, gs, gcc, gss, p;
+    ora_sum yc = {0.0, 0.0}, ys = {0.0, 0.0}, cc = {0.0, 0.0}, ss = {0.0, 0.0};
+    ora_gen_means(t, w, n, wsum, om, tau, &mc, &ms);
+    for (j = 0; j < n; j++) {
+        double arg = om * (t[j] - tau);
+        double dc = cos(arg) - mc;
+        double ds = sin(arg) - ms;
+        ora_sum_add(&yc, w[j] * yw[j] * dc);
+        ora_sum_add(&ys, w[j] * yw[j] * ds);
+        ora_sum_add(&cc, w[j] * dc * dc);
+        ora_sum_add(&ss, w[j] * ds * ds);
+    }
+    gc = ora_sum_get(&yc);
+    gs = ora_sum_get(&ys);
+    gcc = ora_sum_get(&cc);
+    gss = ora_sum_get(&ss);
+    if (sums) {
+        sums[0] = gc;
+        sums[1] = gs;
+        sums[2] = gcc;
+        sums[3] = gss;
+    }
+    p = 0.0;
+    if (gcc > 1e-12 * wsum)
+        p += gc * gc / gcc;
+    if (gss > 1e-12 * wsum)
+        p += gs * gs / gss;
+    return 0.5 * p;
+}
+
+static double ora_gen_power_one(const double *t, const double *yw, const double *w, int64_t n,
+                                double wsum, double yy, double f, int32_t unit, int32_t normalize)
+{
+    double om = ora_omega(f, unit);
+    double tau = ora_gen_tau(t, w, n, wsum, om);
+    double pls = ora_gen_pls(t, yw, w, n, wsum, om, tau, NULL);
+    if (normalize)
+        return 2.0 * pls / yy;
+    return pls;
+}
+
+/* Generalized single-object mode.  w and yw are caller scratch of n doubles. */
+int32_t ora_gen_single(const double *t, const double *y, const double *dy, int64_t n,
+                       double f_min, double f_max, int64_t n_f, int32_t unit, int32_t normalize,
+                       double *w, double *yw, double *pgram, ora_peak *peak, int32_t nthreads)
+{
+    double yy = 0.0, wsum = 0.0;
+    int64_t i;
+    int32_t st = ora_gen_prep(t, y, dy, n, w, yw, &yy, &wsum);
+    if (st != ORA_OK) {
+        ora_fill_row(pgram, n_f, st);
+    } else {
+#pragma omp parallel for schedule(static) num_threads(ora_threads(nthreads))
+        for (i = 0; i < n_f; i++)
+            pgram[i] = ora_gen_power_one(t, yw, w, n, wsum, yy,
+                                         ora_grid_freq(f_min, f_max, n_f, i), unit, normalize);
+    }
+    if (peak)
+        ora_fill_peak(peak, st, pgram, n_f, f_min, f_max, unit);
+    return st;
+}
+
+/*
+ * Generalized batch mode over CSR objects (dy may be NULL).  pgram is
+ * [n_obj * n_f] or NULL.  Returns -1 if scratch memory cannot be had.
+ */
+int32_t ora_gen_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                      const double *y, const double *dy, double f_min, double f_max, int64_t n_f,
+                      int32_t unit, int32_t normalize, double *pgram, ora_peak *peaks,
+                      int32_t nthreads)
+{
+    int64_t o;
+    int32_t failed = 0;
+#pragma omp parallel for schedule(dynamic) num_threads(ora_threads(nthreads))
+    for (o = 0; o < n_obj; o++) {
+        double *row = pgram ? pgram + o * n_f : (double *)malloc(sizeof(double) * (size_t)n_f);
+        int32_t st = ora_range_status(offsets, o, n_obs);
+        int64_t i;
+        if (!row) {
+#pragma omp atomic write
+            failed = 1;
+            continue;
+        }
+        if (st == ORA_OK) {
+            int64_t a = offsets[o], n = offsets[o + 1] - offsets[o];
+            double yy = 0.0, wsum = 0.0;
+            double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            double *yw = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            if (!w || !yw) {
+#pragma omp atomic write
+                failed = 1;
+                free(w);
+                free(yw);
+                if (!pgram)
+                    free(row);
+                continue;
+            }
+            st = ora_gen_prep(t + a, y + a, dy ? dy + a : NULL, n, w, yw, &yy, &wsum);
+            if (st == ORA_OK)
+                for (i = 0; i < n_f; i++)
+                    row[i] = ora_gen_power_one(t + a, yw, w, n, wsum, yy,
+                                               ora_grid_freq(f_min, f_max, n_f, i), unit,
+                                               normalize);
+            free(w);
+            free(yw);
+        }
+        if (st != ORA_OK)
+            ora_fill_row(row, n_f, st);
+        if (peaks)
+            ora_fill_peak(&peaks[o], st, row, n_f, f_min, f_max, unit);
+        if (!pgram)
+            free(row);
+    }
+    return failed ? -1 : ORA_OK;
+}
+
+/* Generalized power at selected (object, bin) pairs; as ora_eval_bins. */
+int32_t ora_gen_eval_bins(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                          const double *y, const double *dy, double f_min, double f_max,
+                          int64_t n_f, int32_t unit, int32_t normalize, const int64_t *obj,
+                          const int64_t *bin, int64_t n_req, double *out, int32_t nthreads)
+{
+    int64_t k;
+    int32_t failed = 0;
+    (void)n_obj;
+#pragma omp parallel for schedule(dynamic) num_threads(ora_threads(nthreads))
+    for (k = 0; k < n_req; k++) {
+        int64_t o = obj[k];
+        int32_t st = ora_range_status(offsets, o, n_obs);
+        double v = NAN;
+        if (st == ORA_OK) {
+            int64_t a = offsets[o], n = offsets[o + 1] - offsets[o];
+            double yy = 0.0, wsum = 0.0;
+            double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            double *yw = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            if (!w || !yw) {
+#pragma omp atomic write
+                failed = 1;
+            } else {
+                st = ora_gen_prep(t + a, y + a, dy ? dy + a : NULL, n, w, yw, &yy, &wsum);
+                if (st == ORA_OK)
+                    v = ora_gen_power_one(t + a, yw, w, n, wsum, yy,
+                                          ora_grid_freq(f_min, f_max, n_f, bin[k]), unit,
+                                          normalize);
+                else if (st == ORA_DEGENERATE)
+                    v = 0.0;
+            }
+            free(w);
+            free(yw);
+        }
+        out[k] = v;
+    }
+    return failed ? -1 : ORA_OK;
+}

@@ -10,6 +10,7 @@ import os
 import pytest
 
 import oracle
+from gen_pins import GEN_PINS
 from oracle_pins import ALL_PINS
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lsp_oracle.c")
@@ -36,6 +37,52 @@ MUTANTS = {
     "window_single_angle": ("ora_sum_add(&ss, sin(2.0 * w * t[j]));",
                             "ora_sum_add(&ss, sin(w * t[j]));"),
 }
+
+# Slips in the generalized periodogram (Section 4.11), caught by its own pins.
+GEN_MUTANTS = {
+    "gen_mean_not_floated": ("ybar = ora_sum_get(&swy) / *wsum;", "ybar = 0.0;"),
+    "gen_weights_not_squared": ("w[j] = dy ? 1.0 / (dy[j] * dy[j]) : 1.0;",
+                                "w[j] = dy ? 1.0 / dy[j] : 1.0;"),
+    "gen_error_check_missing": ("if (dy && !(isfinite(dy[j]) && dy[j] > 0.0))", "if (0)"),
+    "gen_yy_unweighted": ("ora_sum_add(&sq, w[j] * yw[j] * yw[j]);",
+                          "ora_sum_add(&sq, yw[j] * yw[j]);"),
+    "gen_means_unweighted": ("ora_sum_add(&c, w[j] * cos(arg));", "ora_sum_add(&c, cos(arg));"),
+    "gen_tau_not_centred": ("double dc = cos(om * t[j]) - mc;", "double dc = cos(om * t[j]);"),
+    "gen_tau_transposed": ("atan2(2.0 * ora_sum_get(&cs), ora_sum_get(&cc) - ora_sum_get(&ss))",
+                           "atan2(ora_sum_get(&cc) - ora_sum_get(&ss), 2.0 * ora_sum_get(&cs))"),
+    "gen_tau_missing_two": ("ora_sum_get(&ss)) / (2.0 * om);", "ora_sum_get(&ss)) / om;"),
+    "gen_wrong_sign_shift": ("double arg = om * (t[j] - tau);", "double arg = om * (t[j] + tau);"),
+    "gen_shift_not_centred": ("double ds = sin(arg) - ms;", "double ds = sin(arg);"),
+    "gen_numerator_unweighted": ("ora_sum_add(&yc, w[j] * yw[j] * dc);",
+                                 "ora_sum_add(&yc, yw[j] * dc);"),
+    "gen_denominator_from_sine": ("w[j] * yw[j] * ds);\n        ora_sum_add(&cc, w[j] * dc * dc);",
+                                  "w[j] * yw[j] * ds);\n        ora_sum_add(&cc, w[j] * ds * ds);"),
+    "gen_dropped_sine_term": ("p += gs * gs / gss;", "p += 0.0;"),
+    "gen_no_drop_rule": ("if (gss > 1e-12 * wsum)", "if (1)"),
+    "gen_normalisation_missing_two": ("return 2.0 * pls / yy;", "return pls / yy;"),
+}
+
+
+def _caught(name, old, new, pins, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    lib = oracle.compile_source(str(path), str(tmp_path / "libmutant.so"))
+    ora = oracle.Oracle(lib)
+    caught = []
+    for pin in pins:
+        try:
+            pin(ora)
+        except AssertionError:
+            caught.append(pin.__name__)
+    return caught
+
+
+@pytest.mark.parametrize("name", sorted(GEN_MUTANTS))
+def test_gen_mutant_is_caught(name, tmp_path):
+    old, new = GEN_MUTANTS[name]
+    assert _caught(name, old, new, GEN_PINS, tmp_path), f"no pin catches mutant {name}"
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
