@@ -9,6 +9,11 @@ kernel" comparison, and the two periodograms are compared for peak-bin
 agreement.  The oracle (CPU, FP64) is timed on a bounded sample of the same
 workload on this host's cores.
 
+``--method generalized`` times the generalized periodogram instead (Section
+4.11: per-point errors, floating mean) on the same workload drawn with
+photometric errors, and also times the standard periodogram on that input to
+report the cost ratio the paper measures (generalized / standard).
+
 Prints ONE JSON line.
 """
 from __future__ import annotations
@@ -31,6 +36,9 @@ METRIC = "LS obs×freq evals/s and objects/s vs plain FP64 kernel at peak-bin ag
 # recurrence, 2 mul + 2 FMA for a rotation (6 flops) or 2 FMA for the
 # three-term (Chebyshev) recurrence (4 flops).
 FLOPS_PER_EVAL = {"rotation": 14, "chebyshev": 12}
+# Generalized FP32 form: 6 FMA for the sums (12 flops) plus the three-term
+# recurrence's 2 FMA (4 flops).
+FLOPS_PER_EVAL_GEN = 16
 # MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 2.4 GHz x 64 flops/clock/SIMD
 # (32 FMA lanes per clock), the published 157.3 TFLOP/s.
 PEAK_FP32_TFLOPS = 256 * 4 * 2.4e9 * 64 / 1e12
@@ -42,51 +50,81 @@ def valu_ops_per_eval(rec, k):
     if rec == "chebyshev":
         return (4 * k + 4 + 2 * (k - 2) + 10) / k
     return (4 * k + 4 * (k - 1) + 9) / k
-KERNEL_SOURCES = ["paper_2105_04006_amd/csrc/lsp_fp32p.hip",
-                  "paper_2105_04006_amd/csrc/lsp_common.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fp32p_single_4096_traffic.json")
+
+
+# Generalized form: 6K for the sums, 4 + 2(K-2) for the recurrence and about
+# 12 per observation (the standard form's 10 plus the two seed scalings).
+def valu_ops_per_eval_gen(k):
+    return (6 * k + 4 + 2 * (k - 2) + 12) / k
+
+
+KERNEL_SOURCES = {
+    "standard": ["paper_2105_04006_amd/csrc/lsp_fp32p.hip", "paper_2105_04006_amd/csrc/lsp_common.h"],
+    "generalized": ["paper_2105_04006_amd/csrc/lsp_gen.hip",
+                    "paper_2105_04006_amd/csrc/lsp_common.h"],
+}
+TRAFFIC_FILES = {
+    "standard": os.path.join(ROOT, "profiles", "fp32p_single_4096_traffic.json"),
+    "generalized": os.path.join(ROOT, "profiles", "gen_fp32p_single_4096_traffic.json"),
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+def kernel_hash(method="standard"):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[method]:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(method="standard", workload="single_4096"):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+    were taken on the current kernel source and this workload."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[method]) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash(method) or rec.get("workload_name") != workload:
         return None
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, target_evals, threads):
-    """The oracle on every m-th bin of the same object (a bounded sample)."""
+def cpu_baseline(w, target_evals, threads, method="standard"):
+    """The oracle on a bounded sample of the same workload: every m-th bin of
+    the object (one object), or every bin of the first objects (a batch)."""
     import oracle
 
-    stride = max(1, int(round(w.evals / target_evals)))
-    bins = np.arange(0, w.n_f, stride, dtype=np.int64)
-    objs = np.zeros(len(bins), dtype=np.int64)
     oracle.default()
+    if w.n_obj == 1:
+        stride = max(1, int(round(w.evals / target_evals)))
+        bins = np.arange(0, w.n_f, stride, dtype=np.int64)
+        objs = np.zeros(len(bins), dtype=np.int64)
+        what = f"every {stride}th of the {w.n_f} bins ({len(bins)} bins x {w.n_obs} obs"
+    else:
+        per_obj = w.n_f * np.diff(w.offsets)
+        k = max(1, int(np.searchsorted(np.cumsum(per_obj), target_evals)))
+        stride = max(1, int(round(per_obj[:k].sum() / target_evals)))
+        bins1 = np.arange(0, w.n_f, stride, dtype=np.int64)
+        objs = np.repeat(np.arange(k, dtype=np.int64), len(bins1))
+        bins = np.tile(bins1, k)
+        what = f"every {stride}th bin of the first {k} objects ({len(bins)} (object, bin) pairs"
     t0 = time.perf_counter()
-    oracle.eval_bins(w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, objs, bins, threads=threads)
+    if method == "generalized":
+        oracle.gen_eval_bins(w.offsets, w.t, w.y, w.dy, w.f_min, w.f_max, w.n_f, objs, bins,
+                             threads=threads)
+    else:
+        oracle.eval_bins(w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, objs, bins,
+                         threads=threads)
     dt = time.perf_counter() - t0
-    evals = len(bins) * w.n_obs
+    n_t = np.diff(w.offsets)
+    evals = int(n_t[objs].sum())
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th of the {w.n_f} bins ({len(bins)} bins x {w.n_obs} obs, "
-                      f"{evals:.3g} evals) of the same object, {dt:.2f} s wall"}
+            "sample": f"{what}, {evals:.3g} evals) of the same workload, {dt:.2f} s wall"}
 
 
 def main():
@@ -100,7 +138,8 @@ def main():
     ap.add_argument("--k", type=int, default=0, help="frequencies per lane (0: library default)")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--schedule", default="auto", choices=["auto", "grid", "persistent"])
-    ap.add_argument("--cpu-evals", type=float, default=2e8)
+    ap.add_argument("--cpu-evals", type=float, default=6e8,
+                    help="oracle evaluations in the CPU-baseline sample (about 10-30 s of CPU work)")
     ap.add_argument("--fp64-steps", type=int, default=0,
                     help="timed steps of the FP64 reference form (default steps // 8, >= 3)")
     ap.add_argument("--mode", default="lsp", choices=["lsp", "copy"],
@@ -110,6 +149,9 @@ def main():
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
                     help="graph: each timed FP32 step replays the call captured once as a HIP "
                          "graph (lsp_plan_*)")
+    ap.add_argument("--method", default="standard", choices=["standard", "generalized"],
+                    help="generalized: the periodogram with per-point errors and a floating "
+                         "mean (Section 4.11), on the workload drawn with errors")
     ap.add_argument("--learned", action="store_true",
                     help="time the learned band-proposal path on --workload (always on for "
                          "learned_100k)")
@@ -144,7 +186,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "learned_100k" or args.learned:
         return bench_learned(args, torch, dev)
-    w = synth.make_workload(args.workload)
+    gen = args.method == "generalized"
+    w = synth.make_workload(args.workload, errors=gen)
     single = w.n_obj == 1
     log(f"[bench] workload {w.name}: n_obj={w.n_obj} n_obs={w.n_obs} n_f={w.n_f} "
         f"evals={w.evals:.3e}")
@@ -156,6 +199,8 @@ def main():
            "chebyshev": lsp.REC_CHEBYSHEV}[args.recurrence]
     sched = {"auto": lsp.SCHED_AUTO, "grid": lsp.SCHED_GRID,
              "persistent": lsp.SCHED_PERSISTENT}[args.schedule]
+    if gen:
+        kw.update(method="generalized", dy=torch.as_tensor(w.dy, device=dev))
     p32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, schedule=sched,
                           recurrence=rec, k=args.k, waves=args.waves, **kw)
     p64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, **kw)
@@ -182,6 +227,21 @@ def main():
     steps64 = args.fp64_steps if args.fp64_steps > 0 else max(3, args.steps // 8)
     ms64 = timed(p64, steps64)
     log(f"[bench] fp64 {ms64:.4f} ms/step ({steps64} steps)")
+    std_cost = None
+    if gen:
+        # the standard periodogram of the same input, for the cost ratio
+        kws = dict(offsets=off, pgram=single, peaks=True)
+        s32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, **kws)
+        s64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, **kws)
+        s32()
+        s64()
+        ms_s32 = timed(s32, args.steps)
+        ms_s64 = timed(s64, steps64)
+        std_cost = {"fp32_ms_per_step": ms_s32, "fp64_ms_per_step": ms_s64,
+                    "generalized_over_standard_fp32": ms32 / ms_s32,
+                    "generalized_over_standard_fp64": ms64 / ms_s64}
+        log(f"[bench] standard fp32p {ms_s32:.4f} ms, fp64 {ms_s64:.4f} ms; generalized/standard "
+            f"{ms32 / ms_s32:.2f}x (fp32), {ms64 / ms_s64:.2f}x (fp64)")
 
     # dominant kernel's own device time, from events the library records
     # around the main kernel on its launch stream
@@ -210,8 +270,10 @@ def main():
     value = evals / (ms32 * 1e-3)
     rec_name = "rotation" if args.recurrence == "rotation" else "chebyshev"  # auto = chebyshev
     k_lane = args.k if args.k else 16
-    achieved = FLOPS_PER_EVAL[rec_name] * evals / (k_ms * 1e-3) / 1e12
-    valu_ops = valu_ops_per_eval(rec_name, k_lane) * evals / (k_ms * 1e-3)
+    flops_eval = FLOPS_PER_EVAL_GEN if gen else FLOPS_PER_EVAL[rec_name]
+    achieved = flops_eval * evals / (k_ms * 1e-3) / 1e12
+    valu_ops = (valu_ops_per_eval_gen(k_lane) if gen else valu_ops_per_eval(rec_name, k_lane)) \
+        * evals / (k_ms * 1e-3)
     out = {
         "metric": METRIC,
         "value": value,
@@ -229,7 +291,8 @@ def main():
                    "U{%d..%d}" % (int(w.n_t.min()), int(w.n_t.max())), "n_obs": int(w.n_obs),
                    "n_f": w.n_f, "f_range_cycles_per_day": [w.f_min, w.f_max],
                    "form": "fp32 sums, fp64 phase reduction", "output": "pgram f32 + peak"
-                   if single else "peaks", "launch": args.launch},
+                   if single else "peaks", "launch": args.launch,
+                   "method": "generalized (errors 1/dy^2, floating mean)" if gen else "standard"},
         "objects_per_s": w.n_obj / (ms32 * 1e-3),
         "pgram_bytes_per_step": (4 * w.n_f * w.n_obj) if single else 0,
         "pgram_write_GBps": (4 * w.n_f * w.n_obj / (ms32 * 1e-3) / 1e9) if single else 0.0,
@@ -237,6 +300,7 @@ def main():
                            "objects_per_s": w.n_obj / (ms64 * 1e-3)},
         "speedup_vs_fp64": ms64 / ms32,
         "peak_bin_agreement": float(agree.mean()),
+        "generalized_vs_standard": std_cost,
         "max_abs_dpower_vs_fp64": d,
         "roofline": {
             "bound": "alu",
@@ -244,10 +308,10 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic(),
-            "kernel": "fp32p_kernel",
+            "traffic": measured_traffic(args.method, w.name),
+            "kernel": "gen_fp32p_kernel" if gen else "fp32p_kernel",
             "kernel_ms": k_ms,
-            "flops_per_eval": FLOPS_PER_EVAL[rec_name],
+            "flops_per_eval": flops_eval,
             "recurrence": rec_name,
             "k_per_lane": k_lane,
             "valu_lane_ops_per_s": valu_ops,
@@ -259,7 +323,7 @@ def main():
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         log(f"[bench] oracle baseline on {threads} threads")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_evals, threads)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_evals, threads, args.method)
     print(json.dumps(out), flush=True)
 
 

@@ -186,6 +186,42 @@ lsp_status lsp_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const
                      lsp_peak *peaks, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Generalized periodogram (Section 4.11): each observation carries an error
+ * dy_j, and at every trial frequency the model y = a cos wt + b sin wt + c is
+ * fitted by weighted least squares with weights 1 / dy_j^2 (the generalized
+ * Lomb-Scargle method that the paper takes from Astropy, Zechmeister &
+ * Kuerster 2009).  With normalize = 1 the power is the fraction of the
+ * weighted variance about the weighted mean that the two trigonometric terms
+ * explain, in [0, 1]; with normalize = 0 it is half the reduction in chi^2.
+ * The mean is always fitted: subtract_mean has no effect.
+ *   t, y, n_t, offsets, n_obj, n_obs, grid, pgram, peak(s), stream : as
+ *               lsp_single / lsp_batch.
+ *   dy        : device, errors in the layout of y (n_t or n_obs doubles), or
+ *               NULL for unit errors (the floating-mean periodogram).  An object
+ *               with an error that is not finite or not > 0 gets status
+ *               LSP_OBJ_NONFINITE (power NaN, index -1).
+ *   opt       : as lsp_single; form FP64 or FP32P.  The FP32P form has the
+ *               three-term recurrence only and k_per_lane in {0, 4, 8, 12, 16}.
+ *   workspace : >= lsp_gen_workspace_bytes(n_obj, n_obs, grid, opt) bytes
+ *               (n_obj = 1 for lsp_gen_single), 256-byte aligned, owned by the
+ *               caller.
+ * Per-bin terms whose denominator is <= 1e-12 * sum(1/dy^2) are dropped; bins
+ * the FP32P form cannot resolve are recomputed in FP64, as for lsp_single.
+ * Errors as lsp_single / lsp_batch, plus LSP_EUNSUPPORTED for recurrence =
+ * LSP_REC_ROTATION, wave_split = LSP_WSPLIT_ON, or k_per_lane 10 or 32 with
+ * the FP32P form.  lsp_gen_workspace_bytes returns 0 for invalid arguments.
+ */
+size_t lsp_gen_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid *grid,
+                               const lsp_options *opt);
+lsp_status lsp_gen_single(const double *t, const double *y, const double *dy, int64_t n_t,
+                          const lsp_grid *grid, const lsp_options *opt, void *pgram,
+                          lsp_peak *peak, void *workspace, size_t workspace_bytes, void *stream);
+lsp_status lsp_gen_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
+                         const double *y, const double *dy, const lsp_grid *grid,
+                         const lsp_options *opt, void *pgram, lsp_peak *peaks, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/*
  * Row mode: the batch kernels of Section 3.4 applied to chosen parts of the
  * grid, for refining proposed frequency bands or re-running chosen objects
  * (the paper evaluates whole grids only; this is the same per-bin arithmetic

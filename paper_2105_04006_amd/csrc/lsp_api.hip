@@ -20,7 +20,15 @@ constexpr int64_t kMaxGrid = ((int64_t)1 << 31) - 1;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Which periodogram: the standard one (Section 2) or the generalized one
+// with errors and a floating mean (Section 4.11).
+struct Method {
+    bool gen = false;
+    const double* dy = nullptr;  // errors of the generalized form; NULL: unit errors
+};
+
 struct Config {
+    int gen;
     int form;
     int rec;
     int k;
@@ -88,10 +96,11 @@ lsp_status valid_options(const lsp_options* o) {
 // Launch configuration: a pure function of the shape and the options, so that
 // lsp_workspace_bytes and the call agree.
 lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_options* o,
-                   const Rows& rows, Config* c) {
+                   const Rows& rows, Config* c, const Method& method = Method{}) {
     // Launch shapes are sized for the bins of one row.
     const int64_t n_f = rows.row_band ? (rows.band_bins < g->n_f ? rows.band_bins : g->n_f) : g->n_f;
     const bool whole = rows.whole;
+    c->gen = method.gen;
     c->form = o->form;
     // The three-term recurrence needs fewer operations per bin and measured as
     // accurate as the rotation, so it is the default.
@@ -114,8 +123,29 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         // best as single-wave workgroups fed from the per-XCD queues.
         const bool one_row = whole && n_obj == 1;
         c->waves = o->waves_per_wg ? o->waves_per_wg : (one_row ? 4 : 1);
+        if (method.gen) {
+            // The generalized kernel has the three-term recurrence only, no
+            // in-workgroup wave split, and K in {4, 8, 12, 16}.
+            if (o->recurrence == LSP_REC_ROTATION || o->wave_split == LSP_WSPLIT_ON)
+                return LSP_EUNSUPPORTED;
+            if (o->k_per_lane == 10 || o->k_per_lane == 32) return LSP_EUNSUPPORTED;
+        }
         if (o->k_per_lane) {
             c->k = o->k_per_lane;
+        } else if (method.gen) {
+            // 8 instructions per (bin, observation) plus about 12.6 per
+            // observation and lane for the scaled seed, shared by the K bins.
+            const int ks[] = {8, 12, 16};
+            double best = 1e300;
+            c->k = 16;
+            for (int k : ks) {
+                const int64_t tile = (int64_t)kWave * k * c->waves;
+                const double cost = (double)((n_f + tile - 1) / tile * tile) * (8.0 + 12.6 / k);
+                if (cost < best * (1.0 - 1e-9)) {
+                    best = cost;
+                    c->k = k;
+                }
+            }
         } else {
             // Frequencies per lane: the fewest instructions for the row,
             // counting the bins of the last, partly used tile.  Per (bin,
@@ -181,7 +211,9 @@ Layout layout(int64_t n_obj, const lsp_grid* g, const Rows& rows, const Config& 
     L.ill = off;
     off += (f32 && c.split == 1) ? align_up((size_t)rows.n_rows * (size_t)c.tiles_per_row * 4) : 0;
     L.part = off;
-    off += c.split > 1 ? align_up((size_t)c.split * 4 * (size_t)g->n_f * sizeof(float)) : 0;
+    off += c.split > 1
+               ? align_up((size_t)c.split * (c.gen ? 6 : 4) * (size_t)g->n_f * sizeof(float))
+               : 0;
     L.queue = off;
     off += kAlign;
     L.total = off;
@@ -206,7 +238,7 @@ lsp_status valid_rows(const Rows& r, const lsp_grid* grid) {
 lsp_status validate(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
                     const double* y, const lsp_grid* grid, const lsp_options* opt_in,
                     const void* pgram, const lsp_peak* peaks, const void* ws, size_t ws_bytes,
-                    const Rows& rows) {
+                    const Rows& rows, const Method& method = Method{}) {
     (void)offsets;
     if (!grid || !ws) return LSP_EINVAL;
     if (n_obj < 1 || n_obs < 0) return LSP_EINVAL;
@@ -220,7 +252,7 @@ lsp_status validate(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const 
     st = valid_rows(rows, grid);
     if (st != LSP_OK) return st;
     Config c;
-    st = resolve(n_obj, n_obs, grid, &opt, rows, &c);
+    st = resolve(n_obj, n_obs, grid, &opt, rows, &c, method);
     if (st != LSP_OK) return st;
     if (ws_bytes < layout(n_obj, grid, rows, c).total) return LSP_ENOMEM;
     return LSP_OK;
@@ -228,13 +260,14 @@ lsp_status validate(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const 
 
 lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
                const double* y, const lsp_grid* grid, const lsp_options* opt_in, void* pgram,
-               lsp_peak* peaks, void* ws, size_t ws_bytes, void* stream, const Rows& rows) {
-    lsp_status st =
-        validate(offsets, n_obj, n_obs, t, y, grid, opt_in, pgram, peaks, ws, ws_bytes, rows);
+               lsp_peak* peaks, void* ws, size_t ws_bytes, void* stream, const Rows& rows,
+               const Method& method = Method{}) {
+    lsp_status st = validate(offsets, n_obj, n_obs, t, y, grid, opt_in, pgram, peaks, ws,
+                             ws_bytes, rows, method);
     if (st != LSP_OK) return st;
     const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
     Config c;
-    resolve(n_obj, n_obs, grid, &opt, rows, &c);
+    resolve(n_obj, n_obs, grid, &opt, rows, &c, method);
     const Layout L = layout(n_obj, grid, rows, c);
     const int64_t n_groups = rows.n_rows / rows.rows_per_group;
 
@@ -252,6 +285,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     pp.subtract_mean = opt.subtract_mean;
     pp.normalize = opt.normalize;
     pp.meta = at<ObjMeta>(ws, L.meta);
+    pp.dy = method.dy;
+    pp.gen = method.gen;
     if (launch_prep(pp, s) != hipSuccess) return LSP_EHIP;
 
     MainParams mp;
@@ -280,11 +315,17 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     mp.queue = at<unsigned int>(ws, L.queue);
     mp.persistent = c.persistent;
     mp.wave_split = c.ws;
+    mp.dy = method.dy;
+    mp.gen = method.gen;
 
     if (f32 && c.persistent && launch_fill_u32(mp.queue, kXcds, 0u, s) != hipSuccess)
         return LSP_EHIP;
     if (t_main_begin && hipEventRecord(t_main_begin, s) != hipSuccess) return LSP_EHIP;
-    if (f32) {
+    if (method.gen) {
+        if ((f32 ? launch_gen_fp32p(mp, c.k, c.waves, s) : launch_gen_fp64(mp, c.k, c.waves, s)) !=
+            hipSuccess)
+            return LSP_EHIP;
+    } else if (f32) {
         if (launch_fp32p(mp, c.k, c.waves, c.rec, s) != hipSuccess) return LSP_EHIP;
     } else {
         if (launch_fp64(mp, c.k, c.waves, s) != hipSuccess) return LSP_EHIP;
@@ -314,6 +355,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             fp.pad = 0;
             fp.pgram = pgram;
             fp.rec = mp.rec;
+            fp.dy = method.dy;
+            fp.gen = method.gen;
             if (launch_fixup(fp, s) != hipSuccess) return LSP_EHIP;
         } else {
             CombineParams cp;
@@ -329,6 +372,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             cp.n_f = mp.n_f;
             cp.pgram = pgram;
             cp.rec = mp.rec;
+            cp.dy = method.dy;
+            cp.gen = method.gen;
             if (launch_combine(cp, s) != hipSuccess) return LSP_EHIP;
         }
     }
@@ -413,6 +458,42 @@ lsp_status lsp_batch(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const
     if (!offsets) return LSP_EINVAL;
     return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
                     workspace_bytes, stream, lsp::whole_grid(n_obj, grid));
+}
+
+size_t lsp_gen_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                               const lsp_options* opt_in) {
+    if (n_obj < 1 || n_obs < 0 || !lsp::valid_grid(grid)) return 0;
+    const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
+    if (lsp::valid_options(&opt) != LSP_OK) return 0;
+    const lsp::Rows rows = lsp::whole_grid(n_obj, grid);
+    lsp::Method method;
+    method.gen = true;
+    lsp::Config c;
+    if (lsp::resolve(n_obj, n_obs, grid, &opt, rows, &c, method) != LSP_OK) return 0;
+    return lsp::layout(n_obj, grid, rows, c).total;
+}
+
+lsp_status lsp_gen_single(const double* t, const double* y, const double* dy, int64_t n_t,
+                          const lsp_grid* grid, const lsp_options* opt, void* pgram,
+                          lsp_peak* peak, void* workspace, size_t workspace_bytes, void* stream) {
+    if (n_t < 0) return LSP_EINVAL;
+    lsp::Method method;
+    method.gen = true;
+    method.dy = dy;
+    return lsp::run(nullptr, 1, n_t, t, y, grid, opt, pgram, peak, workspace, workspace_bytes,
+                    stream, lsp::whole_grid(1, grid), method);
+}
+
+lsp_status lsp_gen_batch(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                         const double* y, const double* dy, const lsp_grid* grid,
+                         const lsp_options* opt, void* pgram, lsp_peak* peaks, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+    if (!offsets) return LSP_EINVAL;
+    lsp::Method method;
+    method.gen = true;
+    method.dy = dy;
+    return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
+                    workspace_bytes, stream, lsp::whole_grid(n_obj, grid), method);
 }
 
 lsp_status lsp_batch_rows(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,

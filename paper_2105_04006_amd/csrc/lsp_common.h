@@ -28,16 +28,21 @@ constexpr double kVarEps = 1e-20;
 // below this fraction of N is ill-conditioned in FP32 and is recomputed in FP64.
 constexpr float kIllTheta = 1.0f / 32.0f;
 
-// Per-object statistics written by the prep kernel.
+// Per-object statistics written by the prep kernel.  For the generalized
+// periodogram the weights are rescaled to w'_j = wnorm / dy_j^2 with
+// wnorm = N / sum(1/dy^2), so that they sum to N as unit weights do: ybar is
+// then the weighted mean, syy = sum w' (y - ybar)^2, and scale takes half the
+// chi^2 reduction in w' units to the reported power.
 struct ObjMeta {
     int64_t j0;      // first observation of the object in the packed arrays
     int64_t n;       // number of observations
     double ybar;     // mean removed from y (0 when the caller's y is used as is)
-    double syy;      // sum of squared centred magnitudes
+    double syy;      // (weighted) sum of squared centred magnitudes
     double t0;       // time origin: mid-point of the object's time span
-    double scale;    // factor from P_LS to the reported power (2/S_yy or 1)
+    double scale;    // factor from P_LS to the reported power
     int32_t status;  // LSP_OBJ_*
-    int32_t pad[3];
+    int32_t pad;
+    double wnorm;    // generalized form: N / sum(1/dy^2) (1 for unit errors)
 };
 static_assert(sizeof(ObjMeta) == 64, "ObjMeta layout");
 
@@ -160,6 +165,100 @@ __device__ __forceinline__ double power64_bin(const ObjMeta& m, const double* __
     return power64(a, (double)m.n, m.scale);
 }
 
+// ---------------------------------------------------------------------------
+// Generalized periodogram (errors and a floating mean).  With weights w' and
+// weighted-mean-centred magnitudes yw, the sums at angle wt are
+//   c1 = sum w' cos, s1 = sum w' sin, yc = sum w' yw cos, ys = sum w' yw sin,
+//   wcc = sum w' cos^2, wcs = sum w' cos sin (and wss = sum w' sin^2 = N - wcc).
+// Removing the weighted means of cos and sin gives the 2 x 2 moment matrix
+//   M = [[wcc - c1^2/N, wcs - c1 s1/N], [wcs - c1 s1/N, wss - s1^2/N]]
+// and half the chi^2 reduction of the fit is 1/2 g' M^-1 g with g = (yc, ys)
+// (yw has weighted mean 0, so g needs no correction).  The shift tau of the
+// published method rotates onto M's eigenvectors; without forming it, with
+// trace T, R = lambda_+ - lambda_- and Q = |g|^2, the projections of g on the
+// eigenvectors are (Q +- Delta) / 2 and the denominators (T +- R) / 2.
+
+struct SumsGen64 {
+    double c1, s1, yc, ys, wcc, wss, wcs;
+};
+
+__device__ __forceinline__ void sumsgen64_add(SumsGen64& a, double w, double wy, double s,
+                                              double c) {
+    const double wc = w * c, ws = w * s;
+    a.c1 += wc;
+    a.s1 += ws;
+    a.yc = fma(wy, c, a.yc);
+    a.ys = fma(wy, s, a.ys);
+    a.wcc = fma(wc, c, a.wcc);
+    a.wss = fma(ws, s, a.wss);
+    a.wcs = fma(wc, s, a.wcs);
+}
+
+// FP64 power of the generalized form; a term whose denominator is at most
+// kDenEps * N is dropped, as for Eq. 2.
+__device__ __forceinline__ double power64_gen(const SumsGen64& a, double n, double scale) {
+    const double in = 1.0 / n;
+    const double cc = a.wcc - a.c1 * a.c1 * in;
+    const double ss = a.wss - a.s1 * a.s1 * in;
+    const double cs = a.wcs - a.c1 * a.s1 * in;
+    const double tr = cc + ss;
+    const double df = cc - ss;
+    const double r = sqrt(df * df + 4.0 * cs * cs);
+    const double q = a.yc * a.yc + a.ys * a.ys;
+    const double dl = r > 0.0 ? ((a.yc * a.yc - a.ys * a.ys) * df + 4.0 * cs * a.yc * a.ys) / r
+                              : 0.0;
+    double p = 0.0;
+    if (0.5 * (tr + r) > kDenEps * n) p += (q + dl) / (tr + r);
+    if (0.5 * (tr - r) > kDenEps * n) p += (q - dl) / (tr - r);
+    return 0.5 * p * scale;
+}
+
+// The same from FP32 sums, flagging bins whose smaller denominator T - R is
+// too small for FP32 to resolve (they are recomputed in FP64).
+__device__ __forceinline__ float power32_gen(float c1, float s1, float yc, float ys, float wcc,
+                                             float wcs, float n, float scale, bool& ill) {
+    const float in = __builtin_amdgcn_rcpf(n);
+    const float cc = fmaf(-c1 * in, c1, wcc);
+    const float ss = fmaf(-s1 * in, s1, n - wcc);
+    const float cs = fmaf(-c1 * in, s1, wcs);
+    const float tr = cc + ss;
+    const float df = cc - ss;
+    const float r = __builtin_amdgcn_sqrtf(fmaf(df, df, 4.0f * cs * cs));
+    const float dp = tr + r;
+    const float dm = tr - r;
+    ill = !(dm > kIllTheta * n);
+    const float q = fmaf(yc, yc, ys * ys);
+    float dl = 0.0f;
+    if (r > 0.0f)
+        dl = fmaf(fmaf(yc, yc, -(ys * ys)), df, 4.0f * cs * yc * ys) * __builtin_amdgcn_rcpf(r);
+    float p = (q + dl) * __builtin_amdgcn_rcpf(dp);
+    if (dm > 0.0f) p = fmaf(q - dl, __builtin_amdgcn_rcpf(dm), p);
+    return 0.5f * p * scale;
+}
+
+// Weight w' of observation j (1 for unit errors).
+__device__ __forceinline__ double gen_weight(const double* __restrict__ dy, int64_t j,
+                                             double wnorm) {
+    if (!dy) return 1.0;
+    const double e = dy[j];
+    return wnorm / (e * e);
+}
+
+// FP64 generalized power of one (object, frequency) pair from the caller's
+// series (FP64 fix-up of the FP32 form).
+__device__ __forceinline__ double power64_gen_bin(const ObjMeta& m, const double* __restrict__ t,
+                                                  const double* __restrict__ y,
+                                                  const double* __restrict__ dy, double f_cyc) {
+    SumsGen64 a = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = m.j0; j < m.j0 + m.n; ++j) {
+        double s, c;
+        sincos_cycles64(f_cyc, t[j] - m.t0, &s, &c);
+        const double w = gen_weight(dy, j, m.wnorm);
+        sumsgen64_add(a, w, w * (y[j] - m.ybar), s, c);
+    }
+    return power64_gen(a, (double)m.n, m.scale);
+}
+
 // Value written for every bin of an object whose status is not OK.
 __device__ __forceinline__ double fill_value(int32_t status) {
     return status == LSP_OBJ_DEGENERATE ? 0.0 : __builtin_nan("");
@@ -199,6 +298,17 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
 
 __device__ __forceinline__ int32_t uniform_i32(int32_t v) {
     return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+// One queue pop for the whole workgroup: thread 0 takes the next item number
+// and every thread receives it as a wave-uniform value.  The leading barrier
+// keeps thread 0 from overwriting the broadcast slot while other threads may
+// still be reading the previous item's LDS data.
+__device__ __forceinline__ int64_t pop_item(unsigned int* counter, int64_t lo, int64_t* s_item) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_item = lo + (int64_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    return uniform_i64(*s_item);
 }
 
 // A row of work: one object's whole grid, or one band of it.
@@ -254,6 +364,8 @@ struct PrepParams {
     int32_t subtract_mean;
     int32_t normalize;
     ObjMeta* meta;
+    const double* dy = nullptr;  // generalized form: errors (NULL: unit errors)
+    int32_t gen = 0;             // generalized form: weights and a floating mean
 };
 
 struct MainParams {
@@ -280,6 +392,8 @@ struct MainParams {
     unsigned int* queue;     // persistent schedule: kXcds counters
     int32_t persistent;
     int32_t wave_split;      // the waves of a workgroup split observations, not bins
+    const double* dy = nullptr;  // generalized form: errors (NULL: unit errors)
+    int32_t gen = 0;             // generalized form (part holds 6 sums per split)
 };
 
 struct CombineParams {
@@ -293,6 +407,8 @@ struct CombineParams {
     int64_t n_f;
     void* pgram;
     PeakRec* rec;  // [ceil(n_f / kCombineThreads)]
+    const double* dy = nullptr;
+    int32_t gen = 0;
 };
 
 struct FixupParams {
@@ -315,6 +431,8 @@ struct FixupParams {
     int32_t pad;
     void* pgram;
     PeakRec* rec;
+    const double* dy = nullptr;
+    int32_t gen = 0;
 };
 
 struct PeakParams {
@@ -335,6 +453,8 @@ struct PeakParams {
 hipError_t launch_prep(const PrepParams& p, hipStream_t s);
 hipError_t launch_fp64(const MainParams& p, int kf, int waves, hipStream_t s);
 hipError_t launch_fp32p(const MainParams& p, int k, int waves, int rec, hipStream_t s);
+hipError_t launch_gen_fp32p(const MainParams& p, int k, int waves, hipStream_t s);
+hipError_t launch_gen_fp64(const MainParams& p, int kf, int waves, hipStream_t s);
 hipError_t launch_fixup(const FixupParams& p, hipStream_t s);
 hipError_t launch_combine(const CombineParams& p, hipStream_t s);
 hipError_t launch_peaks(const PeakParams& p, hipStream_t s);

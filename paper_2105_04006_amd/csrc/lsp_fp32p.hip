@@ -228,17 +228,6 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
     }
 }
 
-// One queue pop for the whole workgroup: thread 0 takes the next item number
-// and every thread receives it as a wave-uniform value.  The leading barrier
-// keeps thread 0 from overwriting the broadcast slot while other threads may
-// still be reading the previous item's LDS data.
-__device__ __forceinline__ int64_t pop_item(unsigned int* counter, int64_t lo, int64_t* s_item) {
-    __syncthreads();
-    if (threadIdx.x == 0) *s_item = lo + (int64_t)atomicAdd(counter, 1u);
-    __syncthreads();
-    return uniform_i64(*s_item);
-}
-
 template <int K, int W, bool CHEB, bool WS>
 __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
@@ -268,7 +257,8 @@ __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
 }
 
 // Sum the per-split partial sums of a single object in a fixed order, then
-// finalise exactly as the unsplit path does.
+// finalise exactly as the unsplit path does (4 sums per bin for the standard
+// periodogram, 6 for the generalized one).
 __global__ __launch_bounds__(kCombineThreads) void combine_kernel(const CombineParams P) {
     __shared__ PeakRec s_red[kCombineThreads / kWave];
     const int64_t blk = linear_block();
@@ -280,19 +270,33 @@ __global__ __launch_bounds__(kCombineThreads) void combine_kernel(const CombineP
             if (P.pgram) store_pgram(P.pgram, P.pgram_f64, i, fill_value(m.status));
         } else {
             const int64_t nf = P.n_f;
-            float xc = 0.0f, xs = 0.0f, cc = 0.0f, cs = 0.0f;
-            for (int s = 0; s < P.n_split; ++s) {
-                const float* b = P.part + (int64_t)s * 4 * nf;
-                xc += b[i];
-                xs += b[nf + i];
-                cc += b[2 * nf + i];
-                cs += b[3 * nf + i];
-            }
             bool ill;
-            double p = (double)power32(xc, xs, cc, cs, (float)m.n, (float)m.scale, ill);
-            if (ill)
-                p = (double)(float)power64_bin(m, P.t, P.y,
-                                               grid_freq(P.f_min, P.df, i) * P.to_cyc);
+            double p;
+            if (!P.gen) {
+                float xc = 0.0f, xs = 0.0f, cc = 0.0f, cs = 0.0f;
+                for (int s = 0; s < P.n_split; ++s) {
+                    const float* b = P.part + (int64_t)s * 4 * nf;
+                    xc += b[i];
+                    xs += b[nf + i];
+                    cc += b[2 * nf + i];
+                    cs += b[3 * nf + i];
+                }
+                p = (double)power32(xc, xs, cc, cs, (float)m.n, (float)m.scale, ill);
+            } else {
+                float v[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                for (int s = 0; s < P.n_split; ++s) {
+                    const float* b = P.part + (int64_t)s * 6 * nf;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) v[q] += b[q * nf + i];
+                }
+                p = (double)power32_gen(v[0], v[1], v[2], v[3], v[4], v[5], (float)m.n,
+                                        (float)m.scale, ill);
+            }
+            if (ill) {
+                const double f = grid_freq(P.f_min, P.df, i) * P.to_cyc;
+                p = (double)(float)(P.gen ? power64_gen_bin(m, P.t, P.y, P.dy, f)
+                                          : power64_bin(m, P.t, P.y, f));
+            }
             if (P.pgram) store_pgram(P.pgram, P.pgram_f64, i, p);
             best = PeakRec{p, i};
             if (!(p == p)) best = PeakRec{0.0, -1};

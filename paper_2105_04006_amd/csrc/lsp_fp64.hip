@@ -7,7 +7,8 @@
 // formed in cycles in FP64 and reduced exactly by rounding before the library
 // call, which keeps the library on its short-argument path.
 //
-// This file also holds the FP64 fix-up of the FP32 form (fixup_kernel).
+// This file also holds the FP64 fix-up of the FP32 form (fixup_kernel), for
+// the standard and the generalized periodogram.
 //
 // Work decomposition: a workgroup of W wavefronts owns one (object, frequency
 // tile) item; the object is staged through LDS in chunks of kTile observations
@@ -137,8 +138,9 @@ __global__ __launch_bounds__(kFixThreads) void fixup_kernel(const FixupParams P)
             PeakRec best{0.0, -1};
             for (int64_t i = f0 + threadIdx.x; i < f0 + P.tile_freqs && i < rr.f_hi;
                  i += kFixThreads) {
-                const double p = (double)(float)power64_bin(m, P.t, P.y,
-                                                            grid_freq(P.f_min, P.df, i) * P.to_cyc);
+                const double f = grid_freq(P.f_min, P.df, i) * P.to_cyc;
+                const double p = (double)(float)(P.gen ? power64_gen_bin(m, P.t, P.y, P.dy, f)
+                                                       : power64_bin(m, P.t, P.y, f));
                 if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, p);
                 if (better(p, i, best.p, best.i)) best = PeakRec{p, i};
             }

@@ -8,17 +8,23 @@
 // as they stage observations, so nothing per observation is written here and
 // objects whose CSR ranges overlap cannot interfere.  One workgroup per
 // object; all reductions are in a fixed order (bitwise reproducible).
+//
+// Generalized form (Section 4.11): weights 1/dy^2 (unit weights without
+// errors), the weighted mean, and the weighted S_yy; the mean is always
+// removed (it is one of the fitted parameters).  An error that is not finite
+// or not positive makes the object NONFINITE.
 #include "lsp_common.h"
 
 namespace lsp {
 namespace {
 
 struct Red {
-    double sy, syy_raw, tmin, tmax;
+    double sw, sy, syy_raw, tmin, tmax;
     int bad;
 };
 
 __device__ __forceinline__ Red combine(Red a, const Red& b) {
+    a.sw += b.sw;
     a.sy += b.sy;
     a.syy_raw += b.syy_raw;
     a.tmin = fmin(a.tmin, b.tmin);
@@ -33,6 +39,7 @@ __device__ Red block_reduce(Red r, Red* sh) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         Red b;
+        b.sw = __shfl_xor(r.sw, o, kWave);
         b.sy = __shfl_xor(r.sy, o, kWave);
         b.syy_raw = __shfl_xor(r.syy_raw, o, kWave);
         b.tmin = __shfl_xor(r.tmin, o, kWave);
@@ -85,24 +92,37 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const PrepParams P) 
     }
     const int64_t n = j1 - j0;
 
-    Red r = {0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0};
+    Red r = {0.0, 0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0};
     for (int64_t j = j0 + tid; j < j1; j += kPrepThreads) {
         const double tj = P.t[j], yj = P.y[j];
         if (!isfinite(tj) || !isfinite(yj)) r.bad = 1;
-        r.sy += yj;
-        r.syy_raw += yj * yj;
+        double w = 1.0;
+        if (P.gen && P.dy) {
+            const double e = P.dy[j];
+            if (!(isfinite(e) && e > 0.0)) r.bad = 1;
+            w = 1.0 / (e * e);
+        }
+        r.sw += w;
+        r.sy += w * yj;
+        r.syy_raw += w * yj * yj;
         r.tmin = fmin(r.tmin, tj);
         r.tmax = fmax(r.tmax, tj);
     }
     r = block_reduce(r, sh_red);
 
-    const double ybar = (P.subtract_mean && n > 0) ? r.sy / (double)n : 0.0;
+    // Weights are rescaled to sum to N (wnorm / dy^2), which leaves the
+    // normalised power unchanged and keeps the sums on the scale of unit weights.
+    const bool ok_w = P.gen && !r.bad && n > 0 && r.sw > 0.0 && isfinite(r.sw);
+    const double wnorm = ok_w && P.dy ? (double)n / r.sw : 1.0;
+    const double ybar = P.gen ? (ok_w ? r.sy / r.sw : 0.0)
+                              : ((P.subtract_mean && n > 0) ? r.sy / (double)n : 0.0);
     const double t0 = (n > 0 && !r.bad) ? 0.5 * (r.tmin + r.tmax) : 0.0;
 
     double sq = 0.0;
     for (int64_t j = j0 + tid; j < j1; j += kPrepThreads) {
         const double yc = P.y[j] - ybar;
-        sq += yc * yc;
+        const double w = P.gen ? gen_weight(P.dy, j, wnorm) : 1.0;
+        sq += w * yc * yc;
     }
     const double syy = block_sum(sq, sh_sum);
 
@@ -113,13 +133,16 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const PrepParams P) 
         m.ybar = ybar;
         m.syy = syy;
         m.t0 = t0;
+        m.wnorm = wnorm;
         int32_t st = LSP_OBJ_OK;
-        if (r.bad)
+        if (r.bad || (P.gen && n > 0 && !ok_w))
             st = LSP_OBJ_NONFINITE;
-        else if (n < 2 || syy == 0.0 || syy <= kVarEps * r.syy_raw)
+        else if (n < 2 || syy == 0.0 || syy <= kVarEps * r.syy_raw * wnorm)
             st = LSP_OBJ_DEGENERATE;
         m.status = st;
-        m.scale = P.normalize ? (st == LSP_OBJ_OK ? 2.0 / syy : 0.0) : 1.0;
+        // generalized, unnormalised: half the chi^2 reduction in the caller's
+        // weights is 1 / wnorm times that in the rescaled weights
+        m.scale = P.normalize ? (st == LSP_OBJ_OK ? 2.0 / syy : 0.0) : 1.0 / wnorm;
         P.meta[o] = m;
     }
 }

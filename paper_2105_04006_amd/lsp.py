@@ -86,6 +86,15 @@ def lib():
         L.lsp_batch.restype = ctypes.c_int
         L.lsp_batch.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
                                 ctypes.POINTER(Options), vp, vp, vp, sz, vp]
+        L.lsp_gen_workspace_bytes.restype = sz
+        L.lsp_gen_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
+                                              ctypes.POINTER(Options)]
+        L.lsp_gen_single.restype = ctypes.c_int
+        L.lsp_gen_single.argtypes = [vp, vp, vp, i64, ctypes.POINTER(Grid),
+                                     ctypes.POINTER(Options), vp, vp, vp, sz, vp]
+        L.lsp_gen_batch.restype = ctypes.c_int
+        L.lsp_gen_batch.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(Grid),
+                                    ctypes.POINTER(Options), vp, vp, vp, sz, vp]
         L.lsp_rows_workspace_bytes.restype = sz
         L.lsp_rows_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
                                                ctypes.POINTER(Options), i64, i64, ctypes.c_int32]
@@ -203,6 +212,11 @@ def workspace_bytes(n_obj, n_obs, grid, opt):
                                          ctypes.byref(opt)))
 
 
+def gen_workspace_bytes(n_obj, n_obs, grid, opt):
+    return int(lib().lsp_gen_workspace_bytes(int(n_obj), int(n_obs), ctypes.byref(grid),
+                                             ctypes.byref(opt)))
+
+
 def _dev_ptr(x):
     return ctypes.c_void_p(x.data_ptr()) if x is not None else None
 
@@ -225,18 +239,31 @@ class Periodogram:
     Calling the object enqueues the library's kernels on the stream and
     allocates nothing, so it can be timed in a loop or captured in a graph.
     ``offsets=None`` selects single-periodogram mode (lsp_single).
+    ``method="generalized"`` selects the generalized periodogram with errors
+    ``dy`` (None: unit errors) and a floating mean (lsp_gen_single /
+    lsp_gen_batch).
     """
 
     def __init__(self, t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, form=FORM_FP64,
                  normalize=True, subtract_mean=True, pgram=True, pgram_dtype=PGRAM_F32,
                  peaks=True, k=0, waves=0, t_split=0, schedule=SCHED_AUTO,
-                 recurrence=REC_AUTO, wave_split=WSPLIT_AUTO):
+                 recurrence=REC_AUTO, wave_split=WSPLIT_AUTO, method="standard", dy=None):
         _check(t, torch.float64, "t")
         _check(y, torch.float64, "y")
         if t.numel() != y.numel():
             raise ValueError("t and y differ in length")
         if offsets is not None:
             _check(offsets, torch.int64, "offsets")
+        if method not in ("standard", "generalized"):
+            raise ValueError(f"unknown method {method!r}")
+        self.gen = method == "generalized"
+        if dy is not None:
+            if not self.gen:
+                raise ValueError("errors dy are used by the generalized method only")
+            _check(dy, torch.float64, "dy")
+            if dy.numel() != t.numel():
+                raise ValueError("dy and t differ in length")
+        self.dy = dy
         self.t, self.y, self.offsets = t, y, offsets
         self.n_obs = int(t.numel())
         self.n_obj = 1 if offsets is None else int(offsets.numel()) - 1
@@ -244,9 +271,11 @@ class Periodogram:
         self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, t_split,
                                 schedule, recurrence, wave_split)
         dev = t.device
-        nb = workspace_bytes(self.n_obj, self.n_obs, self.grid, self.opt)
+        nb = (gen_workspace_bytes if self.gen else workspace_bytes)(self.n_obj, self.n_obs,
+                                                                   self.grid, self.opt)
         if nb == 0:
-            raise LspError(EINVAL, "lsp_workspace_bytes")
+            raise LspError(EINVAL, "lsp_gen_workspace_bytes" if self.gen
+                           else "lsp_workspace_bytes")
         self.workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
         pdt = torch.float64 if pgram_dtype == PGRAM_F64 else torch.float32
         self.pgram = (torch.empty((self.n_obj, int(n_f)), dtype=pdt, device=dev)
@@ -258,7 +287,20 @@ class Periodogram:
         L = lib()
         s = _stream_handle(stream)
         ws = self.workspace
-        if self.offsets is None:
+        if self.gen and self.offsets is None:
+            st = L.lsp_gen_single(_dev_ptr(self.t), _dev_ptr(self.y), _dev_ptr(self.dy),
+                                  self.n_obs, ctypes.byref(self.grid), ctypes.byref(self.opt),
+                                  _dev_ptr(self.pgram), _dev_ptr(self.peaks_raw), _dev_ptr(ws),
+                                  ws.numel(), s)
+            what = "lsp_gen_single"
+        elif self.gen:
+            st = L.lsp_gen_batch(_dev_ptr(self.offsets), self.n_obj, self.n_obs,
+                                 _dev_ptr(self.t), _dev_ptr(self.y), _dev_ptr(self.dy),
+                                 ctypes.byref(self.grid), ctypes.byref(self.opt),
+                                 _dev_ptr(self.pgram), _dev_ptr(self.peaks_raw), _dev_ptr(ws),
+                                 ws.numel(), s)
+            what = "lsp_gen_batch"
+        elif self.offsets is None:
             st = L.lsp_single(_dev_ptr(self.t), _dev_ptr(self.y), self.n_obs,
                               ctypes.byref(self.grid), ctypes.byref(self.opt),
                               _dev_ptr(self.pgram), _dev_ptr(self.peaks_raw), _dev_ptr(ws),
@@ -276,6 +318,8 @@ class Periodogram:
 
     def capture(self):
         """Record this call into a HIP graph (lsp_plan_create); returns a Plan."""
+        if self.gen:
+            raise NotImplementedError("plans capture the standard periodogram only")
         return Plan(self)
 
     def peaks(self):
@@ -463,4 +507,17 @@ def single(t, y, f_min, f_max, n_f, **kw):
 def batch(offsets, t, y, f_min, f_max, n_f, **kw):
     """CSR batch (Section 3.4); returns (pgram[n_obj, n_f] tensor or None, peaks array)."""
     p = Periodogram(t, y, f_min, f_max, n_f, offsets=offsets, **kw)()
+    return p.pgram, p.peaks()
+
+
+def gen_single(t, y, dy, f_min, f_max, n_f, **kw):
+    """Generalized periodogram of one series (Section 4.11); dy may be None."""
+    p = Periodogram(t, y, f_min, f_max, n_f, offsets=None, method="generalized", dy=dy, **kw)()
+    pk = p.peaks()
+    return (p.pgram[0] if p.pgram is not None else None), (pk[0] if pk is not None else None)
+
+
+def gen_batch(offsets, t, y, dy, f_min, f_max, n_f, **kw):
+    """Generalized periodogram of a CSR batch (Section 4.11); dy may be None."""
+    p = Periodogram(t, y, f_min, f_max, n_f, offsets=offsets, method="generalized", dy=dy, **kw)()
     return p.pgram, p.peaks()

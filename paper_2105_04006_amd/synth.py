@@ -17,6 +17,13 @@ distribution as rejection sampling and yields exactly N_t points.
 Streams: per-object parameters, times, noise and mixture labels come from
 separate PCG64 streams, each consumed in object order, so the first k objects
 of a workload are identical whether k or all objects are generated.
+
+Photometric errors (``errors=True``, for the generalized periodogram of
+Section 4.11, whose ZTF-like records carry per-point errors): dy is drawn
+log-normally around the noise level, sigma * 10^(0.25 z) clipped to
+[0.01, 0.3] mag, from a fifth stream, and the noise of each point is then
+drawn with its own dy (the same standard-normal draws scaled by dy instead of
+sigma), so the errors describe the scatter they come with.
 """
 from __future__ import annotations
 
@@ -57,6 +64,7 @@ class Workload:
     true_freq: np.ndarray = field(default=None)  # cycles/day, NaN for pure noise
     kind: np.ndarray = field(default=None)  # KIND_* per object
     seed: int = 0
+    dy: np.ndarray = field(default=None)  # float64 [n_obs] photometric errors, or None
 
     @property
     def n_obj(self) -> int:
@@ -84,7 +92,8 @@ class Workload:
         n = off[-1]
         return Workload(self.name, off, self.t[:n].copy(), self.y[:n].copy(), self.f_min,
                         self.f_max, self.n_f, self.unit, self.true_freq[:k].copy(),
-                        self.kind[:k].copy(), self.seed)
+                        self.kind[:k].copy(), self.seed,
+                        None if self.dy is None else self.dy[:n].copy())
 
 
 def seasonal_times(u: np.ndarray) -> np.ndarray:
@@ -130,13 +139,19 @@ def _sort_segments(t: np.ndarray, offsets: np.ndarray, chunk: int = 8192) -> np.
     return out
 
 
-def make_workload(name: str, n_obj: int | None = None, seed: int | None = None) -> Workload:
-    """Generate a named workload (optionally only its first n_obj objects)."""
+def make_workload(name: str, n_obj: int | None = None, seed: int | None = None,
+                  errors: bool = False) -> Workload:
+    """Generate a named workload (optionally only its first n_obj objects).
+
+    ``errors=True`` adds per-point photometric errors ``dy`` and draws each
+    point's noise with its own error."""
     full_obj, (nt_lo, nt_hi), (f_min, f_max), n_f, mix, sid = WORKLOADS[name]
     seed = SEED_BASE + sid if seed is None else int(seed)
     k = full_obj if n_obj is None else int(n_obj)
     ss = np.random.SeedSequence(seed)
-    r_len, r_par, r_t, r_noise = (np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(4))
+    # spawn(5) gives the same first four children as spawn(4)
+    r_len, r_par, r_t, r_noise, r_err = (np.random.Generator(np.random.PCG64(s))
+                                         for s in ss.spawn(5))
 
     n_t = r_len.integers(nt_lo, nt_hi + 1, size=full_obj)[:k].astype(np.int64)
     # per-object parameters, drawn for the full population so prefixes agree
@@ -164,11 +179,16 @@ def make_workload(name: str, n_obj: int | None = None, seed: int | None = None) 
     two = kind[owner] == KIND_TWO_HARMONIC
     y = y + np.where(two, ratio[owner] * AMP * np.sin(4.0 * np.pi * t / P + phi2[owner]), 0.0)
     y = np.where(kind[owner] == KIND_NOISE, 0.0, y)
-    y = y + r_noise.normal(0.0, NOISE_SIGMA, size=n_obs)
+    dy = None
+    if errors:
+        dy = np.clip(NOISE_SIGMA * 10.0 ** (0.25 * r_err.standard_normal(n_obs)), 0.01, 0.3)
+        y = y + dy * r_noise.standard_normal(n_obs)
+    else:
+        y = y + r_noise.normal(0.0, NOISE_SIGMA, size=n_obs)
 
     true_freq = np.where(kind == KIND_NOISE, np.nan, 1.0 / period)
     return Workload(name, offsets, t, y, float(f_min), float(f_max), int(n_f), 0, true_freq, kind,
-                    seed)
+                    seed, dy)
 
 
 def pack(series) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

@@ -240,3 +240,52 @@ def test_network_helper_argument_errors(L):
     assert L.lsp_top_k(FAKE, 8, 64, 65, FAKE, None, None) == lsp.EINVAL
     assert L.lsp_gemm_bf16(-1, 4, 4, FAKE, 4, 1, FAKE, 4, 1, None, None, 0, FAKE, None, 4,
                            None) == lsp.EINVAL
+
+
+def test_gen_workspace_bytes():
+    g = lsp.make_grid(0.5, 24.0, 500_000)
+    o32 = lsp.make_options(form=lsp.FORM_FP32P)
+    # one object on a long grid splits observations: 6 partial sums per bin
+    # and split for the generalized form against 4 for the standard one
+    assert lsp.gen_workspace_bytes(1, 4096, g, o32) > lsp.workspace_bytes(1, 4096, g, o32)
+    for form in (lsp.FORM_FP64, lsp.FORM_FP32P):
+        nb = lsp.gen_workspace_bytes(100, 50_000, g, lsp.make_options(form=form))
+        assert nb > 0 and nb % 256 == 0
+    assert lsp.gen_workspace_bytes(0, 10, g, o32) == 0
+    assert lsp.gen_workspace_bytes(1, 10, lsp.make_grid(2.0, 1.0, 10), o32) == 0
+    for o in (lsp.make_options(form=lsp.FORM_FP32P, recurrence=lsp.REC_ROTATION),
+              lsp.make_options(form=lsp.FORM_FP32P, k=10),
+              lsp.make_options(form=lsp.FORM_FP32P, k=32),
+              lsp.make_options(form=lsp.FORM_FP32P, waves=4, wave_split=lsp.WSPLIT_ON)):
+        assert lsp.gen_workspace_bytes(1, 4096, g, o) == 0
+        assert lsp.workspace_bytes(1, 4096, g, o) > 0
+
+
+@cpu_only
+def test_gen_argument_errors(L):
+    g = lsp.make_grid(1.0, 2.0, 100)
+
+    def single(dy=FAKE, t=FAKE, n=16, opt=None, ws=FAKE, nbytes=1 << 30, pgram=FAKE, peak=FAKE):
+        opt = opt or lsp.make_options()
+        return L.lsp_gen_single(t, FAKE, dy, n, ctypes.byref(g), ctypes.byref(opt), pgram, peak,
+                                ws, nbytes, None)
+
+    assert single(t=None) == lsp.EINVAL
+    assert single(ws=None) == lsp.EINVAL
+    assert single(n=-1) == lsp.EINVAL
+    assert single(pgram=None, peak=None) == lsp.EINVAL
+    assert single(nbytes=1) == lsp.ENOMEM
+    assert single(opt=lsp.make_options(form=9)) == lsp.EINVAL
+    assert single(opt=lsp.make_options(t_split=2)) == lsp.EUNSUPPORTED  # FP64 form
+    for o in (lsp.make_options(form=lsp.FORM_FP32P, recurrence=lsp.REC_ROTATION),
+              lsp.make_options(form=lsp.FORM_FP32P, k=10),
+              lsp.make_options(form=lsp.FORM_FP32P, waves=2, wave_split=lsp.WSPLIT_ON)):
+        assert single(opt=o) == lsp.EUNSUPPORTED
+        assert single(dy=None, opt=o) == lsp.EUNSUPPORTED
+    o = lsp.make_options(form=lsp.FORM_FP32P)
+    assert L.lsp_gen_batch(None, 3, 30, FAKE, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE,
+                           FAKE, FAKE, 1 << 30, None) == lsp.EINVAL
+    assert L.lsp_gen_batch(FAKE, 0, 30, FAKE, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE,
+                           FAKE, FAKE, 1 << 30, None) == lsp.EINVAL
+    assert L.lsp_gen_batch(FAKE, 3, 30, FAKE, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE,
+                           FAKE, FAKE, 1, None) == lsp.ENOMEM
