@@ -222,6 +222,52 @@ lsp_status lsp_gen_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, c
                          size_t workspace_bytes, void *stream);
 
 /*
+ * Returning whole periodograms to host memory (Section 3.5).  A pipe owns
+ * n_streams lanes, each with a kernel and a copy HIP stream (default
+ * priority), a pinned host staging buffer of staging_bytes and device buffers
+ * for two chunks of objects (allocated on first use, grown when a later call
+ * needs more), plus copy_threads host threads shared by the lanes;
+ * lsp_pipe_destroy releases everything.  Zero arguments select the defaults:
+ * 1 lane, 16 MiB staging, 128 MiB chunks, 12 copy threads.
+ *   n_streams    : lanes, 1..8
+ *   staging_bytes: >= 2 KiB, a multiple of 512; each half is one DMA piece
+ *   chunk_bytes  : periodogram bytes per chunk of objects (at least one object)
+ *   copy_threads : 1..64 host threads moving staged pieces to the caller's array
+ * Returns LSP_EINVAL for out-of-range arguments or a NULL pipe pointer and
+ * LSP_EHIP if a stream, event or pinned buffer cannot be had (*pipe is NULL).
+ *
+ * lsp_batch_to_host computes the batch (lsp_batch, or lsp_gen_batch when
+ * generalized = 1) chunk by chunk on the pipe's streams and copies the
+ * periodograms and/or peak records into HOST memory, overlapping one chunk's
+ * kernels with another's device-to-host copy and a third's host copy; the
+ * [n_obj x n_f] periodogram is never resident on the device.  It returns when
+ * every byte has arrived.
+ *   offsets, n_obj, n_obs, t, y, grid, opt : as lsp_batch (device inputs);
+ *               t_split must be 0 or 1.
+ *   dy        : device errors for the generalized periodogram, or NULL (must be
+ *               NULL when generalized = 0).
+ *   host_pgram: host (pageable or pinned) array of n_obj * n_f values of
+ *               opt->pgram_dtype, row-major, or NULL.
+ *   host_peaks: host array of n_obj lsp_peak records, or NULL; at least one of
+ *               host_pgram / host_peaks must be given.
+ *   stream    : the caller's stream; the pipe's streams wait until it reaches
+ *               the call before reading the inputs.
+ * The results equal lsp_batch's bit for bit.  Calls on one pipe must not
+ * overlap.  Errors: LSP_EINVAL for NULL pipe, offsets or grid, n_obj < 1,
+ * both outputs NULL, dy with generalized = 0, or options / grid that
+ * lsp_batch (lsp_gen_batch) would reject; LSP_EUNSUPPORTED for t_split > 1;
+ * LSP_EHIP if a device buffer cannot be allocated or a launch or copy fails.
+ */
+typedef struct lsp_pipe_s *lsp_pipe;
+lsp_status lsp_pipe_create(int32_t n_streams, size_t staging_bytes, size_t chunk_bytes,
+                           int32_t copy_threads, lsp_pipe *pipe);
+void lsp_pipe_destroy(lsp_pipe pipe);
+lsp_status lsp_batch_to_host(lsp_pipe pipe, const int64_t *offsets, int64_t n_obj, int64_t n_obs,
+                             const double *t, const double *y, const double *dy,
+                             int32_t generalized, const lsp_grid *grid, const lsp_options *opt,
+                             void *host_pgram, lsp_peak *host_peaks, void *stream);
+
+/*
  * Row mode: the batch kernels of Section 3.4 applied to chosen parts of the
  * grid, for refining proposed frequency bands or re-running chosen objects
  * (the paper evaluates whole grids only; this is the same per-bin arithmetic

@@ -399,6 +399,41 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
 }
 
 }  // namespace
+
+// Whole-grid batch call and its workspace size, for the host-return pipeline.
+// `one_batch` false runs a part of a larger batch: the launch configuration
+// is then the multi-object one even for a single object, so that every part
+// computes exactly what the whole batch would.
+Rows batch_rows(int64_t n_obj, const lsp_grid* grid, bool one_batch) {
+    Rows r = whole_grid(n_obj, grid);
+    r.whole = one_batch;
+    return r;
+}
+
+size_t batch_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                             const lsp_options* opt_in, bool gen, bool one_batch) {
+    if (n_obj < 1 || n_obs < 0 || !valid_grid(grid)) return 0;
+    const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
+    if (valid_options(&opt) != LSP_OK) return 0;
+    const Rows rows = batch_rows(n_obj, grid, one_batch);
+    Method method;
+    method.gen = gen;
+    Config c;
+    if (resolve(n_obj, n_obs, grid, &opt, rows, &c, method) != LSP_OK) return 0;
+    return layout(n_obj, grid, rows, c).total;
+}
+
+lsp_status batch_call(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                      const double* y, const double* dy, bool gen, const lsp_grid* grid,
+                      const lsp_options* opt, void* pgram, lsp_peak* peaks, void* ws,
+                      size_t ws_bytes, void* stream, bool one_batch) {
+    Method method;
+    method.gen = gen;
+    method.dy = dy;
+    return run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, ws, ws_bytes, stream,
+               batch_rows(n_obj, grid, one_batch), method);
+}
+
 }  // namespace lsp
 
 struct lsp_plan_s {

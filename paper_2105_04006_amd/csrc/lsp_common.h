@@ -460,5 +460,16 @@ hipError_t launch_combine(const CombineParams& p, hipStream_t s);
 hipError_t launch_peaks(const PeakParams& p, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* dst, int64_t n, unsigned int v, hipStream_t s);
 
+// Host side (lsp_api.hip): the whole-grid batch call of lsp_batch /
+// lsp_gen_batch and its workspace size.  one_batch = false treats the objects
+// as a part of a larger batch (the multi-object launch configuration even for
+// one object).
+size_t batch_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                             const lsp_options* opt, bool gen, bool one_batch);
+lsp_status batch_call(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                      const double* y, const double* dy, bool gen, const lsp_grid* grid,
+                      const lsp_options* opt, void* pgram, lsp_peak* peaks, void* ws,
+                      size_t ws_bytes, void* stream, bool one_batch);
+
 
 }  // namespace lsp

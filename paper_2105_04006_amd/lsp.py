@@ -75,7 +75,7 @@ def lib():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_2105_04006_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
-        vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        vp, i64, sz, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int32
         L.lsp_default_options.restype = Options
         L.lsp_default_options.argtypes = []
         L.lsp_workspace_bytes.restype = sz
@@ -95,6 +95,13 @@ def lib():
         L.lsp_gen_batch.restype = ctypes.c_int
         L.lsp_gen_batch.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(Grid),
                                     ctypes.POINTER(Options), vp, vp, vp, sz, vp]
+        L.lsp_pipe_create.restype = ctypes.c_int
+        L.lsp_pipe_create.argtypes = [i32, sz, sz, i32, ctypes.POINTER(vp)]
+        L.lsp_pipe_destroy.restype = None
+        L.lsp_pipe_destroy.argtypes = [vp]
+        L.lsp_batch_to_host.restype = ctypes.c_int
+        L.lsp_batch_to_host.argtypes = [vp, vp, i64, i64, vp, vp, vp, i32, ctypes.POINTER(Grid),
+                                        ctypes.POINTER(Options), vp, vp, vp]
         L.lsp_rows_workspace_bytes.restype = sz
         L.lsp_rows_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
                                                ctypes.POINTER(Options), i64, i64, ctypes.c_int32]
@@ -327,6 +334,64 @@ class Periodogram:
         if self.peaks_raw is None:
             return None
         return self.peaks_raw.cpu().numpy().view(PEAK_DTYPE).copy()
+
+
+class HostPipe:
+    """Streams, pinned staging buffers and copy threads for returning batch
+    periodograms to host memory (lsp_pipe_create / lsp_batch_to_host).
+
+    Zero arguments take the library's defaults (1 lane, 16 MiB staging per
+    lane, 128 MiB chunks, 12 copy threads)."""
+
+    def __init__(self, n_streams=0, staging_bytes=0, chunk_bytes=0, copy_threads=0):
+        h = ctypes.c_void_p()
+        st = lib().lsp_pipe_create(int(n_streams), int(staging_bytes), int(chunk_bytes),
+                                   int(copy_threads), ctypes.byref(h))
+        if st != OK:
+            raise LspError(st, "lsp_pipe_create")
+        self.handle = h
+
+    def batch_to_host(self, offsets, t, y, f_min, f_max, n_f, dy=None, method="standard",
+                      unit=CYCLES, pgram=True, peaks=True, stream=None, out=None, **opts):
+        """Batch periodograms (and peaks) into host memory.  Returns
+        (pgram numpy [n_obj, n_f] or None, peak records or None); ``out`` may
+        supply the host array."""
+        _check(offsets, torch.int64, "offsets")
+        _check(t, torch.float64, "t")
+        _check(y, torch.float64, "y")
+        gen = method == "generalized"
+        if dy is not None:
+            _check(dy, torch.float64, "dy")
+        n_obj = int(offsets.numel()) - 1
+        grid = make_grid(f_min, f_max, n_f, unit)
+        opt = make_options(**opts)
+        dt = np.float64 if opt.pgram_dtype == PGRAM_F64 else np.float32
+        if pgram and out is None:
+            out = np.empty((n_obj, int(n_f)), dtype=dt)
+        if pgram and (out.dtype != dt or out.shape != (n_obj, int(n_f))
+                      or not out.flags["C_CONTIGUOUS"]):
+            raise ValueError("out must be a C-contiguous host array of the periodogram's shape")
+        pk = np.zeros(n_obj, dtype=PEAK_DTYPE) if peaks else None
+        st = lib().lsp_batch_to_host(self.handle, _dev_ptr(offsets), n_obj, int(t.numel()),
+                                     _dev_ptr(t), _dev_ptr(y), _dev_ptr(dy), int(gen),
+                                     ctypes.byref(grid), ctypes.byref(opt),
+                                     out.ctypes.data_as(ctypes.c_void_p) if pgram else None,
+                                     pk.ctypes.data_as(ctypes.c_void_p) if peaks else None,
+                                     _stream_handle(stream))
+        if st != OK:
+            raise LspError(st, "lsp_batch_to_host")
+        return (out if pgram else None), pk
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lsp_pipe_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

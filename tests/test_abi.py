@@ -289,3 +289,17 @@ def test_gen_argument_errors(L):
                            FAKE, FAKE, 1 << 30, None) == lsp.EINVAL
     assert L.lsp_gen_batch(FAKE, 3, 30, FAKE, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o), FAKE,
                            FAKE, FAKE, 1, None) == lsp.ENOMEM
+
+
+@cpu_only
+def test_pipe_argument_errors(L):
+    h = ctypes.c_void_p()
+    assert L.lsp_pipe_create(3, 0, 0, 0, None) == lsp.EINVAL
+    for args in ((9, 0, 0, 0), (-1, 0, 0, 0), (3, 1000, 0, 0), (3, 5000, 0, 0),
+                 (3, 0, 0, 65), (3, 0, 0, -2)):
+        assert L.lsp_pipe_create(*args, ctypes.byref(h)) == lsp.EINVAL
+        assert not h.value
+    g = lsp.make_grid(1.0, 2.0, 100)
+    o = lsp.make_options()
+    assert L.lsp_batch_to_host(None, FAKE, 3, 30, FAKE, FAKE, None, 0, ctypes.byref(g),
+                               ctypes.byref(o), FAKE, None, None) == lsp.EINVAL
