@@ -152,6 +152,12 @@ def main():
     ap.add_argument("--method", default="standard", choices=["standard", "generalized"],
                     help="generalized: the periodogram with per-point errors and a floating "
                          "mean (Section 4.11), on the workload drawn with errors")
+    ap.add_argument("--obs-read", default="auto", choices=["auto", "lds", "direct"],
+                    help="FP32 form: observations staged in LDS, or read from global memory "
+                         "after a staging pass")
+    ap.add_argument("--seed-trig", default="auto", choices=["auto", "hw", "lib", "poly"],
+                    help="FP32 form: sin/cos of the reduced seed phases by the hardware, the "
+                         "math library's sincospif, or Taylor polynomials")
     ap.add_argument("--host-return", action="store_true",
                     help="time the whole batch periodogram returned to host memory: one copy of "
                          "the device periodogram into pageable memory against the pinned-staging "
@@ -207,8 +213,12 @@ def main():
              "persistent": lsp.SCHED_PERSISTENT}[args.schedule]
     if gen:
         kw.update(method="generalized", dy=torch.as_tensor(w.dy, device=dev))
+    obs = {"auto": 0, "lds": lsp.OBS_LDS, "direct": lsp.OBS_DIRECT}[args.obs_read]
+    trig = {"auto": 0, "hw": lsp.TRIG_HW, "lib": lsp.TRIG_LIB, "poly": lsp.TRIG_POLY}[args.seed_trig]
+    variant = obs == lsp.OBS_DIRECT or trig in (lsp.TRIG_LIB, lsp.TRIG_POLY)
+    kv = dict(obs_read=obs, seed_trig=trig) if variant else {}
     p32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, schedule=sched,
-                          recurrence=rec, k=args.k, waves=args.waves, **kw)
+                          recurrence=rec, k=args.k, waves=args.waves, **kw, **kv)
     p64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, **kw)
 
     def timed(fn, steps):
@@ -236,7 +246,7 @@ def main():
     std_cost = None
     if gen:
         # the standard periodogram of the same input, for the cost ratio
-        kws = dict(offsets=off, pgram=single, peaks=True)
+        kws = dict(offsets=off, pgram=single, peaks=True)  # standard, default variant
         s32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, **kws)
         s64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, **kws)
         s32()
@@ -314,14 +324,16 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic(args.method, w.name),
+            "traffic": None if variant else measured_traffic(args.method, w.name),
             "kernel": "gen_fp32p_kernel" if gen else "fp32p_kernel",
             "kernel_ms": k_ms,
             "flops_per_eval": flops_eval,
             "recurrence": rec_name,
             "k_per_lane": k_lane,
-            "valu_lane_ops_per_s": valu_ops,
-            "valu_issue_frac": valu_ops / (PEAK_FP32_TFLOPS * 1e12 / 2),
+            "valu_lane_ops_per_s": None if variant else valu_ops,
+            "valu_issue_frac": None if variant else valu_ops / (PEAK_FP32_TFLOPS * 1e12 / 2),
+            "obs_read": args.obs_read,
+            "seed_trig": args.seed_trig,
             "transcendentals_per_s": 2 * evals / k_lane / (k_ms * 1e-3),
         },
         "cpu_baseline": None,

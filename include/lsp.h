@@ -87,6 +87,29 @@ enum {
                             observations; sums are added in LDS in wave order        */
 };
 
+/* How the FP32 form's workgroups read the observations (Sections 3.6 and 4.9
+ * compare shared-memory staging with reading global memory directly). */
+enum {
+    LSP_OBS_AUTO = 0,   /* the library's choice (currently LSP_OBS_LDS)                */
+    LSP_OBS_LDS = 1,    /* each workgroup stages tiles of (t - t0, y - ybar, step
+                           rotation) in LDS; waves read them as broadcasts           */
+    LSP_OBS_DIRECT = 2  /* a staging pass writes those per-observation values once to
+                           the workspace; waves read them from global memory (wave-
+                           uniform loads), no LDS and no barriers in the loop.  The
+                           objects' CSR ranges must not overlap.                      */
+};
+
+/* How the FP32 form takes sin and cos of its FP64-reduced seed phases and of
+ * the per-observation step rotation (Section 4.12 weighs the fast hardware
+ * sine against the library function). */
+enum {
+    LSP_TRIG_AUTO = 0, /* the library's choice (currently LSP_TRIG_HW)                  */
+    LSP_TRIG_HW = 1,   /* hardware v_sin_f32 / v_cos_f32 on the phase in revolutions   */
+    LSP_TRIG_LIB = 2,  /* the HIP math library's sincospif                              */
+    LSP_TRIG_POLY = 3  /* quarter-turn reduction and Taylor polynomials (degree 9 for
+                          sin, 8 for cos) in FP32 FMAs                                */
+};
+
 /* Work scheduling of the batch path. */
 enum {
     LSP_SCHED_AUTO = 0,
@@ -119,13 +142,14 @@ typedef struct {
     int32_t subtract_mean; /* 1: remove each object's mean (FP64) before the sums;
                               0: use y as given (the paper assumes it is zero-mean)     */
     int32_t pgram_dtype;   /* LSP_PGRAM_F32 or LSP_PGRAM_F64                            */
-    int32_t k_per_lane;    /* frequencies per lane: FP32P 4/8/16/32, FP64 1/2/4         */
+    int32_t k_per_lane;    /* frequencies per lane: FP32P 4/8/10/12/16/32, FP64 1/2/4   */
     int32_t waves_per_wg;  /* wavefronts per workgroup: 1, 2 or 4                       */
     int32_t t_split;       /* single object: split of the observation axis, 1..64       */
     int32_t schedule;      /* LSP_SCHED_*                                               */
     int32_t recurrence;    /* LSP_REC_* (FP32 form only)                                */
     int32_t wave_split;    /* LSP_WSPLIT_* (FP32 form only)                             */
-    int32_t reserved[2];
+    int32_t obs_read;      /* LSP_OBS_* (FP32 form only)                                */
+    int32_t seed_trig;     /* LSP_TRIG_* (FP32 form only)                               */
 } lsp_options;
 
 /* One object's peak (40 bytes). */

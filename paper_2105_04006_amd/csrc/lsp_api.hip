@@ -29,6 +29,8 @@ struct Method {
 
 struct Config {
     int gen;
+    int obs;   // LSP_OBS_LDS or LSP_OBS_DIRECT (FP32 form)
+    int trig;  // LSP_TRIG_HW, _LIB or _POLY (FP32 form)
     int form;
     int rec;
     int k;
@@ -40,6 +42,7 @@ struct Config {
     int64_t tiles_per_row;
     int64_t n_items;
     int64_t rec_per_group;
+    int64_t n_obs;
 };
 
 // Rows of work.  The whole-grid entry points use one row per object covering
@@ -59,7 +62,7 @@ Rows whole_grid(int64_t n_obj, const lsp_grid* g) {
 }
 
 struct Layout {
-    size_t meta, rec, ill, part, queue, total;
+    size_t meta, rec, ill, part, queue, stage_t, stage_o, total;
 };
 
 bool valid_grid(const lsp_grid* g) {
@@ -90,6 +93,8 @@ lsp_status valid_options(const lsp_options* o) {
     if (o->schedule < LSP_SCHED_AUTO || o->schedule > LSP_SCHED_PERSISTENT) return LSP_EINVAL;
     if (o->recurrence < LSP_REC_AUTO || o->recurrence > LSP_REC_CHEBYSHEV) return LSP_EINVAL;
     if (o->wave_split < LSP_WSPLIT_AUTO || o->wave_split > LSP_WSPLIT_ON) return LSP_EINVAL;
+    if (o->obs_read < LSP_OBS_AUTO || o->obs_read > LSP_OBS_DIRECT) return LSP_EINVAL;
+    if (o->seed_trig < LSP_TRIG_AUTO || o->seed_trig > LSP_TRIG_POLY) return LSP_EINVAL;
     return LSP_OK;
 }
 
@@ -101,6 +106,20 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     const int64_t n_f = rows.row_band ? (rows.band_bins < g->n_f ? rows.band_bins : g->n_f) : g->n_f;
     const bool whole = rows.whole;
     c->gen = method.gen;
+    c->obs = o->obs_read == LSP_OBS_DIRECT ? LSP_OBS_DIRECT : LSP_OBS_LDS;
+    c->trig = o->seed_trig == LSP_TRIG_AUTO ? LSP_TRIG_HW : o->seed_trig;
+    // The read-path and seed-trig variants exist for the standard FP32 form
+    // with the three-term recurrence, no wave split, K in {8, 16} and 1 or 4
+    // waves per workgroup.
+    const bool variant = c->obs != LSP_OBS_LDS || c->trig != LSP_TRIG_HW;
+    if (variant) {
+        if (o->form != LSP_FORM_FP32P || method.gen) return LSP_EUNSUPPORTED;
+        if (o->recurrence == LSP_REC_ROTATION || o->wave_split == LSP_WSPLIT_ON)
+            return LSP_EUNSUPPORTED;
+        if (!(o->k_per_lane == 0 || o->k_per_lane == 8 || o->k_per_lane == 16))
+            return LSP_EUNSUPPORTED;
+        if (o->waves_per_wg == 2) return LSP_EUNSUPPORTED;
+    }
     c->form = o->form;
     // The three-term recurrence needs fewer operations per bin and measured as
     // accurate as the rotation, so it is the default.
@@ -132,6 +151,8 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         }
         if (o->k_per_lane) {
             c->k = o->k_per_lane;
+        } else if (variant) {
+            c->k = 16;
         } else if (method.gen) {
             // 8 instructions per (bin, observation) plus about 12.6 per
             // observation and lane for the scaled seed, shared by the K bins.
@@ -167,6 +188,10 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
             while ((int64_t)kWave * c->k * c->waves > n_f && c->waves > 1) c->waves /= 2;
         if (!o->k_per_lane)
             while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 4) c->k = c->k > 8 ? 8 : 4;
+        if (variant) {
+            if (c->waves == 2) c->waves = 1;
+            if (c->k < 8) c->k = 8;
+        }
         c->persistent = o->schedule == LSP_SCHED_PERSISTENT ||
                         (o->schedule == LSP_SCHED_AUTO && !one_row);
         // Measured on one 4,096-point object: sharing the waves' bins and
@@ -194,6 +219,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     if (c->tiles_per_row * rows.rows_per_group > kMaxGrid / rows.n_rows / c->split)
         return LSP_EUNSUPPORTED;
     c->n_items = rows.n_rows * c->tiles_per_row * c->split;
+    c->n_obs = n_obs;
     c->rec_per_group = c->split > 1 ? (n_f + kCombineThreads - 1) / kCombineThreads
                                     : c->tiles_per_row * rows.rows_per_group;
     return LSP_OK;
@@ -216,6 +242,12 @@ Layout layout(int64_t n_obj, const lsp_grid* g, const Rows& rows, const Config& 
                : 0;
     L.queue = off;
     off += kAlign;
+    // LSP_OBS_DIRECT: per-observation staged values (indexed like t)
+    const size_t n_obs = c.obs == LSP_OBS_DIRECT ? (size_t)c.n_obs : 0;
+    L.stage_t = off;
+    off += align_up(n_obs * sizeof(double));
+    L.stage_o = off;
+    off += align_up(n_obs * 16);
     L.total = off;
     return L;
 }
@@ -317,6 +349,13 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     mp.wave_split = c.ws;
     mp.dy = method.dy;
     mp.gen = method.gen;
+    if (c.obs == LSP_OBS_DIRECT) {
+        mp.stage_t = at<double>(ws, L.stage_t);
+        mp.stage_o = at<float4>(ws, L.stage_o);
+        if (launch_stage(mp.meta, t, y, n_obj, mp.step_cyc, c.trig, at<double>(ws, L.stage_t),
+                         at<float4>(ws, L.stage_o), s) != hipSuccess)
+            return LSP_EHIP;
+    }
 
     if (f32 && c.persistent && launch_fill_u32(mp.queue, kXcds, 0u, s) != hipSuccess)
         return LSP_EHIP;
@@ -326,7 +365,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             hipSuccess)
             return LSP_EHIP;
     } else if (f32) {
-        if (launch_fp32p(mp, c.k, c.waves, c.rec, s) != hipSuccess) return LSP_EHIP;
+        if (launch_fp32p(mp, c.k, c.waves, c.rec, s, c.obs, c.trig) != hipSuccess)
+            return LSP_EHIP;
     } else {
         if (launch_fp64(mp, c.k, c.waves, s) != hipSuccess) return LSP_EHIP;
     }

@@ -259,6 +259,39 @@ __device__ __forceinline__ double power64_gen_bin(const ObjMeta& m, const double
     return power64_gen(a, (double)m.n, m.scale);
 }
 
+// sin and cos of 2 pi r for a reduced phase |r| <= 1/2 revolution, three ways
+// (LSP_TRIG_*): the hardware's v_sin / v_cos, which take revolutions; the math
+// library's sincospif; or a quarter-turn reduction followed by the Taylor
+// series of sin (to a^9) and cos (to a^8) at |a| <= pi/4, whose truncation
+// errors (a^11/11! < 2e-9, a^10/10! < 3e-8) are below FP32 rounding.
+template <int TRIG>
+__device__ __forceinline__ void seed_sincos(float r, float* s, float* c) {
+    if (TRIG == LSP_TRIG_LIB) {
+        sincospif(2.0f * r, s, c);
+    } else if (TRIG == LSP_TRIG_POLY) {
+        const float q = rintf(4.0f * r);
+        const float a = fmaf(-0.25f, q, r) * 6.283185307179586f;
+        const float a2 = a * a;
+        float ps = fmaf(a2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+        ps = fmaf(a2, ps, 1.0f / 120.0f);
+        ps = fmaf(a2, ps, -1.0f / 6.0f);
+        const float sa = fmaf(a * a2, ps, a);
+        float pc = fmaf(a2, 1.0f / 40320.0f, -1.0f / 720.0f);
+        pc = fmaf(a2, pc, 1.0f / 24.0f);
+        pc = fmaf(a2, pc, -0.5f);
+        const float ca = fmaf(a2, pc, 1.0f);
+        // rotate (cos a, sin a) by q quarter turns
+        const int k = (int)q & 3;
+        const float sx = (k & 1) ? ca : sa;
+        const float cx = (k & 1) ? sa : ca;
+        *s = (k & 2) ? -sx : sx;
+        *c = ((k + 1) & 2) ? -cx : cx;
+    } else {
+        *s = __builtin_amdgcn_sinf(r);
+        *c = __builtin_amdgcn_cosf(r);
+    }
+}
+
 // Value written for every bin of an object whose status is not OK.
 __device__ __forceinline__ double fill_value(int32_t status) {
     return status == LSP_OBJ_DEGENERATE ? 0.0 : __builtin_nan("");
@@ -394,6 +427,10 @@ struct MainParams {
     int32_t wave_split;      // the waves of a workgroup split observations, not bins
     const double* dy = nullptr;  // generalized form: errors (NULL: unit errors)
     int32_t gen = 0;             // generalized form (part holds 6 sums per split)
+    // LSP_OBS_DIRECT: per-observation values written by the staging pass,
+    // indexed like t (t - t0 of the object; (y - ybar, cos step, sin step, 0))
+    const double* stage_t = nullptr;
+    const float4* stage_o = nullptr;
 };
 
 struct CombineParams {
@@ -452,7 +489,12 @@ struct PeakParams {
 
 hipError_t launch_prep(const PrepParams& p, hipStream_t s);
 hipError_t launch_fp64(const MainParams& p, int kf, int waves, hipStream_t s);
-hipError_t launch_fp32p(const MainParams& p, int k, int waves, int rec, hipStream_t s);
+hipError_t launch_fp32p(const MainParams& p, int k, int waves, int rec, hipStream_t s,
+                        int obs_read = LSP_OBS_LDS, int trig = LSP_TRIG_HW);
+// Per-observation staging values for LSP_OBS_DIRECT (one workgroup per object).
+hipError_t launch_stage(const ObjMeta* meta, const double* t, const double* y, int64_t n_obj,
+                        double step_cyc, int trig, double* stage_t, float4* stage_o,
+                        hipStream_t s);
 hipError_t launch_gen_fp32p(const MainParams& p, int k, int waves, hipStream_t s);
 hipError_t launch_gen_fp64(const MainParams& p, int kf, int waves, hipStream_t s);
 hipError_t launch_fixup(const FixupParams& p, hipStream_t s);

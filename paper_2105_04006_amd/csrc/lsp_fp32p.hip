@@ -39,7 +39,74 @@ namespace {
 // wave order, before the finish.  This multiplies the waves working on one
 // object without the per-split partial sums in HBM that the observation split
 // across workgroups needs.
-template <int K, int W, bool CHEB, bool WS>
+// One observation's contribution to a lane's K bins: seed (cos, sin) of the
+// lane's first phase, then the recurrence across its bins.  o = (y - ybar,
+// cos step, sin step, -), tq = t - t0.
+template <int K, bool CHEB, int TRIG>
+__device__ __forceinline__ void accumulate_obs(double fl, double tq, float4 o, float (&xc)[K],
+                                               float (&xs)[K], float (&cc)[K], float (&cs)[K]) {
+    double ph = fl * tq;
+    ph -= rint(ph);
+    const float r = (float)ph;
+    float s, c;
+    seed_sincos<TRIG>(r, &s, &c);
+    if (!CHEB) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            xc[k] = fmaf(o.x, c, xc[k]);
+            xs[k] = fmaf(o.x, s, xs[k]);
+            cc[k] = fmaf(c, c, cc[k]);
+            cs[k] = fmaf(c, s, cs[k]);
+            if (k + 1 < K) {
+                const float cn = fmaf(c, o.y, -(s * o.z));
+                s = fmaf(s, o.y, c * o.z);
+                c = cn;
+            }
+        }
+    } else {
+        // One rotation to reach the second frequency, then the three-term
+        // recurrence x_{k+1} = 2C x_k - x_{k-1}, which cos and sin of an
+        // arithmetic progression of angles obey.
+        const float two_c = o.y + o.y;
+        float cp = c, sp = s;
+        c = fmaf(cp, o.y, -(sp * o.z));
+        s = fmaf(sp, o.y, cp * o.z);
+        xc[0] = fmaf(o.x, cp, xc[0]);
+        xs[0] = fmaf(o.x, sp, xs[0]);
+        cc[0] = fmaf(cp, cp, cc[0]);
+        cs[0] = fmaf(cp, sp, cs[0]);
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            xc[k] = fmaf(o.x, c, xc[k]);
+            xs[k] = fmaf(o.x, s, xs[k]);
+            cc[k] = fmaf(c, c, cc[k]);
+            cs[k] = fmaf(c, s, cs[k]);
+            if (k + 1 < K) {
+                const float cn = fmaf(two_c, c, -cp);
+                const float sn = fmaf(two_c, s, -sp);
+                cp = c;
+                sp = s;
+                c = cn;
+                s = sn;
+            }
+        }
+    }
+}
+
+// Per-observation staged values: t - t0 (FP64) and (y - ybar, cos, sin of the
+// step rotation 2 pi 64 df (t - t0), 0), the step phase reduced in FP64.
+template <int TRIG>
+__device__ __forceinline__ float4 stage_obs(double step_cyc, double tc, double yc) {
+    double sp = step_cyc * tc;
+    sp -= rint(sp);
+    float ss, cs;
+    seed_sincos<TRIG>((float)sp, &ss, &cs);
+    return make_float4((float)yc, cs, ss, 0.0f);
+}
+
+// SRC: LSP_OBS_LDS stages tiles of observations in LDS; LSP_OBS_DIRECT reads
+// the staging pass's values from global memory.  TRIG: LSP_TRIG_*.
+template <int K, int W, bool CHEB, bool WS, int SRC, int TRIG>
 __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, double* s_tau,
                                            float4* s_obs, PeakRec* s_red, float* s_part) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -93,69 +160,24 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 #pragma unroll
     for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
 
-    for (int64_t jt = js; jt < je; jt += kTile) {
-        const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
-        __syncthreads();
-        for (int q = threadIdx.x; q < cnt; q += kWave * W) {
-            const double tc = P.t[jt + q] - m.t0;
-            s_tau[q] = tc;
-            // step rotation: the phase advance over kWave bins, reduced in FP64
-            double sp = P.step_cyc * tc;
-            sp -= rint(sp);
-            const float rs = (float)sp;
-            s_obs[q] = make_float4((float)(P.y[jt + q] - m.ybar), __builtin_amdgcn_cosf(rs),
-                                   __builtin_amdgcn_sinf(rs), 0.0f);
-        }
-        __syncthreads();
-        for (int q = WS ? wave : 0; q < cnt; q += WS ? W : 1) {
-            const double tq = s_tau[q];
-            const float4 o = s_obs[q];  // (y - ybar, cos step, sin step, -)
-            double ph = fl * tq;
-            ph -= rint(ph);
-            const float r = (float)ph;
-            float s = __builtin_amdgcn_sinf(r);
-            float c = __builtin_amdgcn_cosf(r);
-            if (!CHEB) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    xc[k] = fmaf(o.x, c, xc[k]);
-                    xs[k] = fmaf(o.x, s, xs[k]);
-                    cc[k] = fmaf(c, c, cc[k]);
-                    cs[k] = fmaf(c, s, cs[k]);
-                    if (k + 1 < K) {
-                        const float cn = fmaf(c, o.y, -(s * o.z));
-                        s = fmaf(s, o.y, c * o.z);
-                        c = cn;
-                    }
-                }
-            } else {
-                // One rotation to reach the second frequency, then the
-                // three-term recurrence x_{k+1} = 2C x_k - x_{k-1}, which
-                // cos and sin of an arithmetic progression of angles obey.
-                const float two_c = o.y + o.y;
-                float cp = c, sp = s;
-                c = fmaf(cp, o.y, -(sp * o.z));
-                s = fmaf(sp, o.y, cp * o.z);
-                xc[0] = fmaf(o.x, cp, xc[0]);
-                xs[0] = fmaf(o.x, sp, xs[0]);
-                cc[0] = fmaf(cp, cp, cc[0]);
-                cs[0] = fmaf(cp, sp, cs[0]);
-#pragma unroll
-                for (int k = 1; k < K; ++k) {
-                    xc[k] = fmaf(o.x, c, xc[k]);
-                    xs[k] = fmaf(o.x, s, xs[k]);
-                    cc[k] = fmaf(c, c, cc[k]);
-                    cs[k] = fmaf(c, s, cs[k]);
-                    if (k + 1 < K) {
-                        const float cn = fmaf(two_c, c, -cp);
-                        const float sn = fmaf(two_c, s, -sp);
-                        cp = c;
-                        sp = s;
-                        c = cn;
-                        s = sn;
-                    }
-                }
+    if (SRC == LSP_OBS_DIRECT) {
+        // the staging pass's values, read straight from global memory; the
+        // index is wave-uniform, so every lane loads the same address
+        for (int64_t j = js; j < je; ++j)
+            accumulate_obs<K, CHEB, TRIG>(fl, P.stage_t[j], P.stage_o[j], xc, xs, cc, cs);
+    } else {
+        for (int64_t jt = js; jt < je; jt += kTile) {
+            const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
+            __syncthreads();
+            for (int q = threadIdx.x; q < cnt; q += kWave * W) {
+                const double tc = P.t[jt + q] - m.t0;
+                s_tau[q] = tc;
+                // step rotation: the phase advance over kWave bins
+                s_obs[q] = stage_obs<TRIG>(P.step_cyc, tc, P.y[jt + q] - m.ybar);
             }
+            __syncthreads();
+            for (int q = WS ? wave : 0; q < cnt; q += WS ? W : 1)
+                accumulate_obs<K, CHEB, TRIG>(fl, s_tau[q], s_obs[q], xc, xs, cc, cs);
         }
     }
 
@@ -228,7 +250,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
     }
 }
 
-template <int K, int W, bool CHEB, bool WS>
+template <int K, int W, bool CHEB, bool WS, int SRC = LSP_OBS_LDS, int TRIG = LSP_TRIG_HW>
 __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
     __shared__ float4 s_obs[kTile];
@@ -239,7 +261,8 @@ __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
     if (!P.persistent) {
         const int64_t b = linear_block();
         if (b < P.n_items)
-            fp32p_item<K, W, CHEB, WS>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red, s_part);
+            fp32p_item<K, W, CHEB, WS, SRC, TRIG>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red,
+                                                  s_part);
         return;
     }
     const int64_t per = (P.n_items + kXcds - 1) / kXcds;
@@ -250,7 +273,7 @@ __global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
         const int64_t hi = lo + per < P.n_items ? lo + per : P.n_items;
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
-            fp32p_item<K, W, CHEB, WS>(P, item, s_tau, s_obs, s_red, s_part);
+            fp32p_item<K, W, CHEB, WS, SRC, TRIG>(P, item, s_tau, s_obs, s_red, s_part);
             item = pop_item(&P.queue[x], lo, &s_item);
         }
     }
@@ -314,11 +337,11 @@ __global__ __launch_bounds__(kCombineThreads) void combine_kernel(const CombineP
     }
 }
 
-template <int K, int W, bool CHEB, bool WS>
+template <int K, int W, bool CHEB, bool WS, int SRC, int TRIG>
 int occupancy_blocks() {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fp32p_kernel<K, W, CHEB, WS>,
-                                                     kWave * W, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, fp32p_kernel<K, W, CHEB, WS, SRC, TRIG>, kWave * W, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int dev = 0, cus = 0;
@@ -329,12 +352,24 @@ int occupancy_blocks() {
     return per_cu * cus;
 }
 
-template <int K, int W, bool CHEB, bool WS>
+template <int K, int W, bool CHEB, bool WS, int SRC = LSP_OBS_LDS, int TRIG = LSP_TRIG_HW>
 hipError_t launch_kwc(const MainParams& p, hipStream_t s) {
-    const dim3 grid = p.persistent ? dim3((unsigned)occupancy_blocks<K, W, CHEB, WS>())
-                                   : grid_for(p.n_items);
-    hipLaunchKernelGGL((fp32p_kernel<K, W, CHEB, WS>), grid, dim3(kWave * W), 0, s, p);
+    const dim3 grid = p.persistent
+                          ? dim3((unsigned)occupancy_blocks<K, W, CHEB, WS, SRC, TRIG>())
+                          : grid_for(p.n_items);
+    hipLaunchKernelGGL((fp32p_kernel<K, W, CHEB, WS, SRC, TRIG>), grid, dim3(kWave * W), 0, s, p);
     return hipGetLastError();
+}
+
+// The read-path and seed-trig variants: three-term recurrence, no wave split,
+// K in {8, 16}, 1 or 4 waves per workgroup.
+template <int SRC, int TRIG>
+hipError_t launch_variant(const MainParams& p, int k, int waves, hipStream_t s) {
+    if (k == 8 && waves == 1) return launch_kwc<8, 1, true, false, SRC, TRIG>(p, s);
+    if (k == 8 && waves == 4) return launch_kwc<8, 4, true, false, SRC, TRIG>(p, s);
+    if (k == 16 && waves == 1) return launch_kwc<16, 1, true, false, SRC, TRIG>(p, s);
+    if (k == 16 && waves == 4) return launch_kwc<16, 4, true, false, SRC, TRIG>(p, s);
+    return hipErrorInvalidValue;
 }
 
 template <int K, bool CHEB>
@@ -363,10 +398,23 @@ hipError_t launch_c(const MainParams& p, int k, int waves, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_fp32p(const MainParams& p, int k, int waves, int rec, hipStream_t s) {
+hipError_t launch_fp32p(const MainParams& p, int k, int waves, int rec, hipStream_t s,
+                        int obs_read, int trig) {
     if (p.n_items <= 0) return hipSuccess;
-    return rec == LSP_REC_CHEBYSHEV ? launch_c<true>(p, k, waves, s)
-                                    : launch_c<false>(p, k, waves, s);
+    if (obs_read == LSP_OBS_LDS && trig == LSP_TRIG_HW)
+        return rec == LSP_REC_CHEBYSHEV ? launch_c<true>(p, k, waves, s)
+                                        : launch_c<false>(p, k, waves, s);
+    if (rec != LSP_REC_CHEBYSHEV || p.wave_split) return hipErrorInvalidValue;
+    if (obs_read == LSP_OBS_LDS) {
+        if (trig == LSP_TRIG_LIB) return launch_variant<LSP_OBS_LDS, LSP_TRIG_LIB>(p, k, waves, s);
+        if (trig == LSP_TRIG_POLY) return launch_variant<LSP_OBS_LDS, LSP_TRIG_POLY>(p, k, waves, s);
+    } else if (obs_read == LSP_OBS_DIRECT) {
+        if (trig == LSP_TRIG_HW) return launch_variant<LSP_OBS_DIRECT, LSP_TRIG_HW>(p, k, waves, s);
+        if (trig == LSP_TRIG_LIB) return launch_variant<LSP_OBS_DIRECT, LSP_TRIG_LIB>(p, k, waves, s);
+        if (trig == LSP_TRIG_POLY)
+            return launch_variant<LSP_OBS_DIRECT, LSP_TRIG_POLY>(p, k, waves, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_combine(const CombineParams& p, hipStream_t s) {

@@ -147,7 +147,54 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const PrepParams P) 
     }
 }
 
+// Staging pass of LSP_OBS_DIRECT: the per-observation values the main
+// kernel would otherwise stage in LDS, written once per observation of each
+// object (t - t0, and y - ybar with the step rotation of the FP32 form).
+template <int TRIG>
+__global__ __launch_bounds__(kPrepThreads) void stage_kernel(const ObjMeta* __restrict__ meta,
+                                                             const double* __restrict__ t,
+                                                             const double* __restrict__ y,
+                                                             int64_t n_obj, double step_cyc,
+                                                             double* stage_t, float4* stage_o) {
+    const int64_t o = linear_block();
+    if (o >= n_obj) return;
+    const ObjMeta m = meta[o];
+    if (m.status != LSP_OBJ_OK) return;
+    for (int64_t j = m.j0 + threadIdx.x; j < m.j0 + m.n; j += kPrepThreads) {
+        const double tc = t[j] - m.t0;
+        double sp = step_cyc * tc;
+        sp -= rint(sp);
+        float ss, cs;
+        seed_sincos<TRIG>((float)sp, &ss, &cs);
+        stage_t[j] = tc;
+        stage_o[j] = make_float4((float)(y[j] - m.ybar), cs, ss, 0.0f);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_stage(const ObjMeta* meta, const double* t, const double* y, int64_t n_obj,
+                        double step_cyc, int trig, double* stage_t, float4* stage_o,
+                        hipStream_t s) {
+    if (n_obj <= 0) return hipSuccess;
+    const dim3 grid = grid_for(n_obj);
+    switch (trig) {
+        case LSP_TRIG_HW:
+            hipLaunchKernelGGL(stage_kernel<LSP_TRIG_HW>, grid, dim3(kPrepThreads), 0, s, meta, t,
+                               y, n_obj, step_cyc, stage_t, stage_o);
+            break;
+        case LSP_TRIG_LIB:
+            hipLaunchKernelGGL(stage_kernel<LSP_TRIG_LIB>, grid, dim3(kPrepThreads), 0, s, meta,
+                               t, y, n_obj, step_cyc, stage_t, stage_o);
+            break;
+        case LSP_TRIG_POLY:
+            hipLaunchKernelGGL(stage_kernel<LSP_TRIG_POLY>, grid, dim3(kPrepThreads), 0, s, meta,
+                               t, y, n_obj, step_cyc, stage_t, stage_o);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_prep(const PrepParams& p, hipStream_t s) {
     if (p.n_obj <= 0) return hipSuccess;

@@ -27,6 +27,8 @@ PGRAM_F32, PGRAM_F64 = 0, 1
 SCHED_AUTO, SCHED_GRID, SCHED_PERSISTENT = 0, 1, 2
 REC_AUTO, REC_ROTATION, REC_CHEBYSHEV = 0, 1, 2
 WSPLIT_AUTO, WSPLIT_OFF, WSPLIT_ON = 0, 1, 2
+OBS_AUTO, OBS_LDS, OBS_DIRECT = 0, 1, 2
+TRIG_AUTO, TRIG_HW, TRIG_LIB, TRIG_POLY = 0, 1, 2, 3
 
 PEAK_DTYPE = np.dtype(
     [("index", "<i8"), ("freq", "<f8"), ("period", "<f8"), ("power", "<f8"),
@@ -46,7 +48,7 @@ class Options(ctypes.Structure):
                 ("k_per_lane", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
                 ("t_split", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("recurrence", ctypes.c_int32), ("wave_split", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("obs_read", ctypes.c_int32), ("seed_trig", ctypes.c_int32)]
 
 
 class FeatureOptions(ctypes.Structure):
@@ -202,7 +204,7 @@ def make_grid(f_min, f_max, n_f, unit=CYCLES):
 
 def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype=PGRAM_F32, k=0,
                  waves=0, t_split=0, schedule=SCHED_AUTO, recurrence=REC_AUTO,
-                 wave_split=WSPLIT_AUTO):
+                 wave_split=WSPLIT_AUTO, obs_read=0, seed_trig=0):
     o = Options()
     o.form, o.normalize, o.subtract_mean, o.pgram_dtype = (int(form), int(bool(normalize)),
                                                            int(bool(subtract_mean)),
@@ -211,6 +213,8 @@ def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype
         schedule)
     o.recurrence = int(recurrence)
     o.wave_split = int(wave_split)
+    o.obs_read = int(obs_read)
+    o.seed_trig = int(seed_trig)
     return o
 
 
@@ -254,7 +258,8 @@ class Periodogram:
     def __init__(self, t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, form=FORM_FP64,
                  normalize=True, subtract_mean=True, pgram=True, pgram_dtype=PGRAM_F32,
                  peaks=True, k=0, waves=0, t_split=0, schedule=SCHED_AUTO,
-                 recurrence=REC_AUTO, wave_split=WSPLIT_AUTO, method="standard", dy=None):
+                 recurrence=REC_AUTO, wave_split=WSPLIT_AUTO, method="standard", dy=None,
+                 obs_read=0, seed_trig=0):
         _check(t, torch.float64, "t")
         _check(y, torch.float64, "y")
         if t.numel() != y.numel():
@@ -276,7 +281,7 @@ class Periodogram:
         self.n_obj = 1 if offsets is None else int(offsets.numel()) - 1
         self.grid = make_grid(f_min, f_max, n_f, unit)
         self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, t_split,
-                                schedule, recurrence, wave_split)
+                                schedule, recurrence, wave_split, obs_read, seed_trig)
         dev = t.device
         nb = (gen_workspace_bytes if self.gen else workspace_bytes)(self.n_obj, self.n_obs,
                                                                    self.grid, self.opt)

@@ -303,3 +303,22 @@ def test_pipe_argument_errors(L):
     o = lsp.make_options()
     assert L.lsp_batch_to_host(None, FAKE, 3, 30, FAKE, FAKE, None, 0, ctypes.byref(g),
                                ctypes.byref(o), FAKE, None, None) == lsp.EINVAL
+
+
+def test_variant_options():
+    g = lsp.make_grid(1.0, 12.0, 100_000)
+    ok = lsp.make_options(form=lsp.FORM_FP32P, obs_read=lsp.OBS_DIRECT, seed_trig=lsp.TRIG_POLY)
+    base = lsp.workspace_bytes(10, 5000, g, lsp.make_options(form=lsp.FORM_FP32P))
+    # the direct read path adds the staged values: 24 bytes per observation
+    assert lsp.workspace_bytes(10, 5000, g, ok) >= base + 24 * 5000
+    for kw in (dict(form=lsp.FORM_FP64, obs_read=lsp.OBS_DIRECT),
+               dict(form=lsp.FORM_FP64, seed_trig=lsp.TRIG_LIB),
+               dict(form=lsp.FORM_FP32P, seed_trig=lsp.TRIG_LIB, recurrence=lsp.REC_ROTATION),
+               dict(form=lsp.FORM_FP32P, obs_read=lsp.OBS_DIRECT, k=12),
+               dict(form=lsp.FORM_FP32P, obs_read=lsp.OBS_DIRECT, waves=2),
+               dict(form=lsp.FORM_FP32P, seed_trig=lsp.TRIG_POLY, waves=4,
+                    wave_split=lsp.WSPLIT_ON)):
+        assert lsp.workspace_bytes(10, 5000, g, lsp.make_options(**kw)) == 0, kw
+    assert lsp.gen_workspace_bytes(10, 5000, g, ok) == 0
+    for kw in (dict(obs_read=3), dict(obs_read=-1), dict(seed_trig=4)):
+        assert lsp.workspace_bytes(10, 5000, g, lsp.make_options(form=lsp.FORM_FP32P, **kw)) == 0
