@@ -158,6 +158,10 @@ def main():
     ap.add_argument("--seed-trig", default="auto", choices=["auto", "hw", "lib", "poly"],
                     help="FP32 form: sin/cos of the reduced seed phases by the hardware, the "
                          "math library's sincospif, or Taylor polynomials")
+    ap.add_argument("--recovery", action="store_true",
+                    help="asteroid-like population (asteroids_1k): derived vs assigned rotation "
+                         "periods and the observation-cutoff curve, standard and generalized, "
+                         "FP32 and FP64 forms")
     ap.add_argument("--host-return", action="store_true",
                     help="time the whole batch periodogram returned to host memory: one copy of "
                          "the device periodogram into pageable memory against the pinned-staging "
@@ -198,6 +202,8 @@ def main():
         return bench_learned(args, torch, dev)
     if args.host_return:
         return bench_host_return(args, torch, dev)
+    if args.recovery:
+        return bench_recovery(args, torch, dev)
     gen = args.method == "generalized"
     w = synth.make_workload(args.workload, errors=gen)
     single = w.n_obj == 1
@@ -342,6 +348,99 @@ def main():
         threads = min(16, len(os.sched_getaffinity(0)))
         log(f"[bench] oracle baseline on {threads} threads")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_evals, threads, args.method)
+    print(json.dumps(out), flush=True)
+
+
+CUTOFFS = (0, 25, 50, 75, 100, 150, 200, 300, 400, 550)
+
+
+def recovery_curve(p_rot_true_h, p_lc_days, n_t, tol_h=0.1):
+    """Fraction of objects whose derived rotation period (twice the light-curve
+    period at the peak) is within tol_h of the assigned one, overall and for
+    every observation cutoff (objects with at least that many points)."""
+    derived = 2.0 * 24.0 * np.asarray(p_lc_days, dtype=np.float64)
+    ok = np.abs(derived - p_rot_true_h) <= tol_h
+    curve = []
+    for c in CUTOFFS:
+        m = n_t >= c
+        curve.append({"cutoff": c, "objects": int(m.sum()),
+                      "matched": float(ok[m].mean()) if m.any() else None})
+    return float(ok.mean()), curve, ok
+
+
+def bench_recovery(args, torch, dev):
+    """Section 4.2's accuracy study on an asteroid-like population: the peak
+    of each object's periodogram on the paper's batch grid (rad/day,
+    N_f = 200,000) gives the light-curve period; twice it should match the
+    assigned rotation period within 0.1 h.  Timed as whole batches."""
+    from paper_2105_04006_amd import lsp, synth
+
+    w = synth.make_workload("asteroids_1k")
+    n_t = np.diff(w.offsets)
+    log(f"[bench] recovery: {w.name} n_obj={w.n_obj} n_obs={w.n_obs} n_f={w.n_f} "
+        f"N_t median {int(np.median(n_t))}")
+    off = torch.as_tensor(w.offsets, device=dev)
+    t = torch.as_tensor(w.t, device=dev)
+    y = torch.as_tensor(w.y, device=dev)
+    dy = torch.as_tensor(w.dy, device=dev)
+    runs = {}
+    for name, form, method in (("standard_fp32", lsp.FORM_FP32P, "standard"),
+                               ("standard_fp64", lsp.FORM_FP64, "standard"),
+                               ("generalized_fp32", lsp.FORM_FP32P, "generalized"),
+                               ("generalized_fp64", lsp.FORM_FP64, "generalized")):
+        p = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, offsets=off, unit=lsp.ANGULAR,
+                            form=form, method=method, dy=dy if method == "generalized" else None,
+                            pgram=False, peaks=True)
+        p()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 3 if form == lsp.FORM_FP32P else 1
+        for _ in range(steps):
+            p()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        pk = p.peaks()
+        frac, curve, ok = recovery_curve(w.p_rot_hours, pk["period"], n_t)
+        runs[name] = {"ms_per_batch": ms, "objects_per_s": w.n_obj / (ms * 1e-3),
+                      "matched": frac, "curve": curve, "index": pk["index"]}
+        log(f"[bench] {name}: {ms:.2f} ms, matched {frac:.4f}, "
+            f"N_t>=50 {curve[2]['matched']:.4f}")
+    agree = {
+        "standard fp32 vs fp64": float(np.mean(np.abs(runs["standard_fp32"]["index"]
+                                                      - runs["standard_fp64"]["index"]) <= 1)),
+        "generalized fp32 vs fp64": float(np.mean(np.abs(runs["generalized_fp32"]["index"]
+                                                         - runs["generalized_fp64"]["index"])
+                                                  <= 1)),
+    }
+    for r in runs.values():
+        del r["index"]
+    in_grid = float(np.mean(w.p_rot_hours / 2.0 <= 2 * np.pi / w.f_min * 24.0))
+    out = {
+        "metric": "recovered rotation periods (within 0.1 h) on an asteroid-like population",
+        "value": runs["standard_fp32"]["matched"],
+        "unit": "fraction of objects",
+        "n_gpus": 1,
+        "steps": 3,
+        "warmup": 1,
+        "ms_per_step": runs["standard_fp32"]["ms_per_batch"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_obj": w.n_obj, "n_obs": int(w.n_obs), "n_f": w.n_f,
+                   "grid_rad_per_day": [w.f_min, w.f_max],
+                   "n_t": "log-normal, median %d, [%d, %d]" % (int(np.median(n_t)),
+                                                                int(n_t.min()), int(n_t.max())),
+                   "output": "peaks"},
+        "paper_context": "94.9% of ~1,000 synthetic asteroids within 0.1 h; 99% with >= 50 "
+                         "observations; 100% for the 45 objects with >= 550 (Section 4.2)",
+        "rotation_period_on_grid": in_grid,
+        "runs": runs,
+        "peak_agreement_within_one_bin": agree,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

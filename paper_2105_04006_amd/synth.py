@@ -46,6 +46,8 @@ WORKLOADS = {
     "batch_10k": (10_000, (50, 1000), (1.0, 12.0), 100_000, "sine", 3),
     "learned_100k": (100_000, (50, 500), (1.0, 12.0), 200_000, "sine", 4),
     "lsst_200k": (200_000, (20, 500), (0.5, 24.0), 250_000, "lsst", 5),
+    # grid in rad/day (the paper's batch range), see make_asteroids
+    "asteroids_1k": (1_000, (10, 1500), (1.005, 150.796), 200_000, "asteroid", 6),
 }
 
 KIND_SINE, KIND_TWO_HARMONIC, KIND_NOISE = 0, 1, 2
@@ -146,6 +148,8 @@ def make_workload(name: str, n_obj: int | None = None, seed: int | None = None,
     ``errors=True`` adds per-point photometric errors ``dy`` and draws each
     point's noise with its own error."""
     full_obj, (nt_lo, nt_hi), (f_min, f_max), n_f, mix, sid = WORKLOADS[name]
+    if mix == "asteroid":
+        return make_asteroids(name, n_obj, seed)
     seed = SEED_BASE + sid if seed is None else int(seed)
     k = full_obj if n_obj is None else int(n_obj)
     ss = np.random.SeedSequence(seed)
@@ -189,6 +193,83 @@ def make_workload(name: str, n_obj: int | None = None, seed: int | None = None,
     true_freq = np.where(kind == KIND_NOISE, np.nan, 1.0 / period)
     return Workload(name, offsets, t, y, float(f_min), float(f_max), int(n_f), 0, true_freq, kind,
                     seed, dy)
+
+
+# Asteroid-like population (Section 4.2's batch dataset: ~1,000 synthetic
+# asteroids with ZTF-like cadences and photometric errors, a log-normal number
+# of observations, rotation periods of a few hours to a few hundred hours).
+AST_SPAN_DAYS = 1095.0        # three observing years
+AST_NT_MEDIAN = 110.0         # log-normal N_t: median and log-sigma, clipped
+AST_NT_LOG_SIGMA = 0.9
+AST_PROT_MEDIAN_H = 8.0       # rotation periods: log-normal body (median, log-sigma) ...
+AST_PROT_LOG_SIGMA = 0.9
+AST_PROT_MIN_H = 2.0
+AST_SLOW = (0.03, 100.0, 400.0)  # ... and a slow-rotator tail: fraction, log-uniform range (h)
+AST_AMP = (0.1, 0.6)          # peak-to-peak light-curve amplitude, mag, log-uniform
+AST_ERR = (0.02, 0.15)        # per-object photometric error level, mag, log-uniform
+
+
+def make_asteroids(name: str, n_obj: int | None = None, seed: int | None = None) -> Workload:
+    """The asteroid-like population, errors included.
+
+    Cadence: each object is observed on nights drawn from the seasonal
+    calendar (the yearly 120-day gap) over three years, at an evening time
+    0.15-0.35 d into the night; half of the visits get a second exposure 30
+    minutes later, as in survey pair cadences.  Light curve: an elongated body
+    shows two maxima per rotation, so the dominant term is the second harmonic
+    of the rotation frequency (the light-curve period is half the rotation
+    period, which the periodogram finds), plus a weaker first harmonic; each
+    point gets Gaussian noise with its own error dy.  Rotation periods are
+    log-normal around 8 h (main-belt-like) with a 3% tail of slow rotators
+    (100-400 h, a few beyond the grid's 300 h).  true_freq is the light-curve
+    frequency in rad/day (the grid's unit).
+    """
+    full_obj, (nt_lo, nt_hi), (f_min, f_max), n_f, _, sid = WORKLOADS[name]
+    seed = SEED_BASE + sid if seed is None else int(seed)
+    k = full_obj if n_obj is None else int(n_obj)
+    ss = np.random.SeedSequence(seed)
+    r_len, r_par, r_t, r_noise, r_err = (np.random.Generator(np.random.PCG64(s))
+                                         for s in ss.spawn(5))
+    n_t = np.clip(np.round(AST_NT_MEDIAN * np.exp(AST_NT_LOG_SIGMA *
+                                                  r_len.standard_normal(full_obj))),
+                  nt_lo, nt_hi).astype(np.int64)[:k]
+    body = AST_PROT_MEDIAN_H * np.exp(AST_PROT_LOG_SIGMA * r_par.standard_normal(full_obj))
+    body = np.maximum(body, AST_PROT_MIN_H)
+    slow = np.exp(r_par.uniform(np.log(AST_SLOW[1]), np.log(AST_SLOW[2]), size=full_obj))
+    p_rot_h = np.where(r_par.random(full_obj) < AST_SLOW[0], slow, body)[:k]
+    amp = np.exp(r_par.uniform(np.log(AST_AMP[0]), np.log(AST_AMP[1]), size=full_obj))[:k]
+    phi1 = r_par.uniform(0.0, 2.0 * np.pi, size=full_obj)[:k]
+    phi2 = r_par.uniform(0.0, 2.0 * np.pi, size=full_obj)[:k]
+    asym = r_par.uniform(0.05, 0.3, size=full_obj)[:k]
+    err = np.exp(r_par.uniform(np.log(AST_ERR[0]), np.log(AST_ERR[1]), size=full_obj))[:k]
+
+    offsets = np.zeros(k + 1, dtype=np.int64)
+    np.cumsum(n_t, out=offsets[1:])
+    n_obs = int(offsets[-1])
+    owner = np.repeat(np.arange(k, dtype=np.int64), n_t)
+    # nights from the seasonal calendar, evening times, optional pair exposures
+    keep_total = (AST_SPAN_DAYS / YEAR_DAYS) * (YEAR_DAYS - (GAP[1] - GAP[0]))
+    u = r_t.random((n_obs, 3))  # one row per observation keeps prefixes identical
+    night = np.floor(seasonal_times(u[:, 0] * keep_total))
+    t = night + 0.15 + 0.2 * u[:, 1]
+    pair = u[:, 2] < 0.5
+    # a pair's second exposure follows the point before it in the same object
+    idx = np.arange(n_obs)
+    first = np.zeros(n_obs, dtype=bool)
+    first[offsets[:-1][n_t > 0]] = True
+    take = pair & ~first
+    t[take] = t[idx[take] - 1] + 30.0 / 1440.0
+    t = _sort_segments(t, offsets)
+
+    w_rot = 2.0 * np.pi * 24.0 / p_rot_h  # rad/day
+    y = (0.5 * amp[owner] * np.cos(2.0 * w_rot[owner] * t + phi2[owner])
+         + 0.5 * amp[owner] * asym[owner] * np.cos(w_rot[owner] * t + phi1[owner]))
+    dy = np.clip(err[owner] * 10.0 ** (0.15 * r_err.standard_normal(n_obs)), 0.005, 0.5)
+    y = y + dy * r_noise.standard_normal(n_obs)
+    w = Workload(name, offsets, t, y, float(f_min), float(f_max), int(n_f), 1, 2.0 * w_rot,
+                 np.zeros(k, dtype=np.int32), seed, dy)
+    w.p_rot_hours = p_rot_h
+    return w
 
 
 def pack(series) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

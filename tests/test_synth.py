@@ -42,3 +42,30 @@ def test_lsst_mixture_fractions():
     assert abs(frac[0] - 0.6) < 0.015 and abs(frac[1] - 0.3) < 0.015 and abs(frac[2] - 0.1) < 0.01
     assert np.all(np.isnan(w.true_freq[w.kind == synth.KIND_NOISE]))
     assert w.n_t.min() >= 20 and w.n_t.max() <= 500
+
+
+def test_asteroid_population():
+    w = synth.make_workload("asteroids_1k")
+    n_t = np.diff(w.offsets)
+    assert w.n_obj == 1000 and w.unit == 1 and w.dy is not None
+    # log-normal number of observations, clipped to [10, 1500]
+    assert n_t.min() >= 10 and n_t.max() <= 1500
+    assert 90 <= np.median(n_t) <= 130
+    assert 0.1 < np.mean(n_t < 50) < 0.3
+    # times sorted within objects, inside three seasonal years
+    for a, b in zip(w.offsets[:-1], w.offsets[1:]):
+        assert np.all(np.diff(w.t[a:b]) >= 0)
+    assert w.t.min() >= 0.0 and w.t.max() < synth.AST_SPAN_DAYS + 1.0
+    assert not np.any(synth.in_gap(w.t))
+    # survey pairs: a good share of points have a partner 30 minutes earlier
+    d = np.concatenate([np.diff(w.t[a:b]) for a, b in zip(w.offsets[:-1], w.offsets[1:])])
+    assert np.mean(np.abs(d - 30.0 / 1440.0) < 1e-9) > 0.2
+    assert np.all(w.dy > 0)
+    # light-curve frequency = twice the rotation frequency, in rad/day
+    assert np.allclose(w.true_freq, 2.0 * 2.0 * np.pi * 24.0 / w.p_rot_hours)
+    assert w.p_rot_hours.min() >= 2.0 and np.mean(w.p_rot_hours > 300.0) < 0.02
+    # the first k objects do not depend on how many are drawn
+    v = synth.make_workload("asteroids_1k", n_obj=77)
+    n = v.n_obs
+    assert np.array_equal(v.t, w.t[:n]) and np.array_equal(v.y, w.y[:n])
+    assert np.array_equal(v.dy, w.dy[:n]) and np.array_equal(v.p_rot_hours, w.p_rot_hours[:77])
