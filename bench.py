@@ -172,8 +172,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the periodogram of "
-              "independent objects would shard by object across GPUs, which this build does "
-              "not implement.", file=sys.stderr)
+              "independent objects would shard by object across GPUs, which is not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
