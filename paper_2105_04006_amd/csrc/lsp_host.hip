@@ -311,7 +311,11 @@ lsp_status lsp_pipe_create(int32_t n_streams, size_t staging_bytes, size_t chunk
             return LSP_EHIP;
         }
     }
-    p->pool = new (std::nothrow) lsp::CopyPool(copy_threads);
+    try {
+        p->pool = new lsp::CopyPool(copy_threads);
+    } catch (...) {  // thread creation or allocation failed
+        p->pool = nullptr;
+    }
     if (!p->pool) {
         destroy_pipe(p);
         return LSP_EHIP;
@@ -322,10 +326,11 @@ lsp_status lsp_pipe_create(int32_t n_streams, size_t staging_bytes, size_t chunk
 
 void lsp_pipe_destroy(lsp_pipe pipe) { destroy_pipe(pipe); }
 
-lsp_status lsp_batch_to_host(lsp_pipe pipe, const int64_t* offsets, int64_t n_obj, int64_t n_obs,
-                             const double* t, const double* y, const double* dy,
-                             int32_t generalized, const lsp_grid* grid, const lsp_options* opt_in,
-                             void* host_pgram, lsp_peak* host_peaks, void* stream) {
+static lsp_status batch_to_host(lsp_pipe pipe, const int64_t* offsets, int64_t n_obj,
+                                int64_t n_obs, const double* t, const double* y, const double* dy,
+                                int32_t generalized, const lsp_grid* grid,
+                                const lsp_options* opt_in, void* host_pgram, lsp_peak* host_peaks,
+                                void* stream) {
     if (!pipe || !offsets || !grid || n_obj < 1 || n_obs < 0) return LSP_EINVAL;
     if (!(generalized == 0 || generalized == 1)) return LSP_EINVAL;
     if (!generalized && dy) return LSP_EINVAL;
@@ -368,15 +373,26 @@ lsp_status lsp_batch_to_host(lsp_pipe pipe, const int64_t* offsets, int64_t n_ob
             hipStreamWaitEvent(pipe->lanes[i].copy, ready, 0) != hipSuccess)
             st = LSP_EHIP;
     if (st == LSP_OK) {
+        // No C++ exception may leave this C entry point: a lane that cannot
+        // allocate, or a driver thread that cannot start, reports LSP_EHIP.
         std::vector<lsp_status> res(pipe->n_streams, LSP_OK);
         std::vector<std::thread> drivers;
-        for (int i = 1; i < pipe->n_streams; ++i)
-            drivers.emplace_back([&, i] {
+        auto lane = [&](int i) {
+            try {
                 res[i] = run_lane(pipe, i, offsets, n_obj, n_obs, t, y, dy, gen, grid, &opt,
                                   bin_bytes, chunk, static_cast<char*>(host_pgram), host_peaks);
-            });
-        res[0] = run_lane(pipe, 0, offsets, n_obj, n_obs, t, y, dy, gen, grid, &opt, bin_bytes,
-                          chunk, static_cast<char*>(host_pgram), host_peaks);
+            } catch (...) {
+                res[i] = LSP_EHIP;
+            }
+        };
+        for (int i = 1; i < pipe->n_streams; ++i) {
+            try {
+                drivers.emplace_back(lane, i);
+            } catch (...) {
+                lane(i);  // no thread: run this lane's share here
+            }
+        }
+        lane(0);
         for (auto& d : drivers) d.join();
         for (int i = 0; i < pipe->n_streams; ++i) {
             if ((hipStreamSynchronize(pipe->lanes[i].stream) != hipSuccess ||
@@ -388,6 +404,18 @@ lsp_status lsp_batch_to_host(lsp_pipe pipe, const int64_t* offsets, int64_t n_ob
     }
     (void)hipEventDestroy(ready);
     return st;
+}
+
+lsp_status lsp_batch_to_host(lsp_pipe pipe, const int64_t* offsets, int64_t n_obj, int64_t n_obs,
+                             const double* t, const double* y, const double* dy,
+                             int32_t generalized, const lsp_grid* grid, const lsp_options* opt_in,
+                             void* host_pgram, lsp_peak* host_peaks, void* stream) {
+    try {
+        return batch_to_host(pipe, offsets, n_obj, n_obs, t, y, dy, generalized, grid, opt_in,
+                             host_pgram, host_peaks, stream);
+    } catch (...) {  // allocation failure before any thread started
+        return LSP_EHIP;
+    }
 }
 
 }  // extern "C"
