@@ -19,6 +19,7 @@ unnormalised power is half the reduction in chi^2.  The pins:
   - invariances: common scaling of the errors (normalised power unchanged,
     unnormalised scaled by 1/alpha^2), affine maps of y, shifts of t;
   - an observation listed twice weighs as one with error dy / sqrt(2);
+  - equal errors give the unit-error power (unnormalised: scaled by 1/dy^2);
   - three observations are fitted exactly by three parameters (power 1);
   - w = 0 leaves only the constant: power 0;
   - object statuses for short, constant and invalid input.
@@ -110,6 +111,18 @@ def pin_gen_invariances(ora):
     assert np.allclose(pn4, pn, rtol=1e-8, atol=1e-11)
 
 
+def pin_gen_equal_errors_are_unit_errors(ora):
+    # equal errors give equal weights: the normalised power is that of unit
+    # errors, and the unnormalised one scales by 1/dy^2
+    t, y, _ = _obj(61, 33)
+    a, _ = ora.gen_single(t, y, None, 0.02, 1.4, 27)
+    b, _ = ora.gen_single(t, y, np.full(33, 0.37), 0.02, 1.4, 27)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-14), np.abs(a - b).max()
+    au, _ = ora.gen_single(t, y, None, 0.02, 1.4, 27, normalize=False)
+    bu, _ = ora.gen_single(t, y, np.full(33, 0.37), 0.02, 1.4, 27, normalize=False)
+    assert np.allclose(bu * 0.37 ** 2, au, rtol=1e-12, atol=1e-14)
+
+
 def pin_gen_duplicate_is_weight(ora):
     t, y, dy = _obj(31, 25)
     j = 9
@@ -167,6 +180,7 @@ GEN_PINS = [
     pin_gen_sinusoid_with_offset,
     pin_gen_invariances,
     pin_gen_duplicate_is_weight,
+    pin_gen_equal_errors_are_unit_errors,
     pin_gen_three_points_exact,
     pin_gen_zero_frequency,
     pin_gen_statuses,

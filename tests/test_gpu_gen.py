@@ -255,3 +255,16 @@ def test_gen_batch_10k_full_size_sampled_objects(dev):
         assert pk["status"][o] == _oracle.OK
         assert peak_ok(ora_pg, ora_pk["index"], pk["index"][o], FP32_ATOL, 1), o
         assert abs(pk["power"][o] - ora_pg[pk["index"][o]]) <= FP32_ATOL, o
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_gen_wide_error_range(dev, form):
+    # errors spread over six decades (weights over twelve): the power is set
+    # by the best-measured points, which the rescaled FP32 weights must keep
+    rng = np.random.default_rng(47)
+    w = synth.make_workload("batch_10k", n_obj=10)
+    dy = 10.0 ** rng.uniform(-3.0, 3.0, w.n_obs)
+    ora_pg, ora_pk = oracle.gen_batch(w.offsets, w.t, w.y, dy, w.f_min, w.f_max, 1800)
+    pg, pk = gen_batch(dev, w.offsets, w.t, w.y, dy, w.f_min, w.f_max, 1800, form=form,
+                       pgram_dtype=lsp.PGRAM_F64)
+    check_rows(form, pg, pk, ora_pg, ora_pk, f"gen wide error range form={form}")
