@@ -115,16 +115,17 @@ def cpu_baseline(w, target_evals, threads, method="standard"):
         what = f"every {stride}th bin of the first {k} objects ({len(bins)} (object, bin) pairs"
     t0 = time.perf_counter()
     if method == "generalized":
-        oracle.gen_eval_bins(w.offsets, w.t, w.y, w.dy, w.f_min, w.f_max, w.n_f, objs, bins,
-                             threads=threads)
+        vals = oracle.gen_eval_bins(w.offsets, w.t, w.y, w.dy, w.f_min, w.f_max, w.n_f, objs,
+                                    bins, threads=threads)
     else:
-        oracle.eval_bins(w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, objs, bins,
-                         threads=threads)
+        vals = oracle.eval_bins(w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, objs, bins,
+                                threads=threads)
     dt = time.perf_counter() - t0
     n_t = np.diff(w.offsets)
     evals = int(n_t[objs].sum())
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what}, {evals:.3g} evals) of the same workload, {dt:.2f} s wall"}
+            "sample": f"{what}, {evals:.3g} evals) of the same workload, {dt:.2f} s wall"}, \
+        (objs, bins, vals)
 
 
 def main():
@@ -347,7 +348,24 @@ def main():
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         log(f"[bench] oracle baseline on {threads} threads")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_evals, threads, args.method)
+        out["cpu_baseline"], (objs, bins, ora_vals) = cpu_baseline(w, args.cpu_evals, threads,
+                                                                   args.method)
+        # the FP32 form's power at the same (object, bin) pairs, against the
+        # oracle: the bench line states its error against the FP64 oracle
+        if single:
+            got = p32.pgram[0][torch.as_tensor(bins, device=dev)].double().cpu().numpy()
+        else:
+            k = int(objs.max()) + 1
+            sub = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, offsets=off[:k + 1],
+                                  form=lsp.FORM_FP32P, schedule=sched, recurrence=rec, k=args.k,
+                                  waves=args.waves, method=kw.get("method", "standard"),
+                                  dy=kw.get("dy"), pgram=True, peaks=False, **kv)
+            sub()
+            flat = torch.as_tensor(objs * w.n_f + bins, device=dev)
+            got = sub.pgram.view(-1)[flat].double().cpu().numpy()
+        out["oracle_check"] = {"pairs": int(len(bins)),
+                               "max_abs_dpower_vs_oracle": float(np.max(np.abs(got - ora_vals))),
+                               "form": "fp32 (the timed form)"}
     print(json.dumps(out), flush=True)
 
 
