@@ -246,6 +246,25 @@ lsp_status lsp_gen_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, c
                          size_t workspace_bytes, void *stream);
 
 /*
+ * Row mode and plan capture of the generalized periodogram: lsp_batch_rows,
+ * lsp_rows_workspace_bytes and lsp_plan_create with errors dy (device, layout
+ * of y, or NULL for unit errors) after y, and the generalized method's
+ * option rules (see lsp_gen_batch).  Arguments, layouts and errors are
+ * otherwise those of the standard calls; plans are launched and destroyed
+ * with lsp_plan_launch / lsp_plan_destroy.
+ */
+size_t lsp_gen_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid *grid,
+                                    const lsp_options *opt, int64_t n_rows, int64_t band_bins,
+                                    int32_t rows_per_group);
+lsp_status lsp_gen_batch_rows(const int64_t *offsets, int64_t n_obj, int64_t n_obs,
+                              const double *t, const double *y, const double *dy,
+                              const lsp_grid *grid, const lsp_options *opt,
+                              const int32_t *row_obj, const int32_t *row_band, int64_t n_rows,
+                              int64_t band_bins, int32_t rows_per_group, void *pgram,
+                              lsp_peak *peaks, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/*
  * Returning whole periodograms to host memory (Section 3.5).  A pipe owns
  * n_streams lanes, each with a kernel and a copy HIP stream (default
  * priority), a pinned host staging buffer of staging_bytes and device buffers
@@ -347,6 +366,11 @@ lsp_status lsp_plan_create(const int64_t *offsets, int64_t n_obj, int64_t n_obs,
                            const double *y, const lsp_grid *grid, const lsp_options *opt,
                            void *pgram, lsp_peak *peaks, void *workspace, size_t workspace_bytes,
                            lsp_plan *plan);
+lsp_status lsp_gen_plan_create(const int64_t *offsets, int64_t n_obj, int64_t n_obs,
+                               const double *t, const double *y, const double *dy,
+                               const lsp_grid *grid, const lsp_options *opt, void *pgram,
+                               lsp_peak *peaks, void *workspace, size_t workspace_bytes,
+                               lsp_plan *plan);
 lsp_status lsp_plan_launch(lsp_plan plan, void *stream);
 void lsp_plan_destroy(lsp_plan plan);
 

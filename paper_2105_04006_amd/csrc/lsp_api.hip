@@ -503,9 +503,9 @@ size_t lsp_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
     return lsp::layout(n_obj, grid, rows, c).total;
 }
 
-size_t lsp_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
-                                const lsp_options* opt_in, int64_t n_rows, int64_t band_bins,
-                                int32_t rows_per_group) {
+static size_t rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                                   const lsp_options* opt_in, int64_t n_rows, int64_t band_bins,
+                                   int32_t rows_per_group, const lsp::Method& method) {
     if (n_obj < 1 || n_obs < 0 || !lsp::valid_grid(grid)) return 0;
     const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
     if (lsp::valid_options(&opt) != LSP_OK) return 0;
@@ -515,8 +515,24 @@ size_t lsp_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* gr
                          rows_per_group, false};
     if (lsp::valid_rows(rows, grid) != LSP_OK) return 0;
     lsp::Config c;
-    if (lsp::resolve(n_obj, n_obs, grid, &opt, rows, &c) != LSP_OK) return 0;
+    if (lsp::resolve(n_obj, n_obs, grid, &opt, rows, &c, method) != LSP_OK) return 0;
     return lsp::layout(n_obj, grid, rows, c).total;
+}
+
+size_t lsp_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                                const lsp_options* opt, int64_t n_rows, int64_t band_bins,
+                                int32_t rows_per_group) {
+    return rows_workspace_bytes(n_obj, n_obs, grid, opt, n_rows, band_bins, rows_per_group,
+                                lsp::Method{});
+}
+
+size_t lsp_gen_rows_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                                    const lsp_options* opt, int64_t n_rows, int64_t band_bins,
+                                    int32_t rows_per_group) {
+    lsp::Method method;
+    method.gen = true;
+    return rows_workspace_bytes(n_obj, n_obs, grid, opt, n_rows, band_bins, rows_per_group,
+                                method);
 }
 
 lsp_status lsp_single(const double* t, const double* y, int64_t n_t, const lsp_grid* grid,
@@ -571,24 +587,52 @@ lsp_status lsp_gen_batch(const int64_t* offsets, int64_t n_obj, int64_t n_obs, c
                     workspace_bytes, stream, lsp::whole_grid(n_obj, grid), method);
 }
 
+static lsp_status batch_rows(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
+                             const double* t, const double* y, const lsp_grid* grid,
+                             const lsp_options* opt, const int32_t* row_obj,
+                             const int32_t* row_band, int64_t n_rows, int64_t band_bins,
+                             int32_t rows_per_group, void* pgram, lsp_peak* peaks,
+                             void* workspace, size_t workspace_bytes, void* stream,
+                             const lsp::Method& method) {
+    if (!offsets) return LSP_EINVAL;
+    if (!row_obj && n_rows != n_obj * (int64_t)rows_per_group) return LSP_EINVAL;
+    if (!row_band) band_bins = grid ? grid->n_f : 0;
+    const lsp::Rows rows{row_obj, row_band, n_rows, band_bins, rows_per_group, false};
+    return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
+                    workspace_bytes, stream, rows, method);
+}
+
 lsp_status lsp_batch_rows(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
                           const double* y, const lsp_grid* grid, const lsp_options* opt,
                           const int32_t* row_obj, const int32_t* row_band, int64_t n_rows,
                           int64_t band_bins, int32_t rows_per_group, void* pgram,
                           lsp_peak* peaks, void* workspace, size_t workspace_bytes,
                           void* stream) {
-    if (!offsets) return LSP_EINVAL;
-    if (!row_obj && n_rows != n_obj * (int64_t)rows_per_group) return LSP_EINVAL;
-    if (!row_band) band_bins = grid ? grid->n_f : 0;
-    const lsp::Rows rows{row_obj, row_band, n_rows, band_bins, rows_per_group, false};
-    return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
-                    workspace_bytes, stream, rows);
+    return batch_rows(offsets, n_obj, n_obs, t, y, grid, opt, row_obj, row_band, n_rows,
+                      band_bins, rows_per_group, pgram, peaks, workspace, workspace_bytes,
+                      stream, lsp::Method{});
 }
 
-lsp_status lsp_plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
-                           const double* y, const lsp_grid* grid, const lsp_options* opt,
-                           void* pgram, lsp_peak* peaks, void* workspace, size_t workspace_bytes,
-                           lsp_plan* plan) {
+lsp_status lsp_gen_batch_rows(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
+                              const double* t, const double* y, const double* dy,
+                              const lsp_grid* grid, const lsp_options* opt,
+                              const int32_t* row_obj, const int32_t* row_band, int64_t n_rows,
+                              int64_t band_bins, int32_t rows_per_group, void* pgram,
+                              lsp_peak* peaks, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+    lsp::Method method;
+    method.gen = true;
+    method.dy = dy;
+    return batch_rows(offsets, n_obj, n_obs, t, y, grid, opt, row_obj, row_band, n_rows,
+                      band_bins, rows_per_group, pgram, peaks, workspace, workspace_bytes,
+                      stream, method);
+}
+
+static lsp_status plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
+                              const double* t, const double* y, const lsp_grid* grid,
+                              const lsp_options* opt, void* pgram, lsp_peak* peaks,
+                              void* workspace, size_t workspace_bytes, lsp_plan* plan,
+                              const lsp::Method& method) {
     if (!plan) return LSP_EINVAL;
     *plan = nullptr;
     if (!offsets && n_obj != 1) return LSP_EINVAL;
@@ -596,7 +640,8 @@ lsp_status lsp_plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
     // half-open capture behind.
     {
         lsp_status st = lsp::validate(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks,
-                                      workspace, workspace_bytes, lsp::whole_grid(n_obj, grid));
+                                      workspace, workspace_bytes, lsp::whole_grid(n_obj, grid),
+                                      method);
         if (st != LSP_OK) return st;
     }
     hipStream_t cs = nullptr;
@@ -607,7 +652,7 @@ lsp_status lsp_plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
         st = LSP_EHIP;
     } else {
         st = lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
-                      workspace_bytes, cs, lsp::whole_grid(n_obj, grid));
+                      workspace_bytes, cs, lsp::whole_grid(n_obj, grid), method);
         if (hipStreamEndCapture(cs, &graph) != hipSuccess && st == LSP_OK) st = LSP_EHIP;
     }
     (void)hipStreamDestroy(cs);
@@ -628,6 +673,26 @@ lsp_status lsp_plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
     }
     *plan = p;
     return LSP_OK;
+}
+
+lsp_status lsp_plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const double* t,
+                           const double* y, const lsp_grid* grid, const lsp_options* opt,
+                           void* pgram, lsp_peak* peaks, void* workspace, size_t workspace_bytes,
+                           lsp_plan* plan) {
+    return plan_create(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
+                       workspace_bytes, plan, lsp::Method{});
+}
+
+lsp_status lsp_gen_plan_create(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
+                               const double* t, const double* y, const double* dy,
+                               const lsp_grid* grid, const lsp_options* opt, void* pgram,
+                               lsp_peak* peaks, void* workspace, size_t workspace_bytes,
+                               lsp_plan* plan) {
+    lsp::Method method;
+    method.gen = true;
+    method.dy = dy;
+    return plan_create(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
+                       workspace_bytes, plan, method);
 }
 
 lsp_status lsp_plan_launch(lsp_plan plan, void* stream) {

@@ -104,6 +104,18 @@ def lib():
         L.lsp_batch_to_host.restype = ctypes.c_int
         L.lsp_batch_to_host.argtypes = [vp, vp, i64, i64, vp, vp, vp, i32, ctypes.POINTER(Grid),
                                         ctypes.POINTER(Options), vp, vp, vp]
+        L.lsp_gen_rows_workspace_bytes.restype = sz
+        L.lsp_gen_rows_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
+                                                   ctypes.POINTER(Options), i64, i64,
+                                                   ctypes.c_int32]
+        L.lsp_gen_batch_rows.restype = ctypes.c_int
+        L.lsp_gen_batch_rows.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(Grid),
+                                         ctypes.POINTER(Options), vp, vp, i64, i64,
+                                         ctypes.c_int32, vp, vp, vp, sz, vp]
+        L.lsp_gen_plan_create.restype = ctypes.c_int
+        L.lsp_gen_plan_create.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(Grid),
+                                          ctypes.POINTER(Options), vp, vp, vp, sz,
+                                          ctypes.POINTER(vp)]
         L.lsp_rows_workspace_bytes.restype = sz
         L.lsp_rows_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
                                                ctypes.POINTER(Options), i64, i64, ctypes.c_int32]
@@ -329,9 +341,8 @@ class Periodogram:
         return self
 
     def capture(self):
-        """Record this call into a HIP graph (lsp_plan_create); returns a Plan."""
-        if self.gen:
-            raise NotImplementedError("plans capture the standard periodogram only")
+        """Record this call into a HIP graph (lsp_plan_create or
+        lsp_gen_plan_create); returns a Plan."""
         return Plan(self)
 
     def peaks(self):
@@ -406,11 +417,19 @@ class Plan:
     def __init__(self, call):
         self.call = call
         h = ctypes.c_void_p()
-        st = lib().lsp_plan_create(_dev_ptr(call.offsets), call.n_obj, call.n_obs,
-                                   _dev_ptr(call.t), _dev_ptr(call.y), ctypes.byref(call.grid),
-                                   ctypes.byref(call.opt), _dev_ptr(call.pgram),
-                                   _dev_ptr(call.peaks_raw), _dev_ptr(call.workspace),
-                                   call.workspace.numel(), ctypes.byref(h))
+        if getattr(call, "gen", False):
+            st = lib().lsp_gen_plan_create(_dev_ptr(call.offsets), call.n_obj, call.n_obs,
+                                           _dev_ptr(call.t), _dev_ptr(call.y), _dev_ptr(call.dy),
+                                           ctypes.byref(call.grid), ctypes.byref(call.opt),
+                                           _dev_ptr(call.pgram), _dev_ptr(call.peaks_raw),
+                                           _dev_ptr(call.workspace), call.workspace.numel(),
+                                           ctypes.byref(h))
+        else:
+            st = lib().lsp_plan_create(_dev_ptr(call.offsets), call.n_obj, call.n_obs,
+                                       _dev_ptr(call.t), _dev_ptr(call.y), ctypes.byref(call.grid),
+                                       ctypes.byref(call.opt), _dev_ptr(call.pgram),
+                                       _dev_ptr(call.peaks_raw), _dev_ptr(call.workspace),
+                                       call.workspace.numel(), ctypes.byref(h))
         if st != OK:
             raise LspError(st, "lsp_plan_create")
         self.handle = h
@@ -442,7 +461,8 @@ class Rows:
     def __init__(self, offsets, t, y, f_min, f_max, n_f, row_obj, row_band=None, band_bins=0,
                  rows_per_group=1, unit=CYCLES, form=FORM_FP32P, normalize=True,
                  subtract_mean=True, pgram=None, pgram_dtype=PGRAM_F32, peaks=None, k=0,
-                 waves=0, schedule=SCHED_AUTO, recurrence=REC_AUTO, max_rows=None):
+                 waves=0, schedule=SCHED_AUTO, recurrence=REC_AUTO, max_rows=None,
+                 method="standard", dy=None):
         for x, dt, nm in ((t, torch.float64, "t"), (y, torch.float64, "y"),
                           (offsets, torch.int64, "offsets")):
             _check(x, dt, nm)
@@ -452,6 +472,14 @@ class Rows:
             _check(row_band, torch.int32, "row_band")
         if row_obj is None and row_band is None:
             raise ValueError("row mode needs row_obj, row_band or both")
+        if method not in ("standard", "generalized"):
+            raise ValueError(f"unknown method {method!r}")
+        self.gen = method == "generalized"
+        if dy is not None:
+            if not self.gen:
+                raise ValueError("errors dy are used by the generalized method only")
+            _check(dy, torch.float64, "dy")
+        self.dy = dy
         self.t, self.y, self.offsets = t, y, offsets
         self.n_obs = int(t.numel())
         self.n_obj = int(offsets.numel()) - 1
@@ -462,9 +490,9 @@ class Rows:
         self.rows_per_group = int(rows_per_group)
         named = row_obj if row_obj is not None else row_band
         cap = int(max_rows if max_rows is not None else named.numel())
-        nb = int(lib().lsp_rows_workspace_bytes(self.n_obj, self.n_obs, ctypes.byref(self.grid),
-                                                ctypes.byref(self.opt), max(cap, 1),
-                                                self.band_bins, self.rows_per_group))
+        size_fn = lib().lsp_gen_rows_workspace_bytes if self.gen else lib().lsp_rows_workspace_bytes
+        nb = int(size_fn(self.n_obj, self.n_obs, ctypes.byref(self.grid), ctypes.byref(self.opt),
+                         max(cap, 1), self.band_bins, self.rows_per_group))
         if nb == 0:
             raise LspError(EINVAL, "lsp_rows_workspace_bytes")
         self.workspace = torch.empty(nb, dtype=torch.uint8, device=t.device)
@@ -485,15 +513,25 @@ class Rows:
     def __call__(self, stream=None):
         if self.n_rows == 0:
             return self
-        st = lib().lsp_batch_rows(_dev_ptr(self.offsets), self.n_obj, self.n_obs,
-                                  _dev_ptr(self.t), _dev_ptr(self.y), ctypes.byref(self.grid),
-                                  ctypes.byref(self.opt), _dev_ptr(self.row_obj),
-                                  _dev_ptr(self.row_band), self.n_rows, self.band_bins,
-                                  self.rows_per_group, _dev_ptr(self.pgram),
-                                  _dev_ptr(self.peaks_raw), _dev_ptr(self.workspace),
-                                  self.workspace.numel(), _stream_handle(stream))
+        if self.gen:
+            st = lib().lsp_gen_batch_rows(_dev_ptr(self.offsets), self.n_obj, self.n_obs,
+                                          _dev_ptr(self.t), _dev_ptr(self.y), _dev_ptr(self.dy),
+                                          ctypes.byref(self.grid), ctypes.byref(self.opt),
+                                          _dev_ptr(self.row_obj), _dev_ptr(self.row_band),
+                                          self.n_rows, self.band_bins, self.rows_per_group,
+                                          _dev_ptr(self.pgram), _dev_ptr(self.peaks_raw),
+                                          _dev_ptr(self.workspace), self.workspace.numel(),
+                                          _stream_handle(stream))
+        else:
+            st = lib().lsp_batch_rows(_dev_ptr(self.offsets), self.n_obj, self.n_obs,
+                                      _dev_ptr(self.t), _dev_ptr(self.y), ctypes.byref(self.grid),
+                                      ctypes.byref(self.opt), _dev_ptr(self.row_obj),
+                                      _dev_ptr(self.row_band), self.n_rows, self.band_bins,
+                                      self.rows_per_group, _dev_ptr(self.pgram),
+                                      _dev_ptr(self.peaks_raw), _dev_ptr(self.workspace),
+                                      self.workspace.numel(), _stream_handle(stream))
         if st != OK:
-            raise LspError(st, "lsp_batch_rows")
+            raise LspError(st, "lsp_gen_batch_rows" if self.gen else "lsp_batch_rows")
         return self
 
     def peaks(self):

@@ -322,3 +322,24 @@ def test_variant_options():
     assert lsp.gen_workspace_bytes(10, 5000, g, ok) == 0
     for kw in (dict(obs_read=3), dict(obs_read=-1), dict(seed_trig=4)):
         assert lsp.workspace_bytes(10, 5000, g, lsp.make_options(form=lsp.FORM_FP32P, **kw)) == 0
+
+
+@cpu_only
+def test_gen_rows_and_plan_argument_errors(L):
+    g = lsp.make_grid(1.0, 2.0, 100)
+    o = lsp.make_options(form=lsp.FORM_FP32P)
+    assert L.lsp_gen_batch_rows(None, 3, 30, FAKE, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o),
+                                FAKE, FAKE, 8, 10, 4, FAKE, FAKE, FAKE, 1 << 30, None) == lsp.EINVAL
+    assert L.lsp_gen_batch_rows(FAKE, 3, 30, FAKE, FAKE, FAKE, ctypes.byref(g), ctypes.byref(o),
+                                FAKE, FAKE, 8, 10, 3, FAKE, FAKE, FAKE, 1 << 30, None) == lsp.EINVAL
+    rot = lsp.make_options(form=lsp.FORM_FP32P, recurrence=lsp.REC_ROTATION)
+    assert L.lsp_gen_batch_rows(FAKE, 3, 30, FAKE, FAKE, None, ctypes.byref(g),
+                                ctypes.byref(rot), FAKE, FAKE, 8, 10, 4, FAKE, FAKE, FAKE,
+                                1 << 30, None) == lsp.EUNSUPPORTED
+    assert L.lsp_gen_rows_workspace_bytes(3, 30, ctypes.byref(g), ctypes.byref(o), 8, 10, 4) > 0
+    assert L.lsp_gen_rows_workspace_bytes(3, 30, ctypes.byref(g), ctypes.byref(rot), 8, 10, 4) == 0
+    h = ctypes.c_void_p()
+    assert L.lsp_gen_plan_create(FAKE, 3, 30, FAKE, FAKE, None, ctypes.byref(g), ctypes.byref(o),
+                                 FAKE, FAKE, FAKE, 1 << 30, None) == lsp.EINVAL
+    assert L.lsp_gen_plan_create(FAKE, 3, 30, FAKE, FAKE, None, ctypes.byref(g), ctypes.byref(o),
+                                 FAKE, FAKE, FAKE, 1, ctypes.byref(h)) == lsp.ENOMEM

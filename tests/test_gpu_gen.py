@@ -268,3 +268,65 @@ def test_gen_wide_error_range(dev, form):
     pg, pk = gen_batch(dev, w.offsets, w.t, w.y, dy, w.f_min, w.f_max, 1800, form=form,
                        pgram_dtype=lsp.PGRAM_F64)
     check_rows(form, pg, pk, ora_pg, ora_pk, f"gen wide error range form={form}")
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_gen_rows(dev, form):
+    # row mode of the generalized periodogram: whole-grid rows equal
+    # lsp_gen_batch bit for bit; banded rows match the oracle on their bins
+    w = synth.make_workload("batch_10k", n_obj=9, errors=True)
+    n_f, bb = 2000, 250
+    ref, rk = gen_batch(dev, w.offsets, w.t, w.y, w.dy, w.f_min, w.f_max, n_f, form=form,
+                        pgram_dtype=lsp.PGRAM_F64)
+    args = (cuda(w.offsets, dev, torch.int64), cuda(w.t, dev), cuda(w.y, dev), w.f_min, w.f_max,
+            n_f)
+    pg = torch.full((w.n_obj, n_f), -7.0, dtype=torch.float64, device=dev)
+    r = lsp.Rows(*args, row_obj=torch.arange(w.n_obj, dtype=torch.int32, device=dev),
+                 form=form, pgram=pg, pgram_dtype=lsp.PGRAM_F64, method="generalized",
+                 dy=cuda(w.dy, dev))
+    r()
+    torch.cuda.synchronize()
+    assert np.array_equal(pg.cpu().numpy(), ref)
+    assert np.array_equal(r.peaks()["index"], rk["index"])
+    ora_pg, _ = oracle.gen_batch(w.offsets, w.t, w.y, w.dy, w.f_min, w.f_max, n_f)
+    row_obj = torch.tensor([2, 2, 5, 5, 7, 7], dtype=torch.int32, device=dev)
+    row_band = torch.tensor([0, 3, 7, 1, 4, 6], dtype=torch.int32, device=dev)
+    pg2 = torch.full((w.n_obj, n_f), -7.0, dtype=torch.float64, device=dev)
+    r2 = lsp.Rows(*args, row_obj=row_obj, row_band=row_band, band_bins=bb, rows_per_group=2,
+                  form=form, pgram=pg2, pgram_dtype=lsp.PGRAM_F64, method="generalized",
+                  dy=cuda(w.dy, dev))
+    r2()
+    torch.cuda.synchronize()
+    got = pg2.cpu().numpy()
+    for o, b in zip(row_obj.tolist(), row_band.tolist()):
+        sl = slice(b * bb, (b + 1) * bb)
+        if form == lsp.FORM_FP64:
+            assert_fp64_close(got[o, sl], ora_pg[o, sl], f"gen rows object {o} band {b}")
+        else:
+            assert_fp32_close(got[o, sl], ora_pg[o, sl], f"gen rows object {o} band {b}")
+    untouched = np.ones((w.n_obj, n_f), dtype=bool)
+    for o, b in zip(row_obj.tolist(), row_band.tolist()):
+        untouched[o, b * bb:(b + 1) * bb] = False
+    assert np.all(got[untouched] == -7.0)
+
+
+def test_gen_plan_replays(dev):
+    # a generalized call captured once as a HIP graph: every replay, with eager
+    # work in between, reproduces the eager result bit for bit
+    w = synth.make_workload("batch_10k", n_obj=16, errors=True)
+    p = lsp.Periodogram(cuda(w.t, dev), cuda(w.y, dev), w.f_min, w.f_max, 3000,
+                        offsets=cuda(w.offsets, dev, torch.int64), form=lsp.FORM_FP32P,
+                        method="generalized", dy=cuda(w.dy, dev))
+    p()
+    torch.cuda.synchronize()
+    eager, ek = p.pgram.clone(), p.peaks()
+    plan = p.capture()
+    for i in range(3):
+        p.pgram.fill_(-1.0)
+        torch.cuda.synchronize()
+        plan()
+        torch.cuda.synchronize()
+        assert torch.equal(p.pgram, eager), f"replay {i}"
+        assert np.array_equal(p.peaks()["index"], ek["index"])
+        p()  # eager call between replays
+        torch.cuda.synchronize()
