@@ -567,13 +567,19 @@ def bench_learned(args, torch, dev):
     (same peaks, every bin) and the plain FP64 form."""
     from paper_2105_04006_amd import learned, lsp, synth
 
+    gen = args.method == "generalized"
+    method = "generalized" if gen else "standard"
+
     def tens(w):
         return (torch.as_tensor(w.offsets, device=dev), torch.as_tensor(w.t, device=dev),
                 torch.as_tensor(w.y, device=dev))
 
+    def errs(w):
+        return torch.as_tensor(w.dy, device=dev) if gen else None
+
     def full(w, tt, form=lsp.FORM_FP32P):
         return lsp.Periodogram(tt[1], tt[2], w.f_min, w.f_max, w.n_f, offsets=tt[0], form=form,
-                               pgram=False)
+                               pgram=False, unit=w.unit, method=method, dy=errs(w))
 
     def timed(fn, steps):
         torch.cuda.synchronize()
@@ -584,13 +590,19 @@ def bench_learned(args, torch, dev):
         return (time.perf_counter() - t0) * 1e3 / steps
 
     name = args.workload
-    w = synth.make_workload(name)
+    w = synth.make_workload(name, errors=gen) if name != "asteroids_100k" else \
+        synth.make_workload(name)
     geo = learned.BandGeometry(w.n_f, 64)
     log(f"[bench] learned: n_obj={w.n_obj} n_obs={w.n_obs} n_f={w.n_f} "
         f"bands of {geo.band_bins}")
-    wtr = synth.make_workload(name, n_obj=40000, seed=synth.SEED_BASE + 1000)
+    def make(n_obj, seed):
+        if name.startswith("asteroids"):
+            return synth.make_workload(name, n_obj=n_obj, seed=seed)
+        return synth.make_workload(name, n_obj=n_obj, seed=seed, errors=gen)
+
+    wtr = make(40000, synth.SEED_BASE + 1000)
     ttr = tens(wtr)
-    feats = lsp.Features(*ttr, wtr.f_min, wtr.f_max)()
+    feats = lsp.Features(*ttr, wtr.f_min, wtr.f_max, unit=wtr.unit)()
     ptr = full(wtr, ttr)
     ptr()
     labels = learned.peak_bands(ptr.peaks_raw, wtr.n_obj, geo.band_bins, geo.n_bands)
@@ -601,9 +613,10 @@ def bench_learned(args, torch, dev):
     log(f"[bench] trained in {time.perf_counter() - t0:.1f} s, loss {hist[0]:.3f} -> "
         f"{hist[-1]:.3f}")
     del feats, ptr, ttr
-    wva = synth.make_workload(name, n_obj=20000, seed=synth.SEED_BASE + 1001)
+    wva = make(20000, synth.SEED_BASE + 1001)
     tva = tens(wva)
-    lpv = learned.LearnedPeriodogram(net, geo, *tva, wva.f_min, wva.f_max)
+    lpv = learned.LearnedPeriodogram(net, geo, *tva, wva.f_min, wva.f_max, unit=wva.unit,
+                                     method=method, dy=errs(wva))
     lpv.refine_only()
     pva = full(wva, tva)
     pva()
@@ -615,7 +628,7 @@ def bench_learned(args, torch, dev):
 
     tt = tens(w)
     lp = learned.LearnedPeriodogram(net, geo, *tt, w.f_min, w.f_max, mass_min=mass_min,
-                                    power_min=power_min)
+                                    power_min=power_min, unit=w.unit, method=method, dy=errs(w))
     p32 = full(w, tt)
     p64 = full(w, tt, lsp.FORM_FP64)
     for _ in range(max(1, args.warmup)):
@@ -674,10 +687,11 @@ def bench_learned(args, torch, dev):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": w.name, "n_obj": w.n_obj,
-                   "n_t": "U{%d..%d}" % (int(np.diff(w.offsets).min()), int(np.diff(w.offsets).max())),
-                   "n_obs": int(w.n_obs), "n_f": w.n_f, "f_range_cycles_per_day": [w.f_min, w.f_max],
+                   "n_t": "%d..%d" % (int(np.diff(w.offsets).min()), int(np.diff(w.offsets).max())),
+                   "n_obs": int(w.n_obs), "n_f": w.n_f, "f_range": [w.f_min, w.f_max],
+                   "unit": "rad/day" if w.unit == 1 else "cycles/day",
                    "bands": geo.n_bands, "band_bins": geo.band_bins, "top": lp.top,
-                   "network": "1088-512-256-64 BF16 MFMA", "output": "peaks"},
+                   "network": "1088-512-256-64 BF16 MFMA", "output": "peaks", "method": method},
         "objects_per_s": w.n_obj / (ms_l * 1e-3),
         "whole_grid_fp32": {"ms_per_step": ms_32, "objects_per_s": w.n_obj / (ms_32 * 1e-3),
                             "evals_per_s": evals / (ms_32 * 1e-3)},

@@ -268,10 +268,13 @@ class LearnedPeriodogram:
     below mass_min) or whose refined peak is weak (power below power_min) are
     re-run on the whole grid.  Every step is a library kernel; the host only
     reads the number of fallback objects to size the last launch.
+    ``method="generalized"`` refines (and falls back) with the generalized
+    periodogram and errors ``dy`` (Section 4.11); the features are the same.
     """
 
     def __init__(self, net, geometry, offsets, t, y, f_min, f_max, unit=lsp.CYCLES, top=8,
-                 mass_min=0.0, power_min=0.0, k=0, waves=0, proposal="hybrid", top_net=4):
+                 mass_min=0.0, power_min=0.0, k=0, waves=0, proposal="hybrid", top_net=4,
+                 method="standard", dy=None):
         if proposal not in ("network", "coarse", "hybrid"):
             raise ValueError("proposal must be 'network', 'coarse' or 'hybrid'")
         self.net, self.geo, self.top = net, geometry, int(top)
@@ -295,10 +298,11 @@ class LearnedPeriodogram:
         self.count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.refine = lsp.Rows(offsets, t, y, f_min, f_max, geometry.n_f, None,
                                self.idx.view(-1), geometry.band_bins, self.top, unit=unit,
-                               form=lsp.FORM_FP32P, peaks=self.peaks_raw, k=k, waves=waves)
+                               form=lsp.FORM_FP32P, peaks=self.peaks_raw, k=k, waves=waves,
+                               method=method, dy=dy)
         self.full = lsp.Rows(offsets, t, y, f_min, f_max, geometry.n_f, self.objects, None, 0, 1,
                              unit=unit, form=lsp.FORM_FP32P, peaks=self.peaks_raw, k=k,
-                             waves=waves, max_rows=self.n_obj)
+                             waves=waves, max_rows=self.n_obj, method=method, dy=dy)
         self.n_fallback = 0
 
     def propose(self, stream=None):

@@ -48,6 +48,7 @@ WORKLOADS = {
     "lsst_200k": (200_000, (20, 500), (0.5, 24.0), 250_000, "lsst", 5),
     # grid in rad/day (the paper's batch range), see make_asteroids
     "asteroids_1k": (1_000, (10, 1500), (1.005, 150.796), 200_000, "asteroid", 6),
+    "asteroids_100k": (100_000, (10, 1500), (1.005, 150.796), 200_000, "asteroid", 7),
 }
 
 KIND_SINE, KIND_TWO_HARMONIC, KIND_NOISE = 0, 1, 2
