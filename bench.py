@@ -674,6 +674,43 @@ def bench_learned(args, torch, dev):
         return float(np.mean((idx.cpu().numpy() == band[:, None]).any(axis=1)[ok]))
 
     hit_used, hit_net = hit(lp.idx), hit(net8)
+    # diagnostic: coverage if part of the refined bands were the one-day
+    # aliases (f +- 1 cycle/day) of the first proposals
+    alias_bins = (2 * np.pi if w.unit == 1 else 1.0) / ((w.f_max - w.f_min) / w.n_f)
+    used = lp.idx.cpu().numpy().astype(np.int64)
+
+    def alias_cover(n_first, n_alias):
+        first = used[:, :n_first]
+        cand = [first]
+        centre = (first[:, :n_alias] + 0.5) * geo.band_bins
+        for sgn in (-1, 1):
+            a = np.floor((centre + sgn * alias_bins) / geo.band_bins).astype(np.int64)
+            cand.append(np.where((a >= 0) & (a < geo.n_bands), a, -1))
+        c = np.concatenate(cand, axis=1)
+        return float(np.mean((c == band[:, None]).any(axis=1)[ok]))
+
+    def expand_cover(n_first, n_exp, fn):
+        first = used[:, :n_first]
+        cand = [first]
+        for g in fn:
+            a = g(first[:, :n_exp])
+            cand.append(np.where((a >= 0) & (a < geo.n_bands), a, -1))
+        c = np.concatenate(cand, axis=1)
+        return float(np.mean((c == band[:, None]).any(axis=1)[ok]))
+
+    def fband(b, scale):  # band holding scale x the frequency at band b's centre
+        f = w.f_min + (b + 0.5) * geo.band_bins * (w.f_max - w.f_min) / w.n_f
+        return np.floor((scale * f - w.f_min) / (w.f_max - w.f_min) * w.n_f
+                        / geo.band_bins).astype(np.int64)
+
+    alias_hits = {"top4+aliases_of_top2": alias_cover(4, 2), "top6+aliases_of_top1": alias_cover(6, 1),
+                  "top2+aliases_of_top2": alias_cover(2, 2), "top8": alias_cover(8, 0),
+                  "top4+neighbours_of_top2": expand_cover(4, 2, (lambda b: b - 1, lambda b: b + 1)),
+                  "top4+half_double_of_top2": expand_cover(4, 2, (lambda b: fband(b, 0.5),
+                                                                  lambda b: fband(b, 2.0))),
+                  "top16": float(np.mean((np.argsort(-lp.logits.float().cpu().numpy(), axis=1)
+                                          [:, :16] == band[:, None]).any(axis=1)[ok]))}
+    log(f"[bench] alias coverage {alias_hits}")
     hit_heur = hit(lp.idx_coarse) if lp.proposal == "hybrid" else None
     refine_only = lp.peaks()
     rec_refine = float(np.mean(np.abs(refine_only["index"][ok] - ref32["index"][ok]) <= 1))
@@ -702,6 +739,7 @@ def bench_learned(args, torch, dev):
         "peak_bin_agreement": rec32, "peak_bin_agreement_vs_fp64": rec64,
         "peak_bin_agreement_refine_only": rec_refine,
         "proposal": lp.proposal, "top_network": lp.top_net,
+        "alias_coverage_diagnostic": alias_hits,
         "proposal_hit_rate": {"used": hit_used, "network_top8": hit_net,
                               "coarse_power_top8": hit_heur},
         "thresholds": {"mass_min": mass_min, "power_min": power_min},
