@@ -1,0 +1,56 @@
+"""Host-side parts of bench.py that need no GPU: the multi-GPU refusal, the
+recovery curve, the traffic record's validity rules and the instruction
+models used for the roofline's issue fraction."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_recovery_curve():
+    p_rot = np.array([10.0, 20.0, 30.0, 40.0])
+    p_lc_days = np.array([5.0, 10.04, 15.2, 20.0]) / 24.0  # doubled: 10, 20.08, 30.4, 40 h
+    n_t = np.array([10, 60, 200, 600])
+    frac, curve, ok = bench.recovery_curve(p_rot, p_lc_days, n_t)
+    assert list(ok) == [True, True, False, True]
+    assert frac == 0.75
+    by = {c["cutoff"]: c for c in curve}
+    assert by[0]["objects"] == 4 and by[50]["objects"] == 3 and by[550]["objects"] == 1
+    assert abs(by[50]["matched"] - 2 / 3) < 1e-12 and by[550]["matched"] == 1.0
+
+
+def test_traffic_record_rules(tmp_path, monkeypatch):
+    rec = {"kernel_hash": bench.kernel_hash("standard"), "workload_name": "single_4096",
+           "bytes_per_launch": 123}
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps(rec))
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "standard", str(f))
+    assert bench.measured_traffic("standard", "single_4096") == 123
+    assert bench.measured_traffic("standard", "batch_10k") is None  # other workload
+    rec["kernel_hash"] = "0" * 16  # taken on another kernel source
+    f.write_text(json.dumps(rec))
+    assert bench.measured_traffic("standard", "single_4096") is None
+
+
+def test_instruction_models():
+    # the K = 16 loop models: 106 instructions per observation and lane for
+    # the standard form (6.625 per evaluation; SQ_INSTS_VALU reads 6.72 with
+    # the loop overhead) and 140 for the generalized one (8.75; reads 8.88)
+    assert abs(bench.valu_ops_per_eval("chebyshev", 16) - 106 / 16) < 1e-12
+    assert abs(bench.valu_ops_per_eval_gen(16) - 140 / 16) < 1e-12
+    assert bench.FLOPS_PER_EVAL["chebyshev"] == 12 and bench.FLOPS_PER_EVAL_GEN == 16
+    assert abs(bench.PEAK_FP32_TFLOPS - 157.3) < 0.1
