@@ -66,6 +66,7 @@ KERNEL_SOURCES = {
 TRAFFIC_FILES = {
     "standard": os.path.join(ROOT, "profiles", "fp32p_single_4096_traffic.json"),
     "generalized": os.path.join(ROOT, "profiles", "gen_fp32p_single_4096_traffic.json"),
+    ("standard", "batch_10k"): os.path.join(ROOT, "profiles", "fp32p_batch_10k_traffic.json"),
 }
 
 
@@ -84,8 +85,9 @@ def kernel_hash(method="standard"):
 def measured_traffic(method="standard", workload="single_4096"):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
     were taken on the current kernel source and this workload."""
+    path = TRAFFIC_FILES.get((method, workload), TRAFFIC_FILES[method])
     try:
-        with open(TRAFFIC_FILES[method]) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
