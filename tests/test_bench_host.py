@@ -40,7 +40,10 @@ def test_traffic_record_rules(tmp_path, monkeypatch):
     f.write_text(json.dumps(rec))
     monkeypatch.setitem(bench.TRAFFIC_FILES, "standard", str(f))
     assert bench.measured_traffic("standard", "single_4096") == 123
-    assert bench.measured_traffic("standard", "batch_10k") is None  # other workload
+    assert bench.measured_traffic("standard", "lsst_200k") is None  # other workload
+    # a workload with a record of its own reads that record
+    assert bench.measured_traffic("standard", "batch_10k") == \
+        json.load(open(bench.TRAFFIC_FILES[("standard", "batch_10k")]))["bytes_per_launch"]
     rec["kernel_hash"] = "0" * 16  # taken on another kernel source
     f.write_text(json.dumps(rec))
     assert bench.measured_traffic("standard", "single_4096") is None
