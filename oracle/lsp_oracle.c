@@ -27,8 +27,9 @@
  *   - an object with a non-finite time or magnitude is NONFINITE and a CSR range
  *     that is negative, reversed or past the end is BADRANGE: power NaN, index -1.
  *
- * Sums use Neumaier's compensated summation so that the oracle is the more
- * accurate side of every comparison.  Compile with -ffp-contract=off and no
+ * Sums use Neumaier's compensated summation and every angle w (t - tau) is
+ * formed and reduced modulo 2 pi in long double before the double sin and cos,
+ * so that the oracle is the more accurate side of every comparison.  Compile with -ffp-contract=off and no
  * fast-math: every operation is the one written.
  *
  * Parallelism follows the paper's CPU port (Section 4.5): a static split over
@@ -51,6 +52,7 @@
 #define ORA_UNIT_ANGULAR 1
 
 static const double ORA_TWO_PI = 6.283185307179586476925286766559;
+static const long double ORA_TWO_PI_L = 6.283185307179586476925286766559L;
 
 typedef struct {
     int64_t index;
@@ -100,6 +102,31 @@ double ora_period(double f, int32_t unit)
     return ORA_TWO_PI / ora_omega(f, unit);
 }
 
+/* Angular frequency in long double (exact for the angular unit). */
+static long double ora_omega_l(double f, int32_t unit)
+{
+    if (unit == ORA_UNIT_ANGULAR)
+        return (long double)f;
+    return ORA_TWO_PI_L * (long double)f;
+}
+
+/*
+ * sin and cos of the angle w (t - shift).  On the workloads the angle reaches
+ * ~5e5 rad (24 cycles/day over 3,650 days), where forming it in double would
+ * round it by up to ~1e-10 rad -- more than the GPU forms' phases, which are
+ * taken on re-centred times -- so it is formed and reduced modulo 2 pi in long
+ * double (64-bit significand; the reduced angle is off by ~1e-13 rad at most),
+ * and only the reduced angle goes to the double-precision sin and cos.
+ */
+static void ora_sincos(long double w, double t, long double shift, double *s, double *c)
+{
+    long double a = w * ((long double)t - shift);
+    long double k = rintl(a / ORA_TWO_PI_L);
+    double r = (double)(a - k * ORA_TWO_PI_L);
+    *s = sin(r);
+    *c = cos(r);
+}
+
 /*
  * Mean removal (Section 2 assumes zero-mean magnitudes).  Writes the centred
  * magnitudes to yp[n] and their sum of squares to *syy; returns the object's
@@ -137,17 +164,24 @@ int32_t ora_prep(const double *t, const double *y, int64_t n, int32_t subtract_m
 }
 
 /* Eq. 1: tau = atan2(sum sin 2wt, sum cos 2wt) / (2w); tau = 0 at w = 0. */
-double ora_tau(const double *t, int64_t n, double w)
+static long double ora_tau_l(const double *t, int64_t n, long double w)
 {
     int64_t j;
     ora_sum ss = {0.0, 0.0}, sc = {0.0, 0.0};
-    if (w == 0.0)
-        return 0.0;
+    if (w == 0.0L)
+        return 0.0L;
     for (j = 0; j < n; j++) {
-        ora_sum_add(&ss, sin(2.0 * w * t[j]));
-        ora_sum_add(&sc, cos(2.0 * w * t[j]));
+        double s2, c2;
+        ora_sincos(2.0L * w, t[j], 0.0L, &s2, &c2);
+        ora_sum_add(&ss, s2);
+        ora_sum_add(&sc, c2);
     }
-    return atan2(ora_sum_get(&ss), ora_sum_get(&sc)) / (2.0 * w);
+    return (long double)atan2(ora_sum_get(&ss), ora_sum_get(&sc)) / (2.0L * w);
+}
+
+double ora_tau(const double *t, int64_t n, double w)
+{
+    return (double)ora_tau_l(t, n, (long double)w);
 }
 
 /*
@@ -155,15 +189,15 @@ double ora_tau(const double *t, int64_t n, double w)
  * when sums != NULL, stores {YC, YS, CC, SS} = {sum y cos, sum y sin,
  * sum cos^2, sum sin^2} of the shifted phase w (t_j - tau).
  */
-double ora_pls(const double *t, const double *yp, int64_t n, double w, double tau, double *sums)
+static double ora_pls_l(const double *t, const double *yp, int64_t n, long double w,
+                        long double tau, double *sums)
 {
     int64_t j;
     ora_sum yc = {0.0, 0.0}, ys = {0.0, 0.0}, cc = {0.0, 0.0}, ss = {0.0, 0.0};
     double YC, YS, CC, SS, p;
     for (j = 0; j < n; j++) {
-        double arg = w * (t[j] - tau);
-        double c = cos(arg);
-        double s = sin(arg);
+        double c, s;
+        ora_sincos(w, t[j], tau, &s, &c);
         ora_sum_add(&yc, yp[j] * c);
         ora_sum_add(&ys, yp[j] * s);
         ora_sum_add(&cc, c * c);
@@ -187,13 +221,18 @@ double ora_pls(const double *t, const double *yp, int64_t n, double w, double ta
     return 0.5 * p;
 }
 
+double ora_pls(const double *t, const double *yp, int64_t n, double w, double tau, double *sums)
+{
+    return ora_pls_l(t, yp, n, (long double)w, (long double)tau, sums);
+}
+
 /* Power of one object at one frequency (centred magnitudes, known S_yy). */
 static double ora_power_one(const double *t, const double *yp, int64_t n, double syy, double f,
                             int32_t unit, int32_t normalize)
 {
-    double w = ora_omega(f, unit);
-    double tau = ora_tau(t, n, w);
-    double pls = ora_pls(t, yp, n, w, tau, NULL);
+    long double w = ora_omega_l(f, unit);
+    long double tau = ora_tau_l(t, n, w);
+    double pls = ora_pls_l(t, yp, n, w, tau, NULL);
     if (normalize)
         return 2.0 * pls / syy;
     return pls;
@@ -453,54 +492,65 @@ int32_t ora_gen_prep(const double *t, const double *y, const double *dy, int64_t
 }
 
 /* Weighted means of cos(w (t - shift)) and sin(w (t - shift)). */
-static void ora_gen_means(const double *t, const double *w, int64_t n, double wsum, double om,
-                          double shift, double *mc, double *ms)
+static void ora_gen_means(const double *t, const double *w, int64_t n, double wsum,
+                          long double om, long double shift, double *mc, double *ms)
 {
     int64_t j;
     ora_sum c = {0.0, 0.0}, s = {0.0, 0.0};
     for (j = 0; j < n; j++) {
-        double arg = om * (t[j] - shift);
-        ora_sum_add(&c, w[j] * cos(arg));
-        ora_sum_add(&s, w[j] * sin(arg));
+        double sj, cj;
+        ora_sincos(om, t[j], shift, &sj, &cj);
+        ora_sum_add(&c, w[j] * cj);
+        ora_sum_add(&s, w[j] * sj);
     }
     *mc = ora_sum_get(&c) / wsum;
     *ms = ora_sum_get(&s) / wsum;
 }
 
 /* tau of the generalized method: tan(2 w tau) = 2 CS / (CC - SS); 0 at w = 0. */
-double ora_gen_tau(const double *t, const double *w, int64_t n, double wsum, double om)
+static long double ora_gen_tau_l(const double *t, const double *w, int64_t n, double wsum,
+                                 long double om)
 {
     int64_t j;
     double mc, ms;
     ora_sum cc = {0.0, 0.0}, ss = {0.0, 0.0}, cs = {0.0, 0.0};
-    if (om == 0.0)
-        return 0.0;
-    ora_gen_means(t, w, n, wsum, om, 0.0, &mc, &ms);
+    if (om == 0.0L)
+        return 0.0L;
+    ora_gen_means(t, w, n, wsum, om, 0.0L, &mc, &ms);
     for (j = 0; j < n; j++) {
-        double dc = cos(om * t[j]) - mc;
-        double ds = sin(om * t[j]) - ms;
+        double sj, cj, dc, ds;
+        ora_sincos(om, t[j], 0.0L, &sj, &cj);
+        dc = cj - mc;
+        ds = sj - ms;
         ora_sum_add(&cc, w[j] * dc * dc);
         ora_sum_add(&ss, w[j] * ds * ds);
         ora_sum_add(&cs, w[j] * dc * ds);
     }
-    return atan2(2.0 * ora_sum_get(&cs), ora_sum_get(&cc) - ora_sum_get(&ss)) / (2.0 * om);
+    return (long double)atan2(2.0 * ora_sum_get(&cs), ora_sum_get(&cc) - ora_sum_get(&ss)) /
+           (2.0L * om);
+}
+
+double ora_gen_tau(const double *t, const double *w, int64_t n, double wsum, double om)
+{
+    return (double)ora_gen_tau_l(t, w, n, wsum, (long double)om);
 }
 
 /*
  * Half the chi^2 reduction at angular frequency om and a given tau.  When
  * sums != NULL, stores {YC, YS, CC, SS} of the shifted, mean-removed terms.
  */
-double ora_gen_pls(const double *t, const double *yw, const double *w, int64_t n, double wsum,
-                   double om, double tau, double *sums)
+static double ora_gen_pls_l(const double *t, const double *yw, const double *w, int64_t n,
+                            double wsum, long double om, long double tau, double *sums)
 {
     int64_t j;
     double mc, ms, gc, gs, gcc, gss, p;
     ora_sum yc = {0.0, 0.0}, ys = {0.0, 0.0}, cc = {0.0, 0.0}, ss = {0.0, 0.0};
     ora_gen_means(t, w, n, wsum, om, tau, &mc, &ms);
     for (j = 0; j < n; j++) {
-        double arg = om * (t[j] - tau);
-        double dc = cos(arg) - mc;
-        double ds = sin(arg) - ms;
+        double sj, cj, dc, ds;
+        ora_sincos(om, t[j], tau, &sj, &cj);
+        dc = cj - mc;
+        ds = sj - ms;
         ora_sum_add(&yc, w[j] * yw[j] * dc);
         ora_sum_add(&ys, w[j] * yw[j] * ds);
         ora_sum_add(&cc, w[j] * dc * dc);
@@ -524,12 +574,18 @@ double ora_gen_pls(const double *t, const double *yw, const double *w, int64_t n
     return 0.5 * p;
 }
 
+double ora_gen_pls(const double *t, const double *yw, const double *w, int64_t n, double wsum,
+                   double om, double tau, double *sums)
+{
+    return ora_gen_pls_l(t, yw, w, n, wsum, (long double)om, (long double)tau, sums);
+}
+
 static double ora_gen_power_one(const double *t, const double *yw, const double *w, int64_t n,
                                 double wsum, double yy, double f, int32_t unit, int32_t normalize)
 {
-    double om = ora_omega(f, unit);
-    double tau = ora_gen_tau(t, w, n, wsum, om);
-    double pls = ora_gen_pls(t, yw, w, n, wsum, om, tau, NULL);
+    long double om = ora_omega_l(f, unit);
+    long double tau = ora_gen_tau_l(t, w, n, wsum, om);
+    double pls = ora_gen_pls_l(t, yw, w, n, wsum, om, tau, NULL);
     if (normalize)
         return 2.0 * pls / yy;
     return pls;

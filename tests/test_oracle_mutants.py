@@ -18,8 +18,9 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "lsp_oracle.c")
 MUTANTS = {
     "dropped_sine_term": ("p += YS * YS / SS;", "p += 0.0;"),
     "dropped_cosine_term": ("p += YC * YC / CC;", "p += 0.0;"),
-    "wrong_sign_shift": ("double arg = w * (t[j] - tau);", "double arg = w * (t[j] + tau);"),
-    "tau_missing_factor_two": ("/ (2.0 * w);", "/ w;"),
+    "wrong_sign_shift": ("long double a = w * ((long double)t - shift);",
+                         "long double a = w * ((long double)t + shift);"),
+    "tau_missing_factor_two": ("ora_sum_get(&sc)) / (2.0L * w);", "ora_sum_get(&sc)) / w;"),
     "atan2_transposed": ("atan2(ora_sum_get(&ss), ora_sum_get(&sc))",
                          "atan2(ora_sum_get(&sc), ora_sum_get(&ss))"),
     "grid_off_by_one": ("return f_min + df * (double)i;", "return f_min + df * (double)(i + 1);"),
@@ -34,8 +35,8 @@ MUTANTS = {
     "no_degenerate_term_rule": ("if (SS > 1e-12 * (double)n)", "if (1)"),
     "period_missing_two_pi": ("return ORA_TWO_PI / ora_omega(f, unit);",
                               "return 1.0 / ora_omega(f, unit);"),
-    "window_single_angle": ("ora_sum_add(&ss, sin(2.0 * w * t[j]));",
-                            "ora_sum_add(&ss, sin(w * t[j]));"),
+    "window_single_angle": ("ora_sincos(2.0L * w, t[j], 0.0L, &s2, &c2);",
+                            "ora_sincos(w, t[j], 0.0L, &s2, &c2);"),
 }
 
 # Slips in the generalized periodogram (Section 4.11), caught by its own pins.
@@ -46,13 +47,19 @@ GEN_MUTANTS = {
     "gen_error_check_missing": ("if (dy && !(isfinite(dy[j]) && dy[j] > 0.0))", "if (0)"),
     "gen_yy_unweighted": ("ora_sum_add(&sq, w[j] * yw[j] * yw[j]);",
                           "ora_sum_add(&sq, yw[j] * yw[j]);"),
-    "gen_means_unweighted": ("ora_sum_add(&c, w[j] * cos(arg));", "ora_sum_add(&c, cos(arg));"),
-    "gen_tau_not_centred": ("double dc = cos(om * t[j]) - mc;", "double dc = cos(om * t[j]);"),
+    "gen_means_unweighted": ("ora_sum_add(&c, w[j] * cj);", "ora_sum_add(&c, cj);"),
+    "gen_tau_not_centred": ("ora_sincos(om, t[j], 0.0L, &sj, &cj);\n        dc = cj - mc;",
+                            "ora_sincos(om, t[j], 0.0L, &sj, &cj);\n        dc = cj;"),
     "gen_tau_transposed": ("atan2(2.0 * ora_sum_get(&cs), ora_sum_get(&cc) - ora_sum_get(&ss))",
                            "atan2(ora_sum_get(&cc) - ora_sum_get(&ss), 2.0 * ora_sum_get(&cs))"),
-    "gen_tau_missing_two": ("ora_sum_get(&ss)) / (2.0 * om);", "ora_sum_get(&ss)) / om;"),
-    "gen_wrong_sign_shift": ("double arg = om * (t[j] - tau);", "double arg = om * (t[j] + tau);"),
-    "gen_shift_not_centred": ("double ds = sin(arg) - ms;", "double ds = sin(arg);"),
+    "gen_tau_missing_two": ("ora_sum_get(&ss)) /\n           (2.0L * om);",
+                            "ora_sum_get(&ss)) /\n           om;"),
+    "gen_wrong_sign_shift": ("long double a = w * ((long double)t - shift);",
+                             "long double a = w * ((long double)t + shift);"),
+    "gen_shift_not_centred": ("ora_sincos(om, t[j], tau, &sj, &cj);\n        dc = cj - mc;\n"
+                              "        ds = sj - ms;",
+                              "ora_sincos(om, t[j], tau, &sj, &cj);\n        dc = cj - mc;\n"
+                              "        ds = sj;"),
     "gen_numerator_unweighted": ("ora_sum_add(&yc, w[j] * yw[j] * dc);",
                                  "ora_sum_add(&yc, yw[j] * dc);"),
     "gen_denominator_from_sine": ("w[j] * yw[j] * ds);\n        ora_sum_add(&cc, w[j] * dc * dc);",

@@ -1,0 +1,98 @@
+"""The oracle's own rounding stays far below the FP64 parity bound.
+
+Eq. 1 and Eq. 2 are evaluated here a third way, independently of the oracle:
+with 40-digit arithmetic (mpmath), straight from their definition on raw
+times, on objects of the LSST-like population at the top of its grid, where
+the angle w t reaches ~5e5 rad.  The oracle must match to 1e-11 *
+max(P, 1e-3) -- two orders below the 1e-9 * max(P, 1e-3) it is used to
+check the FP64 GPU form with -- in both frequency units and for the
+generalized periodogram.  (An oracle that forms w t in plain double misses
+this by up to ~2e-10: its phases carry ~1e-10 rad of rounding there.)
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_04006_amd import synth
+
+mp = pytest.importorskip("mpmath")
+
+TOL = 1e-11
+
+
+def _pnorm_mp(t, y, w, dy=None):
+    """Normalised power at angular frequency w, 40 digits: Eq. 1 and 2 (or
+    the generalized method's weighted, mean-fitted form) on raw times."""
+    mp.mp.dps = 40
+    tm = [mp.mpf(float(v)) for v in t]
+    if dy is None:
+        wt = [mp.mpf(1)] * len(tm)
+    else:
+        wt = [1 / mp.mpf(float(e)) ** 2 for e in dy]
+    W = mp.fsum(wt)
+    ym = [mp.mpf(float(v)) for v in y]
+    ybar = mp.fsum(a * b for a, b in zip(wt, ym)) / W
+    yp = [v - ybar for v in ym]
+    yy = mp.fsum(a * b * b for a, b in zip(wt, yp))
+    wm = w if isinstance(w, mp.mpf) else mp.mpf(float(w))
+    if dy is None:
+        S = mp.fsum(mp.sin(2 * wm * v) for v in tm)
+        C = mp.fsum(mp.cos(2 * wm * v) for v in tm)
+        tau = mp.atan2(S, C) / (2 * wm)
+        cs = [mp.cos(wm * (v - tau)) for v in tm]
+        sn = [mp.sin(wm * (v - tau)) for v in tm]
+    else:
+        c0 = [mp.cos(wm * v) for v in tm]
+        s0 = [mp.sin(wm * v) for v in tm]
+        mc = mp.fsum(a * b for a, b in zip(wt, c0)) / W
+        ms = mp.fsum(a * b for a, b in zip(wt, s0)) / W
+        CC = mp.fsum(a * (b - mc) ** 2 for a, b in zip(wt, c0))
+        SS = mp.fsum(a * (b - ms) ** 2 for a, b in zip(wt, s0))
+        CS = mp.fsum(a * (b - mc) * (c - ms) for a, b, c in zip(wt, c0, s0))
+        tau = mp.atan2(2 * CS, CC - SS) / (2 * wm)
+        cs = [mp.cos(wm * (v - tau)) for v in tm]
+        sn = [mp.sin(wm * (v - tau)) for v in tm]
+        mcs = mp.fsum(a * b for a, b in zip(wt, cs)) / W
+        mss = mp.fsum(a * b for a, b in zip(wt, sn)) / W
+        cs = [v - mcs for v in cs]
+        sn = [v - mss for v in sn]
+    yc = mp.fsum(a * b * c for a, b, c in zip(wt, yp, cs))
+    ys = mp.fsum(a * b * c for a, b, c in zip(wt, yp, sn))
+    dc = mp.fsum(a * b * b for a, b in zip(wt, cs))
+    ds = mp.fsum(a * b * b for a, b in zip(wt, sn))
+    return float((yc * yc / dc + ys * ys / ds) / yy)
+
+
+def _check(unit, gen):
+    ora = oracle.default()
+    w = synth.make_workload("lsst_200k", n_obj=12, errors=gen)
+    rng = np.random.default_rng(11)
+    scale = 2 * np.pi if unit == oracle.ANGULAR else 1.0
+    worst = 0.0
+    for o in (0, 5, 11):
+        t, y = w.obj(o)
+        dy = w.dy[w.offsets[o]:w.offsets[o + 1]] if gen else None
+        off = np.array([0, len(t)], np.int64)
+        bins = rng.integers(int(0.9 * w.n_f), w.n_f, 6)
+        f_min, f_max = w.f_min * scale, w.f_max * scale
+        if gen:
+            got = ora.gen_eval_bins(off, t, y, dy, f_min, f_max, w.n_f,
+                                    np.zeros(len(bins), np.int64), bins, unit=unit)
+        else:
+            got = ora.eval_bins(off, t, y, f_min, f_max, w.n_f, np.zeros(len(bins), np.int64),
+                                bins, unit=unit)
+        for b, g in zip(bins, got):
+            f = ora.grid_freq(f_min, f_max, w.n_f, int(b))
+            om = mp.mpf(f) if unit == oracle.ANGULAR else 2 * mp.pi * mp.mpf(f)
+            ref = _pnorm_mp(t, y, om, dy)
+            worst = max(worst, abs(g - ref) / max(ref, 1e-3))
+    assert worst <= TOL, worst
+
+
+@pytest.mark.parametrize("unit", [oracle.CYCLES, oracle.ANGULAR], ids=["cycles", "angular"])
+def test_standard_oracle_matches_40_digit_evaluation(unit):
+    _check(unit, gen=False)
+
+
+def test_generalized_oracle_matches_40_digit_evaluation():
+    _check(oracle.CYCLES, gen=True)
