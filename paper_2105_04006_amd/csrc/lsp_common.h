@@ -77,12 +77,28 @@ __device__ __forceinline__ PeakRec wave_best(PeakRec r) {
     return r;
 }
 
-// sin and cos of 2 pi (f_cyc * tau), with the phase reduced exactly to
-// [-1/2, 1/2] cycles in FP64 before the library call.
-__device__ __forceinline__ void sincos_cycles64(double f_cyc, double tau, double* s, double* c) {
-    double ph = f_cyc * tau;
-    ph -= rint(ph);
-    sincospi(2.0 * ph, s, c);
+// A time re-centred on the object's origin, t - t0, as the unevaluated sum
+// hi + lo of its rounded value and the rounding error (Knuth's two-sum, exact
+// for any two doubles).
+__device__ __forceinline__ void recentre64(double t, double t0, double* hi, double* lo) {
+    const double s = __dsub_rn(t, t0);
+    const double bb = __dsub_rn(s, t);
+    *hi = s;
+    *lo = __dsub_rn(__dsub_rn(t, __dsub_rn(s, bb)), __dadd_rn(t0, bb));
+}
+
+// sin and cos of 2 pi f (hi + lo) for a re-centred time hi + lo (recentre64):
+// the product f hi is split exactly into p + e with a fused multiply-add, the
+// whole cycles of p are removed exactly, and e + f lo is added back, so the
+// phase handed to the library is off by its final rounding only (~6e-17
+// cycles), whatever the frequency and time span.  The explicit-rounding
+// intrinsics keep the compiler from fusing the steps of this split.
+__device__ __forceinline__ void sincos_cycles64(double f_cyc, double hi, double lo, double* s,
+                                                double* c) {
+    const double p = __dmul_rn(f_cyc, hi);
+    const double e = fma(f_cyc, hi, -p);
+    const double r = __dadd_rn(__dsub_rn(p, rint(p)), fma(f_cyc, lo, e));
+    sincospi(2.0 * r, s, c);
 }
 
 struct Sums64 {
@@ -158,8 +174,9 @@ __device__ __forceinline__ double power64_bin(const ObjMeta& m, const double* __
                                               const double* __restrict__ y, double f_cyc) {
     Sums64 a = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t j = m.j0; j < m.j0 + m.n; ++j) {
-        double s, c;
-        sincos_cycles64(f_cyc, t[j] - m.t0, &s, &c);
+        double s, c, hi, lo;
+        recentre64(t[j], m.t0, &hi, &lo);
+        sincos_cycles64(f_cyc, hi, lo, &s, &c);
         sums64_add(a, y[j] - m.ybar, s, c);
     }
     return power64(a, (double)m.n, m.scale);
@@ -251,8 +268,9 @@ __device__ __forceinline__ double power64_gen_bin(const ObjMeta& m, const double
                                                   const double* __restrict__ dy, double f_cyc) {
     SumsGen64 a = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t j = m.j0; j < m.j0 + m.n; ++j) {
-        double s, c;
-        sincos_cycles64(f_cyc, t[j] - m.t0, &s, &c);
+        double s, c, hi, lo;
+        recentre64(t[j], m.t0, &hi, &lo);
+        sincos_cycles64(f_cyc, hi, lo, &s, &c);
         const double w = gen_weight(dy, j, m.wnorm);
         sumsgen64_add(a, w, w * (y[j] - m.ybar), s, c);
     }

@@ -4,8 +4,10 @@
 // as in the paper's kernel (Section 3.7): one pass over the object's
 // observations accumulates sum y cos wt, y sin wt, cos^2, sin^2 and cos sin,
 // and Eq. 1 and Eq. 2 are then applied to those sums (power64).  The phase is
-// formed in cycles in FP64 and reduced exactly by rounding before the library
-// call, which keeps the library on its short-argument path.
+// formed in cycles from the re-centred time and its rounding error with an
+// exact split of the frequency-time product (sincos_cycles64), and reduced
+// exactly before the library call, which keeps the library on its
+// short-argument path and the phase accurate to its last rounding.
 //
 // This file also holds the FP64 fix-up of the FP32 form (fixup_kernel), for
 // the standard and the generalized periodogram.
@@ -22,6 +24,7 @@ namespace {
 template <int KF, int W>
 __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
+    __shared__ double s_tlo[kTile];
     __shared__ double s_y[kTile];
     __shared__ PeakRec s_red[W];
 
@@ -69,17 +72,18 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
         const int cnt = (int)((j_end - jt) < kTile ? (j_end - jt) : kTile);
         __syncthreads();
         for (int q = threadIdx.x; q < cnt; q += kWave * W) {
-            s_tau[q] = P.t[jt + q] - m.t0;
+            recentre64(P.t[jt + q], m.t0, &s_tau[q], &s_tlo[q]);
             s_y[q] = P.y[jt + q] - m.ybar;
         }
         __syncthreads();
         for (int q = 0; q < cnt; ++q) {
             const double tq = s_tau[q];
+            const double tl = s_tlo[q];
             const double yq = s_y[q];
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
                 double s, c;
-                sincos_cycles64(fc[k], tq, &s, &c);
+                sincos_cycles64(fc[k], tq, tl, &s, &c);
                 sums64_add(acc[k], yq, s, c);
             }
         }

@@ -209,6 +209,7 @@ __global__ __launch_bounds__(kWave* W) void gen_fp32p_kernel(const MainParams P)
 template <int KF, int W>
 __global__ __launch_bounds__(kWave* W) void gen_fp64_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
+    __shared__ double s_tlo[kTile];
     __shared__ double s_w[kTile];
     __shared__ double s_wy[kTile];
     __shared__ PeakRec s_red[W];
@@ -260,19 +261,20 @@ __global__ __launch_bounds__(kWave* W) void gen_fp64_kernel(const MainParams P) 
         for (int q = threadIdx.x; q < cnt; q += kWave * W) {
             const int64_t j = jt + q;
             const double w = gen_weight(P.dy, j, m.wnorm);
-            s_tau[q] = P.t[j] - m.t0;
+            recentre64(P.t[j], m.t0, &s_tau[q], &s_tlo[q]);
             s_w[q] = w;
             s_wy[q] = w * (P.y[j] - m.ybar);
         }
         __syncthreads();
         for (int q = 0; q < cnt; ++q) {
             const double tq = s_tau[q];
+            const double tl = s_tlo[q];
             const double wq = s_w[q];
             const double wyq = s_wy[q];
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
                 double s, c;
-                sincos_cycles64(fc[k], tq, &s, &c);
+                sincos_cycles64(fc[k], tq, tl, &s, &c);
                 sumsgen64_add(acc[k], wq, wyq, s, c);
             }
         }
