@@ -1,18 +1,24 @@
 """Benchmark of the Lomb-Scargle periodogram hot path on one MI355X.
 
-Default workload (single_4096): one object with N_t = 4,096 seasonal-cadence
-observations, N_f = 500,000 frequencies over [0.5, 24) cycles/day, full FP32
-periodogram (2 MB) plus the peak.  One step = one lsp_single call of the FP32
-form (prep, main kernel, FP64 fix-up check, combine, peak), inputs resident in
-HBM.  The plain FP64 form is timed on the same input for the "vs plain FP64
-kernel" comparison, and the two periodograms are compared for peak-bin
-agreement.  The oracle (CPU, FP64) is timed on a bounded sample of the same
-workload on this host's cores.
+Default workload (lsst_200k): 200,000 objects, N_t uniform in 20..500 with
+seasonal gaps, 60% sinusoids, 30% with a second harmonic, 10% pure noise;
+N_f = 250,000 frequencies over [0.5, 24) cycles/day; every object's peak.
+Three forms run on the same device-resident input (Section 3.4's batch mode):
+  * the FP32 form with FP64 phase reduction on the whole grid -- one timed
+    step is one lsp_batch call (prep, main kernel, FP64 fix-up, peaks); its
+    evals/s is the line's value and its main kernel carries the roofline;
+  * the learned band proposal (features, network, top bands, refine,
+    fallback), trained and calibrated on independent objects before the
+    timed region, under three proposal rules (network, coarse power, hybrid);
+  * the plain FP64 form on the whole grid, the reference every other form's
+    peaks are judged against, object by object.
+The CPU oracle (FP64) checks both whole-grid forms on a sample of the first
+2,000 objects and is timed on that sample on this host's cores.
 
-``--method generalized`` times the generalized periodogram instead (Section
-4.11: per-point errors, floating mean) on the same workload drawn with
-photometric errors, and also times the standard periodogram on that input to
-report the cost ratio the paper measures (generalized / standard).
+Other workloads: single_4096 / single_256 (one object, full FP32 periodogram
+plus peak) and batch_10k time the FP32 and FP64 forms; --method generalized
+times the generalized periodogram (Section 4.11); --host-return and
+--recovery run the host-return and period-recovery studies.
 
 Prints ONE JSON line.
 """
@@ -67,6 +73,7 @@ TRAFFIC_FILES = {
     "standard": os.path.join(ROOT, "profiles", "fp32p_single_4096_traffic.json"),
     "generalized": os.path.join(ROOT, "profiles", "gen_fp32p_single_4096_traffic.json"),
     ("standard", "batch_10k"): os.path.join(ROOT, "profiles", "fp32p_batch_10k_traffic.json"),
+    ("standard", "lsst_200k"): os.path.join(ROOT, "profiles", "fp32p_lsst_200k_traffic.json"),
 }
 
 
@@ -135,16 +142,32 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="single_4096")
+    ap.add_argument("--workload", default="lsst_200k",
+                    help="lsst_200k (default), learned_100k, asteroids_100k: the three forms "
+                         "(fp32 whole grid, learned proposal, fp64) on one batch; single_256, "
+                         "single_4096, batch_10k: the FP32 and FP64 forms")
+    ap.add_argument("--forms", default="fp32,learned,fp64",
+                    help="forms timed on a three-form workload (comma list; fp32 always runs)")
+    ap.add_argument("--proposal", default="hybrid", choices=["hybrid", "coarse", "network"],
+                    help="learned form: the proposal rule timed with --steps (the others run "
+                         "3 steps each for the comparison)")
+    ap.add_argument("--train-objects", type=int, default=40000)
+    ap.add_argument("--val-objects", type=int, default=20000)
+    ap.add_argument("--oracle-objects", type=int, default=2000,
+                    help="three-form workloads: the oracle checks a sample of this many "
+                         "leading objects")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads (0: every core of this process's affinity set)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--recurrence", default="auto", choices=["auto", "rotation", "chebyshev"])
     ap.add_argument("--k", type=int, default=0, help="frequencies per lane (0: library default)")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--schedule", default="auto", choices=["auto", "grid", "persistent"])
-    ap.add_argument("--cpu-evals", type=float, default=6e8,
+    ap.add_argument("--cpu-evals", type=float, default=3e9,
                     help="oracle evaluations in the CPU-baseline sample (about 10-30 s of CPU work)")
     ap.add_argument("--fp64-steps", type=int, default=0,
-                    help="timed steps of the FP64 reference form (default steps // 8, >= 3)")
+                    help="timed steps of the FP64 reference form (default: 2 on a three-form "
+                         "workload, else steps // 8, >= 3)")
     ap.add_argument("--mode", default="lsp", choices=["lsp", "copy"],
                     help="copy: time a plain device-to-device copy of --copy-bytes bytes "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -169,9 +192,6 @@ def main():
                     help="time the whole batch periodogram returned to host memory: one copy of "
                          "the device periodogram into pageable memory against the pinned-staging "
                          "pipeline (lsp_batch_to_host); PCIe-inclusive, not the headline value")
-    ap.add_argument("--learned", action="store_true",
-                    help="time the learned band-proposal path on --workload (always on for "
-                         "learned_100k)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the periodogram of "
@@ -201,8 +221,8 @@ def main():
 
     lsp.lib()  # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
-    if args.workload == "learned_100k" or args.learned:
-        return bench_learned(args, torch, dev)
+    if args.workload in FORM_WORKLOADS and not (args.host_return or args.recovery):
+        return bench_forms(args, torch, dev)
     if args.host_return:
         return bench_host_return(args, torch, dev)
     if args.recovery:
@@ -293,8 +313,9 @@ def main():
 
     evals = w.evals
     value = evals / (ms32 * 1e-3)
-    rec_name = "rotation" if args.recurrence == "rotation" else "chebyshev"  # auto = chebyshev
-    k_lane = args.k if args.k else 16
+    rec_name = "rotation" if p32.launch()["recurrence"] == lsp.REC_ROTATION else "chebyshev"
+    shape = p32.launch()
+    k_lane = shape["k_per_lane"]
     flops_eval = FLOPS_PER_EVAL_GEN if gen else FLOPS_PER_EVAL[rec_name]
     achieved = flops_eval * evals / (k_ms * 1e-3) / 1e12
     valu_ops = (valu_ops_per_eval_gen(k_lane) if gen else valu_ops_per_eval(rec_name, k_lane)) \
@@ -348,10 +369,12 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu:
-        threads = min(16, len(os.sched_getaffinity(0)))
-        log(f"[bench] oracle baseline on {threads} threads")
+        threads, aff = host_threads(args.cpu_threads)
+        log(f"[bench] oracle baseline on {threads} threads (affinity {aff})")
         out["cpu_baseline"], (objs, bins, ora_vals) = cpu_baseline(w, args.cpu_evals, threads,
                                                                    args.method)
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+        out["cpu_baseline"]["affinity_cores"] = aff
         # the FP32 form's power at the same (object, bin) pairs, against the
         # oracle: the bench line states its error against the FP64 oracle
         if single:
@@ -556,34 +579,121 @@ def bench_host_return(args, torch, dev):
     print(json.dumps(out), flush=True)
 
 
-def bench_learned(args, torch, dev):
-    """Learned band proposal on a batch workload (learned_100k: 1e5 objects,
-    N_t 50..500, N_f 2e5 over [1, 12) cycles/day, 64 bands of 3,125 bins, top 8
-    refined; lsst_200k with --learned: 2e5 objects with harmonics and noise).
+FORM_WORKLOADS = ("lsst_200k", "learned_100k", "asteroids_100k")
+KIND_NAMES = {0: "sinusoid", 1: "two_harmonic", 2: "noise"}
 
-    Untimed set-up: train the proposal network on 40,000 independent objects
-    (labels: whole-grid FP32 peaks), calibrate the fallback thresholds on
-    20,000 more for >= 99.9% recovery.  Timed step: features -> network ->
-    top bands -> refine -> fallback selection -> whole-grid fallback, ending
-    with the peaks of all 1e5 objects.  Compared with the whole-grid FP32 batch
-    (same peaks, every bin) and the plain FP64 form."""
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads(requested):
+    """Threads of the oracle: every core of this process's affinity set, or
+    the number requested."""
+    aff = len(os.sched_getaffinity(0))
+    return (int(requested) if requested > 0 else aff), aff
+
+
+def oracle_subset(w, n_sub, target_evals, threads, extra_bins, method="standard"):
+    """The oracle on a bounded sample of the first n_sub objects: every
+    stride-th bin of each (start staggered per object) plus the bins in
+    extra_bins (per-object peak indices of the GPU forms, -1 = none).
+    Returns the sample, the oracle's values and the cpu_baseline record."""
+    import oracle
+
+    oracle.default()
+    n_sub = min(n_sub, w.n_obj)
+    n_t = np.diff(w.offsets)[:n_sub]
+    stride = max(1, int(np.ceil(float(n_t.sum()) * w.n_f / target_evals)))
+    objs, bins = [], []
+    for o in range(n_sub):
+        b = np.arange((o * 7919) % stride, w.n_f, stride, dtype=np.int64)
+        ex = np.unique(np.concatenate([e[o:o + 1] for e in extra_bins]))
+        ex = ex[(ex >= 0) & (ex < w.n_f)]
+        b = np.union1d(b, ex)
+        objs.append(np.full(len(b), o, dtype=np.int64))
+        bins.append(b)
+    objs, bins = np.concatenate(objs), np.concatenate(bins)
+    t0 = time.perf_counter()
+    if method == "generalized":
+        vals = oracle.gen_eval_bins(w.offsets, w.t, w.y, w.dy, w.f_min, w.f_max, w.n_f, objs,
+                                    bins, unit=w.unit, threads=threads)
+    else:
+        vals = oracle.eval_bins(w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, objs, bins,
+                                unit=w.unit, threads=threads)
+    dt = time.perf_counter() - t0
+    evals = int(np.diff(w.offsets)[objs].sum())
+    rec = {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n_sub} objects of the same workload: every {stride}th bin "
+                     f"(start staggered per object) plus the GPU forms' peak bins, "
+                     f"{len(bins)} (object, bin) pairs, {evals:.3g} evals, {dt:.2f} s wall"}
+    return objs, bins, vals, rec
+
+
+def bin_values(w, tensors, form, index, method="standard", dy=None):
+    """Each object's power at one chosen bin (index[o], -1 = none), through
+    row mode with one-bin bands."""
+    import torch
+    from paper_2105_04006_amd import lsp
+
+    off, t, y = tensors
+    band = torch.as_tensor(np.where(index >= 0, index, -1).astype(np.int32), device=t.device)
+    r = lsp.Rows(off, t, y, w.f_min, w.f_max, w.n_f, None, band, 1, 1, unit=w.unit, form=form,
+                 method=method, dy=dy)
+    r()
+    return r.peaks()["power"]
+
+
+def bench_forms(args, torch, dev):
+    """The three forms on one batch workload (default lsst_200k: 2e5 objects,
+    N_t U{20..500}, 60% sinusoids, 30% with a second harmonic, 10% pure
+    noise, N_f = 250,000 over [0.5, 24) cycles/day), each returning every
+    object's peak, inputs resident in HBM:
+      fp32    the FP32 form with FP64 phase reduction on the whole grid (the
+              timed headline: its evals/s is the line's value);
+      learned features -> network -> top bands -> refine -> fallback (the
+              network trained and the thresholds calibrated beforehand, on
+              independent objects, outside the timed region);
+      fp64    the plain FP64 form on the whole grid (the reference form).
+    Peak agreement is judged against the FP64 form on every object; the FP64
+    and FP32 forms are checked against the CPU oracle on a sample of the first
+    2,000 objects, which also times the oracle (cpu_baseline)."""
     from paper_2105_04006_amd import learned, lsp, synth
 
     gen = args.method == "generalized"
     method = "generalized" if gen else "standard"
+    forms = [f for f in args.forms.split(",") if f]
+    name = args.workload
 
-    def tens(w):
-        return (torch.as_tensor(w.offsets, device=dev), torch.as_tensor(w.t, device=dev),
-                torch.as_tensor(w.y, device=dev))
+    def make(n_obj=None, seed=None):
+        if name.startswith("asteroids"):
+            return synth.make_workload(name, n_obj=n_obj, seed=seed)
+        return synth.make_workload(name, n_obj=n_obj, seed=seed, errors=gen)
 
-    def errs(w):
-        return torch.as_tensor(w.dy, device=dev) if gen else None
+    w = make()
+    n_t = np.diff(w.offsets)
+    log(f"[bench] workload {w.name}: n_obj={w.n_obj} n_obs={w.n_obs} n_f={w.n_f} "
+        f"evals={w.evals:.3e}")
+    tt = learned._tensors(w, dev)
+    off, t, y = tt
+    dy = learned._errors(w, dev, method)
+    rec = {"auto": lsp.REC_AUTO, "rotation": lsp.REC_ROTATION,
+           "chebyshev": lsp.REC_CHEBYSHEV}[args.recurrence]
+    sched = {"auto": lsp.SCHED_AUTO, "grid": lsp.SCHED_GRID,
+             "persistent": lsp.SCHED_PERSISTENT}[args.schedule]
 
-    def full(w, tt, form=lsp.FORM_FP32P):
-        return lsp.Periodogram(tt[1], tt[2], w.f_min, w.f_max, w.n_f, offsets=tt[0], form=form,
-                               pgram=False, unit=w.unit, method=method, dy=errs(w))
+    def whole(form, **kw):
+        return lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, offsets=off, form=form,
+                               pgram=False, unit=w.unit, method=method, dy=dy, **kw)
 
-    def timed(fn, steps):
+    def wall(fn, steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -591,162 +701,244 @@ def bench_learned(args, torch, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
-    name = args.workload
-    w = synth.make_workload(name, errors=gen) if name != "asteroids_100k" else \
-        synth.make_workload(name)
-    geo = learned.BandGeometry(w.n_f, 64)
-    log(f"[bench] learned: n_obj={w.n_obj} n_obs={w.n_obs} n_f={w.n_f} "
-        f"bands of {geo.band_bins}")
-    def make(n_obj, seed):
-        if name.startswith("asteroids"):
-            return synth.make_workload(name, n_obj=n_obj, seed=seed)
-        return synth.make_workload(name, n_obj=n_obj, seed=seed, errors=gen)
-
-    wtr = make(40000, synth.SEED_BASE + 1000)
-    ttr = tens(wtr)
-    feats = lsp.Features(*ttr, wtr.f_min, wtr.f_max, unit=wtr.unit)()
-    ptr = full(wtr, ttr)
-    ptr()
-    labels = learned.peak_bands(ptr.peaks_raw, wtr.n_obj, geo.band_bins, geo.n_bands)
-    net = learned.BandNet(dev, seed=7)
-    t0 = time.perf_counter()
-    hist = learned.train_proposer(net, feats, labels, epochs=30, batch=512, lr=1e-3,
-                                  lr_final=3e-5, augment=0.9)
-    log(f"[bench] trained in {time.perf_counter() - t0:.1f} s, loss {hist[0]:.3f} -> "
-        f"{hist[-1]:.3f}")
-    del feats, ptr, ttr
-    wva = make(20000, synth.SEED_BASE + 1001)
-    tva = tens(wva)
-    lpv = learned.LearnedPeriodogram(net, geo, *tva, wva.f_min, wva.f_max, unit=wva.unit,
-                                     method=method, dy=errs(wva))
-    lpv.refine_only()
-    pva = full(wva, tva)
-    pva()
-    mass_min, power_min, n_fb = learned.calibrate(lpv.peaks(), pva.peaks(),
-                                                  lpv.mass.cpu().numpy(), target=0.999)
-    log(f"[bench] calibrated mass_min={mass_min:.4f} power_min={power_min:.4f}: "
-        f"{n_fb}/{wva.n_obj} validation fallbacks")
-    del lpv, pva, tva
-
-    tt = tens(w)
-    lp = learned.LearnedPeriodogram(net, geo, *tt, w.f_min, w.f_max, mass_min=mass_min,
-                                    power_min=power_min, unit=w.unit, method=method, dy=errs(w))
-    p32 = full(w, tt)
-    p64 = full(w, tt, lsp.FORM_FP64)
-    for _ in range(max(1, args.warmup)):
-        lp()
+    # --- FP32 form, whole grid: the headline ------------------------------
+    p32 = whole(lsp.FORM_FP32P, recurrence=rec, schedule=sched, k=args.k, waves=args.waves)
+    shape = p32.launch()
+    for _ in range(args.warmup):
         p32()
-    ms_l = timed(lp, args.steps)
-    log(f"[bench] learned {ms_l:.3f} ms/step ({lp.n_fallback} fallbacks)")
-    ms_32 = timed(p32, args.steps)
-    log(f"[bench] whole-grid fp32 {ms_32:.3f} ms/step")
-    ms_64 = timed(p64, max(1, args.fp64_steps))
-    log(f"[bench] whole-grid fp64 {ms_64:.3f} ms/step")
-
-    # stage breakdown of one learned step (events on the current stream)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record()
-    lp.propose()
-    ev[1].record()
-    lp.refine()
-    ev[2].record()
-    learned.select_fallback(lp.peaks_raw, lp.mass, lp.n_obj, mass_min, power_min, lp.objects,
-                            lp.count)
-    n = int(lp.count.item())
-    if n:
-        lp.full.set_rows(lp.objects[:n])
-        lp.full()
-    ev[3].record()
     torch.cuda.synchronize()
-    stages = {"features_network_topk_ms": ev[0].elapsed_time(ev[1]),
-              "refine_ms": ev[1].elapsed_time(ev[2]),
-              "select_fallback_ms": ev[2].elapsed_time(ev[3])}
-
-    pk, ref32, ref64 = lp.peaks(), p32.peaks(), p64.peaks()
-    ok = ref32["status"] == 0
-    # proposal quality: does the whole-grid peak's band sit among the 8
-    # proposed bands?  Compared with the no-network heuristic that takes the
-    # 8 bands with the largest pooled coarse value.
-    lp.refine_only()
-    net8, _ = learned.top_bands(lp.logits, lp.top)
+    log("[bench] fp32 warm-up done")
+    # each timed step also records events around the main kernel on the
+    # library's launch stream (the kernel's own device time)
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+    for a, b in pairs:
+        a.record()
+        b.record()
     torch.cuda.synchronize()
-    band = ref32["index"] // geo.band_bins
+    t0 = time.perf_counter()
+    for a, b in pairs:
+        lsp.set_stage_events(a.cuda_event, b.cuda_event)
+        p32()
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
+    lsp.set_stage_events(None, None)
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in pairs]))
+    log(f"[bench] fp32 whole grid {ms32:.2f} ms/step, main kernel {k_ms:.2f} ms")
+    pk32 = p32.peaks()
 
-    def hit(idx):
-        return float(np.mean((idx.cpu().numpy() == band[:, None]).any(axis=1)[ok]))
+    # --- learned form --------------------------------------------------------
+    lrn = None
+    if "learned" in forms:
+        props = ("hybrid", "coarse", "network")
+        prop = learned.fit_proposer(
+            lambda n, s: make(n, s), dev, n_train=args.train_objects, n_val=args.val_objects,
+            seed_train=synth.SEED_BASE + 1000, seed_val=synth.SEED_BASE + 1001,
+            method=method, proposals=props, log=lambda m: log("[bench] " + m))
+        runs = {}
+        for pr in props:
+            lp = prop.periodogram(off, t, y, w.f_min, w.f_max, unit=w.unit, proposal=pr,
+                                  method=method, dy=dy)
+            steps = args.steps if pr == args.proposal else max(1, min(3, args.steps))
+            for _ in range(max(1, min(args.warmup, 2))):
+                lp()
+            ms = wall(lp, steps)
+            pk = lp.peaks()
+            idx = lp.idx.cpu().numpy()
+            bb = np.where(idx >= 0, np.minimum(prop.geo.band_bins,
+                                               w.n_f - idx * prop.geo.band_bins), 0).sum(axis=1)
+            fb = lp.objects[:lp.n_fallback].cpu().numpy()
+            evaluated = float(np.sum(n_t * bb) + np.sum(n_t[fb]) * w.n_f)
+            runs[pr] = {"ms_per_step": ms, "steps": steps, "objects_per_s": w.n_obj / (ms * 1e-3),
+                        "whole_grid_equiv_evals_per_s": w.evals / (ms * 1e-3),
+                        "fallback_objects": int(lp.n_fallback),
+                        "evaluated_fraction": evaluated / float(w.evals),
+                        "thresholds": {"mass_min": prop.thresholds[pr][0],
+                                       "power_min": prop.thresholds[pr][1]},
+                        "_peaks": pk, "_idx": idx}
+            log(f"[bench] learned ({pr}) {ms:.2f} ms/step, {lp.n_fallback} fallbacks, "
+                f"evaluated {evaluated / w.evals:.4f} of the grid")
+            if pr == args.proposal:
+                # stage breakdown of one step (events on the current stream)
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                ev[0].record()
+                lp.propose()
+                ev[1].record()
+                lp.refine()
+                ev[2].record()
+                learned.select_fallback(lp.peaks_raw, None if pr == "coarse" else lp.mass,
+                                        lp.n_obj, lp.mass_min, lp.power_min, lp.objects,
+                                        lp.count)
+                nfb = int(lp.count.item())
+                if nfb:
+                    lp.full.set_rows(lp.objects[:nfb])
+                    lp.full()
+                ev[3].record()
+                torch.cuda.synchronize()
+                runs[pr]["stages_ms"] = {"features_network_topk": ev[0].elapsed_time(ev[1]),
+                                         "refine": ev[1].elapsed_time(ev[2]),
+                                         "select_and_fallback": ev[2].elapsed_time(ev[3])}
+            del lp
+        lrn = (prop, runs)
 
-    hit_used, hit_net = hit(lp.idx), hit(net8)
-    # diagnostic: coverage if part of the refined bands were the one-day
-    # aliases (f +- 1 cycle/day) of the first proposals
-    alias_bins = (2 * np.pi if w.unit == 1 else 1.0) / ((w.f_max - w.f_min) / w.n_f)
-    used = lp.idx.cpu().numpy().astype(np.int64)
+    # --- plain FP64 form, whole grid ---------------------------------------
+    pk64 = None
+    ms64 = None
+    if "fp64" in forms:
+        k_warm = int(np.searchsorted(w.offsets, min(w.n_obs, 20000)))
+        k_warm = max(1, min(w.n_obj, k_warm))
+        warm = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, offsets=off[:k_warm + 1],
+                               form=lsp.FORM_FP64, pgram=False, unit=w.unit, method=method,
+                               dy=dy)
+        warm()
+        p64 = whole(lsp.FORM_FP64)
+        steps64 = args.fp64_steps if args.fp64_steps > 0 else 2
+        ms64 = wall(p64, steps64)
+        log(f"[bench] fp64 whole grid {ms64:.1f} ms/step ({steps64} steps)")
+        pk64 = p64.peaks()
+        del p64
 
-    def alias_cover(n_first, n_alias):
-        first = used[:, :n_first]
-        cand = [first]
-        centre = (first[:, :n_alias] + 0.5) * geo.band_bins
-        for sgn in (-1, 1):
-            a = np.floor((centre + sgn * alias_bins) / geo.band_bins).astype(np.int64)
-            cand.append(np.where((a >= 0) & (a < geo.n_bands), a, -1))
-        c = np.concatenate(cand, axis=1)
-        return float(np.mean((c == band[:, None]).any(axis=1)[ok]))
+    # --- agreement, on every object ------------------------------------------
+    ref = pk64 if pk64 is not None else pk32
+    ref_name = "fp64" if pk64 is not None else "fp32"
+    ok = ref["status"] == 0
+    kinds = w.kind if w.kind is not None else np.zeros(w.n_obj, np.int32)
 
-    def expand_cover(n_first, n_exp, fn):
-        first = used[:, :n_first]
-        cand = [first]
-        for g in fn:
-            a = g(first[:, :n_exp])
-            cand.append(np.where((a >= 0) & (a < geo.n_bands), a, -1))
-        c = np.concatenate(cand, axis=1)
-        return float(np.mean((c == band[:, None]).any(axis=1)[ok]))
+    def agreement(pk):
+        hit = np.abs(pk["index"] - ref["index"]) <= 1
+        d = {"all": float(hit[ok].mean())}
+        for kv, kn in KIND_NAMES.items():
+            m = ok & (kinds == kv)
+            if m.any():
+                d[kn] = float(hit[m].mean())
+        d["statuses_equal"] = bool(np.array_equal(pk["status"], ref["status"]))
+        return d
 
-    def fband(b, scale):  # band holding scale x the frequency at band b's centre
-        f = w.f_min + (b + 0.5) * geo.band_bins * (w.f_max - w.f_min) / w.n_f
-        return np.floor((scale * f - w.f_min) / (w.f_max - w.f_min) * w.n_f
-                        / geo.band_bins).astype(np.int64)
+    form_rec = {}
+    f32 = {"ms_per_step": ms32, "steps": args.steps, "objects_per_s": w.n_obj / (ms32 * 1e-3),
+           "evals_per_s": w.evals / (ms32 * 1e-3), "main_kernel_ms": k_ms,
+           "launch": {k: shape[k] for k in ("k_per_lane", "waves_per_wg", "schedule",
+                                            "recurrence", "tile_freqs", "n_items")}}
+    if pk64 is not None:
+        f32["peak_bin_agreement_vs_fp64"] = agreement(pk32)
+        # power error at both peak indices (FP32 form against the FP64 form)
+        p32_at_64 = bin_values(w, tt, lsp.FORM_FP32P, np.where(ok, ref["index"], -1), method,
+                               dy)
+        p64_at_32 = bin_values(w, tt, lsp.FORM_FP64, np.where(ok, pk32["index"], -1), method,
+                               dy)
+        d1 = np.abs(p32_at_64[ok] - ref["power"][ok])
+        d2 = np.abs(pk32["power"][ok] - p64_at_32[ok])
+        f32["max_abs_dpower_vs_fp64_at_both_peaks"] = float(max(d1.max(), d2.max()))
+    form_rec["fp32"] = f32
+    if lrn is not None:
+        prop, runs = lrn
+        band = np.where(ok, ref["index"] // prop.geo.band_bins, -2)
+        for pr, r in runs.items():
+            pk, idx = r.pop("_peaks"), r.pop("_idx")
+            r["peak_bin_agreement_vs_" + ref_name] = agreement(pk)
+            r["peak_bin_agreement_vs_fp32"] = float(np.mean(
+                np.abs(pk["index"][ok] - pk32["index"][ok]) <= 1))
+            r["proposal_covers_peak_band"] = float(np.mean((idx == band[:, None]).any(axis=1)[ok]))
+            if pk64 is not None:
+                p64_at_l = bin_values(w, tt, lsp.FORM_FP64, np.where(ok, pk["index"], -1),
+                                      method, dy)
+                r["max_abs_dpower_vs_fp64_at_own_peak"] = float(np.max(
+                    np.abs(pk["power"][ok] - p64_at_l[ok])))
+        form_rec["learned"] = {"default_proposal": args.proposal, "proposals": runs,
+                               "train_objects": prop.n_train, "val_objects": prop.n_val,
+                               "train_seconds": prop.train_seconds,
+                               "train_loss": [prop.history[0], prop.history[-1]],
+                               "network": "1088-512-256-64 BF16 MFMA, FP32 accumulation"}
+    if ms64 is not None:
+        form_rec["fp64"] = {"ms_per_step": ms64, "steps": steps64,
+                            "objects_per_s": w.n_obj / (ms64 * 1e-3),
+                            "evals_per_s": w.evals / (ms64 * 1e-3)}
+        form_rec["fp32"]["speedup_vs_fp64"] = ms64 / ms32
+        if lrn is not None:
+            for r in lrn[1].values():
+                r["speedup_vs_fp64"] = ms64 / r["ms_per_step"]
+                r["speedup_vs_fp32_whole_grid"] = ms32 / r["ms_per_step"]
 
-    alias_hits = {"top4+aliases_of_top2": alias_cover(4, 2), "top6+aliases_of_top1": alias_cover(6, 1),
-                  "top2+aliases_of_top2": alias_cover(2, 2), "top8": alias_cover(8, 0),
-                  "top4+neighbours_of_top2": expand_cover(4, 2, (lambda b: b - 1, lambda b: b + 1)),
-                  "top4+half_double_of_top2": expand_cover(4, 2, (lambda b: fband(b, 0.5),
-                                                                  lambda b: fband(b, 2.0))),
-                  "top16": float(np.mean((np.argsort(-lp.logits.float().cpu().numpy(), axis=1)
-                                          [:, :16] == band[:, None]).any(axis=1)[ok]))}
-    log(f"[bench] alias coverage {alias_hits}")
-    hit_heur = hit(lp.idx_coarse) if lp.proposal == "hybrid" else None
-    refine_only = lp.peaks()
-    rec_refine = float(np.mean(np.abs(refine_only["index"][ok] - ref32["index"][ok]) <= 1))
-    rec32 = float(np.mean(np.abs(pk["index"][ok] - ref32["index"][ok]) <= 1))
-    rec64 = float(np.mean(np.abs(pk["index"][ok] - ref64["index"][ok]) <= 1))
-    evals = w.evals
-    refine_evals = float(np.sum(np.diff(w.offsets))) * 8 * geo.band_bins
+    rec_name = "rotation" if shape["recurrence"] == lsp.REC_ROTATION else "chebyshev"
+    k_lane = shape["k_per_lane"]
+    flops_eval = FLOPS_PER_EVAL_GEN if gen else FLOPS_PER_EVAL[rec_name]
+    achieved = flops_eval * w.evals / (k_ms * 1e-3) / 1e12
+    valu_ops = (valu_ops_per_eval_gen(k_lane) if gen else valu_ops_per_eval(rec_name, k_lane)) \
+        * w.evals / (k_ms * 1e-3)
     out = {
-        "metric": METRIC, "value": evals / (ms_l * 1e-3), "unit": "evals/s (whole-grid equivalent)",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_l,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+        "metric": METRIC,
+        "value": w.evals / (ms32 * 1e-3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n_obj": w.n_obj,
-                   "n_t": "%d..%d" % (int(np.diff(w.offsets).min()), int(np.diff(w.offsets).max())),
+                   "n_t": "U{%d..%d}" % (int(n_t.min()), int(n_t.max()))
+                   if not name.startswith("asteroids") else "log-normal",
                    "n_obs": int(w.n_obs), "n_f": w.n_f, "f_range": [w.f_min, w.f_max],
                    "unit": "rad/day" if w.unit == 1 else "cycles/day",
-                   "bands": geo.n_bands, "band_bins": geo.band_bins, "top": lp.top,
-                   "network": "1088-512-256-64 BF16 MFMA", "output": "peaks", "method": method},
-        "objects_per_s": w.n_obj / (ms_l * 1e-3),
-        "whole_grid_fp32": {"ms_per_step": ms_32, "objects_per_s": w.n_obj / (ms_32 * 1e-3),
-                            "evals_per_s": evals / (ms_32 * 1e-3)},
-        "fp64_reference": {"ms_per_step": ms_64, "objects_per_s": w.n_obj / (ms_64 * 1e-3),
-                           "evals_per_s": evals / (ms_64 * 1e-3)},
-        "speedup_vs_whole_grid_fp32": ms_32 / ms_l, "speedup_vs_fp64": ms_64 / ms_l,
-        "fallback_objects": lp.n_fallback, "refined_evals": refine_evals,
-        "peak_bin_agreement": rec32, "peak_bin_agreement_vs_fp64": rec64,
-        "peak_bin_agreement_refine_only": rec_refine,
-        "proposal": lp.proposal, "top_network": lp.top_net,
-        "alias_coverage_diagnostic": alias_hits,
-        "proposal_hit_rate": {"used": hit_used, "network_top8": hit_net,
-                              "coarse_power_top8": hit_heur},
-        "thresholds": {"mass_min": mass_min, "power_min": power_min},
-        "stages": stages, "train_loss": [hist[0], hist[-1]],
+                   "timed_form": "fp32 sums, fp64 phase reduction, whole grid",
+                   "output": "peaks", "method": method},
+        "objects_per_s": w.n_obj / (ms32 * 1e-3),
+        "forms": form_rec,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": measured_traffic(args.method, w.name),
+            "kernel": "gen_fp32p_kernel" if gen else "fp32p_kernel",
+            "kernel_ms": k_ms,
+            "flops_per_eval": flops_eval,
+            "evals_per_launch": int(w.evals),
+            "recurrence": rec_name,
+            "k_per_lane": k_lane,
+            "valu_lane_ops_per_s": valu_ops,
+            "valu_issue_frac": valu_ops / (PEAK_FP32_TFLOPS * 1e12 / 2),
+            "transcendentals_per_s": 2 * w.evals / k_lane / (k_ms * 1e-3),
+        },
+        "cpu_baseline": None,
     }
+    if not args.no_cpu:
+        threads, aff = host_threads(args.cpu_threads)
+        log(f"[bench] oracle on {threads} threads (affinity {aff})")
+        extra = [ref["index"], pk32["index"]]
+        objs, bins, ora, cb = oracle_subset(w, args.oracle_objects, args.cpu_evals, threads,
+                                            extra, method)
+        cb["cpu_model"] = cpu_model()
+        cb["affinity_cores"] = aff
+        out["cpu_baseline"] = cb
+        k = int(objs.max()) + 1
+        chk = {"objects": k, "pairs": int(len(bins))}
+        flat = torch.as_tensor(objs * w.n_f + bins, device=dev)
+        for fname, form in (("fp32", lsp.FORM_FP32P), ("fp64", lsp.FORM_FP64)):
+            if fname == "fp64" and "fp64" not in forms:
+                continue
+            kw = dict(recurrence=rec, schedule=sched, k=args.k, waves=args.waves) \
+                if form == lsp.FORM_FP32P else {}
+            sub = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, offsets=off[:k + 1], form=form,
+                                  pgram=True, peaks=True, unit=w.unit, method=method, dy=dy,
+                                  pgram_dtype=lsp.PGRAM_F64 if form == lsp.FORM_FP64
+                                  else lsp.PGRAM_F32, **kw)
+            sub()
+            got = sub.pgram.view(-1)[flat].double().cpu().numpy()
+            spk = sub.peaks()
+            full_pk = pk32 if form == lsp.FORM_FP32P else pk64
+            same = bool(np.array_equal(spk[:k].tobytes(), full_pk[:k].tobytes()))
+            d = np.abs(got - ora)
+            chk[fname] = {"max_abs_dpower": float(np.nanmax(d)),
+                          "max_rel_dpower": float(np.nanmax(d / np.maximum(ora, 1e-3))),
+                          "subset_peaks_equal_full_run": same}
+            del sub
+        out["oracle_check"] = chk
+        log(f"[bench] oracle check {chk}")
     print(json.dumps(out), flush=True)
 
 

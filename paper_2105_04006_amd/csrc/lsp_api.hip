@@ -708,6 +708,37 @@ void lsp_plan_destroy(lsp_plan plan) {
     delete plan;
 }
 
+lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
+                               const lsp_options* opt_in, int32_t generalized,
+                               lsp_options* resolved, int64_t* tile_freqs, int64_t* n_items) {
+    if (!grid || !resolved || n_obj < 1 || n_obs < 0 || !lsp::is_bool(generalized))
+        return LSP_EINVAL;
+    if (!lsp::valid_grid(grid)) return LSP_EINVAL;
+    const lsp_options opt = opt_in ? *opt_in : lsp_default_options();
+    lsp_status st = lsp::valid_options(&opt);
+    if (st != LSP_OK) return st;
+    lsp::Method method;
+    method.gen = generalized != 0;
+    lsp::Config c;
+    st = lsp::resolve(n_obj, n_obs, grid, &opt, lsp::whole_grid(n_obj, grid), &c, method);
+    if (st != LSP_OK) return st;
+    lsp_options r = opt;
+    r.k_per_lane = c.k;
+    r.waves_per_wg = c.waves;
+    r.t_split = c.split;
+    r.schedule = c.persistent ? LSP_SCHED_PERSISTENT : LSP_SCHED_GRID;
+    if (c.form == LSP_FORM_FP32P) {
+        r.recurrence = c.rec;
+        r.wave_split = c.ws ? LSP_WSPLIT_ON : LSP_WSPLIT_OFF;
+        r.obs_read = c.obs;
+        r.seed_trig = c.trig;
+    }
+    *resolved = r;
+    if (tile_freqs) *tile_freqs = c.tile_freqs;
+    if (n_items) *n_items = c.n_items;
+    return LSP_OK;
+}
+
 lsp_status lsp_set_stage_events(void* main_begin, void* main_end) {
     if ((main_begin == nullptr) != (main_end == nullptr)) return LSP_EINVAL;
     lsp::t_main_begin = static_cast<hipEvent_t>(main_begin);

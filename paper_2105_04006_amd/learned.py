@@ -316,13 +316,14 @@ class LearnedPeriodogram:
         L = lsp.lib()
         n, nb = self.n_obj, self.geo.n_bands
         feats = self.net.normalize_rows(self.feat(stream), stream=stream)
-        self.net.standardize(feats, out=self.x, stream=stream)
-        self.net.forward(self.x, logits=self.logits, stream=stream)
-        first = self.idx if self.proposal == "network" else self.idx_net
-        _ok(L.lsp_top_k(_p(self.logits), n, nb, self.top_net, _p(first), _p(self.mass),
-                        _s(stream)), "lsp_top_k")
-        if self.proposal == "network":
-            return
+        if self.proposal != "coarse":  # "coarse": the method without the network
+            self.net.standardize(feats, out=self.x, stream=stream)
+            self.net.forward(self.x, logits=self.logits, stream=stream)
+            first = self.idx if self.proposal == "network" else self.idx_net
+            _ok(L.lsp_top_k(_p(self.logits), n, nb, self.top_net, _p(first), _p(self.mass),
+                            _s(stream)), "lsp_top_k")
+            if self.proposal == "network":
+                return
         # row normalisation is increasing within a row, so band maxima of the
         # normalised coarse block rank bands as the raw power does
         _ok(L.lsp_band_max(_p(feats), n, feats.shape[1], 0, nb, lsp.FEAT_COARSE // nb,
@@ -341,7 +342,9 @@ class LearnedPeriodogram:
 
     def __call__(self, stream=None):
         self.refine_only(stream)
-        select_fallback(self.peaks_raw, self.mass, self.n_obj, self.mass_min, self.power_min,
+        # the coarse rule has no proposal mass: only the refined power decides
+        mass = None if self.proposal == "coarse" else self.mass
+        select_fallback(self.peaks_raw, mass, self.n_obj, self.mass_min, self.power_min,
                         self.objects, self.count, stream)
         n = int(self.count.item())  # synchronises: sizes the fallback launch
         self.n_fallback = n
@@ -419,7 +422,8 @@ def calibrate(refined, full, mass, target=0.999):
     """Thresholds (mass_min, power_min) that keep the recovery rate on a
     validation set at or above `target` with the fewest fallbacks.
 
-    refined, full: peak arrays (refine only, whole grid); mass: proposal mass.
+    refined, full: peak arrays (refine only, whole grid); mass: proposal mass
+    (None for a rule that has none).
     An object is recovered if its refined peak is within one bin of the
     whole-grid peak; a fallback object is recovered by construction."""
     ok = full["status"] == 0
@@ -430,7 +434,11 @@ def calibrate(refined, full, mass, target=0.999):
     if n == 0:
         return 0.0, 0.0, 0
     q = np.linspace(0.0, 1.0, 101)
-    m_grid = np.unique(np.concatenate([[0.0], np.quantile(mass[ok], q), [2.0]]))
+    if mass is None:  # a rule without proposal mass: only the power threshold
+        mass = np.ones(len(refined), np.float32)
+        m_grid = np.zeros(1)
+    else:
+        m_grid = np.unique(np.concatenate([[0.0], np.quantile(mass[ok], q), [2.0]]))
     p_grid = np.unique(np.concatenate([[0.0], np.quantile(pw[ok], q), [2.0]]))
     best = (2.0, 2.0, n + 1)
     for mm in m_grid:
@@ -440,3 +448,91 @@ def calibrate(refined, full, mass, target=0.999):
             if miss <= allowed and int(fb.sum()) < best[2]:
                 best = (float(mm), float(pm), int(fb.sum()))
     return best
+
+
+def _tensors(w, device):
+    return (torch.as_tensor(w.offsets, device=device), torch.as_tensor(w.t, device=device),
+            torch.as_tensor(w.y, device=device))
+
+
+def _errors(w, device, method):
+    return torch.as_tensor(w.dy, device=device) if method == "generalized" else None
+
+
+def whole_grid_peaks(w, tensors, method="standard", dy=None):
+    """Peaks of a whole CSR batch on its full grid (FP32 form): the labels of
+    training and the reference of calibration."""
+    off, t, y = tensors
+    p = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, offsets=off, form=lsp.FORM_FP32P,
+                        pgram=False, unit=w.unit, method=method, dy=dy)
+    p()
+    return p
+
+
+class Proposer:
+    """A trained band-proposal network with its band geometry and the fallback
+    thresholds calibrated for each proposal rule (see fit_proposer)."""
+
+    def __init__(self, net, geometry, thresholds, history, train_seconds, n_train, n_val):
+        self.net, self.geo = net, geometry
+        self.thresholds = thresholds  # proposal -> (mass_min, power_min, validation fallbacks)
+        self.history = history
+        self.train_seconds = train_seconds
+        self.n_train, self.n_val = n_train, n_val
+
+    def periodogram(self, offsets, t, y, f_min, f_max, unit=lsp.CYCLES, proposal="hybrid",
+                    method="standard", dy=None, **kw):
+        mass_min, power_min, _ = self.thresholds[proposal]
+        return LearnedPeriodogram(self.net, self.geo, offsets, t, y, f_min, f_max, unit=unit,
+                                  mass_min=mass_min, power_min=power_min, proposal=proposal,
+                                  method=method, dy=dy, **kw)
+
+
+def fit_proposer(make, device, n_train=40000, n_val=20000, seed_train=None, seed_val=None,
+                 n_bands=64, method="standard", proposals=("hybrid",), epochs=30, batch=512,
+                 target=0.999, net_seed=7, log=None):
+    """Train the proposal network on objects the method itself labels, then
+    calibrate the fallback thresholds on independent objects.
+
+    make(n_obj, seed) returns a synthetic Workload of the target population
+    (its grid is the grid the proposals are for).  Training labels are the
+    bands of the whole-grid FP32 peaks of n_train objects; for every rule in
+    `proposals` the thresholds are chosen on n_val other objects so that at
+    least `target` of them recover the whole-grid peak within one bin with the
+    fewest fallbacks (calibrate)."""
+    import time
+
+    wtr = make(n_train, seed_train)
+    geo = BandGeometry(wtr.n_f, n_bands)
+    ttr = _tensors(wtr, device)
+    feats = lsp.Features(*ttr, wtr.f_min, wtr.f_max, unit=wtr.unit)()
+    ptr = whole_grid_peaks(wtr, ttr, method, _errors(wtr, device, method))
+    labels = peak_bands(ptr.peaks_raw, wtr.n_obj, geo.band_bins, geo.n_bands)
+    net = BandNet(device, seed=net_seed, dims=DIMS[:-1] + (n_bands,))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train_proposer(net, feats, labels, epochs=epochs, batch=batch, lr=1e-3,
+                          lr_final=3e-5, augment=0.9)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    if log:
+        log(f"trained on {wtr.n_obj} objects in {train_s:.1f} s, loss {hist[0]:.3f} -> "
+            f"{hist[-1]:.3f}")
+    del feats, ptr, ttr, labels
+    wva = make(n_val, seed_val)
+    tva = _tensors(wva, device)
+    dva = _errors(wva, device, method)
+    full = whole_grid_peaks(wva, tva, method, dva).peaks()
+    thresholds = {}
+    for prop in proposals:
+        lpv = LearnedPeriodogram(net, geo, *tva, wva.f_min, wva.f_max, unit=wva.unit,
+                                 proposal=prop, method=method, dy=dva)
+        lpv.refine_only()
+        mass = None if prop == "coarse" else lpv.mass.cpu().numpy()
+        thresholds[prop] = calibrate(lpv.peaks(), full, mass, target=target)
+        if log:
+            mm, pm, nfb = thresholds[prop]
+            log(f"calibrated {prop}: mass_min={mm:.4f} power_min={pm:.4f}, "
+                f"{nfb}/{wva.n_obj} validation fallbacks")
+        del lpv
+    return Proposer(net, geo, thresholds, hist, train_s, wtr.n_obj, wva.n_obj)

@@ -179,6 +179,11 @@ def lib():
         L.lsp_features.restype = ctypes.c_int
         L.lsp_features.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
                                    ctypes.POINTER(FeatureOptions), vp, vp, sz, vp]
+        L.lsp_describe_launch.restype = ctypes.c_int
+        L.lsp_describe_launch.argtypes = [i64, i64, ctypes.POINTER(Grid), ctypes.POINTER(Options),
+                                          i32, ctypes.POINTER(Options),
+                                          ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64)]
         L.lsp_set_stage_events.restype = ctypes.c_int
         L.lsp_set_stage_events.argtypes = [vp, vp]
         L.lsp_version.restype = ctypes.c_int32
@@ -200,6 +205,22 @@ def set_stage_events(begin, end):
     st = lib().lsp_set_stage_events(begin, end)
     if st != OK:
         raise LspError(st, "lsp_set_stage_events")
+
+
+def describe_launch(n_obj, n_obs, grid, opt, generalized=False):
+    """The launch shape a whole-grid call resolves (lsp_describe_launch):
+    a dict with the resolved k_per_lane, waves_per_wg, t_split, schedule,
+    recurrence, wave_split, obs_read, seed_trig, tile_freqs and n_items."""
+    out = Options()
+    tf, ni = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = lib().lsp_describe_launch(int(n_obj), int(n_obs), ctypes.byref(grid), ctypes.byref(opt),
+                                   int(bool(generalized)), ctypes.byref(out), ctypes.byref(tf),
+                                   ctypes.byref(ni))
+    if st != OK:
+        raise LspError(st, "lsp_describe_launch")
+    d = {name: int(getattr(out, name)) for name, _ in Options._fields_}
+    d["tile_freqs"], d["n_items"] = int(tf.value), int(ni.value)
+    return d
 
 
 def status_string(status):
@@ -339,6 +360,10 @@ class Periodogram:
         if st != OK:
             raise LspError(st, what)
         return self
+
+    def launch(self):
+        """The launch shape this call resolves (see describe_launch)."""
+        return describe_launch(self.n_obj, self.n_obs, self.grid, self.opt, self.gen)
 
     def capture(self):
         """Record this call into a HIP graph (lsp_plan_create or

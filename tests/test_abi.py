@@ -343,3 +343,37 @@ def test_gen_rows_and_plan_argument_errors(L):
                                  FAKE, FAKE, FAKE, 1 << 30, None) == lsp.EINVAL
     assert L.lsp_gen_plan_create(FAKE, 3, 30, FAKE, FAKE, None, ctypes.byref(g), ctypes.byref(o),
                                  FAKE, FAKE, FAKE, 1, ctypes.byref(h)) == lsp.ENOMEM
+
+
+def test_describe_launch_resolves_the_shape():
+    """lsp_describe_launch reports the configuration the call would use: the
+    cost model's K for the FP32 form, the single-object observation split, the
+    persistent schedule for batches, and the caller's explicit choices."""
+    g = lsp.make_grid(0.5, 24.0, 500_000)
+    one = lsp.describe_launch(1, 4096, g, lsp.make_options(form=lsp.FORM_FP32P))
+    assert one["k_per_lane"] in (8, 10, 12, 16) and one["waves_per_wg"] == 4
+    assert one["t_split"] > 1 and one["schedule"] == lsp.SCHED_GRID
+    assert one["recurrence"] == lsp.REC_CHEBYSHEV
+    assert one["tile_freqs"] == 64 * one["k_per_lane"] * one["waves_per_wg"]
+    tiles = -(-500_000 // one["tile_freqs"])
+    assert one["n_items"] == tiles * one["t_split"]
+    gb = lsp.make_grid(0.5, 24.0, 250_000)
+    many = lsp.describe_launch(200_000, 52_000_000, gb, lsp.make_options(form=lsp.FORM_FP32P))
+    assert many["schedule"] == lsp.SCHED_PERSISTENT and many["t_split"] == 1
+    assert many["waves_per_wg"] == 1
+    assert many["n_items"] == 200_000 * -(-250_000 // many["tile_freqs"])
+    fixed = lsp.describe_launch(10, 5000, gb, lsp.make_options(
+        form=lsp.FORM_FP32P, k=12, recurrence=lsp.REC_ROTATION, schedule=lsp.SCHED_GRID))
+    assert (fixed["k_per_lane"], fixed["recurrence"], fixed["schedule"]) == \
+        (12, lsp.REC_ROTATION, lsp.SCHED_GRID)
+    f64 = lsp.describe_launch(10, 5000, gb, lsp.make_options(form=lsp.FORM_FP64))
+    assert f64["k_per_lane"] in (1, 2, 4) and f64["schedule"] == lsp.SCHED_GRID
+    gen = lsp.describe_launch(10, 5000, gb, lsp.make_options(form=lsp.FORM_FP32P), True)
+    assert gen["k_per_lane"] in (8, 12, 16)
+    with pytest.raises(lsp.LspError):
+        lsp.describe_launch(0, 10, gb, lsp.make_options())
+    with pytest.raises(lsp.LspError):
+        lsp.describe_launch(2, 10, gb, lsp.make_options(form=lsp.FORM_FP32P, t_split=4))
+    with pytest.raises(lsp.LspError):
+        lsp.describe_launch(2, 10, gb, lsp.make_options(form=lsp.FORM_FP32P,
+                                                        recurrence=lsp.REC_ROTATION), True)

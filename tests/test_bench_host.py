@@ -40,10 +40,13 @@ def test_traffic_record_rules(tmp_path, monkeypatch):
     f.write_text(json.dumps(rec))
     monkeypatch.setitem(bench.TRAFFIC_FILES, "standard", str(f))
     assert bench.measured_traffic("standard", "single_4096") == 123
-    assert bench.measured_traffic("standard", "lsst_200k") is None  # other workload
-    # a workload with a record of its own reads that record
-    assert bench.measured_traffic("standard", "batch_10k") == \
-        json.load(open(bench.TRAFFIC_FILES[("standard", "batch_10k")]))["bytes_per_launch"]
+    assert bench.measured_traffic("standard", "learned_100k") is None  # other workload
+    # a workload with a record of its own reads that record while it was taken
+    # on the current kernel source
+    own = json.load(open(bench.TRAFFIC_FILES[("standard", "batch_10k")]))
+    expect = own["bytes_per_launch"] if own["kernel_hash"] == bench.kernel_hash("standard") \
+        else None
+    assert bench.measured_traffic("standard", "batch_10k") == expect
     rec["kernel_hash"] = "0" * 16  # taken on another kernel source
     f.write_text(json.dumps(rec))
     assert bench.measured_traffic("standard", "single_4096") is None

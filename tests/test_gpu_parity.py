@@ -333,12 +333,14 @@ def test_full_single_4096(dev):
     say(f"single_4096 full n_f={w.n_f}")
     pg64, pk64 = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64,
                             pgram_dtype=lsp.PGRAM_F64)
-    pg32, pk32 = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P)
+    pg32, pk32 = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P,
+                            recurrence=lsp.REC_ROTATION)
     pgc, pkc = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P,
                           recurrence=lsp.REC_CHEBYSHEV)
     say(f"    rotation max |dP| vs fp64 {np.max(np.abs(pg32 - pg64)):.3g}, "
         f"chebyshev {np.max(np.abs(pgc - pg64)):.3g}")
     assert_fp32_close(pgc, pg64, "single_4096 chebyshev vs fp64 (all bins)")
+    assert_fp32_close(pg32, pg64, "single_4096 rotation vs fp64 (all bins)")
     assert abs(int(pkc["index"]) - int(pk64["index"])) <= 1
     rng = np.random.default_rng(0)
     top = np.argsort(pg64)[-64:]
@@ -366,7 +368,7 @@ def test_full_batch_10k_peaks(dev):
     _, pk64 = run_batch(dev, w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64,
                         pgram=False)
     _, pk32 = run_batch(dev, w.offsets, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P,
-                        pgram=False, schedule=lsp.SCHED_PERSISTENT)
+                        pgram=False, schedule=lsp.SCHED_PERSISTENT, recurrence=lsp.REC_ROTATION)
     assert np.all(pk64["status"] == 0) and np.all(pk32["status"] == 0)
     agree = np.abs(pk32["index"] - pk64["index"]) <= 1
     assert agree.mean() >= 0.999, f"peak agreement {agree.mean():.4%}"

@@ -21,9 +21,9 @@ TOL = 1e-11
 
 
 def _pnorm_mp(t, y, w, dy=None):
-    """Normalised power at angular frequency w, 40 digits: Eq. 1 and 2 (or
-    the generalized method's weighted, mean-fitted form) on raw times."""
-    mp.mp.dps = 40
+    """Normalised power at angular frequency w (an mpmath number formed at the
+    working precision, 40 digits): Eq. 1 and 2 (or the generalized method's
+    weighted, mean-fitted form) on raw times."""
     tm = [mp.mpf(float(v)) for v in t]
     if dy is None:
         wt = [mp.mpf(1)] * len(tm)
@@ -64,6 +64,7 @@ def _pnorm_mp(t, y, w, dy=None):
 
 
 def _check(unit, gen):
+    mp.mp.dps = 40  # before any angular frequency is formed in mpmath
     ora = oracle.default()
     w = synth.make_workload("lsst_200k", n_obj=12, errors=gen)
     rng = np.random.default_rng(11)
