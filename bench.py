@@ -933,8 +933,12 @@ def bench_forms(args, torch, dev):
             full_pk = pk32 if form == lsp.FORM_FP32P else pk64
             same = bool(np.array_equal(spk[:k].tobytes(), full_pk[:k].tobytes()))
             d = np.abs(got - ora)
+            rel = d / np.maximum(ora, 1e-3)
+            k_w = int(np.nanargmax(rel))
             chk[fname] = {"max_abs_dpower": float(np.nanmax(d)),
-                          "max_rel_dpower": float(np.nanmax(d / np.maximum(ora, 1e-3))),
+                          "max_rel_dpower": float(rel[k_w]),
+                          "worst_pair": {"object": int(objs[k_w]), "bin": int(bins[k_w]),
+                                         "p_oracle": float(ora[k_w]), "p_gpu": float(got[k_w])},
                           "subset_peaks_equal_full_run": same}
             del sub
         out["oracle_check"] = chk

@@ -53,9 +53,13 @@ struct PeakRec {
 };
 
 // Frequency of grid index i, rounded exactly as f_min + df * i written out in
-// IEEE double (no fused multiply-add), so every path agrees on the grid.
+// IEEE double: the product and the sum each rounded, never fused, so every
+// path (and the oracle) evaluates the same frequencies.  HIP's __dmul_rn and
+// __dadd_rn are plain operators that the compiler may still fuse; the pragma
+// is what forbids it.
 __device__ __forceinline__ double grid_freq(double f_min, double df, int64_t i) {
-    return __dadd_rn(f_min, __dmul_rn(df, (double)i));
+#pragma clang fp contract(off)
+    return f_min + df * (double)i;
 }
 
 // (p, i) ordering of the argmax: larger power wins, lower index on ties; NaN
@@ -81,23 +85,25 @@ __device__ __forceinline__ PeakRec wave_best(PeakRec r) {
 // hi + lo of its rounded value and the rounding error (Knuth's two-sum, exact
 // for any two doubles).
 __device__ __forceinline__ void recentre64(double t, double t0, double* hi, double* lo) {
-    const double s = __dsub_rn(t, t0);
-    const double bb = __dsub_rn(s, t);
+#pragma clang fp contract(off)
+    const double s = t - t0;
+    const double bb = s - t;
     *hi = s;
-    *lo = __dsub_rn(__dsub_rn(t, __dsub_rn(s, bb)), __dadd_rn(t0, bb));
+    *lo = (t - (s - bb)) - (t0 + bb);
 }
 
 // sin and cos of 2 pi f (hi + lo) for a re-centred time hi + lo (recentre64):
 // the product f hi is split exactly into p + e with a fused multiply-add, the
 // whole cycles of p are removed exactly, and e + f lo is added back, so the
 // phase handed to the library is off by its final rounding only (~6e-17
-// cycles), whatever the frequency and time span.  The explicit-rounding
-// intrinsics keep the compiler from fusing the steps of this split.
+// cycles), whatever the frequency and time span.  Contraction is off: fusing
+// p - rint(p) into fma(f, hi, -rint(p)) would count e twice.
 __device__ __forceinline__ void sincos_cycles64(double f_cyc, double hi, double lo, double* s,
                                                 double* c) {
-    const double p = __dmul_rn(f_cyc, hi);
+#pragma clang fp contract(off)
+    const double p = f_cyc * hi;
     const double e = fma(f_cyc, hi, -p);
-    const double r = __dadd_rn(__dsub_rn(p, rint(p)), fma(f_cyc, lo, e));
+    const double r = (p - rint(p)) + fma(f_cyc, lo, e);
     sincospi(2.0 * r, s, c);
 }
 
