@@ -40,7 +40,9 @@ typedef enum {
     LSP_EINVAL = 1,       /* bad argument (NULL pointer, empty grid, bad enum ...) */
     LSP_ENOMEM = 2,       /* workspace smaller than lsp_workspace_bytes()          */
     LSP_EHIP = 3,         /* the HIP runtime refused a launch                      */
-    LSP_EUNSUPPORTED = 4  /* valid but unsupported combination of options          */
+    LSP_EUNSUPPORTED = 4, /* valid but unsupported combination of options          */
+    LSP_ESCRATCH = 5      /* lsp_batch_static: the call needs more scratch than the
+                             library's static device array holds                    */
 } lsp_status;
 
 /* Per-object status carried in lsp_peak.status. */
@@ -208,6 +210,30 @@ lsp_status lsp_single(const double *t, const double *y, int64_t n_t, const lsp_g
 lsp_status lsp_batch(const int64_t *offsets, int64_t n_obj, int64_t n_obs, const double *t,
                      const double *y, const lsp_grid *grid, const lsp_options *opt, void *pgram,
                      lsp_peak *peaks, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * lsp_batch without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The scratch lsp_batch takes from `workspace` comes
+ * instead from a static device array of LSP_STATIC_SCRATCH_BYTES that every
+ * GPU the library runs on holds from the library's first use on it until the
+ * process ends.  The call allocates nothing and, like lsp_batch, enqueues only
+ * kernels on `stream`; its results equal lsp_batch's bit for bit (same
+ * kernels, same launch configuration).
+ *   All arguments: as lsp_batch.
+ * The array's contents persist from call to call (each call re-initialises
+ * what it reads), and all calls on one GPU share it: calls that overlap on
+ * one GPU -- concurrent streams, host threads, or graph launches that may run
+ * at the same time -- race and must be serialised by the caller.
+ * Errors: as lsp_batch; LSP_ESCRATCH (nothing enqueued) when
+ * lsp_workspace_bytes(n_obj, n_obs, grid, opt) exceeds
+ * LSP_STATIC_SCRATCH_BYTES; LSP_EHIP if the array's device address cannot
+ * be obtained.
+ */
+#define LSP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+lsp_status lsp_batch_static(const int64_t *offsets, int64_t n_obj, int64_t n_obs,
+                            const double *t, const double *y, const lsp_grid *grid,
+                            const lsp_options *opt, void *pgram, lsp_peak *peaks, void *stream);
 
 /*
  * Generalized periodogram (Section 4.11): each observation carries an error

@@ -8,6 +8,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <new>
 
 #include "lsp_common.h"
@@ -481,6 +482,32 @@ struct lsp_plan_s {
     hipGraphExec_t exec;
 };
 
+// Scratch of lsp_batch_static: one copy of this array lives on every device
+// the library's code object is loaded on.  In host code `scratch` is only a
+// stand-in symbol, never a device address: the address is looked up once per
+// device with hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[LSP_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// The calling thread's current device and its copy of `scratch` (nullptr on
+// failure).  The lookup runs once per device, with that device current.
+void* device_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void* ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    });
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 extern "C" {
 
 lsp_options lsp_default_options(void) {
@@ -549,6 +576,26 @@ lsp_status lsp_batch(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const
     if (!offsets) return LSP_EINVAL;
     return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, workspace,
                     workspace_bytes, stream, lsp::whole_grid(n_obj, grid));
+}
+
+lsp_status lsp_batch_static(const int64_t* offsets, int64_t n_obj, int64_t n_obs,
+                            const double* t, const double* y, const lsp_grid* grid,
+                            const lsp_options* opt, void* pgram, lsp_peak* peaks, void* stream) {
+    if (!offsets || !grid) return LSP_EINVAL;
+    const size_t need = lsp_workspace_bytes(n_obj, n_obs, grid, opt);
+    if (need == 0) {
+        // invalid arguments: let the common validation name the error (the
+        // stand-in workspace is never dereferenced)
+        alignas(256) static const unsigned char kStandIn[1] = {0};
+        const lsp_status st = lsp::validate(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks,
+                                            kStandIn, 0, lsp::whole_grid(n_obj, grid));
+        return st == LSP_OK || st == LSP_ENOMEM ? LSP_EINVAL : st;
+    }
+    if (need > LSP_STATIC_SCRATCH_BYTES) return LSP_ESCRATCH;
+    void* ws = device_scratch();
+    if (!ws) return LSP_EHIP;
+    return lsp::run(offsets, n_obj, n_obs, t, y, grid, opt, pgram, peaks, ws,
+                    LSP_STATIC_SCRATCH_BYTES, stream, lsp::whole_grid(n_obj, grid));
 }
 
 size_t lsp_gen_workspace_bytes(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
@@ -753,6 +800,7 @@ const char* lsp_status_string(lsp_status status) {
         case LSP_ENOMEM: return "workspace too small";
         case LSP_EHIP: return "HIP launch failed";
         case LSP_EUNSUPPORTED: return "unsupported option combination";
+        case LSP_ESCRATCH: return "call exceeds the static scratch of lsp_batch_static";
         default: return "unknown status";
     }
 }

@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblsp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lsp.h")
 
-OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ESCRATCH = 0, 1, 2, 3, 4, 5
+STATIC_SCRATCH_BYTES = 64 << 20  # LSP_STATIC_SCRATCH_BYTES
 OBJ_OK, OBJ_DEGENERATE, OBJ_BADRANGE, OBJ_NONFINITE = 0, 1, 2, 3
 FORM_FP64, FORM_FP32P = 0, 1
 CYCLES, ANGULAR = 0, 1
@@ -88,6 +89,9 @@ def lib():
         L.lsp_batch.restype = ctypes.c_int
         L.lsp_batch.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
                                 ctypes.POINTER(Options), vp, vp, vp, sz, vp]
+        L.lsp_batch_static.restype = ctypes.c_int
+        L.lsp_batch_static.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(Grid),
+                                       ctypes.POINTER(Options), vp, vp, vp]
         L.lsp_gen_workspace_bytes.restype = sz
         L.lsp_gen_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Grid),
                                               ctypes.POINTER(Options)]
@@ -628,6 +632,25 @@ def autotune(t, y, f_min, f_max, n_f, offsets=None, unit=CYCLES, normalize=True,
         raise LspError(st, "lsp_autotune")
     return dict(k=tuned.k_per_lane, waves=tuned.waves_per_wg, recurrence=tuned.recurrence,
                 schedule=tuned.schedule, t_split=tuned.t_split, wave_split=tuned.wave_split)
+
+
+def batch_static(offsets, t, y, f_min, f_max, n_f, pgram=None, peaks=None, unit=CYCLES,
+                 stream=None, **opts):
+    """lsp_batch_static: lsp_batch with the library's static scratch instead of
+    a workspace (nothing is allocated by the call).  pgram / peaks are caller
+    tensors (a [n_obj, n_f] periodogram of the options' dtype, n_obj * 40
+    bytes of peak records); returns the status (raises on anything but OK)."""
+    _check(t, torch.float64, "t")
+    _check(y, torch.float64, "y")
+    _check(offsets, torch.int64, "offsets")
+    grid = make_grid(f_min, f_max, n_f, unit)
+    opt = make_options(**opts)
+    st = lib().lsp_batch_static(_dev_ptr(offsets), int(offsets.numel()) - 1, int(t.numel()),
+                                _dev_ptr(t), _dev_ptr(y), ctypes.byref(grid), ctypes.byref(opt),
+                                _dev_ptr(pgram), _dev_ptr(peaks), _stream_handle(stream))
+    if st != OK:
+        raise LspError(st, "lsp_batch_static")
+    return st
 
 
 def single(t, y, f_min, f_max, n_f, **kw):

@@ -377,3 +377,32 @@ def test_describe_launch_resolves_the_shape():
     with pytest.raises(lsp.LspError):
         lsp.describe_launch(2, 10, gb, lsp.make_options(form=lsp.FORM_FP32P,
                                                         recurrence=lsp.REC_ROTATION), True)
+
+
+@cpu_only
+def test_batch_static_argument_errors(L):
+    """lsp_batch_static rejects bad arguments and calls too large for its
+    static scratch on the host, before looking up any device memory."""
+    g = lsp.make_grid(0.5, 24.0, 250_000)
+    o = lsp.make_options(form=lsp.FORM_FP32P)
+
+    def call(off=FAKE, n_obj=4, n_obs=100, grid=g, opt=o, pgram=None, peaks=FAKE):
+        return L.lsp_batch_static(off, n_obj, n_obs, FAKE, FAKE,
+                                  ctypes.byref(grid) if grid is not None else None,
+                                  ctypes.byref(opt), pgram, peaks, None)
+
+    assert call(off=None) == lsp.EINVAL
+    assert call(grid=None) == lsp.EINVAL
+    assert call(n_obj=0) == lsp.EINVAL
+    assert call(grid=lsp.make_grid(2.0, 1.0, 10)) == lsp.EINVAL
+    assert call(opt=lsp.make_options(form=9)) == lsp.EINVAL
+    assert call(opt=lsp.make_options(form=lsp.FORM_FP32P, t_split=4)) == lsp.EUNSUPPORTED
+    assert lsp.workspace_bytes(200_000, 52_000_000, g, o) > lsp.STATIC_SCRATCH_BYTES
+    assert call(n_obj=200_000, n_obs=52_000_000) == lsp.ESCRATCH
+    assert lsp.status_string(lsp.ESCRATCH) != lsp.status_string(lsp.ENOMEM)
+
+
+def test_static_scratch_size_matches_header():
+    text = open(lsp.HEADER).read()
+    assert "#define LSP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)" in text
+    assert lsp.STATIC_SCRATCH_BYTES == 64 << 20
