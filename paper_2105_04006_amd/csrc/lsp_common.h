@@ -316,6 +316,61 @@ __device__ __forceinline__ void seed_sincos(float r, float* s, float* c) {
     }
 }
 
+// One observation's contribution to a lane's K bins (the FP32 hot loop of the
+// periodogram and of the coarse proposal features): seed (cos, sin) of the
+// lane's first phase, then the recurrence across its bins.  o = (y - ybar,
+// cos step, sin step, -), tq = t - t0.
+template <int K, bool CHEB, int TRIG>
+__device__ __forceinline__ void accumulate_obs(double fl, double tq, float4 o, float (&xc)[K],
+                                               float (&xs)[K], float (&cc)[K], float (&cs)[K]) {
+    double ph = fl * tq;
+    ph -= rint(ph);
+    const float r = (float)ph;
+    float s, c;
+    seed_sincos<TRIG>(r, &s, &c);
+    if (!CHEB) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            xc[k] = fmaf(o.x, c, xc[k]);
+            xs[k] = fmaf(o.x, s, xs[k]);
+            cc[k] = fmaf(c, c, cc[k]);
+            cs[k] = fmaf(c, s, cs[k]);
+            if (k + 1 < K) {
+                const float cn = fmaf(c, o.y, -(s * o.z));
+                s = fmaf(s, o.y, c * o.z);
+                c = cn;
+            }
+        }
+    } else {
+        // One rotation to reach the second frequency, then the three-term
+        // recurrence x_{k+1} = 2C x_k - x_{k-1}, which cos and sin of an
+        // arithmetic progression of angles obey.
+        const float two_c = o.y + o.y;
+        float cp = c, sp = s;
+        c = fmaf(cp, o.y, -(sp * o.z));
+        s = fmaf(sp, o.y, cp * o.z);
+        xc[0] = fmaf(o.x, cp, xc[0]);
+        xs[0] = fmaf(o.x, sp, xs[0]);
+        cc[0] = fmaf(cp, cp, cc[0]);
+        cs[0] = fmaf(cp, sp, cs[0]);
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            xc[k] = fmaf(o.x, c, xc[k]);
+            xs[k] = fmaf(o.x, s, xs[k]);
+            cc[k] = fmaf(c, c, cc[k]);
+            cs[k] = fmaf(c, s, cs[k]);
+            if (k + 1 < K) {
+                const float cn = fmaf(two_c, c, -cp);
+                const float sn = fmaf(two_c, s, -sp);
+                cp = c;
+                sp = s;
+                c = cn;
+                s = sn;
+            }
+        }
+    }
+}
+
 // Value written for every bin of an object whose status is not OK.
 __device__ __forceinline__ double fill_value(int32_t status) {
     return status == LSP_OBJ_DEGENERATE ? 0.0 : __builtin_nan("");

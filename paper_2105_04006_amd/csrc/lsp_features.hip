@@ -14,9 +14,10 @@
 //     [f_min, f_max), max-pooled over runs of 8 bins and averaged over the
 //     groups -> features [0, 1024).  The group's own mean is not removed
 //     again: that only changes power near zero frequency, and it keeps the
-//     loop identical to the FP32 hot loop of the main kernel (FP64 phase
+//     loop the FP32 hot loop of the main kernel (accumulate_obs: FP64 phase
 //     reduction, hardware sin/cos per observation, three-term recurrence
-//     across a lane's frequencies, four sums).
+//     across a lane's frequencies, four sums), with the same FP64 recompute
+//     of bins FP32 cannot resolve.
 //   window_kernel : one wavefront per object computes sampling and magnitude
 //     statistics in FP64 and the spectral window at 53 probe frequencies
 //     (FP64 phases, hardware FP32 sin/cos, FP64 sums) -> features [1024, 1088).
@@ -35,7 +36,6 @@ constexpr int kCoarseK = 16;     // frequencies per lane
 constexpr int kCoarseW = 1;      // wavefronts per workgroup
 constexpr int kCoarseTile = kWave * kCoarseK * kCoarseW;  // 1,024 bins
 constexpr int kTilesPerObj = LSP_FEAT_COARSE * LSP_FEAT_POOL / kCoarseTile;
-constexpr float kDenEps32 = 1e-5f;  // drop a term whose denominator is below this * N
 constexpr int kProbes = LSP_FEAT_WINDOW - 11;
 
 static_assert(LSP_FEAT_POOL == 8, "pooling uses three lane-exchange steps");
@@ -54,6 +54,26 @@ struct FeatParams {
     float* out;            // [n_obj][LSP_FEAT_DIM]
     unsigned int* queue;   // kXcds item counters (zeroed before the launch)
 };
+
+// Normalised power of the observations [g0, g0 + n) of one object (magnitudes
+// centred on the object's mean, normalised by the group's own sum of
+// squares) at f_cyc cycles per time unit, in FP64 as the main kernel's FP64
+// form computes it: exact re-centred phases, library sin/cos, Eq. 1-2 through
+// power64 with its drop rule.
+__device__ double group_power64(const double* __restrict__ t, const double* __restrict__ y,
+                                double t0, double ybar, int64_t g0, int64_t n, double f_cyc) {
+    Sums64 a = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double syy = 0.0;
+    for (int64_t j = g0; j < g0 + n; ++j) {
+        double s, c, hi, lo;
+        recentre64(t[j], t0, &hi, &lo);
+        sincos_cycles64(f_cyc, hi, lo, &s, &c);
+        const double yj = y[j] - ybar;
+        sums64_add(a, yj, s, c);
+        syy = fma(yj, yj, syy);
+    }
+    return syy > 0.0 ? power64(a, (double)n, 2.0 / syy) : 0.0;
+}
 
 __device__ __forceinline__ float pool8_max(float v) {
     v = fmaxf(v, __shfl_xor(v, 1, kWave));
@@ -84,18 +104,23 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
         float xc[K], xs[K], cc[K], cs[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
-        // group count and sum of squares of y - ybar (wave-uniform)
+        // group count, first observation and sum of squares of y - ybar
+        // (wave-uniform)
         int ns = 0;
+        int64_t g0 = m.j0;
         float syy = 0.0f;
 
-        // Close the current group: add its pooled power to the features if it
-        // has enough observations.
-        auto close_group = [&]() {
+        // Close the current group, the observations [g0, g0 + ns): add its
+        // pooled power to the features if it has enough observations.  As in
+        // the main kernel, a bin whose smaller shifted denominator N - R is at
+        // most N/32 cannot be resolved in FP32 and is recomputed in FP64 from
+        // the group's observations (group_power64); the others keep the FP32
+        // value, with the hardware reciprocals (about 1 ulp).  The next group
+        // starts at j_next.
+        auto close_group = [&](int64_t j_next) {
             if (ns >= P.min_obs) {
                 const float N = (float)ns;
                 const float inv_s = syy > 0.0f ? 1.0f / syy : 0.0f;
-                // hardware reciprocals (about 1 ulp): the features are inputs
-                // to a ranking, not reported powers
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const float C2 = 2.0f * cc[k] - N;
@@ -107,10 +132,15 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
                                        __builtin_amdgcn_rcpf(R)
                                  : 0.0f;
                     const float dp = N + R, dm = N - R;
-                    float p = 0.0f;
-                    if (dp > kDenEps32 * N) p += (A + B) * __builtin_amdgcn_rcpf(dp);
-                    if (dm > kDenEps32 * N) p += (A - B) * __builtin_amdgcn_rcpf(dm);
-                    p = fminf(fmaxf(p * inv_s, 0.0f), 1.0f);
+                    float p;
+                    if (dm > kIllTheta * N) {
+                        p = ((A + B) * __builtin_amdgcn_rcpf(dp) + (A - B) * __builtin_amdgcn_rcpf(dm)) *
+                            inv_s;
+                    } else {
+                        const double f = grid_freq(P.f_min, P.df, i0 + (int64_t)kWave * k) * P.to_cyc;
+                        p = (float)group_power64(P.t, P.y, m.t0, m.ybar, g0, ns, f);
+                    }
+                    p = fminf(fmaxf(p, 0.0f), 1.0f);
                     feat[k] += pool8_max(p);
                 }
                 ++n_good;
@@ -118,6 +148,7 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
 #pragma unroll
             for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
             ns = 0;
+            g0 = j_next;
             syy = 0.0f;
         };
 
@@ -143,40 +174,15 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
                 // A season boundary closes the current group once it holds
                 // min_obs observations; sparser seasons merge with the next.
                 // Every lane reads the same slot, so the flag is wave-uniform.
-                if (uniform_i32(o.w != 0.0f ? 1 : 0) && ns >= P.min_obs) close_group();
-                const double ph0 = fl * s_tau[q];
-                const float r = (float)(ph0 - rint(ph0));
-                // Lane frequencies f, f + 64 df, ...: one rotation by the step
-                // angle, then the three-term recurrence x_{k+1} = 2C x_k - x_{k-1}.
-                float sp = __builtin_amdgcn_sinf(r);
-                float cp = __builtin_amdgcn_cosf(r);
-                float c = fmaf(cp, o.y, -(sp * o.z));
-                float s = fmaf(sp, o.y, cp * o.z);
-                const float two_c = o.y + o.y;
-                xc[0] = fmaf(o.x, cp, xc[0]);
-                xs[0] = fmaf(o.x, sp, xs[0]);
-                cc[0] = fmaf(cp, cp, cc[0]);
-                cs[0] = fmaf(cp, sp, cs[0]);
-#pragma unroll
-                for (int k = 1; k < K; ++k) {
-                    xc[k] = fmaf(o.x, c, xc[k]);
-                    xs[k] = fmaf(o.x, s, xs[k]);
-                    cc[k] = fmaf(c, c, cc[k]);
-                    cs[k] = fmaf(c, s, cs[k]);
-                    if (k + 1 < K) {
-                        const float cn = fmaf(two_c, c, -cp);
-                        const float sn = fmaf(two_c, s, -sp);
-                        cp = c;
-                        sp = s;
-                        c = cn;
-                        s = sn;
-                    }
-                }
+                if (uniform_i32(o.w != 0.0f ? 1 : 0) && ns >= P.min_obs) close_group(jt + q);
+                // the main kernel's hot loop: FP64-reduced seed, hardware
+                // sin/cos, three-term recurrence across the lane's bins
+                accumulate_obs<K, true, LSP_TRIG_HW>(fl, s_tau[q], o, xc, xs, cc, cs);
                 ++ns;
                 syy = fmaf(o.x, o.x, syy);
             }
         }
-        close_group();
+        close_group(j_end);
     }
 
     const float inv = n_good > 0 ? 1.0f / (float)n_good : 0.0f;
@@ -187,16 +193,6 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
             out[q] = feat[k] * inv;
         }
     }
-}
-
-// One queue pop for the workgroup: thread 0 takes the next item number and
-// every thread receives it as a wave-uniform value (the leading barrier keeps
-// the broadcast slot from being overwritten while it may still be read).
-__device__ __forceinline__ int64_t pop_coarse(unsigned int* counter, int64_t lo, int64_t* s_item) {
-    __syncthreads();
-    if (threadIdx.x == 0) *s_item = lo + (int64_t)atomicAdd(counter, 1u);
-    __syncthreads();
-    return uniform_i64(*s_item);
 }
 
 // Resident workgroups take (object, tile) items from eight per-XCD queues, as
@@ -213,10 +209,10 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
         const int x = (x0 + d) % kXcds;
         const int64_t lo = (int64_t)x * per;
         const int64_t hi = lo + per < n_items ? lo + per : n_items;
-        int64_t item = pop_coarse(&P.queue[x], lo, &s_item);
+        int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
             coarse_item(P, item, s_tau, s_obs);
-            item = pop_coarse(&P.queue[x], lo, &s_item);
+            item = pop_item(&P.queue[x], lo, &s_item);
         }
     }
 }

@@ -34,65 +34,6 @@
 namespace lsp {
 namespace {
 
-// WS (wave split): the W waves of a workgroup share the same 64 K bins and
-// each takes every W-th staged observation; their sums are added in LDS, in
-// wave order, before the finish.  This multiplies the waves working on one
-// object without the per-split partial sums in HBM that the observation split
-// across workgroups needs.
-// One observation's contribution to a lane's K bins: seed (cos, sin) of the
-// lane's first phase, then the recurrence across its bins.  o = (y - ybar,
-// cos step, sin step, -), tq = t - t0.
-template <int K, bool CHEB, int TRIG>
-__device__ __forceinline__ void accumulate_obs(double fl, double tq, float4 o, float (&xc)[K],
-                                               float (&xs)[K], float (&cc)[K], float (&cs)[K]) {
-    double ph = fl * tq;
-    ph -= rint(ph);
-    const float r = (float)ph;
-    float s, c;
-    seed_sincos<TRIG>(r, &s, &c);
-    if (!CHEB) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            xc[k] = fmaf(o.x, c, xc[k]);
-            xs[k] = fmaf(o.x, s, xs[k]);
-            cc[k] = fmaf(c, c, cc[k]);
-            cs[k] = fmaf(c, s, cs[k]);
-            if (k + 1 < K) {
-                const float cn = fmaf(c, o.y, -(s * o.z));
-                s = fmaf(s, o.y, c * o.z);
-                c = cn;
-            }
-        }
-    } else {
-        // One rotation to reach the second frequency, then the three-term
-        // recurrence x_{k+1} = 2C x_k - x_{k-1}, which cos and sin of an
-        // arithmetic progression of angles obey.
-        const float two_c = o.y + o.y;
-        float cp = c, sp = s;
-        c = fmaf(cp, o.y, -(sp * o.z));
-        s = fmaf(sp, o.y, cp * o.z);
-        xc[0] = fmaf(o.x, cp, xc[0]);
-        xs[0] = fmaf(o.x, sp, xs[0]);
-        cc[0] = fmaf(cp, cp, cc[0]);
-        cs[0] = fmaf(cp, sp, cs[0]);
-#pragma unroll
-        for (int k = 1; k < K; ++k) {
-            xc[k] = fmaf(o.x, c, xc[k]);
-            xs[k] = fmaf(o.x, s, xs[k]);
-            cc[k] = fmaf(c, c, cc[k]);
-            cs[k] = fmaf(c, s, cs[k]);
-            if (k + 1 < K) {
-                const float cn = fmaf(two_c, c, -cp);
-                const float sn = fmaf(two_c, s, -sp);
-                cp = c;
-                sp = s;
-                c = cn;
-                s = sn;
-            }
-        }
-    }
-}
-
 // Per-observation staged values: t - t0 (FP64) and (y - ybar, cos, sin of the
 // step rotation 2 pi 64 df (t - t0), 0), the step phase reduced in FP64.
 template <int TRIG>
@@ -106,6 +47,11 @@ __device__ __forceinline__ float4 stage_obs(double step_cyc, double tc, double y
 
 // SRC: LSP_OBS_LDS stages tiles of observations in LDS; LSP_OBS_DIRECT reads
 // the staging pass's values from global memory.  TRIG: LSP_TRIG_*.
+// WS (wave split): the W waves of a workgroup share the same 64 K bins and
+// each takes every W-th staged observation; their sums are added in LDS, in
+// wave order, before the finish.  This multiplies the waves working on one
+// object without the per-split partial sums in HBM that the observation split
+// across workgroups needs.
 template <int K, int W, bool CHEB, bool WS, int SRC, int TRIG>
 __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, double* s_tau,
                                            float4* s_obs, PeakRec* s_red, float* s_part) {
