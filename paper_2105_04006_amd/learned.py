@@ -184,13 +184,13 @@ class BandNet:
         logits = self.forward(x_bf16, stream=stream)
         h1, h2 = self._bufs["h1"], self._bufs["h2"]
         W1, W2, W3 = self.w_bf16
-        g3 = self._buf("g3", (n, d3), torch.float32)
-        g3b = self._buf("g3b", (n, d3), torch.int16)
+        g3 = self._buf("dlogits", (n, d3), torch.float32)
+        g3b = self._buf("dlogits_bf16", (n, d3), torch.int16)
         loss_rows = self._buf("loss", (n,), torch.float32)
         _ok(lsp.lib().lsp_softmax_xent(_p(logits), _p(labels), n, d3, ctypes.c_float(1.0 / n),
                                        _p(g3), _p(g3b), _p(loss_rows), _s(stream)),
             "lsp_softmax_xent")
-        grads = [self._buf(f"g{i}", tuple(p.shape), torch.float32)
+        grads = [self._buf(f"grad{i}", tuple(p.shape), torch.float32)
                  for i, p in enumerate(self.master)]
         dW1, db1, dW2, db2, dW3, db3 = grads
         # layer 3: dW3 = h2^T g3, db3 = sum g3, dz2 = (g3 W3^T) * (h2 > 0)

@@ -13,7 +13,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from paper_2105_04006_amd import lsp, synth  # noqa: E402
-from test_gpu_parity import cuda, dev, say  # noqa: E402,F401
+from test_gpu_parity import cuda, dev, peak_ok, say  # noqa: E402,F401
 
 pytestmark = pytest.mark.gpu
 
@@ -84,4 +84,37 @@ def test_to_host_large_batch(dev):
     ref, rk = device_batch(dev, w, w.n_f, form=lsp.FORM_FP32P)
     assert np.array_equal(pg, ref)
     assert np.array_equal(pk.view(np.uint8), rk.view(np.uint8))
+    pipe.close()
+
+
+@pytest.mark.parametrize("method", ["standard", "generalized"])
+def test_to_host_against_oracle(dev, method):
+    """The host arrays themselves against the oracle's batch mode (Section
+    3.5's returned periodograms, Section 3.4's peaks): every bin of 37 objects
+    in both forms, FP64 within 1e-9 * max(P, 1e-3) and FP32 within 1e-3, with
+    one pipe shape whose staging pieces and chunks divide nothing evenly."""
+    import oracle
+
+    gen = method == "generalized"
+    w = synth.make_workload("batch_10k", n_obj=37, errors=gen)
+    n_f = 3001
+    if gen:
+        ora_pg, ora_pk = oracle.gen_batch(w.offsets, w.t, w.y, w.dy, w.f_min, w.f_max, n_f)
+    else:
+        ora_pg, ora_pk = oracle.batch(w.offsets, w.t, w.y, w.f_min, w.f_max, n_f)
+    pipe = lsp.HostPipe(3, 24 << 10, 200 << 10, 5)
+    for form, dt in ((lsp.FORM_FP64, lsp.PGRAM_F64), (lsp.FORM_FP32P, lsp.PGRAM_F32)):
+        pg, pk = host_batch(pipe, dev, w, n_f, dy=w.dy if gen else None, method=method,
+                            form=form, pgram_dtype=dt)
+        err = np.abs(pg.astype(np.float64) - ora_pg)
+        if form == lsp.FORM_FP64:
+            assert np.all(err <= 1e-9 * np.maximum(ora_pg, 1e-3)), err.max()
+        else:
+            assert err.max() <= 1e-3
+        for o in range(w.n_obj):
+            if form == lsp.FORM_FP64:
+                assert peak_ok(ora_pg[o], ora_pk["index"][o], pk["index"][o], 1e-9)
+            else:
+                assert peak_ok(ora_pg[o], ora_pk["index"][o], pk["index"][o], 2e-3, bins=1)
+        assert np.array_equal(pk["status"], ora_pk["status"])
     pipe.close()

@@ -25,6 +25,14 @@ def say(msg):
     sys.stdout.flush()
 
 
+U32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+def gamma(k):
+    """Bound factor of a k-term FP32 sum in any order (products exact)."""
+    return k * U32 / (1.0 - k * U32)
+
+
 def bits(a, dev):
     return torch.as_tensor(mlp_ref.bf16_bits(a).view(np.int16), device=dev)
 
@@ -35,18 +43,20 @@ def test_gemm_plain_and_transposed(dev, M, N, K):
     A = mlp_ref.bf16_round(rng.normal(size=(M, K)))
     B = mlp_ref.bf16_round(rng.normal(size=(K, N)))
     ref = A @ B
-    tol = 1e-5 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() + 1e-6
+    # BF16 products are exact in FP32; the K-term FP32 accumulation, in any
+    # order, is within gamma(K) sum |a||b| of the exact sum
+    tol = gamma(K) * (np.abs(A) @ np.abs(B))
     C = torch.empty((M, N), dtype=torch.float32, device=dev)
     say(f"gemm {M}x{N}x{K}")
     learned.gemm(bits(A, dev), bits(B, dev), M, N, K, K, 1, N, 1, C=C)
     torch.cuda.synchronize()
-    assert np.max(np.abs(C.cpu().numpy() - ref)) <= tol
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= tol)
     # the same product from transposed storage of both operands
     At, Bt = bits(np.ascontiguousarray(A.T), dev), bits(np.ascontiguousarray(B.T), dev)
     C2 = torch.empty((M, N), dtype=torch.float32, device=dev)
     learned.gemm(At, Bt, M, N, K, 1, M, 1, K, C=C2)
     torch.cuda.synchronize()
-    assert np.max(np.abs(C2.cpu().numpy() - ref)) <= tol
+    assert np.all(np.abs(C2.cpu().numpy() - ref) <= tol)
 
 
 def test_gemm_epilogues(dev):
@@ -62,13 +72,15 @@ def test_gemm_epilogues(dev):
                  bias=torch.as_tensor(bias, device=dev), relu=True)
     torch.cuda.synchronize()
     ref = np.maximum(A @ B + bias, 0.0)
-    assert np.max(np.abs(Cf.cpu().numpy() - ref)) <= 1e-4
+    # K products and the bias in FP32; ReLU does not enlarge the error
+    tol = gamma(K + 1) * (np.abs(A) @ np.abs(B) + np.abs(bias))
+    assert np.all(np.abs(Cf.cpu().numpy() - ref) <= tol)
     cb = mlp_ref.from_bf16_bits(Cb.cpu().numpy().view(np.uint16))
     assert np.array_equal(cb, mlp_ref.bf16_round(Cf.cpu().numpy()))
     learned.gemm(bits(A, dev), bits(B, dev), M, N, K, K, 1, N, 1, C=Cf, mask=bits(mask, dev))
     torch.cuda.synchronize()
     ref = (A @ B) * (mask > 0)
-    assert np.max(np.abs(Cf.cpu().numpy() - ref)) <= 1e-4
+    assert np.all(np.abs(Cf.cpu().numpy() - ref) <= gamma(K) * (np.abs(A) @ np.abs(B)))
 
 
 def test_small_kernels(dev):
@@ -87,58 +99,165 @@ def test_small_kernels(dev):
                               ctypes.c_float(1.0 / n), p(g), None, p(loss), None) == 0
     ref_loss, ref_g = mlp_ref.softmax_xent(z.astype(np.float64), lab)
     torch.cuda.synchronize()
-    assert abs(loss.cpu().numpy().mean() - ref_loss) <= 1e-5
-    assert np.max(np.abs(g.cpu().numpy() - ref_g)) <= 1e-6
+    # FP32 softmax of exact FP32 logits: expf of z - max ((|z - max| + 1) u),
+    # the 64-term sum and the division (72 u in all, relative to p), the
+    # subtraction at the label and the scaling by 1/n; the loss row's
+    # logarithm and additions (70 + 3 |loss|) u
+    zz = z.astype(np.float64) - z.max(axis=1, keepdims=True)
+    pr = np.exp(zz)
+    pr /= pr.sum(axis=1, keepdims=True)
+    keep = (lab >= 0) & (lab < c)
+    rows = np.arange(n)[keep]
+    loss_rows = np.zeros(n)
+    loss_rows[rows] = -np.log(pr[rows, lab[keep]])
+    assert np.all(np.abs(loss.cpu().numpy() - loss_rows) <= U32 * (70.0 + 3.0 * loss_rows))
+    e_g = ((np.abs(zz) + 72.0) * U32 * pr + 2.0 * U32 + U32 * np.abs(ref_g * n)) / n
+    assert np.all(np.abs(g.cpu().numpy() - ref_g) <= np.where(keep[:, None], e_g, 0.0))
     cs = torch.empty(c, dtype=torch.float32, device=dev)
     assert L.lsp_col_sums(p(zt), n, c, p(cs), None) == 0
     torch.cuda.synchronize()
-    assert np.allclose(cs.cpu().numpy(), z.astype(np.float64).sum(axis=0), atol=1e-4)
+    # FP32 column sums, any order
+    assert np.all(np.abs(cs.cpu().numpy() - z.astype(np.float64).sum(axis=0))
+                  <= gamma(n) * np.abs(z).astype(np.float64).sum(axis=0))
     mean = torch.empty(c, dtype=torch.float32, device=dev)
     inv = torch.empty(c, dtype=torch.float32, device=dev)
     assert L.lsp_col_stats(p(zt), n, c, p(mean), p(inv), None) == 0
     torch.cuda.synchronize()
-    assert np.allclose(mean.cpu().numpy(), z.mean(axis=0), atol=1e-5)
-    assert np.allclose(inv.cpu().numpy(), 1.0 / z.astype(np.float64).std(axis=0), rtol=1e-5)
+    # FP64 two-pass statistics rounded once to FP32: half an FP32 ulp, plus
+    # the FP64 sums' own error (n 2^-53 relative, far below it)
+    zd = z.astype(np.float64)
+    assert np.all(np.abs(mean.cpu().numpy() - zd.mean(axis=0))
+                  <= U32 * np.abs(zd.mean(axis=0)) + n * 2.0 ** -53 * np.abs(zd).mean(axis=0))
+    want_inv = 1.0 / zd.std(axis=0)
+    assert np.all(np.abs(inv.cpu().numpy() - want_inv) <= (U32 + (n + 4) * 2.0 ** -53) * want_inv)
     idx, mass = learned.top_bands(zt, k=8)
     torch.cuda.synchronize()
     order = np.argsort(-z, axis=1, kind="stable")[:, :8]
     assert np.array_equal(idx.cpu().numpy(), order)
     e = np.exp(z - z.max(axis=1, keepdims=True))
     pm = e / e.sum(axis=1, keepdims=True)
-    assert np.allclose(mass.cpu().numpy(), np.take_along_axis(pm, order, 1).sum(1), atol=1e-5)
+    # 8 FP32 softmax probabilities (as above) and their FP32 sum
+    want_mass = np.take_along_axis(pm, order, 1).sum(1)
+    e_mass = (np.abs(z - z.max(axis=1, keepdims=True)).max(axis=1) + 80.0) * U32 * want_mass
+    assert np.all(np.abs(mass.cpu().numpy() - want_mass) <= e_mass)
+
+
+def bf16_of(h):
+    """BF16 bits (int16 tensor) -> float64 numpy values."""
+    return mlp_ref.from_bf16_bits(h.cpu().numpy().view(np.uint16))
+
+
+def check_store(got, z, e, what):
+    """A BF16 store of an FP32 result: got must be a round-to-nearest BF16 value
+    of some number within e of the FP64 value z, so |got - z| <= e + half a
+    BF16 ulp of (|z| + e), i.e. <= e + 2^-8 (|z| + e); where z is not within e
+    of a rounding boundary the two must agree exactly (counted, not asserted)."""
+    lim = e + 2.0 ** -8 * (np.abs(z) + e)
+    err = np.abs(got - z)
+    same = float(np.mean(got == mlp_ref.bf16_round(z)))
+    say(f"  {what}: max |d| / bound {np.max(err / np.maximum(lim, 1e-300)):.3g}, "
+        f"equal to the rounded FP64 value: {same:.4f}")
+    assert np.all(err <= lim), what
+
+
+def check_sum(got, z, e, what):
+    err = np.abs(got - z)
+    say(f"  {what}: max |d| / bound {np.max(err / np.maximum(e, 1e-300)):.3g}")
+    assert np.all(err <= e), what
 
 
 def test_training_step_matches_reference(dev):
-    """One forward/backward/Adam step of the full-size network on the GPU vs the
-    BF16-emulated FP64 reference of the same arithmetic."""
+    """One forward/backward step of the full-size network, checked stage by
+    stage: every GEMM, softmax and column sum against FP64 arithmetic on the
+    exact BF16/FP32 operands the GPU itself stored for that stage.
+
+    Bounds, per element (u = 2^-24): a K-term product (plus bias) accumulated
+    in FP32 is within gamma(K + 1) (|A| |B| + |bias|) of its FP64 value, the
+    BF16 operands' products being exact in FP32; a BF16 store of such a result
+    adds at most half a BF16 ulp (check_store); conversions of the GPU's own
+    FP32 values to BF16 are exact roundings; softmax gradients move by at
+    most 2 p_i max_k |dz_k| / n under logit errors dz, plus FP32 rounding
+    of exp(z - max) (u |z - max| for the argument, 1 ulp for expf), of the
+    64-term sum and of the division ((|z - max| + 72) u p_i / n), and of the
+    subtraction and scaling (u |p - onehot| + 2u at the label); the loss row,
+    log-sum-exp minus the label's logit, by at most 2 max_k |dz_k| plus
+    (70 + 3 |loss|) u.  Then one Adam step moves every parameter by at most
+    lr."""
     rng = np.random.default_rng(5)
     n = 96
+    d0, d1, d2, d3 = mlp_ref.DIMS
     params = mlp_ref.init_params(9)
     for pp in params[1::2]:
         pp += rng.normal(0, 0.05, size=pp.shape)
-    x = mlp_ref.bf16_round(rng.normal(size=(n, 1088)))
-    labels = rng.integers(0, 64, size=n).astype(np.int32)
+    x = mlp_ref.bf16_round(rng.normal(size=(n, d0)))
+    labels = rng.integers(0, d3, size=n).astype(np.int32)
     net = learned.BandNet(dev, params=params)
     xb = bits(x, dev)
     lab = torch.as_tensor(labels, device=dev)
     loss_rows, grads = net.gradients(xb, lab)
     torch.cuda.synchronize()
-    bparams = [mlp_ref.bf16_round(p) if i % 2 == 0 else p.astype(np.float32).astype(np.float64)
-               for i, p in enumerate(params)]
+    B = net._bufs
+    W1, W2, W3 = (bf16_of(w) for w in net.w_bf16)
+    b1, b2, b3 = (net.master[i].double().cpu().numpy() for i in (1, 3, 5))
+    a = np.abs
+    # forward
+    h1 = bf16_of(B["h1"])
+    z1 = x @ W1 + b1
+    check_store(h1, np.maximum(z1, 0.0), gamma(d0 + 1) * (a(x) @ a(W1) + a(b1)), "h1")
+    h2 = bf16_of(B["h2"])
+    z2 = h1 @ W2 + b2
+    check_store(h2, np.maximum(z2, 0.0), gamma(d1 + 1) * (a(h1) @ a(W2) + a(b2)), "h2")
+    z3 = h2 @ W3 + b3
+    e3 = gamma(d2 + 1) * (a(h2) @ a(W3) + a(b3))
+    zz = z3 - z3.max(axis=1, keepdims=True)
+    p = np.exp(zz)
+    p /= p.sum(axis=1, keepdims=True)
+    emax = e3.max(axis=1, keepdims=True)
+    ref_rows = np.log(np.exp(zz).sum(axis=1)) - zz[np.arange(n), labels]
+    check_sum(loss_rows.double().cpu().numpy(), ref_rows,
+              2.0 * emax[:, 0] + U32 * (70.0 + 3.0 * a(ref_rows)), "loss rows")
+    g3 = B["dlogits"].double().cpu().numpy()
+    onehot = np.zeros((n, d3))
+    onehot[np.arange(n), labels] = 1.0
+    e_p = 2.0 * p * emax + (a(zz) + 72.0) * U32 * p  # logits error; expf, 64-term sum, divide
+    check_sum(g3, (p - onehot) / n, (e_p + 2.0 * U32 * onehot + U32 * a(p - onehot)) / n,
+              "softmax gradient")
+    g3b = bf16_of(B["dlogits_bf16"])
+    assert np.array_equal(g3b, mlp_ref.bf16_round(g3)), "g3 -> BF16"
+    # backward: each gradient from the GPU's own stored operands
+    dW1, db1, dW2, db2, dW3, db3 = (g.double().cpu().numpy() for g in grads)
+    check_sum(dW3, h2.T @ g3b, gamma(n) * (a(h2).T @ a(g3b)), "dW3")
+    check_sum(db3, g3.sum(axis=0), gamma(n) * a(g3).sum(axis=0), "db3")
+    dz2 = B["dz2"].double().cpu().numpy()
+    u2 = g3b @ W3.T
+    check_sum(dz2, u2 * (h2 > 0), gamma(d3) * (a(g3b) @ a(W3.T)) * (h2 > 0), "dz2")
+    dz2b = bf16_of(B["dz2b"])
+    assert np.array_equal(dz2b, mlp_ref.bf16_round(dz2)), "dz2 -> BF16"
+    check_sum(dW2, h1.T @ dz2b, gamma(n) * (a(h1).T @ a(dz2b)), "dW2")
+    check_sum(db2, dz2.sum(axis=0), gamma(n) * a(dz2).sum(axis=0), "db2")
+    dz1 = B["dz1"].double().cpu().numpy()
+    u1 = dz2b @ W2.T
+    check_sum(dz1, u1 * (h1 > 0), gamma(d2) * (a(dz2b) @ a(W2.T)) * (h1 > 0), "dz1")
+    dz1b = bf16_of(B["dz1b"])
+    assert np.array_equal(dz1b, mlp_ref.bf16_round(dz1)), "dz1 -> BF16"
+    check_sum(dW1, x.T @ dz1b, gamma(n) * (a(x).T @ a(dz1b)), "dW1")
+    check_sum(db1, dz1.sum(axis=0), gamma(n) * a(dz1).sum(axis=0), "db1")
+    # the end-to-end distance to the BF16-emulated reference run of the same
+    # step (informative: rounding choices may differ near BF16 boundaries)
+    bparams = [mlp_ref.bf16_round(q) if i % 2 == 0 else q.astype(np.float32).astype(np.float64)
+               for i, q in enumerate(params)]
     logits, cache = mlp_ref.forward(bparams, x, bf16=True)
-    ref_loss, dl = mlp_ref.softmax_xent(logits, labels)
-    ref_grads = mlp_ref.backward(bparams, cache, dl, bf16=True)
-    assert abs(loss_rows.cpu().numpy().mean() - ref_loss) <= 2e-3 * max(1.0, ref_loss)
-    for name, g, r in zip(["dW1", "db1", "dW2", "db2", "dW3", "db3"], grads, ref_grads):
-        g = g.cpu().numpy()
-        err = np.max(np.abs(g - r)) / (np.max(np.abs(r)) + 1e-12)
-        say(f"  {name}: max rel err {err:.3g}")
-        assert err <= 2e-2, name
-    before = [p.clone() for p in net.master]
+    _, dl = mlp_ref.softmax_xent(logits, labels)
+    for name, g, r in zip(["dW1", "db1", "dW2", "db2", "dW3", "db3"],
+                          (dW1, db1, dW2, db2, dW3, db3),
+                          mlp_ref.backward(bparams, cache, dl, bf16=True)):
+        say(f"  end to end {name}: max |d| / max |ref| "
+            f"{np.max(a(g - r)) / (np.max(a(r)) + 1e-12):.3g}")
+    before = [q.clone() for q in net.master]
     net.train_step(xb, lab, lr=1e-3)
     torch.cuda.synchronize()
-    for b, a in zip(before, net.master):
-        d = (a - b).abs().max().item()
+    for b, q in zip(before, net.master):
+        d = (q - b).abs().max().item()
         assert 0.0 < d <= 1.01e-3  # the first Adam step moves each parameter by <= lr
 
 
@@ -194,7 +313,11 @@ def test_row_normalize_pool_stats_and_shift(dev):
     sd = c.std(axis=1, keepdims=True)
     want = np.where(sd > 0, (c - c.mean(axis=1, keepdims=True)) / np.where(sd > 0, sd, 1), 0.0)
     got = xt.cpu().numpy()
-    assert np.max(np.abs(got[:, :1024] - want)) <= 1e-5
+    # FP64 statistics (one pass: relative error ~ count 2^-53 (1 + mean^2 /
+    # var)) and one FP32 rounding of each output
+    mu2 = c.mean(axis=1, keepdims=True) ** 2 / np.where(sd > 0, sd * sd, 1.0)
+    e_rn = U32 * np.abs(want) + 1024 * 2.0 ** -52 * (1.0 + mu2) * (np.abs(want) + 1.0)
+    assert np.all(np.abs(got[:, :1024] - want) <= e_rn)
     assert np.array_equal(got[:, 1024:], x[:, 1024:])
     # pooled column statistics over the coarse block
     mean = torch.empty(d, dtype=torch.float32, device=dev)
@@ -203,10 +326,18 @@ def test_row_normalize_pool_stats_and_shift(dev):
     assert L.lsp_pool_stats(p(mean), p(inv), 0, 1024, None) == 0
     torch.cuda.synchronize()
     blk = got[:, :1024].astype(np.float64)
-    assert np.allclose(mean.cpu().numpy()[:1024], blk.mean(), atol=1e-6)
-    assert np.allclose(inv.cpu().numpy()[:1024], 1.0 / blk.std(), rtol=1e-5)
-    assert np.allclose(inv.cpu().numpy()[1024:], 1.0 / got[:, 1024:].astype(np.float64).std(0),
-                       rtol=1e-5)
+    # pooled from per-column FP32 statistics (each within half an FP32 ulp):
+    # the pooled mean within 2 u |mean|-scale, the pooled 1/std within a few
+    # u relative (the per-column values enter var_j + m_j^2 with relative
+    # error <= 2 u each, then the difference with the squared mean, whose
+    # cancellation is bounded by (mean^2 + E x^2) / var)
+    bm, bv = blk.mean(), blk.var()
+    amp = (bm * bm + (blk * blk).mean()) / bv
+    assert abs(mean.cpu().numpy()[0] - bm) <= 4 * U32 * np.abs(blk).mean()
+    assert np.all(np.abs(inv.cpu().numpy()[:1024] * np.sqrt(bv) - 1.0) <= 4 * U32 * amp + 2 * U32)
+    oth = got[:, 1024:].astype(np.float64)
+    w_inv = 1.0 / oth.std(0)
+    assert np.all(np.abs(inv.cpu().numpy()[1024:] - w_inv) <= (U32 + (n + 4) * 2.0 ** -53) * w_inv)
     # shift augmentation on BF16 rows
     xb = torch.as_tensor(rng.integers(-2000, 2000, size=(n, d)).astype(np.int16), device=dev)
     lab = rng.integers(-1, 64, n).astype(np.int32)
