@@ -42,8 +42,9 @@ struct Config {
     int64_t tile_freqs;
     int64_t tiles_per_row;
     int64_t n_items;
-    int64_t rec_per_group;
+    int64_t rec_per_group;  // records per group (tile records or combine blocks)
     int64_t n_obs;
+    bool keys;              // FP32 form, unsplit: per-group peak keys + tile flag bits
 };
 
 // Rows of work.  The whole-grid entry points use one row per object covering
@@ -63,7 +64,8 @@ Rows whole_grid(int64_t n_obj, const lsp_grid* g) {
 }
 
 struct Layout {
-    size_t meta, rec, ill, part, queue, stage_t, stage_o, total;
+    size_t meta, rec, keys, bits, queue, part, stage_t, stage_o, total;
+    size_t zero_words;  // u32 words cleared before the main kernel, from `keys` (key mode)
 };
 
 bool valid_grid(const lsp_grid* g) {
@@ -223,6 +225,10 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     c->n_obs = n_obs;
     c->rec_per_group = c->split > 1 ? (n_f + kCombineThreads - 1) / kCombineThreads
                                     : c->tiles_per_row * rows.rows_per_group;
+    // The FP32 forms merge each group's peak into one 64-bit key whose index
+    // field holds 32 bits (peak_key).
+    c->keys = c->form == LSP_FORM_FP32P && c->split == 1;
+    if (c->keys && g->n_f > (int64_t)0xFFFFFFFE) return LSP_EUNSUPPORTED;
     return LSP_OK;
 }
 
@@ -231,18 +237,26 @@ Layout layout(int64_t n_obj, const lsp_grid* g, const Rows& rows, const Config& 
     size_t off = 0;
     const bool f32 = c.form == LSP_FORM_FP32P;
     const size_t n_groups = (size_t)(rows.n_rows / rows.rows_per_group);
+    (void)f32;
     L.meta = off;
     off += align_up((size_t)n_obj * sizeof(ObjMeta));
     L.rec = off;
-    off += align_up(n_groups * (size_t)c.rec_per_group * sizeof(PeakRec));
-    L.ill = off;
-    off += (f32 && c.split == 1) ? align_up((size_t)rows.n_rows * (size_t)c.tiles_per_row * 4) : 0;
+    off += c.keys ? 0 : align_up(n_groups * (size_t)c.rec_per_group * sizeof(PeakRec));
+    // key mode: group keys, tile flag bits and the queue counters back to back,
+    // so that one fill clears them
+    const size_t n_words = c.keys ? ((size_t)rows.n_rows * (size_t)c.tiles_per_row + 31) / 32 : 0;
+    L.keys = off;
+    off += c.keys ? n_groups * sizeof(unsigned long long) : 0;
+    L.bits = off;
+    off += n_words * 4;
+    L.queue = off;
+    off += kXcds * 4;
+    L.zero_words = c.keys ? (off - L.keys) / 4 : 0;
+    off = align_up(off);
     L.part = off;
     off += c.split > 1
                ? align_up((size_t)c.split * (c.gen ? 6 : 4) * (size_t)g->n_f * sizeof(float))
                : 0;
-    L.queue = off;
-    off += kAlign;
     // LSP_OBS_DIRECT: per-observation staged values (indexed like t)
     const size_t n_obs = c.obs == LSP_OBS_DIRECT ? (size_t)c.n_obs : 0;
     L.stage_t = off;
@@ -342,8 +356,9 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     mp.n_split = c.split;
     mp.pgram_f64 = opt.pgram_dtype == LSP_PGRAM_F64;
     mp.pgram = pgram;
-    mp.rec = at<PeakRec>(ws, L.rec);
-    mp.ill = (f32 && c.split == 1) ? at<uint32_t>(ws, L.ill) : nullptr;
+    mp.rec = c.keys ? nullptr : at<PeakRec>(ws, L.rec);
+    mp.keys = c.keys ? at<unsigned long long>(ws, L.keys) : nullptr;
+    mp.ill_bits = c.keys ? at<uint32_t>(ws, L.bits) : nullptr;
     mp.part = c.split > 1 ? at<float>(ws, L.part) : nullptr;
     mp.queue = at<unsigned int>(ws, L.queue);
     mp.persistent = c.persistent;
@@ -358,8 +373,15 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             return LSP_EHIP;
     }
 
-    if (f32 && c.persistent && launch_fill_u32(mp.queue, kXcds, 0u, s) != hipSuccess)
+    // key mode: clear keys, flag bits and queue counters in one fill kernel
+    // (a kernel, not a memset node, so that captured graphs replay it safely)
+    if (c.keys) {
+        if (launch_fill_u32(at<unsigned int>(ws, L.keys), (int64_t)L.zero_words, 0u, s) !=
+            hipSuccess)
+            return LSP_EHIP;
+    } else if (f32 && c.persistent && launch_fill_u32(mp.queue, kXcds, 0u, s) != hipSuccess) {
         return LSP_EHIP;
+    }
     if (t_main_begin && hipEventRecord(t_main_begin, s) != hipSuccess) return LSP_EHIP;
     if (method.gen) {
         if ((f32 ? launch_gen_fp32p(mp, c.k, c.waves, s) : launch_gen_fp64(mp, c.k, c.waves, s)) !=
@@ -378,7 +400,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             fp.meta = mp.meta;
             fp.t = t;
             fp.y = y;
-            fp.ill = mp.ill;
+            fp.ill_bits = mp.ill_bits;
+            fp.keys = mp.keys;
             fp.f_min = mp.f_min;
             fp.df = df;
             fp.to_cyc = to_cyc;
@@ -423,6 +446,7 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
         PeakParams kp;
         kp.meta = mp.meta;
         kp.rec = mp.rec;
+        kp.keys = mp.keys;
         kp.n_obj = n_obj;
         kp.n_groups = n_groups;
         kp.row_obj = rows.row_obj;

@@ -70,6 +70,24 @@ __device__ __forceinline__ bool better(double p, int64_t i, double bp, int64_t b
     return p > bp || (p == bp && i < bi);
 }
 
+// The FP32 forms reduce each group's peak with one 64-bit atomic maximum:
+// the key holds the power's FP32 bit pattern above the complement of the bin
+// index, so that unsigned order is the argmax order of `better` -- larger
+// power first, then the lower index (powers are >= 0, whose bit patterns
+// order like their values; -0 is mapped to +0).  Key 0 means no bin.  Bin
+// indices must stay below 2^32 - 1.
+__device__ __forceinline__ unsigned long long peak_key(double p, int64_t i) {
+    const float pf = (float)p;
+    const uint32_t pb = __float_as_uint(pf > 0.0f ? pf : 0.0f);
+    return ((unsigned long long)pb << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
+}
+
+__device__ __forceinline__ PeakRec key_peak(unsigned long long k) {
+    if (k == 0ull) return PeakRec{0.0, -1};
+    return PeakRec{(double)__uint_as_float((uint32_t)(k >> 32)),
+                   (int64_t)(0xFFFFFFFFu - (uint32_t)k)};
+}
+
 __device__ __forceinline__ PeakRec wave_best(PeakRec r) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -498,8 +516,10 @@ struct MainParams {
     int32_t n_split;        // observation-axis split (single object only)
     int32_t pgram_f64;
     void* pgram;             // NULL: peaks only
-    PeakRec* rec;            // [n_rows * tiles_per_row] when n_split == 1
-    uint32_t* ill;           // [n_rows * tiles_per_row]: tile needs the FP64 fix-up
+    PeakRec* rec;            // FP64 form: [n_rows * tiles_per_row] tile records
+    unsigned long long* keys;  // FP32 form, n_split == 1: [n_groups] peak keys (peak_key)
+    uint32_t* ill_bits;      // FP32 form, n_split == 1: bit per tile, set when the tile
+                             // needs the FP64 fix-up (its key then comes from the fix-up)
     float* part;             // [n_split][4][n_f] when n_split > 1
     unsigned int* queue;     // persistent schedule: kXcds counters
     int32_t persistent;
@@ -531,7 +551,8 @@ struct FixupParams {
     const ObjMeta* meta;
     const double* t;
     const double* y;
-    const uint32_t* ill;
+    const uint32_t* ill_bits;  // bit per tile (MainParams::ill_bits)
+    unsigned long long* keys;  // group peak keys the recomputed tiles are merged into
     double f_min, df, to_cyc;
     int64_t n_f;
     int64_t n_obj;
@@ -553,7 +574,8 @@ struct FixupParams {
 
 struct PeakParams {
     const ObjMeta* meta;
-    const PeakRec* rec;
+    const PeakRec* rec;               // records, rec_per_obj per group (or NULL)
+    const unsigned long long* keys;   // or one peak key per group (FP32 forms)
     int64_t n_obj;
     int64_t n_groups;        // groups of rows; group g covers rows [g R, (g+1) R)
     const int32_t* row_obj;  // object of each row, or NULL (group g is object g)

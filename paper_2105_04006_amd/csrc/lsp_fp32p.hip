@@ -69,28 +69,17 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
         rr.f_lo + ftile * tile_freqs + (WS ? 0 : (int64_t)wave * kWave * K) + lane;
     const int64_t f_hi = rr.f_hi;
     const bool owner = !WS || wave == 0;  // the wave that finishes the tile's bins
-    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) {  // invalid row or empty tile
-        if (threadIdx.x == 0 && P.n_split == 1) {
-            P.rec[tile] = PeakRec{0.0, -1};
-            P.ill[tile] = 0u;
-        }
-        return;
-    }
+    // invalid row or empty tile: no bin, nothing to record
+    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) return;
     const ObjMeta m = P.meta[obj];
 
     if (m.status != LSP_OBJ_OK) {
-        if (P.n_split == 1) {
-            if (P.pgram && owner) {
-                const double v = fill_value(m.status);
+        if (P.n_split == 1 && P.pgram && owner) {
+            const double v = fill_value(m.status);
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int64_t i = i0 + (int64_t)kWave * k;
-                    if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
-                }
-            }
-            if (threadIdx.x == 0) {
-                P.rec[tile] = PeakRec{0.0, -1};
-                P.ill[tile] = 0u;
+            for (int k = 0; k < K; ++k) {
+                const int64_t i = i0 + (int64_t)kWave * k;
+                if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
             }
         }
         return;
@@ -180,8 +169,9 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
             if (better(p, i, best.p, best.i)) best = PeakRec{p, i};
         }
     }
-    // A tile holding an ill-conditioned bin is recomputed in FP64 by the
-    // fix-up kernel, which overwrites its bins and its record.
+    // The tile's best bin goes into its group's peak key.  A tile holding an
+    // ill-conditioned bin instead sets its bit for the fix-up kernel, which
+    // recomputes the whole tile in FP64, rewrites its bins and merges its best.
     any_ill = __syncthreads_or(any_ill);
     best = wave_best(best);
     if (lane == 0) s_red[wave] = best;
@@ -191,8 +181,10 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 #pragma unroll
         for (int w = 1; w < W; ++w)
             if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
-        P.rec[tile] = b;
-        P.ill[tile] = any_ill ? 1u : 0u;
+        if (any_ill)
+            atomicOr(&P.ill_bits[tile >> 5], 1u << (tile & 31));
+        else if (b.i >= 0)
+            atomicMax(&P.keys[row / P.rows_per_group], peak_key(b.p, b.i));
     }
 }
 

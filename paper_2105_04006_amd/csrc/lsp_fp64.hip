@@ -113,10 +113,10 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
 }
 
 // FP64 recompute of FP32-form tiles flagged ill-conditioned.  Workgroups stride
-// over the tile flags 256 at a time, collect the flagged ones in LDS, and
+// over the tiles' flag bits 256 at a time, collect the flagged ones in LDS, and
 // recompute every bin of each such tile from the FP64 series (rounding the
 // power to FP32 so the argmax still compares FP32 values), then rewrite the
-// tile's periodogram bins and record.
+// tile's periodogram bins and merge its best bin into the group's peak key.
 constexpr int kFixThreads = 256;
 
 __global__ __launch_bounds__(kFixThreads) void fixup_kernel(const FixupParams P) {
@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kFixThreads) void fixup_kernel(const FixupParams P)
         if (threadIdx.x == 0) s_count = 0;
         __syncthreads();
         const int64_t mine = base + threadIdx.x;
-        if (mine < P.n_tiles && P.ill[mine]) s_list[atomicAdd(&s_count, 1)] = mine;
+        if (mine < P.n_tiles && ((P.ill_bits[mine >> 5] >> (mine & 31)) & 1u))
+            s_list[atomicAdd(&s_count, 1)] = mine;
         __syncthreads();
         const int count = uniform_i32(s_count);
         for (int q = 0; q < count; ++q) {
@@ -155,7 +156,8 @@ __global__ __launch_bounds__(kFixThreads) void fixup_kernel(const FixupParams P)
                 PeakRec b = s_red[0];
                 for (int w = 1; w < kFixThreads / kWave; ++w)
                     if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
-                P.rec[tile] = b;
+                if (rr.obj >= 0 && b.i >= 0)
+                    atomicMax(&P.keys[row / P.rows_per_group], peak_key(b.p, b.i));
             }
             __syncthreads();
         }

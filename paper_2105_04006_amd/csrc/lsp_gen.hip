@@ -42,28 +42,17 @@ __device__ __forceinline__ void gen_item(const MainParams& P, int64_t item, doub
     const int64_t obj = rr.obj;
     const int64_t i0 = rr.f_lo + ftile * tile_freqs + (int64_t)wave * kWave * K + lane;
     const int64_t f_hi = rr.f_hi;
-    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) {
-        if (threadIdx.x == 0 && P.n_split == 1) {
-            P.rec[tile] = PeakRec{0.0, -1};
-            P.ill[tile] = 0u;
-        }
-        return;
-    }
+    // invalid row or empty tile: no bin, nothing to record
+    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) return;
     const ObjMeta m = P.meta[obj];
 
     if (m.status != LSP_OBJ_OK) {
-        if (P.n_split == 1) {
-            if (P.pgram) {
-                const double v = fill_value(m.status);
+        if (P.n_split == 1 && P.pgram) {
+            const double v = fill_value(m.status);
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int64_t i = i0 + (int64_t)kWave * k;
-                    if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
-                }
-            }
-            if (threadIdx.x == 0) {
-                P.rec[tile] = PeakRec{0.0, -1};
-                P.ill[tile] = 0u;
+            for (int k = 0; k < K; ++k) {
+                const int64_t i = i0 + (int64_t)kWave * k;
+                if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
             }
         }
         return;
@@ -175,8 +164,10 @@ __device__ __forceinline__ void gen_item(const MainParams& P, int64_t item, doub
 #pragma unroll
         for (int w = 1; w < W; ++w)
             if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
-        P.rec[tile] = b;
-        P.ill[tile] = any_ill ? 1u : 0u;
+        if (any_ill)
+            atomicOr(&P.ill_bits[tile >> 5], 1u << (tile & 31));
+        else if (b.i >= 0)
+            atomicMax(&P.keys[row / P.rows_per_group], peak_key(b.p, b.i));
     }
 }
 

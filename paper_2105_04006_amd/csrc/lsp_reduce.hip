@@ -1,5 +1,6 @@
-// lsp_reduce.hip -- per-object peak from the per-tile (power, index) records,
-// and a small fill kernel for queue counters.
+// lsp_reduce.hip -- per-object peak from the per-tile (power, index) records
+// (FP64 form and split single objects) or from the per-group peak keys the
+// FP32 forms merge atomically, and a small fill kernel for counters and flags.
 //
 // Section 3.3 takes the argmax of the periodogram (first maximal index) and
 // converts it to a period, p = 2 pi / w; Section 3.4 keeps, per object, the best
@@ -13,6 +14,26 @@ namespace lsp {
 namespace {
 
 constexpr int kPeakThreads = 256;
+
+// The peak record of one object from its best (power, index).
+__device__ __forceinline__ lsp_peak make_peak(const PeakParams& P, const ObjMeta& m, PeakRec b) {
+    lsp_peak pk;
+    pk.status = m.status;
+    pk.reserved = 0;
+    if (m.status == LSP_OBJ_OK && b.i >= 0) {
+        const double f = grid_freq(P.f_min, P.df, b.i);
+        pk.index = b.i;
+        pk.freq = f;
+        pk.period = P.unit == LSP_UNIT_ANGULAR ? kTwoPi / f : 1.0 / f;
+        pk.power = b.p;
+    } else {
+        pk.index = -1;
+        pk.freq = __builtin_nan("");
+        pk.period = __builtin_nan("");
+        pk.power = m.status == LSP_OBJ_OK ? __builtin_nan("") : fill_value(m.status);
+    }
+    return pk;
+}
 
 __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(const PeakParams P) {
     __shared__ PeakRec s_red[kPeakThreads / kWave];
@@ -38,23 +59,19 @@ __global__ __launch_bounds__(kPeakThreads) void peaks_kernel(const PeakParams P)
         PeakRec b = s_red[0];
         for (int w = 1; w < kPeakThreads / kWave; ++w)
             if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
-        lsp_peak pk;
-        pk.status = m.status;
-        pk.reserved = 0;
-        if (m.status == LSP_OBJ_OK && b.i >= 0) {
-            const double f = grid_freq(P.f_min, P.df, b.i);
-            pk.index = b.i;
-            pk.freq = f;
-            pk.period = P.unit == LSP_UNIT_ANGULAR ? kTwoPi / f : 1.0 / f;
-            pk.power = b.p;
-        } else {
-            pk.index = -1;
-            pk.freq = __builtin_nan("");
-            pk.period = __builtin_nan("");
-            pk.power = m.status == LSP_OBJ_OK ? __builtin_nan("") : fill_value(m.status);
-        }
-        P.peaks[o] = pk;
+        P.peaks[o] = make_peak(P, m, b);
     }
+}
+
+// The FP32 forms' groups: one thread per group decodes the group's peak key.
+__global__ __launch_bounds__(kPeakThreads) void peaks_from_keys_kernel(const PeakParams P) {
+    const int64_t grp = linear_block() * kPeakThreads + threadIdx.x;
+    if (grp >= P.n_groups) return;
+    const int64_t o = P.row_obj ? (int64_t)P.row_obj[grp * P.rows_per_group] : grp;
+    if (o < 0 || o >= P.n_obj) return;
+    const ObjMeta m = P.meta[o];
+    const PeakRec b = m.status == LSP_OBJ_OK ? key_peak(P.keys[grp]) : PeakRec{0.0, -1};
+    P.peaks[o] = make_peak(P, m, b);
 }
 
 __global__ void fill_u32_kernel(unsigned int* dst, int64_t n, unsigned int v) {
@@ -66,7 +83,12 @@ __global__ void fill_u32_kernel(unsigned int* dst, int64_t n, unsigned int v) {
 
 hipError_t launch_peaks(const PeakParams& p, hipStream_t s) {
     if (p.n_groups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(peaks_kernel, grid_for(p.n_groups), dim3(kPeakThreads), 0, s, p);
+    if (p.keys)
+        hipLaunchKernelGGL(peaks_from_keys_kernel,
+                           grid_for((p.n_groups + kPeakThreads - 1) / kPeakThreads),
+                           dim3(kPeakThreads), 0, s, p);
+    else
+        hipLaunchKernelGGL(peaks_kernel, grid_for(p.n_groups), dim3(kPeakThreads), 0, s, p);
     return hipGetLastError();
 }
 

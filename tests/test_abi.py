@@ -397,8 +397,12 @@ def test_batch_static_argument_errors(L):
     assert call(grid=lsp.make_grid(2.0, 1.0, 10)) == lsp.EINVAL
     assert call(opt=lsp.make_options(form=9)) == lsp.EINVAL
     assert call(opt=lsp.make_options(form=lsp.FORM_FP32P, t_split=4)) == lsp.EUNSUPPORTED
-    assert lsp.workspace_bytes(200_000, 52_000_000, g, o) > lsp.STATIC_SCRATCH_BYTES
-    assert call(n_obj=200_000, n_obs=52_000_000) == lsp.ESCRATCH
+    # the FP32 form of the 200,000-object LSST-like batch fits (per-object peak
+    # keys); the FP64 form's per-tile records do not
+    assert lsp.workspace_bytes(200_000, 52_000_000, g, o) <= lsp.STATIC_SCRATCH_BYTES
+    o64 = lsp.make_options(form=lsp.FORM_FP64)
+    assert lsp.workspace_bytes(200_000, 52_000_000, g, o64) > lsp.STATIC_SCRATCH_BYTES
+    assert call(n_obj=200_000, n_obs=52_000_000, opt=o64) == lsp.ESCRATCH
     assert lsp.status_string(lsp.ESCRATCH) != lsp.status_string(lsp.ENOMEM)
 
 

@@ -63,8 +63,8 @@ def test_static_scratch_matches_workspace_call_twice(dev, form):
 def test_static_scratch_refuses_oversized_calls(dev):
     w, (off, t, y) = _inputs(dev, 10, synth.SEED_BASE + 7003)
     grid = lsp.make_grid(w.f_min, w.f_max, 250_000)
-    opt = lsp.make_options(form=lsp.FORM_FP32P)
-    big = 200_000  # objects whose workspace needs ~1 GB: refused before anything is read
+    opt = lsp.make_options(form=lsp.FORM_FP64)
+    big = 200_000  # the FP64 form's per-tile records need ~1.6 GB: refused before any read
     assert lsp.workspace_bytes(big, w.n_obs, grid, opt) > lsp.STATIC_SCRATCH_BYTES
     peaks = torch.zeros(w.n_obj * lsp.PEAK_BYTES, dtype=torch.uint8, device=dev)
     st = lsp.lib().lsp_batch_static(ctypes.c_void_p(off.data_ptr()), big, w.n_obs,
