@@ -818,7 +818,8 @@ def bench_forms(args, torch, dev):
     f32 = {"ms_per_step": ms32, "steps": args.steps, "objects_per_s": w.n_obj / (ms32 * 1e-3),
            "evals_per_s": w.evals / (ms32 * 1e-3), "main_kernel_ms": k_ms,
            "launch": {k: shape[k] for k in ("k_per_lane", "waves_per_wg", "schedule",
-                                            "recurrence", "tile_freqs", "n_items")}}
+                                            "recurrence", "tile_freqs", "tiles_per_item",
+                                            "n_items")}}
     if pk64 is not None:
         f32["peak_bin_agreement_vs_fp64"] = agreement(pk32)
         # power error at both peak indices (FP32 form against the FP64 form)

@@ -590,19 +590,21 @@ lsp_status lsp_select_fallback(const lsp_peak *peaks, const float *mass, int64_t
  * The launch shape a whole-grid call (lsp_single when n_obj == 1, else
  * lsp_batch; lsp_gen_* when generalized == 1) resolves for this shape and
  * these options: the tuning fields of `opt` left at 0 filled with the
- * library's choices, the bins one workgroup covers and the number of work
- * items.  It is what the call would enqueue; nothing is launched.  Used to
- * state the K, recurrence and schedule behind a measurement (the work per
- * bin of Section 2 depends on them).
+ * library's choices, the bins one frequency tile covers, the consecutive
+ * tiles one work item takes and the number of work items.  It is what the
+ * call would enqueue; nothing is launched.  Used to state the K, recurrence
+ * and schedule behind a measurement (the work per bin of Section 2 depends
+ * on them).
  *   resolved : host, receives the options with every AUTO / 0 field resolved
  *              (form, normalize, subtract_mean and pgram_dtype as given).
- *   tile_freqs, n_items : host, may be NULL.
+ *   tile_freqs, tiles_per_item, n_items : host, may be NULL.
  * Errors: LSP_EINVAL / LSP_EUNSUPPORTED as the call itself would return them
  * (NULL grid or resolved, n_obj < 1, n_obs < 0, bad grid or options).
  */
 lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid *grid,
                                const lsp_options *opt, int32_t generalized,
-                               lsp_options *resolved, int64_t *tile_freqs, int64_t *n_items);
+                               lsp_options *resolved, int64_t *tile_freqs,
+                               int64_t *tiles_per_item, int64_t *n_items);
 
 /*
  * Optional instrumentation for profiling.  After a call with non-NULL

@@ -41,6 +41,8 @@ struct Config {
     int ws;
     int64_t tile_freqs;
     int64_t tiles_per_row;
+    int64_t tiles_per_item;  // consecutive frequency tiles per work item
+    int64_t chunks_per_row;
     int64_t n_items;
     int64_t rec_per_group;  // records per group (tile records or combine blocks)
     int64_t n_obs;
@@ -221,7 +223,23 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     c->tiles_per_row = (n_f + c->tile_freqs - 1) / c->tile_freqs;
     if (c->tiles_per_row * rows.rows_per_group > kMaxGrid / rows.n_rows / c->split)
         return LSP_EUNSUPPORTED;
-    c->n_items = rows.n_rows * c->tiles_per_row * c->split;
+    // The standard FP32 form gives each work item up to 16 consecutive
+    // frequency tiles of one row -- one queue pop and one peak-key merge per
+    // item, and an object that fits in one staging pass is staged once --
+    // while items stay small against one wave's share of the launch: about
+    // 200 items per resident wave (4,096 on the chip), so that the last items
+    // do not leave the chip idle.  Measured: lsst_200k (49 M tiles, 16 per
+    // item) 0.5% faster; batch_10k (1 M tiles) 6% slower at 14 per item,
+    // where this rule keeps 1.
+    c->tiles_per_item = 1;
+    if (o->form == LSP_FORM_FP32P && !method.gen && c->split == 1) {
+        int64_t tpi = rows.n_rows * c->tiles_per_row / (200 * 4096);
+        if (tpi > 16) tpi = 16;
+        if (tpi > c->tiles_per_row) tpi = c->tiles_per_row;
+        c->tiles_per_item = tpi > 1 ? tpi : 1;
+    }
+    c->chunks_per_row = (c->tiles_per_row + c->tiles_per_item - 1) / c->tiles_per_item;
+    c->n_items = rows.n_rows * c->chunks_per_row * c->split;
     c->n_obs = n_obs;
     c->rec_per_group = c->split > 1 ? (n_f + kCombineThreads - 1) / kCombineThreads
                                     : c->tiles_per_row * rows.rows_per_group;
@@ -352,6 +370,8 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
     mp.rows_per_group = rows.rows_per_group;
     mp.pad_rows = 0;
     mp.tiles_per_row = c.tiles_per_row;
+    mp.tiles_per_item = c.tiles_per_item;
+    mp.chunks_per_row = c.chunks_per_row;
     mp.n_items = c.n_items;
     mp.n_split = c.split;
     mp.pgram_f64 = opt.pgram_dtype == LSP_PGRAM_F64;
@@ -781,7 +801,8 @@ void lsp_plan_destroy(lsp_plan plan) {
 
 lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid* grid,
                                const lsp_options* opt_in, int32_t generalized,
-                               lsp_options* resolved, int64_t* tile_freqs, int64_t* n_items) {
+                               lsp_options* resolved, int64_t* tile_freqs,
+                               int64_t* tiles_per_item, int64_t* n_items) {
     if (!grid || !resolved || n_obj < 1 || n_obs < 0 || !lsp::is_bool(generalized))
         return LSP_EINVAL;
     if (!lsp::valid_grid(grid)) return LSP_EINVAL;
@@ -806,6 +827,7 @@ lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid* gri
     }
     *resolved = r;
     if (tile_freqs) *tile_freqs = c.tile_freqs;
+    if (tiles_per_item) *tiles_per_item = c.tiles_per_item;
     if (n_items) *n_items = c.n_items;
     return LSP_OK;
 }

@@ -82,6 +82,21 @@ __device__ __forceinline__ unsigned long long peak_key(double p, int64_t i) {
     return ((unsigned long long)pb << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
 }
 
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+    return a > b ? a : b;
+}
+
+// Largest key of the wavefront, in every lane.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)k, off, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(k >> 32), off, kWave);
+        k = umax64(k, ((unsigned long long)hi << 32) | lo);
+    }
+    return k;
+}
+
 __device__ __forceinline__ PeakRec key_peak(unsigned long long k) {
     if (k == 0ull) return PeakRec{0.0, -1};
     return PeakRec{(double)__uint_as_float((uint32_t)(k >> 32)),
@@ -161,34 +176,24 @@ __device__ __forceinline__ double power64(const Sums64& s, double n, double scal
 
 // Power from FP32 sums (cc = sum cos^2, cs = sum cos sin; sum sin^2 = N - cc).
 // The shift needs no angle: with C2 + i S2 = sum e^{2iwt} and R = |C2 + i S2|,
-// the shifted denominators are (N + R)/2 and (N - R)/2 and the half-angle
-// formulas give cos and sin of w tau.  `ill` reports a bin whose N - R is too
-// small for FP32 to resolve.
+// the shifted denominators are (N + R)/2 and (N - R)/2, and with A = xc^2 + xs^2
+// and B R = (xc^2 - xs^2) C2 + 2 xc xs S2 (the numerators' sum and difference,
+// rotated by the half angle) Eq. 2 becomes
+//   P_LS = (A + B)/(2 (N + R)) + (A - B)/(2 (N - R)) = (A N - B R) / (N^2 - R^2):
+// one reciprocal, no square root and no angle.  `ill` reports a bin whose
+// N - R is at most N/32 (R^2 >= (31/32)^2 N^2), where FP32 sums cannot
+// resolve the sine term; such bins are recomputed in FP64.
 __device__ __forceinline__ float power32(float xc, float xs, float cc, float cs, float n,
                                          float scale, bool& ill) {
     const float c2 = fmaf(2.0f, cc, -n);
     const float s2 = 2.0f * cs;
-    const float r = __builtin_amdgcn_sqrtf(fmaf(c2, c2, s2 * s2));
-    const float dp = n + r;
-    const float dm = n - r;
-    ill = !(dm > kIllTheta * n);
-    float ca = 1.0f, sa = 0.0f;
-    if (r > 0.0f) {
-        const float ir = __builtin_amdgcn_rcpf(r);
-        const float cos2a = c2 * ir, sin2a = s2 * ir;
-        if (cos2a >= 0.0f) {
-            ca = __builtin_amdgcn_sqrtf(0.5f + 0.5f * cos2a);
-            sa = 0.5f * sin2a * __builtin_amdgcn_rcpf(ca);
-        } else {
-            sa = copysignf(__builtin_amdgcn_sqrtf(0.5f - 0.5f * cos2a), sin2a);
-            ca = 0.5f * sin2a * __builtin_amdgcn_rcpf(sa);
-        }
-    }
-    const float ycs = fmaf(xc, ca, xs * sa);
-    const float ysn = fmaf(xs, ca, -(xc * sa));
-    float p = ycs * ycs * __builtin_amdgcn_rcpf(dp);
-    if (dm > 0.0f) p = fmaf(ysn * ysn, __builtin_amdgcn_rcpf(dm), p);
-    return p * scale;
+    const float r2 = fmaf(c2, c2, s2 * s2);
+    const float n2 = n * n;
+    ill = !(r2 < (1.0f - kIllTheta) * (1.0f - kIllTheta) * n2);
+    const float a = fmaf(xc, xc, xs * xs);
+    const float br = fmaf(fmaf(xc, xc, -(xs * xs)), c2, 2.0f * xc * xs * s2);
+    // A N - B R >= 0 exactly; rounding must not report a negative power
+    return fmaxf(fmaf(a, n, -br), 0.0f) * __builtin_amdgcn_rcpf(n2 - r2) * scale;
 }
 
 // FP64 power of one (object, frequency) pair straight from the caller's
@@ -512,7 +517,9 @@ struct MainParams {
     int32_t rows_per_group;
     int32_t pad_rows;
     int64_t tiles_per_row;  // frequency tiles per row
-    int64_t n_items;        // n_rows * tiles_per_row * n_split
+    int64_t tiles_per_item; // consecutive frequency tiles per work item (FP32 form)
+    int64_t chunks_per_row; // ceil(tiles_per_row / tiles_per_item)
+    int64_t n_items;        // n_rows * chunks_per_row * n_split
     int32_t n_split;        // observation-axis split (single object only)
     int32_t pgram_f64;
     void* pgram;             // NULL: peaks only

@@ -59,8 +59,9 @@ struct FeatParams {
 // centred on the object's mean, normalised by the group's own sum of
 // squares) at f_cyc cycles per time unit, in FP64 as the main kernel's FP64
 // form computes it: exact re-centred phases, library sin/cos, Eq. 1-2 through
-// power64 with its drop rule.
-__device__ double group_power64(const double* __restrict__ t, const double* __restrict__ y,
+// power64 with its drop rule.  Not inlined: its FP64 registers stay out of
+// the coarse kernel's hot loop.
+__device__ __noinline__ double group_power64(const double* __restrict__ t, const double* __restrict__ y,
                                 double t0, double ybar, int64_t g0, int64_t n, double f_cyc) {
     Sums64 a = {0.0, 0.0, 0.0, 0.0, 0.0};
     double syy = 0.0;
@@ -75,16 +76,31 @@ __device__ double group_power64(const double* __restrict__ t, const double* __re
     return syy > 0.0 ? power64(a, (double)n, 2.0 / syy) : 0.0;
 }
 
+// Maximum over each run of 8 lanes, in all 8 lanes, through DPP lane moves:
+// swap neighbours (quad_perm 1,0,3,2), swap pairs (quad_perm 2,3,0,1), then
+// mirror within each half-row of 8 lanes (lane i with lane 7 - i), which pairs
+// each 4-lane maximum with the other's.
+__device__ __forceinline__ float dpp_f32(float v, int ctrl_sel) {
+    const int x = __float_as_int(v);
+    int r;
+    switch (ctrl_sel) {
+        case 0: r = __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false); break;
+        case 1: r = __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false); break;
+        default: r = __builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false); break;
+    }
+    return __int_as_float(r);
+}
+
 __device__ __forceinline__ float pool8_max(float v) {
-    v = fmaxf(v, __shfl_xor(v, 1, kWave));
-    v = fmaxf(v, __shfl_xor(v, 2, kWave));
-    v = fmaxf(v, __shfl_xor(v, 4, kWave));
+    v = fmaxf(v, dpp_f32(v, 0));
+    v = fmaxf(v, dpp_f32(v, 1));
+    v = fmaxf(v, dpp_f32(v, 2));
     return v;
 }
 
 // One (object, 1,024-bin tile) item; called by every thread of the workgroup.
 __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, double* s_tau,
-                                            float4* s_obs) {
+                                            float4* s_obs, float* s_fix) {
     constexpr int K = kCoarseK;
     const int64_t obj = item / kTilesPerObj;
     const int tile = (int)(item - obj * kTilesPerObj);
@@ -115,34 +131,53 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
         // the main kernel, a bin whose smaller shifted denominator N - R is at
         // most N/32 cannot be resolved in FP32 and is recomputed in FP64 from
         // the group's observations (group_power64); the others keep the FP32
-        // value, with the hardware reciprocals (about 1 ulp).  The next group
+        // value, with a hardware reciprocal (about 1 ulp).  The next group
         // starts at j_next.
         auto close_group = [&](int64_t j_next) {
             if (ns >= P.min_obs) {
                 const float N = (float)ns;
                 const float inv_s = syy > 0.0f ? 1.0f / syy : 0.0f;
+                float p32[K];
+                uint32_t ill = 0u;  // bins of this lane FP32 cannot resolve
+                // With C2 + i S2 = sum exp(2iwt), R = |C2 + i S2|, A = xc^2 + xs^2
+                // and B R = (xc^2 - xs^2) C2 + 2 xc xs S2, twice P_LS is
+                // (A + B)/(N + R) + (A - B)/(N - R) = 2 (A N - B R)/(N^2 - R^2):
+                // one reciprocal and no square root per bin.  N - R <= N/32
+                // (the main kernel's rule) is R^2 >= (31/32)^2 N^2.
+                const float N2 = N * N;
+                const float ill_r2 = (1.0f - kIllTheta) * (1.0f - kIllTheta) * N2;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const float C2 = 2.0f * cc[k] - N;
+                    const float C2 = fmaf(2.0f, cc[k], -N);
                     const float S2 = 2.0f * cs[k];
-                    const float R = sqrtf(C2 * C2 + S2 * S2);
-                    const float A = xc[k] * xc[k] + xs[k] * xs[k];
-                    const float B =
-                        R > 0.0f ? ((xc[k] * xc[k] - xs[k] * xs[k]) * C2 + 2.0f * xc[k] * xs[k] * S2) *
-                                       __builtin_amdgcn_rcpf(R)
-                                 : 0.0f;
-                    const float dp = N + R, dm = N - R;
-                    float p;
-                    if (dm > kIllTheta * N) {
-                        p = ((A + B) * __builtin_amdgcn_rcpf(dp) + (A - B) * __builtin_amdgcn_rcpf(dm)) *
-                            inv_s;
-                    } else {
-                        const double f = grid_freq(P.f_min, P.df, i0 + (int64_t)kWave * k) * P.to_cyc;
-                        p = (float)group_power64(P.t, P.y, m.t0, m.ybar, g0, ns, f);
-                    }
-                    p = fminf(fmaxf(p, 0.0f), 1.0f);
-                    feat[k] += pool8_max(p);
+                    const float R2 = fmaf(C2, C2, S2 * S2);
+                    const float A = fmaf(xc[k], xc[k], xs[k] * xs[k]);
+                    const float BR =
+                        fmaf(fmaf(xc[k], xc[k], -(xs[k] * xs[k])), C2, 2.0f * xc[k] * xs[k] * S2);
+                    p32[k] = 2.0f * fmaxf(fmaf(A, N, -BR), 0.0f) * __builtin_amdgcn_rcpf(N2 - R2) *
+                             inv_s;
+                    if (!(R2 < ill_r2)) ill |= 1u << k;
                 }
+                // FP64 recompute of the unresolvable bins, one bin at a time
+                // (a rolled loop, so that the FP64 path stays out of the
+                // unrolled code and its registers), through LDS
+                if (__any(ill != 0u)) {
+#pragma unroll 1
+                    for (int k = 0; k < K; ++k) {
+                        if ((ill >> k) & 1u) {
+                            const double f =
+                                grid_freq(P.f_min, P.df, i0 + (int64_t)kWave * k) * P.to_cyc;
+                            s_fix[(wave * K + k) * kWave + lane] =
+                                (float)group_power64(P.t, P.y, m.t0, m.ybar, g0, ns, f);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if ((ill >> k) & 1u) p32[k] = s_fix[(wave * K + k) * kWave + lane];
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    feat[k] += pool8_max(fminf(fmaxf(p32[k], 0.0f), 1.0f));
                 ++n_good;
             }
 #pragma unroll
@@ -164,20 +199,24 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
                 double sp = P.step_cyc * tc;
                 sp -= rint(sp);
                 const float rs = (float)sp;
-                const bool starts = j > m.j0 && tj - P.t[j - 1] > P.gap;
+                // (the previous time is loaded unconditionally, clamped to the
+                // object's first observation, so the two loads go out together)
+                const double tprev = P.t[j > m.j0 ? j - 1 : j];
+                const bool starts = j > m.j0 && tj - tprev > P.gap;
                 s_obs[q] = make_float4((float)(P.y[j] - m.ybar), __builtin_amdgcn_cosf(rs),
                                        __builtin_amdgcn_sinf(rs), starts ? 1.0f : 0.0f);
             }
             __syncthreads();
             for (int q = 0; q < cnt; ++q) {
                 const float4 o = s_obs[q];
+                const double tq = s_tau[q];  // both reads in flight together
                 // A season boundary closes the current group once it holds
                 // min_obs observations; sparser seasons merge with the next.
                 // Every lane reads the same slot, so the flag is wave-uniform.
                 if (uniform_i32(o.w != 0.0f ? 1 : 0) && ns >= P.min_obs) close_group(jt + q);
                 // the main kernel's hot loop: FP64-reduced seed, hardware
                 // sin/cos, three-term recurrence across the lane's bins
-                accumulate_obs<K, true, LSP_TRIG_HW>(fl, s_tau[q], o, xc, xs, cc, cs);
+                accumulate_obs<K, true, LSP_TRIG_HW>(fl, tq, o, xc, xs, cc, cs);
                 ++ns;
                 syy = fmaf(o.x, o.x, syy);
             }
@@ -198,9 +237,14 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
 // Resident workgroups take (object, tile) items from eight per-XCD queues, as
 // the batch periodogram does; a workgroup that drains its own XCD's queue
 // moves on to the next one and exits once every queue is empty.
-__global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParams P) {
+// Four waves per SIMD (at most 128 VGPRs), as the main kernel's K = 16 loop:
+// the hot loop stays spill-free; the rare FP64 recompute and the staging loop
+// keep a few values in scratch.
+__global__ __launch_bounds__(kWave* kCoarseW)
+    __attribute__((amdgpu_waves_per_eu(4))) void coarse_kernel(const FeatParams P) {
     __shared__ double s_tau[kTile];
     __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, new-season flag)
+    __shared__ float s_fix[kCoarseK * kWave * kCoarseW];  // FP64-recomputed bins
     __shared__ int64_t s_item;
     const int64_t n_items = P.n_obj * kTilesPerObj;
     const int64_t per = (n_items + kXcds - 1) / kXcds;
@@ -211,7 +255,7 @@ __global__ __launch_bounds__(kWave* kCoarseW) void coarse_kernel(const FeatParam
         const int64_t hi = lo + per < n_items ? lo + per : n_items;
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
-            coarse_item(P, item, s_tau, s_obs);
+            coarse_item(P, item, s_tau, s_obs, s_fix);
             item = pop_item(&P.queue[x], lo, &s_item);
         }
     }

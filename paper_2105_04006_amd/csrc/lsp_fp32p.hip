@@ -59,137 +59,166 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
     const int wave = threadIdx.x / kWave;
     constexpr int WT = WS ? 1 : W;  // waves across the tile's frequencies
     const int64_t tile_freqs = (int64_t)kWave * K * WT;
-    const int64_t tile = item / P.n_split;
-    const int split = (int)(item - tile * P.n_split);
-    const int64_t row = tile / P.tiles_per_row;
-    const int64_t ftile = tile - row * P.tiles_per_row;
+    // item = (row, chunk of tiles_per_item consecutive frequency tiles,
+    // observation split); a split object has one tile per chunk
+    const int64_t chunk_id = item / P.n_split;
+    const int split = (int)(item - chunk_id * P.n_split);
+    const int64_t row = chunk_id / P.chunks_per_row;
+    const int64_t chunk = chunk_id - row * P.chunks_per_row;
     const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;
-    const int64_t i0 =
-        rr.f_lo + ftile * tile_freqs + (WS ? 0 : (int64_t)wave * kWave * K) + lane;
+    const int64_t t_lo = chunk * P.tiles_per_item;
+    const int64_t t_hi = t_lo + P.tiles_per_item < P.tiles_per_row ? t_lo + P.tiles_per_item
+                                                                   : P.tiles_per_row;
+    const int64_t lane_off = (WS ? 0 : (int64_t)wave * kWave * K) + lane;
     const int64_t f_hi = rr.f_hi;
     const bool owner = !WS || wave == 0;  // the wave that finishes the tile's bins
-    // invalid row or empty tile: no bin, nothing to record
-    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) return;
+    // invalid row or empty chunk: no bin, nothing to record
+    if (obj < 0 || rr.f_lo + t_lo * tile_freqs >= f_hi) return;
     const ObjMeta m = P.meta[obj];
 
     if (m.status != LSP_OBJ_OK) {
         if (P.n_split == 1 && P.pgram && owner) {
             const double v = fill_value(m.status);
+            for (int64_t ft = t_lo; ft < t_hi; ++ft)
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int64_t i = i0 + (int64_t)kWave * k;
-                if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
-            }
+                for (int k = 0; k < K; ++k) {
+                    const int64_t i = rr.f_lo + ft * tile_freqs + lane_off + (int64_t)kWave * k;
+                    if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
+                }
         }
         return;
     }
 
-    const int64_t chunk = (m.n + P.n_split - 1) / P.n_split;
-    const int64_t lo = (int64_t)split * chunk < m.n ? (int64_t)split * chunk : m.n;
-    const int64_t hi = lo + chunk < m.n ? lo + chunk : m.n;
+    const int64_t span = (m.n + P.n_split - 1) / P.n_split;
+    const int64_t lo = (int64_t)split * span < m.n ? (int64_t)split * span : m.n;
+    const int64_t hi = lo + span < m.n ? lo + span : m.n;
     const int64_t js = m.j0 + lo, je = m.j0 + hi;
-    const double fl = grid_freq(P.f_min, P.df, i0) * P.to_cyc;
+    // an object that fits in one staging pass is staged once for all the
+    // chunk's tiles
+    const bool one_pass = je - js <= kTile;
 
-    float xc[K], xs[K], cc[K], cs[K];
+    unsigned long long best = 0ull;  // this lane's best key over the chunk's resolvable tiles
+    for (int64_t ft = t_lo; ft < t_hi; ++ft) {
+        if (rr.f_lo + ft * tile_freqs >= f_hi) break;
+        const int64_t i0 = rr.f_lo + ft * tile_freqs + lane_off;
+        const double fl = grid_freq(P.f_min, P.df, i0) * P.to_cyc;
+
+        float xc[K], xs[K], cc[K], cs[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
+        for (int k = 0; k < K; ++k) xc[k] = xs[k] = cc[k] = cs[k] = 0.0f;
 
-    if (SRC == LSP_OBS_DIRECT) {
-        // the staging pass's values, read straight from global memory; the
-        // index is wave-uniform, so every lane loads the same address
-        for (int64_t j = js; j < je; ++j)
-            accumulate_obs<K, CHEB, TRIG>(fl, P.stage_t[j], P.stage_o[j], xc, xs, cc, cs);
-    } else {
-        for (int64_t jt = js; jt < je; jt += kTile) {
-            const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
-            __syncthreads();
-            for (int q = threadIdx.x; q < cnt; q += kWave * W) {
-                const double tc = P.t[jt + q] - m.t0;
-                s_tau[q] = tc;
-                // step rotation: the phase advance over kWave bins
-                s_obs[q] = stage_obs<TRIG>(P.step_cyc, tc, P.y[jt + q] - m.ybar);
+        if (SRC == LSP_OBS_DIRECT) {
+            // the staging pass's values, read straight from global memory; the
+            // index is wave-uniform, so every lane loads the same address
+            for (int64_t j = js; j < je; ++j)
+                accumulate_obs<K, CHEB, TRIG>(fl, P.stage_t[j], P.stage_o[j], xc, xs, cc, cs);
+        } else {
+            for (int64_t jt = js; jt < je; jt += kTile) {
+                const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
+                if (!one_pass || ft == t_lo) {
+                    __syncthreads();
+                    for (int q = threadIdx.x; q < cnt; q += kWave * W) {
+                        const double tc = P.t[jt + q] - m.t0;
+                        s_tau[q] = tc;
+                        // step rotation: the phase advance over kWave bins
+                        s_obs[q] = stage_obs<TRIG>(P.step_cyc, tc, P.y[jt + q] - m.ybar);
+                    }
+                    __syncthreads();
+                }
+                for (int q = WS ? wave : 0; q < cnt; q += WS ? W : 1)
+                    accumulate_obs<K, CHEB, TRIG>(fl, s_tau[q], s_obs[q], xc, xs, cc, cs);
             }
-            __syncthreads();
-            for (int q = WS ? wave : 0; q < cnt; q += WS ? W : 1)
-                accumulate_obs<K, CHEB, TRIG>(fl, s_tau[q], s_obs[q], xc, xs, cc, cs);
         }
-    }
 
-    if (WS) {
-        // add the other waves' sums into wave 0's, one array at a time
-        auto gather = [&](float(&v)[K]) {
-            __syncthreads();
-            if (wave > 0) {
+        if (WS) {
+            // add the other waves' sums into wave 0's, one array at a time
+            auto gather = [&](float(&v)[K]) {
+                __syncthreads();
+                if (wave > 0) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) s_part[((wave - 1) * K + k) * kWave + lane] = v[k];
-            }
-            __syncthreads();
-            if (wave == 0) {
+                    for (int k = 0; k < K; ++k) s_part[((wave - 1) * K + k) * kWave + lane] = v[k];
+                }
+                __syncthreads();
+                if (wave == 0) {
 #pragma unroll
-                for (int w = 1; w < W; ++w)
+                    for (int w = 1; w < W; ++w)
 #pragma unroll
-                    for (int k = 0; k < K; ++k) v[k] += s_part[((w - 1) * K + k) * kWave + lane];
-            }
-        };
-        gather(xc);
-        gather(xs);
-        gather(cc);
-        gather(cs);
-    }
+                        for (int k = 0; k < K; ++k) v[k] += s_part[((w - 1) * K + k) * kWave + lane];
+                }
+            };
+            gather(xc);
+            gather(xs);
+            gather(cc);
+            gather(cs);
+        }
 
-    if (P.n_split > 1) {
-        const int64_t nf = P.n_f;
-        float* base = P.part + (int64_t)split * 4 * nf;
+        if (P.n_split > 1) {
+            const int64_t nf = P.n_f;
+            float* base = P.part + (int64_t)split * 4 * nf;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int64_t i = i0 + (int64_t)kWave * k;
+                if (owner && i < f_hi) {
+                    base[i] = xc[k];
+                    base[nf + i] = xs[k];
+                    base[2 * nf + i] = cc[k];
+                    base[3 * nf + i] = cs[k];
+                }
+            }
+            continue;
+        }
+
+        unsigned long long tb = 0ull;  // the tile's best key in this lane
+        const float n = (float)m.n;
+        const float scale = (float)m.scale;
+        bool any_ill = false;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int64_t i = i0 + (int64_t)kWave * k;
             if (owner && i < f_hi) {
-                base[i] = xc[k];
-                base[nf + i] = xs[k];
-                base[2 * nf + i] = cc[k];
-                base[3 * nf + i] = cs[k];
+                bool ill;
+                const float p = power32(xc[k], xs[k], cc[k], cs[k], n, scale, ill);
+                any_ill |= ill;
+                if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, (double)p);
+                if (p == p) tb = umax64(tb, peak_key(p, i));  // NaN never wins
             }
         }
-        return;
-    }
-
-    PeakRec best{0.0, -1};
-    const float n = (float)m.n;
-    const float scale = (float)m.scale;
-    bool any_ill = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t i = i0 + (int64_t)kWave * k;
-        if (owner && i < f_hi) {
-            bool ill;
-            const double p = (double)power32(xc[k], xs[k], cc[k], cs[k], n, scale, ill);
-            any_ill |= ill;
-            if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, p);
-            if (better(p, i, best.p, best.i)) best = PeakRec{p, i};
+        // A tile holding an ill-conditioned bin sets its bit for the fix-up
+        // kernel, which recomputes the whole tile in FP64, rewrites its bins
+        // and merges its best into the group's key; the other tiles' bins
+        // join the running best.
+        any_ill = __syncthreads_or(any_ill);
+        if (any_ill) {
+            if (threadIdx.x == 0) {
+                const int64_t tile = row * P.tiles_per_row + ft;
+                atomicOr(&P.ill_bits[tile >> 5], 1u << (tile & 31));
+            }
+        } else {
+            best = umax64(best, tb);
         }
     }
-    // The tile's best bin goes into its group's peak key.  A tile holding an
-    // ill-conditioned bin instead sets its bit for the fix-up kernel, which
-    // recomputes the whole tile in FP64, rewrites its bins and merges its best.
-    any_ill = __syncthreads_or(any_ill);
-    best = wave_best(best);
-    if (lane == 0) s_red[wave] = best;
+    if (P.n_split > 1) return;
+
+    // the chunk's best bin goes into its group's peak key (one atomic per item)
+    best = wave_max_u64(best);
+    unsigned long long* s_key = reinterpret_cast<unsigned long long*>(s_red);
+    if (lane == 0) s_key[wave] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
-        PeakRec b = s_red[0];
+        unsigned long long b = s_key[0];
 #pragma unroll
-        for (int w = 1; w < W; ++w)
-            if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
-        if (any_ill)
-            atomicOr(&P.ill_bits[tile >> 5], 1u << (tile & 31));
-        else if (b.i >= 0)
-            atomicMax(&P.keys[row / P.rows_per_group], peak_key(b.p, b.i));
+        for (int w = 1; w < W; ++w) b = umax64(b, s_key[w]);
+        if (b != 0ull) atomicMax(&P.keys[row / P.rows_per_group], b);
     }
 }
 
+// Up to K = 16 the kernel must keep four waves per SIMD (at most 128 VGPRs):
+// with three, the VALU waits on latency more often.
 template <int K, int W, bool CHEB, bool WS, int SRC = LSP_OBS_LDS, int TRIG = LSP_TRIG_HW>
-__global__ __launch_bounds__(kWave* W) void fp32p_kernel(const MainParams P) {
+__global__ __launch_bounds__(kWave* W)
+    __attribute__((amdgpu_waves_per_eu(K <= 16 && !WS ? 4 : 1))) void fp32p_kernel(
+        const MainParams P) {
     __shared__ double s_tau[kTile];
     __shared__ float4 s_obs[kTile];
     __shared__ PeakRec s_red[W];

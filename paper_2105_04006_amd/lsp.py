@@ -187,6 +187,7 @@ def lib():
         L.lsp_describe_launch.argtypes = [i64, i64, ctypes.POINTER(Grid), ctypes.POINTER(Options),
                                           i32, ctypes.POINTER(Options),
                                           ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_int64)]
         L.lsp_set_stage_events.restype = ctypes.c_int
         L.lsp_set_stage_events.argtypes = [vp, vp]
@@ -214,16 +215,18 @@ def set_stage_events(begin, end):
 def describe_launch(n_obj, n_obs, grid, opt, generalized=False):
     """The launch shape a whole-grid call resolves (lsp_describe_launch):
     a dict with the resolved k_per_lane, waves_per_wg, t_split, schedule,
-    recurrence, wave_split, obs_read, seed_trig, tile_freqs and n_items."""
+    recurrence, wave_split, obs_read, seed_trig, tile_freqs, tiles_per_item and
+    n_items."""
     out = Options()
-    tf, ni = ctypes.c_int64(0), ctypes.c_int64(0)
+    tf, tpi, ni = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     st = lib().lsp_describe_launch(int(n_obj), int(n_obs), ctypes.byref(grid), ctypes.byref(opt),
                                    int(bool(generalized)), ctypes.byref(out), ctypes.byref(tf),
-                                   ctypes.byref(ni))
+                                   ctypes.byref(tpi), ctypes.byref(ni))
     if st != OK:
         raise LspError(st, "lsp_describe_launch")
     d = {name: int(getattr(out, name)) for name, _ in Options._fields_}
-    d["tile_freqs"], d["n_items"] = int(tf.value), int(ni.value)
+    d["tile_freqs"], d["tiles_per_item"], d["n_items"] = int(tf.value), int(tpi.value), \
+        int(ni.value)
     return d
 
 

@@ -361,7 +361,12 @@ def test_describe_launch_resolves_the_shape():
     many = lsp.describe_launch(200_000, 52_000_000, gb, lsp.make_options(form=lsp.FORM_FP32P))
     assert many["schedule"] == lsp.SCHED_PERSISTENT and many["t_split"] == 1
     assert many["waves_per_wg"] == 1
-    assert many["n_items"] == 200_000 * -(-250_000 // many["tile_freqs"])
+    tiles_row = -(-250_000 // many["tile_freqs"])
+    assert many["tiles_per_item"] == 16  # 49 M tiles: up to 16 consecutive tiles per item
+    assert many["n_items"] == 200_000 * -(-tiles_row // 16)
+    assert one["tiles_per_item"] == 1  # a split object keeps one tile per item
+    few = lsp.describe_launch(10, 5000, gb, lsp.make_options(form=lsp.FORM_FP32P))
+    assert few["tiles_per_item"] == 1 and few["n_items"] == 10 * -(-250_000 // few["tile_freqs"])
     fixed = lsp.describe_launch(10, 5000, gb, lsp.make_options(
         form=lsp.FORM_FP32P, k=12, recurrence=lsp.REC_ROTATION, schedule=lsp.SCHED_GRID))
     assert (fixed["k_per_lane"], fixed["recurrence"], fixed["schedule"]) == \
@@ -370,6 +375,7 @@ def test_describe_launch_resolves_the_shape():
     assert f64["k_per_lane"] in (1, 2, 4) and f64["schedule"] == lsp.SCHED_GRID
     gen = lsp.describe_launch(10, 5000, gb, lsp.make_options(form=lsp.FORM_FP32P), True)
     assert gen["k_per_lane"] in (8, 12, 16)
+    assert f64["tiles_per_item"] == 1
     with pytest.raises(lsp.LspError):
         lsp.describe_launch(0, 10, gb, lsp.make_options())
     with pytest.raises(lsp.LspError):
