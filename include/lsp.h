@@ -123,6 +123,10 @@ enum {
 /*
  * Uniform half-open grid of Section 2: df = (f_max - f_min) / n_f and
  * f_i = f_min + i * df for i = 0 .. n_f - 1 (f_max itself is excluded).
+ * The FP32 forms merge each object's peak into a 64-bit key whose index field
+ * holds 32 bits, so unless a single object's observations are split across
+ * workgroups (t_split > 1) they accept n_f <= 2^32 - 2 and return
+ * LSP_EUNSUPPORTED beyond; the FP64 form takes any n_f.
  */
 typedef struct {
     double f_min;
