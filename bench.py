@@ -137,6 +137,11 @@ def cpu_baseline(w, target_evals, threads, method="standard"):
         (objs, bins, vals)
 
 
+def order_code(name):
+    from paper_2105_04006_amd import lsp
+    return {"auto": lsp.ORDER_AUTO, "input": lsp.ORDER_INPUT, "lpt": lsp.ORDER_LPT}[name]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +168,8 @@ def main():
     ap.add_argument("--k", type=int, default=0, help="frequencies per lane (0: library default)")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--schedule", default="auto", choices=["auto", "grid", "persistent"])
+    ap.add_argument("--order", default="auto", choices=["auto", "input", "lpt"],
+                    help="order of a batch's rows (longest first, or as given)")
     ap.add_argument("--cpu-evals", type=float, default=3e9,
                     help="oracle evaluations in the CPU-baseline sample (about 10-30 s of CPU work)")
     ap.add_argument("--fp64-steps", type=int, default=0,
@@ -246,9 +253,10 @@ def main():
     trig = {"auto": 0, "hw": lsp.TRIG_HW, "lib": lsp.TRIG_LIB, "poly": lsp.TRIG_POLY}[args.seed_trig]
     variant = obs == lsp.OBS_DIRECT or trig in (lsp.TRIG_LIB, lsp.TRIG_POLY)
     kv = dict(obs_read=obs, seed_trig=trig) if variant else {}
+    order = order_code(args.order)
     p32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, schedule=sched,
-                          recurrence=rec, k=args.k, waves=args.waves, **kw, **kv)
-    p64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, **kw)
+                          recurrence=rec, k=args.k, waves=args.waves, order=order, **kw, **kv)
+    p64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, order=order, **kw)
 
     def timed(fn, steps):
         torch.cuda.synchronize()
@@ -691,7 +699,8 @@ def bench_forms(args, torch, dev):
 
     def whole(form, **kw):
         return lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, offsets=off, form=form,
-                               pgram=False, unit=w.unit, method=method, dy=dy, **kw)
+                               pgram=False, unit=w.unit, method=method, dy=dy,
+                               order=order_code(args.order), **kw)
 
     def wall(fn, steps):
         torch.cuda.synchronize()

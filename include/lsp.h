@@ -112,6 +112,16 @@ enum {
                           sin, 8 for cos) in FP32 FMAs                                */
 };
 
+/* Order in which a batch's rows (objects, or (object, band) rows of
+ * lsp_batch_rows) are handed to the workgroups.  No result depends on it:
+ * every bin and every peak is computed the same way in any order. */
+enum {
+    LSP_ORDER_AUTO = 0,  /* the library's choice: LPT for calls of >= 1e10 terms     */
+    LSP_ORDER_INPUT = 1, /* rows in the order given                                  */
+    LSP_ORDER_LPT = 2    /* longest processing time first: rows by descending N_t,
+                            dealt round-robin over the 8 XCDs (lsp_row_order)      */
+};
+
 /* Work scheduling of the batch path. */
 enum {
     LSP_SCHED_AUTO = 0,
@@ -156,6 +166,8 @@ typedef struct {
     int32_t wave_split;    /* LSP_WSPLIT_* (FP32 form only)                             */
     int32_t obs_read;      /* LSP_OBS_* (FP32 form only)                                */
     int32_t seed_trig;     /* LSP_TRIG_* (FP32 form only)                               */
+    int32_t order;         /* LSP_ORDER_* (batches and row mode)                        */
+    int32_t reserved;      /* 0                                                         */
 } lsp_options;
 
 /* One object's peak (40 bytes). */
@@ -609,6 +621,35 @@ lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid *gri
                                const lsp_options *opt, int32_t generalized,
                                lsp_options *resolved, int64_t *tile_freqs,
                                int64_t *tiles_per_item, int64_t *n_items);
+
+/*
+ * The longest-first row order the batch calls use with LSP_ORDER_LPT
+ * (Graham's longest-processing-time-first rule for independent jobs).  The
+ * paper gives each object its own thread block (Section 3.4) and leaves the
+ * order to the hardware; here a row's cost is the observation count of its
+ * object, offsets[o+1] - offsets[o] (0 for a negative count, an object index
+ * outside 0..n_obj-1 or a negative band), compared exactly below 1,024 and to
+ * 1/64 of an octave above.  Position s of the descending order is dealt to XCD
+ * s % 8: perm lists XCD 0's rows, then XCD 1's, ..., each run in descending
+ * cost; the runs are contiguous and balanced (the first n_rows % 8 runs hold
+ * one row more).  Rows of equal cost appear in no particular order.
+ *   offsets        : device, n_obj + 1 int64 (CSR offsets as lsp_batch).
+ *   row_obj        : device int32[n_rows], or NULL: row r is object
+ *                    r / rows_per_group (then n_rows = n_obj * rows_per_group).
+ *   row_band       : device int32[n_rows], or NULL; as lsp_batch_rows.
+ *   perm           : device int32[n_rows], written: a permutation of 0..n_rows-1.
+ *   workspace      : device, >= lsp_row_order_workspace_bytes() bytes,
+ *                    256-aligned, scratch.
+ * Errors: LSP_EINVAL for NULL offsets/perm/workspace, n_obj < 1, n_rows < 1 or
+ * above 2^31 - 1, rows_per_group < 1, a row count that does not match, or a
+ * misaligned workspace; LSP_ENOMEM for a short workspace; LSP_EHIP if a launch
+ * fails.  Asynchronous on `stream`; enqueues kernels only (no memset, no
+ * allocation).
+ */
+size_t lsp_row_order_workspace_bytes(void);
+lsp_status lsp_row_order(const int64_t *offsets, int64_t n_obj, const int32_t *row_obj,
+                         const int32_t *row_band, int64_t n_rows, int32_t rows_per_group,
+                         int32_t *perm, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Optional instrumentation for profiling.  After a call with non-NULL

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "liblsp.so")
 
 SOURCES = ["lsp_api.hip", "lsp_prep.hip", "lsp_fp64.hip", "lsp_fp32p.hip", "lsp_reduce.hip",
            "lsp_tune.hip", "lsp_mlp.hip", "lsp_features.hip", "lsp_gen.hip",
-           "lsp_host.hip"]
+           "lsp_host.hip", "lsp_order.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

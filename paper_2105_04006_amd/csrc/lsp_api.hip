@@ -47,6 +47,7 @@ struct Config {
     int64_t rec_per_group;  // records per group (tile records or combine blocks)
     int64_t n_obs;
     bool keys;              // FP32 form, unsplit: per-group peak keys + tile flag bits
+    bool lpt;               // rows handed out longest first (lsp_order.hip)
 };
 
 // Rows of work.  The whole-grid entry points use one row per object covering
@@ -66,7 +67,7 @@ Rows whole_grid(int64_t n_obj, const lsp_grid* g) {
 }
 
 struct Layout {
-    size_t meta, rec, keys, bits, queue, part, stage_t, stage_o, total;
+    size_t meta, rec, keys, bits, queue, part, stage_t, stage_o, perm, hist, total;
     size_t zero_words;  // u32 words cleared before the main kernel, from `keys` (key mode)
 };
 
@@ -100,6 +101,7 @@ lsp_status valid_options(const lsp_options* o) {
     if (o->wave_split < LSP_WSPLIT_AUTO || o->wave_split > LSP_WSPLIT_ON) return LSP_EINVAL;
     if (o->obs_read < LSP_OBS_AUTO || o->obs_read > LSP_OBS_DIRECT) return LSP_EINVAL;
     if (o->seed_trig < LSP_TRIG_AUTO || o->seed_trig > LSP_TRIG_POLY) return LSP_EINVAL;
+    if (o->order < LSP_ORDER_AUTO || o->order > LSP_ORDER_LPT) return LSP_EINVAL;
     return LSP_OK;
 }
 
@@ -247,6 +249,15 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     // field holds 32 bits (peak_key).
     c->keys = c->form == LSP_FORM_FP32P && c->split == 1;
     if (c->keys && g->n_f > (int64_t)0xFFFFFFFE) return LSP_EUNSUPPORTED;
+    // Longest-first order needs rows of different objects to order.  By
+    // default it is used for calls of at least 1e10 (observation, bin) terms,
+    // where its four small launches cost under 1%.  Measured: a heavy-tailed
+    // population (asteroids_100k, N_t 10..1500) 1.3% faster; batch_10k and
+    // lsst_200k (uniform N_t) unchanged.
+    const bool orderable =
+        rows.n_rows > 1 && rows.n_rows <= (int64_t)INT32_MAX && n_obj > 1 && c->split == 1;
+    const double terms = (double)n_obs * (double)n_f * ((double)rows.n_rows / (double)n_obj);
+    c->lpt = orderable && (o->order == LSP_ORDER_LPT || (o->order == LSP_ORDER_AUTO && terms >= 1e10));
     return LSP_OK;
 }
 
@@ -281,6 +292,11 @@ Layout layout(int64_t n_obj, const lsp_grid* g, const Rows& rows, const Config& 
     off += align_up(n_obs * sizeof(double));
     L.stage_o = off;
     off += align_up(n_obs * 16);
+    // longest-first order: the rank -> row permutation and the sort's buckets
+    L.perm = off;
+    off += c.lpt ? align_up((size_t)rows.n_rows * sizeof(int32_t)) : 0;
+    L.hist = off;
+    off += c.lpt ? align_up((size_t)kOrderBuckets * sizeof(unsigned int)) : 0;
     L.total = off;
     return L;
 }
@@ -401,6 +417,20 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
             return LSP_EHIP;
     } else if (f32 && c.persistent && launch_fill_u32(mp.queue, kXcds, 0u, s) != hipSuccess) {
         return LSP_EHIP;
+    }
+    if (c.lpt) {
+        OrderParams op;
+        op.offsets = offsets;
+        op.n_obj = n_obj;
+        op.row_obj = rows.row_obj;
+        op.row_band = rows.row_band;
+        op.n_rows = rows.n_rows;
+        op.rows_per_group = rows.rows_per_group;
+        op.pad = 0;
+        op.hist = at<unsigned int>(ws, L.hist);
+        op.perm = at<int32_t>(ws, L.perm);
+        if (launch_row_order(op, s) != hipSuccess) return LSP_EHIP;
+        mp.row_perm = op.perm;
     }
     if (t_main_begin && hipEventRecord(t_main_begin, s) != hipSuccess) return LSP_EHIP;
     if (method.gen) {
@@ -819,6 +849,7 @@ lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid* gri
     r.waves_per_wg = c.waves;
     r.t_split = c.split;
     r.schedule = c.persistent ? LSP_SCHED_PERSISTENT : LSP_SCHED_GRID;
+    r.order = c.lpt ? LSP_ORDER_LPT : LSP_ORDER_INPUT;
     if (c.form == LSP_FORM_FP32P) {
         r.recurrence = c.rec;
         r.wave_split = c.ws ? LSP_WSPLIT_ON : LSP_WSPLIT_OFF;
@@ -830,6 +861,33 @@ lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid* gri
     if (tiles_per_item) *tiles_per_item = c.tiles_per_item;
     if (n_items) *n_items = c.n_items;
     return LSP_OK;
+}
+
+size_t lsp_row_order_workspace_bytes(void) {
+    return (lsp::kOrderBuckets * sizeof(unsigned int) + 255) / 256 * 256;
+}
+
+lsp_status lsp_row_order(const int64_t* offsets, int64_t n_obj, const int32_t* row_obj,
+                         const int32_t* row_band, int64_t n_rows, int32_t rows_per_group,
+                         int32_t* perm, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!offsets || !perm || !workspace || n_obj < 1 || n_rows < 1 || rows_per_group < 1)
+        return LSP_EINVAL;
+    if (n_rows > (int64_t)INT32_MAX) return LSP_EINVAL;
+    if (!row_obj && n_rows != n_obj * (int64_t)rows_per_group) return LSP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % lsp::kAlign) return LSP_EINVAL;
+    if (workspace_bytes < lsp_row_order_workspace_bytes()) return LSP_ENOMEM;
+    lsp::OrderParams op;
+    op.offsets = offsets;
+    op.n_obj = n_obj;
+    op.row_obj = row_obj;
+    op.row_band = row_band;
+    op.n_rows = n_rows;
+    op.rows_per_group = rows_per_group;
+    op.pad = 0;
+    op.hist = static_cast<unsigned int*>(workspace);
+    op.perm = perm;
+    return lsp::launch_row_order(op, static_cast<hipStream_t>(stream)) == hipSuccess ? LSP_OK
+                                                                                      : LSP_EHIP;
 }
 
 lsp_status lsp_set_stage_events(void* main_begin, void* main_end) {

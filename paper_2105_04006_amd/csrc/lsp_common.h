@@ -478,6 +478,21 @@ __device__ __forceinline__ RowRange decode_row(const int32_t* row_obj, const int
 }
 
 
+// The row a work item's rank stands for: the rank itself, or, under the
+// longest-first order, the row the ordering kernels placed at that rank
+// (wave-uniform, like the rank).
+__device__ __forceinline__ int64_t item_row(const int32_t* perm, int64_t rank) {
+    return perm ? uniform_i64((int64_t)perm[rank]) : rank;
+}
+
+// The first row rank of XCD x's share when n_rows ranks are dealt out in
+// eight contiguous, balanced runs (the first n_rows % 8 runs one longer); the
+// longest-first order places its rows the same way.
+__device__ __forceinline__ int64_t xcd_first_rank(int x, int64_t n_rows) {
+    const int64_t base = n_rows / kXcds, rem = n_rows % kXcds;
+    return (int64_t)x * base + (x < rem ? (int64_t)x : rem);
+}
+
 // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs,
 // so block b runs on XCD b % 8.  Remap so that each XCD receives a contiguous
 // run of items (and hence the same objects stay in one XCD's L2).
@@ -529,6 +544,7 @@ struct MainParams {
                              // needs the FP64 fix-up (its key then comes from the fix-up)
     float* part;             // [n_split][4][n_f] when n_split > 1
     unsigned int* queue;     // persistent schedule: kXcds counters
+    const int32_t* row_perm = nullptr;  // rank -> row (longest first); NULL: rank = row
     int32_t persistent;
     int32_t wave_split;      // the waves of a workgroup split observations, not bins
     const double* dy = nullptr;  // generalized form: errors (NULL: unit errors)
@@ -609,6 +625,21 @@ hipError_t launch_fixup(const FixupParams& p, hipStream_t s);
 hipError_t launch_combine(const CombineParams& p, hipStream_t s);
 hipError_t launch_peaks(const PeakParams& p, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* dst, int64_t n, unsigned int v, hipStream_t s);
+
+// Longest-first row order (lsp_order.hip).
+constexpr int kOrderBuckets = 1024 + 53 * 64;  // N_t < 1024 exact, 64 per octave above
+struct OrderParams {
+    const int64_t* offsets;  // CSR offsets of the objects (n_obj + 1)
+    int64_t n_obj;
+    const int32_t* row_obj;   // object of each row, or NULL (row r is object r / rows_per_group)
+    const int32_t* row_band;  // band of each row, or NULL; a negative band costs nothing
+    int64_t n_rows;
+    int32_t rows_per_group;
+    int32_t pad;
+    unsigned int* hist;  // kOrderBuckets counters (cleared by the launcher)
+    int32_t* perm;       // [n_rows]: rank -> row
+};
+hipError_t launch_row_order(const OrderParams& p, hipStream_t s);
 
 // Host side (lsp_api.hip): the whole-grid batch call of lsp_batch /
 // lsp_gen_batch and its workspace size.  one_batch = false treats the objects

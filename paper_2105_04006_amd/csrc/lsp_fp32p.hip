@@ -63,8 +63,9 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
     // observation split); a split object has one tile per chunk
     const int64_t chunk_id = item / P.n_split;
     const int split = (int)(item - chunk_id * P.n_split);
-    const int64_t row = chunk_id / P.chunks_per_row;
-    const int64_t chunk = chunk_id - row * P.chunks_per_row;
+    const int64_t rank = chunk_id / P.chunks_per_row;
+    const int64_t chunk = chunk_id - rank * P.chunks_per_row;
+    const int64_t row = item_row(P.row_perm, rank);
     const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;
     const int64_t t_lo = chunk * P.tiles_per_item;
@@ -232,12 +233,14 @@ __global__ __launch_bounds__(kWave* W)
                                                   s_part);
         return;
     }
-    const int64_t per = (P.n_items + kXcds - 1) / kXcds;
+    // each XCD's queue holds the items of one contiguous run of row ranks
+    const int64_t per_row = P.chunks_per_row * P.n_split;
+    const int64_t n_rows = P.n_items / per_row;
     const int x0 = (int)(blockIdx.x % kXcds);
     for (int d = 0; d < kXcds; ++d) {
         const int x = (x0 + d) % kXcds;
-        const int64_t lo = (int64_t)x * per;
-        const int64_t hi = lo + per < P.n_items ? lo + per : P.n_items;
+        const int64_t lo = xcd_first_rank(x, n_rows) * per_row;
+        const int64_t hi = xcd_first_rank(x + 1, n_rows) * per_row;
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
             fp32p_item<K, W, CHEB, WS, SRC, TRIG>(P, item, s_tau, s_obs, s_red, s_part);

@@ -33,9 +33,11 @@ __global__ __launch_bounds__(kWave* W) void fp64_kernel(const MainParams P) {
     const int64_t tile_freqs = (int64_t)kWave * KF * W;
     const int64_t b = linear_block();
     if (b >= P.n_items) return;
-    const int64_t item = xcd_remap(b, P.n_items);
-    const int64_t row = item / P.tiles_per_row;
-    const int64_t ftile = item - row * P.tiles_per_row;
+    const int64_t rank_item = xcd_remap(b, P.n_items);
+    const int64_t rank = rank_item / P.tiles_per_row;
+    const int64_t ftile = rank_item - rank * P.tiles_per_row;
+    const int64_t row = item_row(P.row_perm, rank);
+    const int64_t item = row * P.tiles_per_row + ftile;  // the tile's record
     const RowRange rr = decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;
     const int64_t i0 = rr.f_lo + ftile * tile_freqs + (int64_t)wave * kWave * KF + lane;

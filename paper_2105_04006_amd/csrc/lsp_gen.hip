@@ -33,10 +33,12 @@ __device__ __forceinline__ void gen_item(const MainParams& P, int64_t item, doub
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int64_t tile_freqs = (int64_t)kWave * K * W;
-    const int64_t tile = item / P.n_split;
-    const int split = (int)(item - tile * P.n_split);
-    const int64_t row = tile / P.tiles_per_row;
-    const int64_t ftile = tile - row * P.tiles_per_row;
+    const int64_t rank_tile = item / P.n_split;
+    const int split = (int)(item - rank_tile * P.n_split);
+    const int64_t rank = rank_tile / P.tiles_per_row;
+    const int64_t ftile = rank_tile - rank * P.tiles_per_row;
+    const int64_t row = item_row(P.row_perm, rank);
+    const int64_t tile = row * P.tiles_per_row + ftile;  // the tile's flag bit
     const RowRange rr =
         decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;
@@ -183,12 +185,14 @@ __global__ __launch_bounds__(kWave* W) void gen_fp32p_kernel(const MainParams P)
         if (b < P.n_items) gen_item<K, W>(P, xcd_remap(b, P.n_items), s_tau, s_obs, s_red);
         return;
     }
-    const int64_t per = (P.n_items + kXcds - 1) / kXcds;
+    // each XCD's queue holds the items of one contiguous run of row ranks
+    const int64_t per_row = P.tiles_per_row * P.n_split;
+    const int64_t n_rows = P.n_items / per_row;
     const int x0 = (int)(blockIdx.x % kXcds);
     for (int d = 0; d < kXcds; ++d) {
         const int x = (x0 + d) % kXcds;
-        const int64_t lo = (int64_t)x * per;
-        const int64_t hi = lo + per < P.n_items ? lo + per : P.n_items;
+        const int64_t lo = xcd_first_rank(x, n_rows) * per_row;
+        const int64_t hi = xcd_first_rank(x + 1, n_rows) * per_row;
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
             gen_item<K, W>(P, item, s_tau, s_obs, s_red);
@@ -210,9 +214,11 @@ __global__ __launch_bounds__(kWave* W) void gen_fp64_kernel(const MainParams P) 
     const int64_t tile_freqs = (int64_t)kWave * KF * W;
     const int64_t b = linear_block();
     if (b >= P.n_items) return;
-    const int64_t item = xcd_remap(b, P.n_items);
-    const int64_t row = item / P.tiles_per_row;
-    const int64_t ftile = item - row * P.tiles_per_row;
+    const int64_t rank_item = xcd_remap(b, P.n_items);
+    const int64_t rank = rank_item / P.tiles_per_row;
+    const int64_t ftile = rank_item - rank * P.tiles_per_row;
+    const int64_t row = item_row(P.row_perm, rank);
+    const int64_t item = row * P.tiles_per_row + ftile;  // the tile's record
     const RowRange rr =
         decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;

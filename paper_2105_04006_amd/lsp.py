@@ -30,6 +30,7 @@ REC_AUTO, REC_ROTATION, REC_CHEBYSHEV = 0, 1, 2
 WSPLIT_AUTO, WSPLIT_OFF, WSPLIT_ON = 0, 1, 2
 OBS_AUTO, OBS_LDS, OBS_DIRECT = 0, 1, 2
 TRIG_AUTO, TRIG_HW, TRIG_LIB, TRIG_POLY = 0, 1, 2, 3
+ORDER_AUTO, ORDER_INPUT, ORDER_LPT = 0, 1, 2
 
 PEAK_DTYPE = np.dtype(
     [("index", "<i8"), ("freq", "<f8"), ("period", "<f8"), ("power", "<f8"),
@@ -49,7 +50,8 @@ class Options(ctypes.Structure):
                 ("k_per_lane", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
                 ("t_split", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("recurrence", ctypes.c_int32), ("wave_split", ctypes.c_int32),
-                ("obs_read", ctypes.c_int32), ("seed_trig", ctypes.c_int32)]
+                ("obs_read", ctypes.c_int32), ("seed_trig", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FeatureOptions(ctypes.Structure):
@@ -189,6 +191,10 @@ def lib():
                                           ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_int64)]
+        L.lsp_row_order_workspace_bytes.restype = sz
+        L.lsp_row_order_workspace_bytes.argtypes = []
+        L.lsp_row_order.restype = ctypes.c_int
+        L.lsp_row_order.argtypes = [vp, i64, vp, vp, i64, i32, vp, vp, sz, vp]
         L.lsp_set_stage_events.restype = ctypes.c_int
         L.lsp_set_stage_events.argtypes = [vp, vp]
         L.lsp_version.restype = ctypes.c_int32
@@ -230,6 +236,31 @@ def describe_launch(n_obj, n_obs, grid, opt, generalized=False):
     return d
 
 
+def row_order(offsets, row_obj=None, row_band=None, rows_per_group=1, n_rows=None,
+              stream=None):
+    """lsp_row_order: the longest-first rank -> row permutation (int32 device
+    tensor) of the rows of a batch, as the batch calls use it with
+    ORDER_LPT."""
+    _check(offsets, torch.int64, "offsets")
+    n_obj = int(offsets.numel()) - 1
+    if row_obj is not None:
+        _check(row_obj, torch.int32, "row_obj")
+        n_rows = int(row_obj.numel())
+    elif n_rows is None:
+        n_rows = n_obj * int(rows_per_group)
+    if row_band is not None:
+        _check(row_band, torch.int32, "row_band")
+    perm = torch.empty(int(n_rows), dtype=torch.int32, device=offsets.device)
+    nb = int(lib().lsp_row_order_workspace_bytes())
+    ws = torch.empty(nb, dtype=torch.uint8, device=offsets.device)
+    st = lib().lsp_row_order(_dev_ptr(offsets), n_obj, _dev_ptr(row_obj), _dev_ptr(row_band),
+                             int(n_rows), int(rows_per_group), _dev_ptr(perm), _dev_ptr(ws), nb,
+                             _stream_handle(stream))
+    if st != OK:
+        raise LspError(st, "lsp_row_order")
+    return perm
+
+
 def status_string(status):
     return lib().lsp_status_string(int(status)).decode()
 
@@ -244,7 +275,7 @@ def make_grid(f_min, f_max, n_f, unit=CYCLES):
 
 def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype=PGRAM_F32, k=0,
                  waves=0, t_split=0, schedule=SCHED_AUTO, recurrence=REC_AUTO,
-                 wave_split=WSPLIT_AUTO, obs_read=0, seed_trig=0):
+                 wave_split=WSPLIT_AUTO, obs_read=0, seed_trig=0, order=ORDER_AUTO):
     o = Options()
     o.form, o.normalize, o.subtract_mean, o.pgram_dtype = (int(form), int(bool(normalize)),
                                                            int(bool(subtract_mean)),
@@ -255,6 +286,7 @@ def make_options(form=FORM_FP64, normalize=True, subtract_mean=True, pgram_dtype
     o.wave_split = int(wave_split)
     o.obs_read = int(obs_read)
     o.seed_trig = int(seed_trig)
+    o.order = int(order)
     return o
 
 
@@ -299,7 +331,7 @@ class Periodogram:
                  normalize=True, subtract_mean=True, pgram=True, pgram_dtype=PGRAM_F32,
                  peaks=True, k=0, waves=0, t_split=0, schedule=SCHED_AUTO,
                  recurrence=REC_AUTO, wave_split=WSPLIT_AUTO, method="standard", dy=None,
-                 obs_read=0, seed_trig=0):
+                 obs_read=0, seed_trig=0, order=ORDER_AUTO):
         _check(t, torch.float64, "t")
         _check(y, torch.float64, "y")
         if t.numel() != y.numel():
@@ -321,7 +353,7 @@ class Periodogram:
         self.n_obj = 1 if offsets is None else int(offsets.numel()) - 1
         self.grid = make_grid(f_min, f_max, n_f, unit)
         self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, t_split,
-                                schedule, recurrence, wave_split, obs_read, seed_trig)
+                                schedule, recurrence, wave_split, obs_read, seed_trig, order)
         dev = t.device
         nb = (gen_workspace_bytes if self.gen else workspace_bytes)(self.n_obj, self.n_obs,
                                                                    self.grid, self.opt)
@@ -494,7 +526,7 @@ class Rows:
                  rows_per_group=1, unit=CYCLES, form=FORM_FP32P, normalize=True,
                  subtract_mean=True, pgram=None, pgram_dtype=PGRAM_F32, peaks=None, k=0,
                  waves=0, schedule=SCHED_AUTO, recurrence=REC_AUTO, max_rows=None,
-                 method="standard", dy=None):
+                 method="standard", dy=None, order=ORDER_AUTO):
         for x, dt, nm in ((t, torch.float64, "t"), (y, torch.float64, "y"),
                           (offsets, torch.int64, "offsets")):
             _check(x, dt, nm)
@@ -517,7 +549,7 @@ class Rows:
         self.n_obj = int(offsets.numel()) - 1
         self.grid = make_grid(f_min, f_max, n_f, unit)
         self.opt = make_options(form, normalize, subtract_mean, pgram_dtype, k, waves, 0,
-                                schedule, recurrence)
+                                schedule, recurrence, order=order)
         self.band_bins = int(band_bins) if row_band is not None else 0
         self.rows_per_group = int(rows_per_group)
         named = row_obj if row_obj is not None else row_band

@@ -34,11 +34,30 @@ def test_exports_every_declared_function(L):
         assert hasattr(L, n), f"{n} declared in include/lsp.h but not exported"
 
 
-def test_struct_sizes_match_header():
+def test_struct_sizes_match_header(tmp_path):
     assert ctypes.sizeof(lsp.Grid) == 32
-    assert ctypes.sizeof(lsp.Options) == 48
+    assert ctypes.sizeof(lsp.Options) == 56
     assert lsp.PEAK_DTYPE.itemsize == lsp.PEAK_BYTES == 40
     assert ctypes.sizeof(lsp.FeatureOptions) == 16
+    # the ctypes mirrors against the header itself, field by field
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    fields = [name for name, _ in lsp.Options._fields_]
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lsp.h"\nint main(void) {\n'
+                   '  printf("%zu %zu %zu %zu\\n", sizeof(lsp_grid), sizeof(lsp_options), '
+                   'sizeof(lsp_peak), sizeof(lsp_feature_options));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(lsp_options, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c11", "-I", str(lsp.HEADER.rsplit("/", 1)[0]), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert [int(v) for v in out[:4]] == [ctypes.sizeof(lsp.Grid), ctypes.sizeof(lsp.Options),
+                                         lsp.PEAK_BYTES, ctypes.sizeof(lsp.FeatureOptions)]
+    assert [int(v) for v in out[4:]] == [getattr(lsp.Options, f).offset for f in fields]
 
 
 def test_feature_constants_match_header():
@@ -138,7 +157,8 @@ def test_argument_errors_are_reported_before_any_launch(L):
     for o in (lsp.make_options(form=3), lsp.make_options(pgram_dtype=2), bad_norm, bad_mean,
               lsp.make_options(k=3), lsp.make_options(form=lsp.FORM_FP32P, k=2),
               lsp.make_options(waves=3), lsp.make_options(t_split=65),
-              lsp.make_options(schedule=9)):
+              lsp.make_options(schedule=9), lsp.make_options(order=3),
+              lsp.make_options(order=-1)):
         assert _single(L, opt=o) == lsp.EINVAL
     assert _single(L, opt=lsp.make_options(t_split=2)) == lsp.EUNSUPPORTED
     assert _single(L, opt=lsp.make_options(schedule=lsp.SCHED_PERSISTENT)) == lsp.EUNSUPPORTED
@@ -376,6 +396,16 @@ def test_describe_launch_resolves_the_shape():
     gen = lsp.describe_launch(10, 5000, gb, lsp.make_options(form=lsp.FORM_FP32P), True)
     assert gen["k_per_lane"] in (8, 12, 16)
     assert f64["tiles_per_item"] == 1
+    # row order: longest first by default for large batches (>= 1e10 terms),
+    # as given for small ones and for a single object, and on request
+    assert many["order"] == lsp.ORDER_LPT and few["order"] == lsp.ORDER_INPUT
+    assert one["order"] == lsp.ORDER_INPUT
+    for od in (lsp.ORDER_INPUT, lsp.ORDER_LPT):
+        assert lsp.describe_launch(10, 5000, gb, lsp.make_options(order=od))["order"] == od
+        assert lsp.describe_launch(200_000, 52_000_000, gb, lsp.make_options(
+            form=lsp.FORM_FP32P, order=od))["order"] == od
+    assert lsp.describe_launch(1, 4096, g, lsp.make_options(
+        form=lsp.FORM_FP32P, order=lsp.ORDER_LPT))["order"] == lsp.ORDER_INPUT
     with pytest.raises(lsp.LspError):
         lsp.describe_launch(0, 10, gb, lsp.make_options())
     with pytest.raises(lsp.LspError):
@@ -416,3 +446,25 @@ def test_static_scratch_size_matches_header():
     text = open(lsp.HEADER).read()
     assert "#define LSP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)" in text
     assert lsp.STATIC_SCRATCH_BYTES == 64 << 20
+
+
+@cpu_only
+def test_row_order_argument_errors(L):
+    nb = L.lsp_row_order_workspace_bytes()
+    assert nb >= 4416 * 4 and nb % 256 == 0
+
+    def call(offsets=FAKE, n_obj=10, row_obj=None, row_band=None, n_rows=10, rpg=1, perm=FAKE,
+             ws=FAKE, ws_bytes=nb):
+        return L.lsp_row_order(offsets, n_obj, row_obj, row_band, n_rows, rpg, perm, ws,
+                               ws_bytes, None)
+
+    assert call(offsets=None) == lsp.EINVAL
+    assert call(perm=None) == lsp.EINVAL
+    assert call(ws=None) == lsp.EINVAL
+    assert call(n_obj=0) == lsp.EINVAL
+    assert call(n_rows=0) == lsp.EINVAL
+    assert call(rpg=0) == lsp.EINVAL
+    assert call(n_rows=11) == lsp.EINVAL              # row r is object r / rows_per_group
+    assert call(n_rows=20, rpg=2, ws=ctypes.c_void_p((1 << 20) + 8)) == lsp.EINVAL
+    assert call(row_obj=FAKE, n_rows=1 << 31) == lsp.EINVAL
+    assert call(ws_bytes=nb - 1) == lsp.ENOMEM
