@@ -167,6 +167,10 @@ def main():
     ap.add_argument("--recurrence", default="auto", choices=["auto", "rotation", "chebyshev"])
     ap.add_argument("--k", type=int, default=0, help="frequencies per lane (0: library default)")
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--t-split", type=int, default=0,
+                    help="single object: split of the observation axis (0: library default)")
+    ap.add_argument("--wave-split", default="auto", choices=["auto", "off", "on"],
+                    help="FP32 form: the waves of a workgroup split the observations")
     ap.add_argument("--schedule", default="auto", choices=["auto", "grid", "persistent"])
     ap.add_argument("--order", default="auto", choices=["auto", "input", "lpt"],
                     help="order of a batch's rows (longest first, or as given)")
@@ -254,8 +258,10 @@ def main():
     variant = obs == lsp.OBS_DIRECT or trig in (lsp.TRIG_LIB, lsp.TRIG_POLY)
     kv = dict(obs_read=obs, seed_trig=trig) if variant else {}
     order = order_code(args.order)
+    wsp = {"auto": lsp.WSPLIT_AUTO, "off": lsp.WSPLIT_OFF, "on": lsp.WSPLIT_ON}[args.wave_split]
     p32 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, schedule=sched,
-                          recurrence=rec, k=args.k, waves=args.waves, order=order, **kw, **kv)
+                          recurrence=rec, k=args.k, waves=args.waves, order=order,
+                          wave_split=wsp, t_split=args.t_split, **kw, **kv)
     p64 = lsp.Periodogram(t, y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP64, order=order, **kw)
 
     def timed(fn, steps):

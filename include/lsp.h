@@ -159,7 +159,7 @@ typedef struct {
                               0: use y as given (the paper assumes it is zero-mean)     */
     int32_t pgram_dtype;   /* LSP_PGRAM_F32 or LSP_PGRAM_F64                            */
     int32_t k_per_lane;    /* frequencies per lane: FP32P 4/8/10/12/16/32, FP64 1/2/4   */
-    int32_t waves_per_wg;  /* wavefronts per workgroup: 1, 2 or 4                       */
+    int32_t waves_per_wg;  /* wavefronts per workgroup: 1, 2 or 4; 8 with wave_split on  */
     int32_t t_split;       /* single object: split of the observation axis, 1..64       */
     int32_t schedule;      /* LSP_SCHED_*                                               */
     int32_t recurrence;    /* LSP_REC_* (FP32 form only)                                */

@@ -84,7 +84,7 @@ lsp_status valid_options(const lsp_options* o) {
     if (!is_bool(o->normalize) || !is_bool(o->subtract_mean)) return LSP_EINVAL;
     if (!(o->pgram_dtype == LSP_PGRAM_F32 || o->pgram_dtype == LSP_PGRAM_F64)) return LSP_EINVAL;
     if (!(o->waves_per_wg == 0 || o->waves_per_wg == 1 || o->waves_per_wg == 2 ||
-          o->waves_per_wg == 4))
+          o->waves_per_wg == 4 || o->waves_per_wg == 8))
         return LSP_EINVAL;
     if (o->form == LSP_FORM_FP64) {
         if (!(o->k_per_lane == 0 || o->k_per_lane == 1 || o->k_per_lane == 2 ||
@@ -125,7 +125,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
             return LSP_EUNSUPPORTED;
         if (!(o->k_per_lane == 0 || o->k_per_lane == 8 || o->k_per_lane == 16))
             return LSP_EUNSUPPORTED;
-        if (o->waves_per_wg == 2) return LSP_EUNSUPPORTED;
+        if (o->waves_per_wg == 2 || o->waves_per_wg == 8) return LSP_EUNSUPPORTED;
     }
     c->form = o->form;
     // The three-term recurrence needs fewer operations per bin and measured as
@@ -142,7 +142,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         if (!o->k_per_lane)
             while ((int64_t)kWave * c->k * c->waves > n_f && c->k > 1) c->k /= 2;
         if (o->t_split > 1) return LSP_EUNSUPPORTED;
-        if (o->schedule == LSP_SCHED_PERSISTENT) return LSP_EUNSUPPORTED;
+        if (o->schedule == LSP_SCHED_PERSISTENT || o->waves_per_wg == 8) return LSP_EUNSUPPORTED;
     } else {
         // Measured defaults: one object on the whole grid runs best with four
         // waves per workgroup sharing its staged observations; many rows run
@@ -154,7 +154,8 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
             // in-workgroup wave split, and K in {4, 8, 12, 16}.
             if (o->recurrence == LSP_REC_ROTATION || o->wave_split == LSP_WSPLIT_ON)
                 return LSP_EUNSUPPORTED;
-            if (o->k_per_lane == 10 || o->k_per_lane == 32) return LSP_EUNSUPPORTED;
+            if (o->k_per_lane == 10 || o->k_per_lane == 32 || o->waves_per_wg == 8)
+                return LSP_EUNSUPPORTED;
         }
         if (o->k_per_lane) {
             c->k = o->k_per_lane;
@@ -206,6 +207,8 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         // cent of the default (the extra registers cost a wave per SIMD), so
         // it is used only on request.
         c->ws = c->waves > 1 && o->wave_split == LSP_WSPLIT_ON;
+        // eight waves per workgroup exist only with the wave split
+        if (c->waves == 8 && !c->ws) return LSP_EUNSUPPORTED;
         if (o->t_split > 1) {
             if (n_obj != 1 || !whole) return LSP_EUNSUPPORTED;
             c->split = o->t_split;

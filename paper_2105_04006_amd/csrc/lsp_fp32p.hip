@@ -48,8 +48,8 @@ __device__ __forceinline__ float4 stage_obs(double step_cyc, double tc, double y
 // SRC: LSP_OBS_LDS stages tiles of observations in LDS; LSP_OBS_DIRECT reads
 // the staging pass's values from global memory.  TRIG: LSP_TRIG_*.
 // WS (wave split): the W waves of a workgroup share the same 64 K bins and
-// each takes every W-th staged observation; their sums are added in LDS, in
-// wave order, before the finish.  This multiplies the waves working on one
+// each takes every W-th staged observation; their sums are added in LDS, as a
+// fixed tree over the waves, before the finish.  This multiplies the waves working on one
 // object without the per-split partial sums in HBM that the observation split
 // across workgroups needs.
 template <int K, int W, bool CHEB, bool WS, int SRC, int TRIG>
@@ -127,25 +127,31 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
                     }
                     __syncthreads();
                 }
-                for (int q = WS ? wave : 0; q < cnt; q += WS ? W : 1)
+                // (the wave index is uniform across the wave; say so, so that the
+                // staged reads stay scalar-addressed broadcasts)
+                for (int q = WS ? uniform_i32(wave) : 0; q < cnt; q += WS ? W : 1)
                     accumulate_obs<K, CHEB, TRIG>(fl, s_tau[q], s_obs[q], xc, xs, cc, cs);
             }
         }
 
         if (WS) {
-            // add the other waves' sums into wave 0's, one array at a time
+            // add the waves' sums into wave 0's, one array at a time, as a
+            // tree: in each round the upper half of the remaining waves hands
+            // its sums through LDS to the lower half (a fixed order)
             auto gather = [&](float(&v)[K]) {
-                __syncthreads();
-                if (wave > 0) {
 #pragma unroll
-                    for (int k = 0; k < K; ++k) s_part[((wave - 1) * K + k) * kWave + lane] = v[k];
-                }
-                __syncthreads();
-                if (wave == 0) {
+                for (int half = W / 2; half >= 1; half /= 2) {
+                    __syncthreads();
+                    if (wave >= half && wave < 2 * half) {
 #pragma unroll
-                    for (int w = 1; w < W; ++w)
+                        for (int k = 0; k < K; ++k)
+                            s_part[((wave - half) * K + k) * kWave + lane] = v[k];
+                    }
+                    __syncthreads();
+                    if (wave < half) {
 #pragma unroll
-                        for (int k = 0; k < K; ++k) v[k] += s_part[((w - 1) * K + k) * kWave + lane];
+                        for (int k = 0; k < K; ++k) v[k] += s_part[(wave * K + k) * kWave + lane];
+                    }
                 }
             };
             gather(xc);
@@ -218,13 +224,13 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
 // with three, the VALU waits on latency more often.
 template <int K, int W, bool CHEB, bool WS, int SRC = LSP_OBS_LDS, int TRIG = LSP_TRIG_HW>
 __global__ __launch_bounds__(kWave* W)
-    __attribute__((amdgpu_waves_per_eu(K <= 16 && !WS ? 4 : 1))) void fp32p_kernel(
+    __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : 1))) void fp32p_kernel(
         const MainParams P) {
     __shared__ double s_tau[kTile];
     __shared__ float4 s_obs[kTile];
     __shared__ PeakRec s_red[W];
     __shared__ int64_t s_item;
-    __shared__ float s_part[WS ? (W - 1) * K * kWave : 1];
+    __shared__ float s_part[WS ? (W / 2) * K * kWave : 1];
 
     if (!P.persistent) {
         const int64_t b = linear_block();
@@ -349,6 +355,7 @@ hipError_t launch_kc(const MainParams& p, int waves, hipStream_t s) {
         case 1: return launch_kwc<K, 1, CHEB, false>(p, s);
         case 2: return ws ? launch_kwc<K, 2, CHEB, true>(p, s) : launch_kwc<K, 2, CHEB, false>(p, s);
         case 4: return ws ? launch_kwc<K, 4, CHEB, true>(p, s) : launch_kwc<K, 4, CHEB, false>(p, s);
+        case 8: return ws ? launch_kwc<K, 8, CHEB, true>(p, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -406,6 +406,20 @@ def test_describe_launch_resolves_the_shape():
             form=lsp.FORM_FP32P, order=od))["order"] == od
     assert lsp.describe_launch(1, 4096, g, lsp.make_options(
         form=lsp.FORM_FP32P, order=lsp.ORDER_LPT))["order"] == lsp.ORDER_INPUT
+    # eight waves per workgroup: FP32 form with the wave split only
+    ws8 = lsp.describe_launch(1, 4096, g, lsp.make_options(
+        form=lsp.FORM_FP32P, waves=8, k=16, wave_split=lsp.WSPLIT_ON))
+    assert (ws8["waves_per_wg"], ws8["wave_split"], ws8["t_split"]) == (8, lsp.WSPLIT_ON, 1)
+    assert ws8["tile_freqs"] == 64 * 16 and ws8["n_items"] == -(-500_000 // 1024)
+    for o in (lsp.make_options(form=lsp.FORM_FP32P, waves=8),
+              lsp.make_options(form=lsp.FORM_FP64, waves=8),
+              lsp.make_options(form=lsp.FORM_FP32P, waves=8, wave_split=lsp.WSPLIT_ON,
+                               seed_trig=lsp.TRIG_LIB)):
+        with pytest.raises(lsp.LspError):
+            lsp.describe_launch(1, 4096, g, o)
+    with pytest.raises(lsp.LspError):
+        lsp.describe_launch(1, 4096, g, lsp.make_options(
+            form=lsp.FORM_FP32P, waves=8, wave_split=lsp.WSPLIT_ON), generalized=True)
     with pytest.raises(lsp.LspError):
         lsp.describe_launch(0, 10, gb, lsp.make_options())
     with pytest.raises(lsp.LspError):

@@ -324,6 +324,28 @@ def test_fp32p_observation_split(dev):
         assert peak_ok(ora_pg, ora_pk["index"], pk["index"], 2 * FP32_ATOL, bins=1)
 
 
+def test_fp32p_wave_split(dev):
+    """The in-workgroup wave split (the waves of a workgroup share bins and
+    take every W-th observation, sums added in LDS as a fixed tree): 2, 4 and
+    8 waves, with and without the observation split, single object and batch,
+    against the oracle."""
+    t, y, _ = synth.sine_object(3000, 34)
+    ora_pg, ora_pk = oracle.single(t, y, 1.0, 12.0, 5000)
+    for waves, k, split in ((2, 16, 1), (4, 16, 1), (8, 16, 1), (8, 12, 1), (8, 8, 3), (4, 10, 2)):
+        say(f"fp32p wave split: waves={waves} k={k} t_split={split}")
+        pg, pk = run_single(dev, t, y, 1.0, 12.0, 5000, form=lsp.FORM_FP32P, waves=waves, k=k,
+                            t_split=split, wave_split=lsp.WSPLIT_ON)
+        assert_fp32_close(pg, ora_pg, f"waves={waves} k={k} split={split}")
+        assert peak_ok(ora_pg, ora_pk["index"], pk["index"], 2 * FP32_ATOL, bins=1)
+    w = synth.make_workload("batch_10k", n_obj=24)
+    ora_pg, ora_pk = oracle.batch(w.offsets, w.t, w.y, w.f_min, w.f_max, 3000)
+    pg, pk = run_batch(dev, w.offsets, w.t, w.y, w.f_min, w.f_max, 3000, form=lsp.FORM_FP32P,
+                       waves=8, k=16, wave_split=lsp.WSPLIT_ON)
+    assert_fp32_close(pg, ora_pg, "batch, 8 waves")
+    for o in range(w.n_obj):
+        assert peak_ok(ora_pg[o], ora_pk["index"][o], pk["index"][o], 2 * FP32_ATOL, bins=1)
+
+
 # -------------------------------------------------------------- full-size cases
 
 def test_full_single_4096(dev):
