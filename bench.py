@@ -749,7 +749,10 @@ def bench_forms(args, torch, dev):
         prop = learned.fit_proposer(
             lambda n, s: make(n, s), dev, n_train=args.train_objects, n_val=args.val_objects,
             seed_train=synth.SEED_BASE + 1000, seed_val=synth.SEED_BASE + 1001,
-            method=method, proposals=props, log=lambda m: log("[bench] " + m))
+            method=method, proposals=props, log=lambda m: log("[bench] " + m),
+            # 99.93% on 20,000 validation objects keeps the evaluated batch at
+            # >= 99.9% despite the sampling spread (about +-0.02%)
+            target=0.9993)
         runs = {}
         for pr in props:
             lp = prop.periodogram(off, t, y, w.f_min, w.f_max, unit=w.unit, proposal=pr,
@@ -759,7 +762,7 @@ def bench_forms(args, torch, dev):
                 lp()
             ms = wall(lp, steps)
             pk = lp.peaks()
-            idx = lp.idx.cpu().numpy()
+            idx = lp.rows.cpu().numpy()  # the bands kept for refinement
             bb = np.where(idx >= 0, np.minimum(prop.geo.band_bins,
                                                w.n_f - idx * prop.geo.band_bins), 0).sum(axis=1)
             fb = lp.objects[:lp.n_fallback].cpu().numpy()
@@ -769,7 +772,9 @@ def bench_forms(args, torch, dev):
                         "fallback_objects": int(lp.n_fallback),
                         "evaluated_fraction": evaluated / float(w.evals),
                         "thresholds": {"mass_min": prop.thresholds[pr][0],
-                                       "power_min": prop.thresholds[pr][1]},
+                                       "power_min": prop.thresholds[pr][1],
+                                       "alpha": prop.thresholds[pr][3],
+                                       "tau": prop.thresholds[pr][4]},
                         "_peaks": pk, "_idx": idx}
             log(f"[bench] learned ({pr}) {ms:.2f} ms/step, {lp.n_fallback} fallbacks, "
                 f"evaluated {evaluated / w.evals:.4f} of the grid")
@@ -855,6 +860,7 @@ def bench_forms(args, torch, dev):
             r["peak_bin_agreement_vs_fp32"] = float(np.mean(
                 np.abs(pk["index"][ok] - pk32["index"][ok]) <= 1))
             r["proposal_covers_peak_band"] = float(np.mean((idx == band[:, None]).any(axis=1)[ok]))
+            r["mean_refined_bands"] = float(np.mean((idx >= 0).sum(axis=1)))
             if pk64 is not None:
                 p64_at_l = bin_values(w, tt, lsp.FORM_FP64, np.where(ok, pk["index"], -1),
                                       method, dy)

@@ -557,6 +557,22 @@ lsp_status lsp_top_k(const float *logits, int64_t n, int32_t c, int32_t k, int32
 lsp_status lsp_band_max(const float *x, int64_t n, int32_t d, int32_t start, int32_t n_bands,
                         int32_t group, float *out, void *stream);
 
+/* Adaptive band count.  Row i's `top` proposed bands idx [n x top] -- the
+ * first n_net from the network in decreasing probability, the rest by
+ * decreasing coarse power (as lsp_top_k and lsp_merge_bands leave them) --
+ * are copied to out [n x top] or replaced by -1 (a row lsp_batch_rows skips):
+ * a network slot is kept while the softmax mass of the kept network slots
+ * before it is below tau (the first is always kept; tau > 1 keeps all); a
+ * coarse slot is kept if score[i][band] >= alpha * max_b score[i][b] (alpha
+ * <= 0 keeps all; the first slot of a row with n_net = 0 is always kept).
+ * logits, score: [n x c] FP32 (c <= 128 bands), logits required when
+ * n_net > 0, score may be NULL (coarse slots then kept).  kept_mass [n] (may
+ * be NULL) receives the softmax mass of the kept network slots.  Errors:
+ * LSP_EINVAL for bad sizes, NaN thresholds or missing arrays; LSP_EHIP. */
+lsp_status lsp_trim_bands(const int32_t *idx, int64_t n, int32_t top, int32_t n_net,
+                          const float *logits, const float *score, int32_t c, float tau,
+                          float alpha, int32_t *out, float *kept_mass, void *stream);
+
 /* Per row, merge two band lists: the entries of a [n x ka] in order, then
  * those of b [n x kb] not already taken, until k_out (<= 128) distinct
  * non-negative bands are in out [n x k_out]; -1 fills the rest (a row with

@@ -456,6 +456,64 @@ __global__ __launch_bounds__(256) void top_k_kernel(const float* __restrict__ lo
     if (lane == 0 && mass) mass[row] = taken / se;
 }
 
+// Adaptive band count, one wavefront per row.  Row i's `top` proposed bands
+// idx[i][r] -- slots r < n_net from the network in decreasing probability,
+// the rest in decreasing coarse power -- are copied to out[i][r] or replaced
+// by -1:
+//   a network slot is kept while the softmax mass of the kept network slots
+//   before it is below tau (the first is always kept);
+//   a coarse slot is kept if its band's score is at least alpha times the
+//   row's largest band score (the first slot of a row without network slots
+//   is always kept).
+// kept_mass[i] (if not NULL) receives the softmax mass of the kept network
+// slots, each probability exp(z_b - max z) / sum_j exp(z_j - max z) in FP32.
+__global__ __launch_bounds__(256) void trim_bands_kernel(
+    const int32_t* __restrict__ idx, int64_t n, int32_t top, int32_t n_net,
+    const float* __restrict__ logits, const float* __restrict__ score, int32_t c, float tau,
+    float alpha, int32_t* __restrict__ out, float* __restrict__ kept_mass) {
+    const int64_t row = linear_block() * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    // softmax normaliser of the logits and the largest band score (c <= 128)
+    float mx = -INFINITY, se = 0.f, smax = -INFINITY;
+    if (logits) {
+        const float* z = logits + row * c;
+        const float v0 = lane < c ? z[lane] : -INFINITY;
+        const float v1 = lane + 64 < c ? z[lane + 64] : -INFINITY;
+        mx = fmaxf(v0, v1);
+        for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        se = (lane < c ? expf(v0 - mx) : 0.f) + (lane + 64 < c ? expf(v1 - mx) : 0.f);
+        for (int off = 32; off >= 1; off >>= 1) se += __shfl_xor(se, off, 64);
+    }
+    if (score) {
+        const float* q = score + row * c;
+        smax = fmaxf(lane < c ? q[lane] : -INFINITY, lane + 64 < c ? q[lane + 64] : -INFINITY);
+        for (int off = 32; off >= 1; off >>= 1) smax = fmaxf(smax, __shfl_xor(smax, off, 64));
+    }
+    if (lane != 0) return;
+    const int32_t* in = idx + row * top;
+    int32_t* o = out + row * top;
+    float cum = 0.f;
+    bool any_net = false;
+    for (int32_t r = 0; r < top; ++r) {
+        const int32_t b = in[r];
+        bool keep = false;
+        if (b >= 0 && b < c) {
+            if (r < n_net) {
+                keep = !any_net || cum < tau;
+                if (keep) {
+                    any_net = true;
+                    if (logits) cum += expf(logits[row * c + b] - mx) / se;
+                }
+            } else {
+                keep = (n_net == 0 && r == 0) || !score || score[row * c + b] >= alpha * smax;
+            }
+        }
+        o[r] = keep ? b : -1;
+    }
+    if (kept_mass) kept_mass[row] = cum;
+}
+
 }  // namespace
 }  // namespace lsp
 
@@ -591,6 +649,20 @@ lsp_status lsp_merge_bands(const int32_t* a, int32_t ka, const int32_t* b, int32
     if (n == 0) return LSP_OK;
     hipLaunchKernelGGL(lsp::merge_bands_kernel, lsp::grid_for((n + 255) / 256), dim3(256), 0,
                        static_cast<hipStream_t>(stream), a, ka, b, kb, n, k_out, out);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
+}
+
+lsp_status lsp_trim_bands(const int32_t* idx, int64_t n, int32_t top, int32_t n_net,
+                          const float* logits, const float* score, int32_t c, float tau,
+                          float alpha, int32_t* out, float* kept_mass, void* stream) {
+    if (n < 0 || top < 1 || top > 128 || n_net < 0 || n_net > top || c < 1 || c > 128)
+        return LSP_EINVAL;
+    if (!(tau == tau) || !(alpha == alpha)) return LSP_EINVAL;
+    if (n > 0 && (!idx || !out || (n_net > 0 && !logits))) return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    hipLaunchKernelGGL(lsp::trim_bands_kernel, lsp::grid_for((n + 3) / 4), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), idx, n, top, n_net, logits, score, c, tau,
+                       alpha, out, kept_mass);
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
 

@@ -242,6 +242,20 @@ def peak_bands(peaks_raw, n, band_bins, n_bands, out=None, stream=None):
     return out
 
 
+def trim_bands(idx, n_net, logits, score, tau, alpha, out=None, kept_mass=None, stream=None):
+    """lsp_trim_bands: per row of proposed bands idx [n x top], keep network
+    slots (the first n_net) while the kept softmax mass is below tau and
+    coarse slots whose band score reaches alpha times the row's largest;
+    the others become -1 in out.  Returns (out, kept_mass)."""
+    n, top = idx.shape
+    c = (logits if logits is not None else score).shape[1]
+    out = torch.empty_like(idx) if out is None else out
+    _ok(lsp.lib().lsp_trim_bands(_p(idx), int(n), int(top), int(n_net), _p(logits), _p(score),
+                                 int(c), ctypes.c_float(tau), ctypes.c_float(alpha), _p(out),
+                                 _p(kept_mass), _s(stream)), "lsp_trim_bands")
+    return out, kept_mass
+
+
 def select_fallback(peaks_raw, mass, n, mass_min, power_min, objects, count, stream=None):
     """Objects to re-run on the whole grid (lsp_select_fallback); fills objects[:count]."""
     _ok(lsp.lib().lsp_select_fallback(_p(peaks_raw), _p(mass), int(n), ctypes.c_float(mass_min),
@@ -263,9 +277,12 @@ class LearnedPeriodogram:
     computed on a fraction of the grid).
 
     For each object: features -> standardise -> network -> the `top` bands to
-    refine (see propose) -> the FP32 batch kernels on those bands only (row mode)
-    -> objects whose proposal is uncertain (softmax mass of the refined bands
-    below mass_min) or whose refined peak is weak (power below power_min) are
+    refine (see propose), of which only the confident ones are kept (network
+    bands until their softmax mass reaches tau, coarse-power bands whose
+    score reaches alpha times the object's largest; lsp_trim_bands) -> the
+    FP32 batch kernels on those bands only (row mode) -> objects whose
+    proposal is uncertain (softmax mass of the refined network bands below
+    mass_min) or whose refined peak is weak (power below power_min) are
     re-run on the whole grid.  Every step is a library kernel; the host only
     reads the number of fallback objects to size the last launch.
     ``method="generalized"`` refines (and falls back) with the generalized
@@ -274,7 +291,7 @@ class LearnedPeriodogram:
 
     def __init__(self, net, geometry, offsets, t, y, f_min, f_max, unit=lsp.CYCLES, top=8,
                  mass_min=0.0, power_min=0.0, k=0, waves=0, proposal="hybrid", top_net=4,
-                 method="standard", dy=None):
+                 method="standard", dy=None, alpha=0.0, tau=2.0):
         if proposal not in ("network", "coarse", "hybrid"):
             raise ValueError("proposal must be 'network', 'coarse' or 'hybrid'")
         self.net, self.geo, self.top = net, geometry, int(top)
@@ -283,11 +300,13 @@ class LearnedPeriodogram:
         self.offsets, self.t, self.y = offsets, t, y
         self.n_obj = int(offsets.numel()) - 1
         self.mass_min, self.power_min = float(mass_min), float(power_min)
+        self.alpha, self.tau = float(alpha), float(tau)
         dev = t.device
         self.feat = lsp.Features(offsets, t, y, f_min, f_max, unit=unit)
         self.x = torch.empty((self.n_obj, net.dims[0]), dtype=torch.int16, device=dev)
         self.logits = torch.empty((self.n_obj, net.dims[-1]), dtype=torch.float32, device=dev)
         self.idx = torch.empty((self.n_obj, self.top), dtype=torch.int32, device=dev)
+        self.rows = torch.empty((self.n_obj, self.top), dtype=torch.int32, device=dev)
         self.idx_net = torch.empty((self.n_obj, self.top_net), dtype=torch.int32, device=dev)
         self.idx_coarse = torch.empty((self.n_obj, self.top), dtype=torch.int32, device=dev)
         self.band_score = torch.empty((self.n_obj, geometry.n_bands), dtype=torch.float32,
@@ -297,7 +316,7 @@ class LearnedPeriodogram:
         self.objects = torch.empty(self.n_obj, dtype=torch.int32, device=dev)
         self.count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.refine = lsp.Rows(offsets, t, y, f_min, f_max, geometry.n_f, None,
-                               self.idx.view(-1), geometry.band_bins, self.top, unit=unit,
+                               self.rows.view(-1), geometry.band_bins, self.top, unit=unit,
                                form=lsp.FORM_FP32P, peaks=self.peaks_raw, k=k, waves=waves,
                                method=method, dy=dy)
         self.full = lsp.Rows(offsets, t, y, f_min, f_max, geometry.n_f, self.objects, None, 0, 1,
@@ -306,8 +325,9 @@ class LearnedPeriodogram:
         self.n_fallback = 0
 
     def propose(self, stream=None):
-        """Features, network and top bands; fills self.idx (the bands to
-        refine) and self.mass (the network's softmax mass on its own picks).
+        """Features, network and top bands; fills self.idx (the `top`
+        proposed bands), self.rows (those kept, -1 for the others) and
+        self.mass (the network's softmax mass on its kept picks).
 
         proposal="network": the network's `top` most probable bands.
         proposal="coarse": the `top` bands whose pooled coarse power peaks
@@ -316,24 +336,37 @@ class LearnedPeriodogram:
         L = lsp.lib()
         n, nb = self.n_obj, self.geo.n_bands
         feats = self.net.normalize_rows(self.feat(stream), stream=stream)
-        if self.proposal != "coarse":  # "coarse": the method without the network
+        net = self.proposal != "coarse"  # "coarse": the method without the network
+        if net:
             self.net.standardize(feats, out=self.x, stream=stream)
             self.net.forward(self.x, logits=self.logits, stream=stream)
             first = self.idx if self.proposal == "network" else self.idx_net
-            _ok(L.lsp_top_k(_p(self.logits), n, nb, self.top_net, _p(first), _p(self.mass),
+            _ok(L.lsp_top_k(_p(self.logits), n, nb, self.top_net, _p(first), None,
                             _s(stream)), "lsp_top_k")
-            if self.proposal == "network":
-                return
-        # row normalisation is increasing within a row, so band maxima of the
-        # normalised coarse block rank bands as the raw power does
-        _ok(L.lsp_band_max(_p(feats), n, feats.shape[1], 0, nb, lsp.FEAT_COARSE // nb,
-                           _p(self.band_score), _s(stream)), "lsp_band_max")
-        target = self.idx if self.proposal == "coarse" else self.idx_coarse
-        _ok(L.lsp_top_k(_p(self.band_score), n, nb, self.top, _p(target), None, _s(stream)),
-            "lsp_top_k")
+        if self.proposal != "network":
+            # row normalisation is increasing within a row, so band maxima of
+            # the normalised coarse block rank bands as the raw power does
+            _ok(L.lsp_band_max(_p(feats), n, feats.shape[1], 0, nb, lsp.FEAT_COARSE // nb,
+                               _p(self.band_score), _s(stream)), "lsp_band_max")
+            target = self.idx if self.proposal == "coarse" else self.idx_coarse
+            _ok(L.lsp_top_k(_p(self.band_score), n, nb, self.top, _p(target), None, _s(stream)),
+                "lsp_top_k")
         if self.proposal == "hybrid":
             _ok(L.lsp_merge_bands(_p(self.idx_net), self.top_net, _p(self.idx_coarse), self.top,
                                   n, self.top, _p(self.idx), _s(stream)), "lsp_merge_bands")
+        self.trim(self.alpha, self.tau, stream)
+
+    @property
+    def n_net(self):
+        """Proposed slots that come from the network (the first ones)."""
+        return {"network": self.top, "coarse": 0, "hybrid": self.top_net}[self.proposal]
+
+    def trim(self, alpha, tau, stream=None):
+        """Keep the confident proposed bands (lsp_trim_bands) in self.rows."""
+        net = self.proposal != "coarse"
+        trim_bands(self.idx, self.n_net, self.logits if net else None,
+                   self.band_score if self.proposal != "network" else None, tau, alpha,
+                   out=self.rows, kept_mass=self.mass if net else None, stream=stream)
 
     def refine_only(self, stream=None):
         self.propose(stream)
@@ -418,36 +451,131 @@ def train_proposer(net, feats, labels, epochs=20, batch=1024, lr=1e-3, lr_final=
     return hist
 
 
-def calibrate(refined, full, mass, target=0.999):
+def calibrate(refined, full, mass, target=0.999, weights=None):
     """Thresholds (mass_min, power_min) that keep the recovery rate on a
-    validation set at or above `target` with the fewest fallbacks.
+    validation set at or above `target` with the fewest fallbacks (or, with
+    `weights`, the least total weight of fallback objects -- e.g. their
+    observation counts, to which a whole-grid re-run is proportional).
+    Returns (mass_min, power_min, number of fallbacks).
 
     refined, full: peak arrays (refine only, whole grid); mass: proposal mass
     (None for a rule that has none).
     An object is recovered if its refined peak is within one bin of the
     whole-grid peak; a fallback object is recovered by construction."""
+    mm, pm, n_fb, _ = _calibrate(refined, full, mass, target, weights)
+    return mm, pm, n_fb
+
+
+def _calibrate(refined, full, mass, target, weights, n_quantiles=101):
+    """calibrate, also returning the fallback weight.  For each mass
+    threshold, every power threshold is scored at once: the misses are the
+    unrecovered objects at or above it, the fallbacks those below it."""
     ok = full["status"] == 0
     hit = ok & (np.abs(refined["index"] - full["index"]) <= 1)
     n = int(ok.sum())
+    if n == 0:
+        return 0.0, 0.0, 0, 0.0
     allowed = int(np.floor((1.0 - target) * n))
     pw = np.where(np.isfinite(refined["power"]), refined["power"], -1.0)
-    if n == 0:
-        return 0.0, 0.0, 0
-    q = np.linspace(0.0, 1.0, 101)
+    w = np.ones(len(refined)) if weights is None else np.asarray(weights, np.float64)
+    q = np.linspace(0.0, 1.0, n_quantiles)
     if mass is None:  # a rule without proposal mass: only the power threshold
         mass = np.ones(len(refined), np.float32)
         m_grid = np.zeros(1)
     else:
         m_grid = np.unique(np.concatenate([[0.0], np.quantile(mass[ok], q), [2.0]]))
     p_grid = np.unique(np.concatenate([[0.0], np.quantile(pw[ok], q), [2.0]]))
-    best = (2.0, 2.0, n + 1)
+    best = (2.0, 2.0, n + 1, np.inf)
     for mm in m_grid:
-        for pm in p_grid:
-            fb = ok & ((mass < mm) | (pw < pm) | (refined["index"] < 0))
-            miss = int((ok & ~hit & ~fb).sum())
-            if miss <= allowed and int(fb.sum()) < best[2]:
-                best = (float(mm), float(pm), int(fb.sum()))
+        base = ok & ((mass < mm) | (refined["index"] < 0))  # fall back whatever the power
+        cand = ok & ~base                                    # fall back iff power < pm
+        miss_pw = np.sort(pw[cand & ~hit])
+        miss = len(miss_pw) - np.searchsorted(miss_pw, p_grid, side="left")
+        order = np.argsort(pw[cand], kind="stable")
+        cand_pw = pw[cand][order]
+        cum_w = np.concatenate([[0.0], np.cumsum(w[cand][order])])
+        below = np.searchsorted(cand_pw, p_grid, side="left")
+        fb_w = float(w[base].sum()) + cum_w[below]
+        key = np.where(miss <= allowed, fb_w, np.inf)
+        j = int(np.argmin(key))
+        if key[j] < best[3]:
+            best = (float(mm), float(p_grid[j]), int(base.sum() + below[j]), float(key[j]))
     return best
+
+
+def _group_peaks(index, power, kept):
+    """Peak of each object over its kept slots: highest power, lowest bin on
+    ties (the order the row-mode kernels merge a group's rows in)."""
+    pw = np.where(kept & (index >= 0), power, -np.inf)
+    m = pw.max(axis=1)
+    at_max = (pw == m[:, None]) & np.isfinite(m)[:, None]
+    idx = np.where(at_max, index, np.iinfo(np.int64).max).min(axis=1)
+    out = np.zeros(len(index), lsp.PEAK_DTYPE)
+    out["index"] = np.where(np.isfinite(m), idx, -1)
+    out["power"] = np.where(np.isfinite(m), m, np.nan)
+    return out
+
+
+ALPHAS = (0.0, 0.3, 0.5, 0.6, 0.7, 0.8, 0.85, 0.9, 0.95, 0.98, 1.0)
+TAUS = (2.0, 0.999, 0.99, 0.98, 0.95, 0.9, 0.8, 0.7, 0.6, 0.5)
+
+
+def calibrate_bands(lp, full, n_t, target=0.999, alphas=ALPHAS, taus=TAUS, log=None):
+    """Band trimming and fallback thresholds for one proposal rule, chosen on
+    a validation set: the (alpha, tau, mass_min, power_min) that evaluate the
+    fewest (observation, bin) terms -- kept bands of every object plus the
+    whole grid of every fallback object -- with at least `target` of the
+    objects recovering their whole-grid peak within one bin.
+
+    lp: a LearnedPeriodogram over the validation objects (its proposals are
+    computed here); full: their whole-grid peaks; n_t: their observation
+    counts.  Every proposed slot's band is refined on its own once (row mode,
+    one row per object); each candidate trimming then picks its objects'
+    peaks from those, with the kernels' own keep decisions (lsp_trim_bands).
+    Returns ((mass_min, power_min, fallbacks, alpha, tau), evaluated fraction
+    of the whole grid)."""
+    geo = lp.geo
+    lp.propose()
+    n, top = lp.idx.shape
+    slot_index = np.full((n, top), -1, np.int64)
+    slot_power = np.full((n, top), -np.inf)
+    for r in range(top):
+        col = lp.idx[:, r].contiguous()
+        rows = lsp.Rows(lp.offsets, lp.t, lp.y, lp.refine.grid.f_min, lp.refine.grid.f_max,
+                        geo.n_f, None, col, geo.band_bins, 1, unit=lp.refine.grid.unit,
+                        form=lsp.FORM_FP32P, method="generalized" if lp.refine.gen else "standard",
+                        dy=lp.refine.dy)
+        rows()
+        pk = rows.peaks()
+        slot_index[:, r] = pk["index"]
+        slot_power[:, r] = np.where(np.isfinite(pk["power"]), pk["power"], -np.inf)
+        del rows
+    idx = lp.idx.cpu().numpy().astype(np.int64)
+    bins = np.where(idx >= 0, np.minimum(geo.band_bins, geo.n_f - idx * geo.band_bins), 0)
+    n_t = np.asarray(n_t, np.float64)
+    whole = float(n_t.sum()) * geo.n_f
+    net = lp.proposal != "coarse"
+    a_grid = alphas if lp.proposal != "network" else (0.0,)
+    t_grid = taus if net else (2.0,)
+    best = None
+    for a in a_grid:
+        for tau in t_grid:
+            lp.trim(a, tau)
+            kept = lp.rows.cpu().numpy() >= 0
+            mass = lp.mass.cpu().numpy() if net else None
+            refined = _group_peaks(slot_index, slot_power, kept)
+            refine_terms = float(np.sum(n_t * np.sum(kept * bins, axis=1)))
+            mm, pm, n_fb, fb_w = _calibrate(refined, full, mass, target, n_t, n_quantiles=51)
+            total = refine_terms + fb_w * geo.n_f
+            if best is None or total < best[0]:
+                best = (total, (mm, pm, n_fb, float(a), float(tau)))
+    lp.trim(best[1][3], best[1][4])
+    if log:
+        mm, pm, n_fb, a, tau = best[1]
+        log(f"calibrated {lp.proposal}: alpha={a} tau={tau} mass_min={mm:.4f} "
+            f"power_min={pm:.4f}, {n_fb}/{n} validation fallbacks, evaluated "
+            f"{best[0] / whole:.4f} of the grid")
+    return best[1], best[0] / whole
 
 
 def _tensors(w, device):
@@ -475,22 +603,23 @@ class Proposer:
 
     def __init__(self, net, geometry, thresholds, history, train_seconds, n_train, n_val):
         self.net, self.geo = net, geometry
-        self.thresholds = thresholds  # proposal -> (mass_min, power_min, validation fallbacks)
+        # proposal -> (mass_min, power_min, validation fallbacks, alpha, tau)
+        self.thresholds = thresholds
         self.history = history
         self.train_seconds = train_seconds
         self.n_train, self.n_val = n_train, n_val
 
     def periodogram(self, offsets, t, y, f_min, f_max, unit=lsp.CYCLES, proposal="hybrid",
                     method="standard", dy=None, **kw):
-        mass_min, power_min, _ = self.thresholds[proposal]
+        mass_min, power_min, _, alpha, tau = self.thresholds[proposal]
         return LearnedPeriodogram(self.net, self.geo, offsets, t, y, f_min, f_max, unit=unit,
                                   mass_min=mass_min, power_min=power_min, proposal=proposal,
-                                  method=method, dy=dy, **kw)
+                                  method=method, dy=dy, alpha=alpha, tau=tau, **kw)
 
 
 def fit_proposer(make, device, n_train=40000, n_val=20000, seed_train=None, seed_val=None,
                  n_bands=64, method="standard", proposals=("hybrid",), epochs=30, batch=512,
-                 target=0.999, net_seed=7, log=None):
+                 target=0.999, net_seed=7, log=None, adaptive=True):
     """Train the proposal network on objects the method itself labels, then
     calibrate the fallback thresholds on independent objects.
 
@@ -498,8 +627,10 @@ def fit_proposer(make, device, n_train=40000, n_val=20000, seed_train=None, seed
     (its grid is the grid the proposals are for).  Training labels are the
     bands of the whole-grid FP32 peaks of n_train objects; for every rule in
     `proposals` the thresholds are chosen on n_val other objects so that at
-    least `target` of them recover the whole-grid peak within one bin with the
-    fewest fallbacks (calibrate)."""
+    least `target` of them recover the whole-grid peak within one bin: with
+    `adaptive`, jointly with the band trimming, for the fewest evaluated
+    terms (calibrate_bands); otherwise for all `top` bands and the fewest
+    fallbacks (calibrate)."""
     import time
 
     wtr = make(n_train, seed_train)
@@ -523,16 +654,20 @@ def fit_proposer(make, device, n_train=40000, n_val=20000, seed_train=None, seed
     tva = _tensors(wva, device)
     dva = _errors(wva, device, method)
     full = whole_grid_peaks(wva, tva, method, dva).peaks()
+    n_t = np.diff(wva.offsets)
     thresholds = {}
     for prop in proposals:
         lpv = LearnedPeriodogram(net, geo, *tva, wva.f_min, wva.f_max, unit=wva.unit,
                                  proposal=prop, method=method, dy=dva)
-        lpv.refine_only()
-        mass = None if prop == "coarse" else lpv.mass.cpu().numpy()
-        thresholds[prop] = calibrate(lpv.peaks(), full, mass, target=target)
-        if log:
-            mm, pm, nfb = thresholds[prop]
-            log(f"calibrated {prop}: mass_min={mm:.4f} power_min={pm:.4f}, "
-                f"{nfb}/{wva.n_obj} validation fallbacks")
+        if adaptive:
+            thresholds[prop], _ = calibrate_bands(lpv, full, n_t, target=target, log=log)
+        else:
+            lpv.refine_only()
+            mass = None if prop == "coarse" else lpv.mass.cpu().numpy()
+            thresholds[prop] = calibrate(lpv.peaks(), full, mass, target=target) + (0.0, 2.0)
+            if log:
+                mm, pm, nfb = thresholds[prop][:3]
+                log(f"calibrated {prop}: mass_min={mm:.4f} power_min={pm:.4f}, "
+                    f"{nfb}/{wva.n_obj} validation fallbacks")
         del lpv
     return Proposer(net, geo, thresholds, hist, train_s, wtr.n_obj, wva.n_obj)

@@ -166,6 +166,8 @@ def lib():
         L.lsp_top_k.argtypes = [vp, i64, i32, i32, vp, vp, vp]
         L.lsp_band_max.restype = ctypes.c_int
         L.lsp_band_max.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp]
+        L.lsp_trim_bands.restype = ctypes.c_int
+        L.lsp_trim_bands.argtypes = [vp, i64, i32, i32, vp, vp, i32, f32, f32, vp, vp, vp]
         L.lsp_merge_bands.restype = ctypes.c_int
         L.lsp_merge_bands.argtypes = [vp, i32, vp, i32, i64, i32, vp, vp]
         L.lsp_row_normalize.restype = ctypes.c_int

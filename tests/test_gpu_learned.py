@@ -80,7 +80,7 @@ def test_refined_peaks_match_oracle(dev, trained):
     lp = learned.LearnedPeriodogram(net, geo, *tens, w.f_min, w.f_max)
     lp.refine_only()
     pk = lp.peaks()
-    idx = lp.idx.cpu().numpy()
+    idx = lp.rows.cpu().numpy()  # the bands kept for refinement
     obj = np.nonzero(pk["index"] >= 0)[0][:60]
     ora = oracle.eval_bins(w.offsets, w.t, w.y, w.f_min, w.f_max, N_F, obj, pk["index"][obj])
     assert np.max(np.abs(ora - pk["power"][obj])) <= 1e-3
@@ -115,7 +115,7 @@ def test_calibrated_recovery(dev, trained):
     # objects) against the whole grid of every object, observation-weighted
     n_t = np.diff(wt.offsets).astype(np.float64)
     fb = lpt.objects[:lpt.n_fallback].cpu().numpy()
-    idx = lpt.idx.cpu().numpy()
+    idx = lpt.rows.cpu().numpy()
     bins = np.array([sum(min(geo.band_bins, N_F - b * geo.band_bins) for b in r if b >= 0)
                      for r in idx], dtype=np.float64)
     work = float(np.sum(n_t * bins) + np.sum(n_t[fb]) * N_F)

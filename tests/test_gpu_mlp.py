@@ -385,3 +385,80 @@ def test_band_max_and_merge(dev):
                 want.append(int(v))
         want += [-1] * (8 - len(want))
         assert list(got[i]) == want, i
+
+
+def _trim_reference(idx, n_net, logits, score, tau, alpha):
+    """The keep rule in FP64: (kept bands, kept mass, per-slot distance of the
+    decision from its threshold)."""
+    n, top = idx.shape
+    out = np.full_like(idx, -1)
+    mass = np.zeros(n)
+    margin = np.full(idx.shape, np.inf)
+    for i in range(n):
+        if logits is not None:
+            z = logits[i].astype(np.float64)
+            p = np.exp(z - z.max())
+            p /= p.sum()
+        smax = score[i].max() if score is not None else 0.0
+        cum, any_net = 0.0, False
+        for r in range(top):
+            b = idx[i, r]
+            if b < 0:
+                continue
+            if r < n_net:
+                keep = (not any_net) or cum < tau
+                if any_net:
+                    margin[i, r] = abs(cum - tau)
+                if keep:
+                    any_net = True
+                    cum += p[b]
+            else:
+                keep = (n_net == 0 and r == 0) or score is None or score[i, b] >= alpha * smax
+                if score is not None and not (n_net == 0 and r == 0):
+                    margin[i, r] = abs(float(score[i, b]) - alpha * float(smax))
+            out[i, r] = b if keep else -1
+        mass[i] = cum
+    return out, mass, margin
+
+
+def test_trim_bands(dev):
+    """lsp_trim_bands against the keep rule in FP64: identical decisions
+    except within 1e-5 of a threshold (FP32 softmax and product), kept mass
+    within 1e-5."""
+    rng = np.random.default_rng(22)
+    n, c, top = 400, 64, 8
+    logits = rng.normal(0, 2.0, (n, c)).astype(np.float32)
+    score = rng.uniform(0, 1, (n, c)).astype(np.float32)
+    idx = np.full((n, top), -1, np.int32)
+    for i in range(n):
+        net = list(np.argsort(-logits[i].astype(np.float64), kind="stable")[:4])
+        rest = [b for b in np.argsort(-score[i].astype(np.float64), kind="stable") if b not in net]
+        row = net + rest[: top - 4]
+        if i % 10 == 0:
+            row[-2:] = [-1, -1]
+        idx[i] = row
+    it = torch.as_tensor(idx, device=dev)
+    lt = torch.as_tensor(logits, device=dev)
+    st = torch.as_tensor(score, device=dev)
+    cases = [(4, True, True, 2.0, 0.0), (4, True, True, 0.9, 0.5), (4, True, True, 0.5, 0.8),
+             (4, True, True, 0.0, 1.0), (top, True, False, 0.95, 0.0),
+             (0, False, True, 2.0, 0.6), (0, False, True, 0.0, 0.999)]
+    for n_net, use_l, use_s, tau, alpha in cases:
+        say(f"trim n_net={n_net} tau={tau} alpha={alpha}")
+        km = torch.empty(n, dtype=torch.float32, device=dev)
+        out, _ = learned.trim_bands(it, n_net, lt if use_l else None, st if use_s else None,
+                                    tau, alpha, kept_mass=km if use_l else None)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        want, mass, margin = _trim_reference(idx, n_net, logits if use_l else None,
+                                             score if use_s else None, tau, alpha)
+        differ = got != want
+        assert np.all(margin[differ] < 1e-5), (n_net, tau, alpha)
+        if use_l:
+            assert np.all(np.abs(km.cpu().numpy() - mass) <= 1e-5)
+        # kept network slots form a prefix, and the first valid slot is kept
+        for i in range(n):
+            valid = idx[i] >= 0
+            assert got[i][valid][0] == idx[i][valid][0]
+            k = got[i, :n_net] >= 0
+            assert not np.any(k[1:] & ~k[:-1]) or np.any(idx[i, :n_net] < 0)

@@ -54,3 +54,54 @@ def test_calibrate_ignores_objects_without_peak():
     mass = np.ones(n)
     mm, pm, n_fb = learned.calibrate(refined, full, mass)
     assert n_fb == 0
+
+
+def _calibrate_by_loop(refined, full, mass, target, weights):
+    """The threshold search written as the plain double loop."""
+    ok = full["status"] == 0
+    hit = ok & (np.abs(refined["index"] - full["index"]) <= 1)
+    n = int(ok.sum())
+    allowed = int(np.floor((1.0 - target) * n))
+    pw = np.where(np.isfinite(refined["power"]), refined["power"], -1.0)
+    q = np.linspace(0.0, 1.0, 101)
+    m_grid = np.unique(np.concatenate([[0.0], np.quantile(mass[ok], q), [2.0]]))
+    p_grid = np.unique(np.concatenate([[0.0], np.quantile(pw[ok], q), [2.0]]))
+    best = (2.0, 2.0, n + 1, np.inf)
+    for mm in m_grid:
+        for pm in p_grid:
+            fb = ok & ((mass < mm) | (pw < pm) | (refined["index"] < 0))
+            miss = int((ok & ~hit & ~fb).sum())
+            wt = float(weights[fb].sum())
+            if miss <= allowed and wt < best[3]:
+                best = (float(mm), float(pm), int(fb.sum()), wt)
+    return best
+
+
+def test_vectorised_calibration_equals_the_loop():
+    rng = np.random.default_rng(4)
+    n = 3000
+    full = _peaks(rng.integers(0, 10**4, n), rng.uniform(0.1, 1, n),
+                  status=(rng.random(n) < 0.02).astype(np.int32))
+    idx = full["index"].copy()
+    miss = rng.random(n) < 0.05
+    idx[miss] += rng.integers(2, 50, miss.sum())
+    idx[rng.random(n) < 0.01] = -1
+    power = np.where(miss, rng.uniform(0.0, 0.6, n), full["power"])
+    power[rng.random(n) < 0.01] = np.nan
+    refined = _peaks(idx, power)
+    mass = np.where(miss, rng.uniform(0, 0.7, n), rng.uniform(0.3, 1.0, n))
+    for weights in (np.ones(n), rng.integers(20, 500, n).astype(np.float64)):
+        for target in (0.99, 0.999):
+            got = learned._calibrate(refined, full, mass, target, weights)
+            want = _calibrate_by_loop(refined, full, mass, target, weights)
+            assert got[:3] == want[:3] and abs(got[3] - want[3]) < 1e-6
+
+
+def test_group_peaks_pick_highest_power_then_lowest_bin():
+    index = np.array([[5, 9, 2], [7, -1, 3], [-1, -1, -1], [4, 8, 1]])
+    power = np.array([[0.5, 0.9, 0.9], [0.2, 0.99, 0.1], [1.0, 1.0, 1.0], [0.3, 0.7, 0.8]])
+    kept = np.array([[True, True, True], [True, True, False], [True, True, True],
+                     [True, True, False]])
+    pk = learned._group_peaks(index, power, kept)
+    assert pk["index"].tolist() == [2, 7, -1, 8]   # tie 0.9 -> bin 2; -1 rows never win
+    assert pk["power"][0] == 0.9 and np.isnan(pk["power"][2])
