@@ -643,9 +643,10 @@ lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid *gri
  * (Graham's longest-processing-time-first rule for independent jobs).  The
  * paper gives each object its own thread block (Section 3.4) and leaves the
  * order to the hardware; here a row's cost is the observation count of its
- * object, offsets[o+1] - offsets[o] (0 for a negative count, an object index
- * outside 0..n_obj-1 or a negative band), compared exactly below 1,024 and to
- * 1/64 of an octave above.  Position s of the descending order is dealt to XCD
+ * object, offsets[o+1] - offsets[o] (0 for a negative count), compared exactly
+ * below 1,024 and to 1/64 of an octave above; rows with no work at all (an
+ * object index outside 0..n_obj-1 or a negative band) come after every other
+ * row.  Position s of the descending order is dealt to XCD
  * s % 8: perm lists XCD 0's rows, then XCD 1's, ..., each run in descending
  * cost; the runs are contiguous and balanced (the first n_rows % 8 runs hold
  * one row more).  Rows of equal cost appear in no particular order.

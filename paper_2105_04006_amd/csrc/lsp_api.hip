@@ -299,7 +299,8 @@ Layout layout(int64_t n_obj, const lsp_grid* g, const Rows& rows, const Config& 
     L.perm = off;
     off += c.lpt ? align_up((size_t)rows.n_rows * sizeof(int32_t)) : 0;
     L.hist = off;
-    off += c.lpt ? align_up((size_t)kOrderBuckets * sizeof(unsigned int)) : 0;
+    off += c.lpt ? align_up((size_t)(kOrderBlocks + 1) * kOrderBuckets * sizeof(unsigned int))
+                 : 0;
     L.total = off;
     return L;
 }
@@ -431,9 +432,11 @@ lsp_status run(const int64_t* offsets, int64_t n_obj, int64_t n_obs, const doubl
         op.rows_per_group = rows.rows_per_group;
         op.pad = 0;
         op.hist = at<unsigned int>(ws, L.hist);
+        op.total = op.hist + (size_t)kOrderBlocks * kOrderBuckets;
         op.perm = at<int32_t>(ws, L.perm);
         if (launch_row_order(op, s) != hipSuccess) return LSP_EHIP;
         mp.row_perm = op.perm;
+        mp.n_work = op.total + (kOrderBuckets - 1);
     }
     if (t_main_begin && hipEventRecord(t_main_begin, s) != hipSuccess) return LSP_EHIP;
     if (method.gen) {
@@ -867,7 +870,8 @@ lsp_status lsp_describe_launch(int64_t n_obj, int64_t n_obs, const lsp_grid* gri
 }
 
 size_t lsp_row_order_workspace_bytes(void) {
-    return (lsp::kOrderBuckets * sizeof(unsigned int) + 255) / 256 * 256;
+    return ((size_t)(lsp::kOrderBlocks + 1) * lsp::kOrderBuckets * sizeof(unsigned int) + 255) /
+           256 * 256;
 }
 
 lsp_status lsp_row_order(const int64_t* offsets, int64_t n_obj, const int32_t* row_obj,
@@ -888,6 +892,7 @@ lsp_status lsp_row_order(const int64_t* offsets, int64_t n_obj, const int32_t* r
     op.rows_per_group = rows_per_group;
     op.pad = 0;
     op.hist = static_cast<unsigned int*>(workspace);
+    op.total = op.hist + (size_t)lsp::kOrderBlocks * lsp::kOrderBuckets;
     op.perm = perm;
     return lsp::launch_row_order(op, static_cast<hipStream_t>(stream)) == hipSuccess ? LSP_OK
                                                                                       : LSP_EHIP;

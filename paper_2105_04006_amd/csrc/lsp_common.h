@@ -493,6 +493,22 @@ __device__ __forceinline__ int64_t xcd_first_rank(int x, int64_t n_rows) {
     return (int64_t)x * base + (x < rem ? (int64_t)x : rem);
 }
 
+// The end of XCD x's queue: the items of its run of ranks, cut, under the
+// longest-first order, after the ranks that hold rows with work (position
+// s of the sorted order sits in XCD s % 8's run, so XCD x holds the
+// positions below n_work that are x mod 8).
+__device__ __forceinline__ int64_t xcd_queue_end(int x, int64_t n_rows, int64_t per_row,
+                                                 const unsigned int* n_work) {
+    int64_t end = xcd_first_rank(x + 1, n_rows);
+    if (n_work) {
+        const int64_t nw = uniform_i64((int64_t)*n_work);
+        const int64_t mine = nw > x ? (nw - x + kXcds - 1) / kXcds : 0;
+        const int64_t cut = xcd_first_rank(x, n_rows) + mine;
+        if (cut < end) end = cut;
+    }
+    return end * per_row;
+}
+
 // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs,
 // so block b runs on XCD b % 8.  Remap so that each XCD receives a contiguous
 // run of items (and hence the same objects stay in one XCD's L2).
@@ -545,6 +561,9 @@ struct MainParams {
     float* part;             // [n_split][4][n_f] when n_split > 1
     unsigned int* queue;     // persistent schedule: kXcds counters
     const int32_t* row_perm = nullptr;  // rank -> row (longest first); NULL: rank = row
+    // with row_perm: the number of rows with work (they hold the first ranks
+    // of every XCD's run); the persistent schedule stops each queue there
+    const unsigned int* n_work = nullptr;
     int32_t persistent;
     int32_t wave_split;      // the waves of a workgroup split observations, not bins
     const double* dy = nullptr;  // generalized form: errors (NULL: unit errors)
@@ -627,7 +646,9 @@ hipError_t launch_peaks(const PeakParams& p, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* dst, int64_t n, unsigned int v, hipStream_t s);
 
 // Longest-first row order (lsp_order.hip).
-constexpr int kOrderBuckets = 1024 + 53 * 64;  // N_t < 1024 exact, 64 per octave above
+// N_t < 1024 exact, 64 per octave above, and one bucket for rows with no work
+constexpr int kOrderBuckets = 1024 + 53 * 64 + 1;
+constexpr int kOrderBlocks = 64;               // workgroups of the two-level sort
 struct OrderParams {
     const int64_t* offsets;  // CSR offsets of the objects (n_obj + 1)
     int64_t n_obj;
@@ -636,7 +657,8 @@ struct OrderParams {
     int64_t n_rows;
     int32_t rows_per_group;
     int32_t pad;
-    unsigned int* hist;  // kOrderBuckets counters (cleared by the launcher)
+    unsigned int* hist;   // [kOrderBlocks x kOrderBuckets] per-workgroup counts (scratch)
+    unsigned int* total;  // [kOrderBuckets] bucket counts, then first positions (scratch)
     int32_t* perm;       // [n_rows]: rank -> row
 };
 hipError_t launch_row_order(const OrderParams& p, hipStream_t s);

@@ -79,23 +79,20 @@ __device__ __noinline__ double group_power64(const double* __restrict__ t, const
 // Maximum over each run of 8 lanes, in all 8 lanes, through DPP lane moves:
 // swap neighbours (quad_perm 1,0,3,2), swap pairs (quad_perm 2,3,0,1), then
 // mirror within each half-row of 8 lanes (lane i with lane 7 - i), which pairs
-// each 4-lane maximum with the other's.
-__device__ __forceinline__ float dpp_f32(float v, int ctrl_sel) {
-    const int x = __float_as_int(v);
-    int r;
-    switch (ctrl_sel) {
-        case 0: r = __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false); break;
-        case 1: r = __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false); break;
-        default: r = __builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false); break;
-    }
-    return __int_as_float(r);
+// each 4-lane maximum with the other's.  The values are non-negative floats,
+// whose bit patterns order as the values do, so the maximum is taken on the
+// integers (no NaN handling, and the lane move folds into the max).
+template <int CTRL>
+__device__ __forceinline__ int dpp_max_i32(int x) {
+    return max(x, __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float pool8_max(float v) {
-    v = fmaxf(v, dpp_f32(v, 0));
-    v = fmaxf(v, dpp_f32(v, 1));
-    v = fmaxf(v, dpp_f32(v, 2));
-    return v;
+    int x = __float_as_int(v);
+    x = dpp_max_i32<0xB1>(x);
+    x = dpp_max_i32<0x4E>(x);
+    x = dpp_max_i32<0x141>(x);
+    return __int_as_float(x);
 }
 
 // One (object, 1,024-bin tile) item; called by every thread of the workgroup.
@@ -136,9 +133,9 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
         auto close_group = [&](int64_t j_next) {
             if (ns >= P.min_obs) {
                 const float N = (float)ns;
-                const float inv_s = syy > 0.0f ? 1.0f / syy : 0.0f;
+                const float scale2 = syy > 0.0f ? 2.0f / syy : 0.0f;
                 float p32[K];
-                uint32_t ill = 0u;  // bins of this lane FP32 cannot resolve
+                float r2max = 0.0f;  // largest R^2 of this lane's bins
                 // With C2 + i S2 = sum exp(2iwt), R = |C2 + i S2|, A = xc^2 + xs^2
                 // and B R = (xc^2 - xs^2) C2 + 2 xc xs S2, twice P_LS is
                 // (A + B)/(N + R) + (A - B)/(N - R) = 2 (A N - B R)/(N^2 - R^2):
@@ -154,14 +151,21 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
                     const float A = fmaf(xc[k], xc[k], xs[k] * xs[k]);
                     const float BR =
                         fmaf(fmaf(xc[k], xc[k], -(xs[k] * xs[k])), C2, 2.0f * xc[k] * xs[k] * S2);
-                    p32[k] = 2.0f * fmaxf(fmaf(A, N, -BR), 0.0f) * __builtin_amdgcn_rcpf(N2 - R2) *
-                             inv_s;
-                    if (!(R2 < ill_r2)) ill |= 1u << k;
+                    p32[k] = fmaxf(fmaf(A, N, -BR), 0.0f) * __builtin_amdgcn_rcpf(N2 - R2) * scale2;
+                    r2max = fmaxf(r2max, R2);
                 }
                 // FP64 recompute of the unresolvable bins, one bin at a time
                 // (a rolled loop, so that the FP64 path stays out of the
-                // unrolled code and its registers), through LDS
-                if (__any(ill != 0u)) {
+                // unrolled code and its registers), through LDS; which bins
+                // they are is worked out only here, where some are
+                if (__any(!(r2max < ill_r2))) {
+                    uint32_t ill = 0u;  // bins of this lane FP32 cannot resolve
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const float C2 = fmaf(2.0f, cc[k], -N);
+                        const float S2 = 2.0f * cs[k];
+                        if (!(fmaf(C2, C2, S2 * S2) < ill_r2)) ill |= 1u << k;
+                    }
 #pragma unroll 1
                     for (int k = 0; k < K; ++k) {
                         if ((ill >> k) & 1u) {
@@ -203,8 +207,10 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
                 // object's first observation, so the two loads go out together)
                 const double tprev = P.t[j > m.j0 ? j - 1 : j];
                 const bool starts = j > m.j0 && tj - tprev > P.gap;
+                // (the new-season flag is kept as integer bits, read back as
+                // a wave-uniform integer)
                 s_obs[q] = make_float4((float)(P.y[j] - m.ybar), __builtin_amdgcn_cosf(rs),
-                                       __builtin_amdgcn_sinf(rs), starts ? 1.0f : 0.0f);
+                                       __builtin_amdgcn_sinf(rs), __int_as_float(starts ? 1 : 0));
             }
             __syncthreads();
             for (int q = 0; q < cnt; ++q) {
@@ -213,7 +219,7 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
                 // A season boundary closes the current group once it holds
                 // min_obs observations; sparser seasons merge with the next.
                 // Every lane reads the same slot, so the flag is wave-uniform.
-                if (uniform_i32(o.w != 0.0f ? 1 : 0) && ns >= P.min_obs) close_group(jt + q);
+                if (uniform_i32(__float_as_int(o.w)) && ns >= P.min_obs) close_group(jt + q);
                 // the main kernel's hot loop: FP64-reduced seed, hardware
                 // sin/cos, three-term recurrence across the lane's bins
                 accumulate_obs<K, true, LSP_TRIG_HW>(fl, tq, o, xc, xs, cc, cs);
@@ -243,7 +249,7 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
 __global__ __launch_bounds__(kWave* kCoarseW)
     __attribute__((amdgpu_waves_per_eu(4))) void coarse_kernel(const FeatParams P) {
     __shared__ double s_tau[kTile];
-    __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, new-season flag)
+    __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, new-season flag bits)
     __shared__ float s_fix[kCoarseK * kWave * kCoarseW];  // FP64-recomputed bins
     __shared__ int64_t s_item;
     const int64_t n_items = P.n_obj * kTilesPerObj;

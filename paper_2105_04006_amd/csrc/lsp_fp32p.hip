@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kWave* W)
     for (int d = 0; d < kXcds; ++d) {
         const int x = (x0 + d) % kXcds;
         const int64_t lo = xcd_first_rank(x, n_rows) * per_row;
-        const int64_t hi = xcd_first_rank(x + 1, n_rows) * per_row;
+        const int64_t hi = xcd_queue_end(x, n_rows, per_row, P.n_work);
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
             fp32p_item<K, W, CHEB, WS, SRC, TRIG>(P, item, s_tau, s_obs, s_red, s_part);

@@ -5,8 +5,9 @@
     order in XCD s % 8's run, the runs contiguous and balanced.  With
     observation counts below 1,024 (compared exactly) each run must equal the
     descending order dealt round-robin; above, each entry may differ from it
-    only within a bucket (1/64 of an octave).  Rows of invalid objects and
-    negative bands cost nothing and come last.
+    only within a bucket (1/64 of an octave).  Rows with no work (invalid
+    objects, negative bands) come after every other row, empty objects' rows
+    among the cheapest.
   * The order changes no result: periodograms and peaks are bitwise equal
     under input and longest-first order for the FP32 form (persistent and grid
     schedules), the FP64 form, both generalized forms, row mode, and replays
@@ -88,15 +89,17 @@ def test_row_order_rows_bands_and_invalid_rows(dev):
     rng = np.random.default_rng(12)
     n_obj = 300
     n_t = rng.integers(5, 900, size=n_obj)
+    n_t[:4] = 0  # empty objects: rows that still write fill values
     # 8 (object, band) rows per object in shuffled order, some bands negative
-    # and some objects out of range
+    # and some objects out of range: rows with no work, which come after all
+    # others (cost -1 here)
     row_obj = np.repeat(np.arange(n_obj), 8)
     row_band = np.tile(np.arange(8), n_obj)
     sh = rng.permutation(len(row_obj))
     row_obj, row_band = row_obj[sh], row_band[sh]
     row_band[rng.choice(len(row_band), 50, replace=False)] = -1
     row_obj[rng.choice(len(row_obj), 20, replace=False)] = n_obj + 5
-    cost = np.where((row_band >= 0) & (row_obj < n_obj), n_t[np.minimum(row_obj, n_obj - 1)], 0)
+    cost = np.where((row_band >= 0) & (row_obj < n_obj), n_t[np.minimum(row_obj, n_obj - 1)], -1)
     perm = _perm(dev, n_t, row_obj=torch.as_tensor(row_obj.astype(np.int32), device=dev),
                  row_band=torch.as_tensor(row_band.astype(np.int32), device=dev))
     _check_dealt(cost.astype(np.int64), perm, exact=True)
