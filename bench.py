@@ -145,8 +145,11 @@ def order_code(name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 on the three-form workloads, whose FP32 step "
+                         "takes about 1.5 s, 200 on the others)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warm-up steps (default: 5, or 10 with 200 timed steps)")
     ap.add_argument("--workload", default="lsst_200k",
                     help="lsst_200k (default), learned_100k, asteroids_100k: the three forms "
                          "(fp32 whole grid, learned proposal, fp64) on one batch; single_256, "
@@ -204,6 +207,10 @@ def main():
                          "the device periodogram into pageable memory against the pinned-staging "
                          "pipeline (lsp_batch_to_host); PCIe-inclusive, not the headline value")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 20 if args.workload in FORM_WORKLOADS and args.mode == "lsp" else 200
+    if args.warmup is None:
+        args.warmup = 5 if args.steps <= 20 else 10
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the periodogram of "
               "independent objects would shard by object across GPUs, which is not "
