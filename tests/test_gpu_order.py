@@ -174,3 +174,28 @@ def test_longest_first_row_mode_and_graph_replays(dev):
         assert torch.equal(p.pgram, ref_pg), f"replay {rep}"
         assert np.array_equal(p.peaks(), ref_pk)
     del plan
+
+
+@pytest.mark.parametrize("form", [lsp.FORM_FP32P, lsp.FORM_FP64])
+def test_rows_without_work(dev, form):
+    """Row mode whose rows all have no work (every band negative): under
+    longest-first order every XCD queue is empty; no bin is written and every
+    group's peak is empty, as under input order."""
+    w = synth.make_workload("batch_10k", n_obj=40)
+    off = torch.as_tensor(w.offsets, device=dev)
+    t = torch.as_tensor(w.t, device=dev)
+    y = torch.as_tensor(w.y, device=dev)
+    row_band = torch.full((w.n_obj * 4,), -1, dtype=torch.int32, device=dev)
+    res = []
+    for od in (lsp.ORDER_INPUT, lsp.ORDER_LPT):
+        say(f"rows without work form={form} order={od}")
+        pg = torch.full((w.n_obj, 3000), -1.0, dtype=torch.float32, device=dev)
+        r = lsp.Rows(off, t, y, w.f_min, w.f_max, 3000, None, row_band, band_bins=750,
+                     rows_per_group=4, form=form, pgram=pg, order=od)
+        r()
+        torch.cuda.synchronize()
+        assert torch.all(pg == -1.0)
+        res.append(r.peaks())
+    # empty peaks carry NaN frequencies and periods: compare the records' bits
+    assert res[0].tobytes() == res[1].tobytes()
+    assert np.all(res[1]["index"] == -1)
