@@ -37,6 +37,7 @@ constexpr int kCoarseW = 1;      // wavefronts per workgroup
 constexpr int kCoarseTile = kWave * kCoarseK * kCoarseW;  // 1,024 bins
 constexpr int kTilesPerObj = LSP_FEAT_COARSE * LSP_FEAT_POOL / kCoarseTile;
 constexpr int kProbes = LSP_FEAT_WINDOW - 11;
+constexpr int kWindowStage = 1024;  // objects up to this many points keep t - t0 in LDS
 
 static_assert(LSP_FEAT_POOL == 8, "pooling uses three lane-exchange steps");
 static_assert(kTilesPerObj * kCoarseTile == LSP_FEAT_COARSE * LSP_FEAT_POOL, "tile split");
@@ -53,6 +54,7 @@ struct FeatParams {
     int32_t pad;
     float* out;            // [n_obj][LSP_FEAT_DIM]
     unsigned int* queue;   // kXcds item counters (zeroed before the launch)
+    double probe[kProbes];  // spectral-window probe frequencies, 10^-3 .. 30 log-spaced
 };
 
 // Normalised power of the observations [g0, g0 + n) of one object (magnitudes
@@ -287,6 +289,7 @@ __device__ __forceinline__ double wave_min(double v) {
 
 // One wavefront per object.
 __global__ __launch_bounds__(kWave) void window_kernel(const FeatParams P) {
+    __shared__ double s_tc[kWindowStage];
     const int64_t obj = linear_block();
     if (obj >= P.n_obj) return;
     const int lane = threadIdx.x;
@@ -388,13 +391,18 @@ __global__ __launch_bounds__(kWave) void window_kernel(const FeatParams P) {
     // taken from the object's mid-span origin (the modulus does not depend on
     // it) and reduced to [-1/2, 1/2] cycles in FP64, then the hardware FP32
     // sin/cos (argument in revolutions) as in the periodogram kernels, summed
-    // in FP64.
-    const double lstep = (log10(30.0) + 3.0) / (double)(kProbes - 1);
+    // in FP64.  The probe frequencies come with the parameters; an object of
+    // up to kWindowStage points reads its t - t0 from LDS for every probe.
+    const bool staged = n <= kWindowStage;
+    if (staged) {
+        for (int64_t j = j0 + lane; j < j1; j += kWave) s_tc[j - j0] = P.t[j] - m.t0;
+        __syncthreads();
+    }
     for (int p = 0; p < kProbes; ++p) {
-        const double f = pow(10.0, -3.0 + (double)p * lstep);
+        const double f = P.probe[p];
         double sc = 0.0, ss = 0.0;
         for (int64_t j = j0 + lane; j < j1; j += kWave) {
-            double ph = f * (P.t[j] - m.t0);
+            double ph = f * (staged ? s_tc[j - j0] : P.t[j] - m.t0);
             ph -= rint(ph);
             const float r = (float)ph;
             sc += (double)__builtin_amdgcn_cosf(r);
@@ -428,6 +436,8 @@ static hipError_t launch_features(const ObjMeta* meta, unsigned int* queue, cons
     p.pad = 0;
     p.out = out;
     p.queue = queue;
+    const double lstep = (log10(30.0) + 3.0) / (double)(kProbes - 1);
+    for (int q = 0; q < kProbes; ++q) p.probe[q] = pow(10.0, -3.0 + (double)q * lstep);
     hipError_t e0 = launch_fill_u32(queue, kXcds, 0u, s);
     if (e0 != hipSuccess) return e0;
     int per_cu = 0, dev = 0, cus = 0;
