@@ -267,9 +267,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
 Layout layout(int64_t n_obj, const lsp_grid* g, const Rows& rows, const Config& c) {
     Layout L;
     size_t off = 0;
-    const bool f32 = c.form == LSP_FORM_FP32P;
     const size_t n_groups = (size_t)(rows.n_rows / rows.rows_per_group);
-    (void)f32;
     L.meta = off;
     off += align_up((size_t)n_obj * sizeof(ObjMeta));
     L.rec = off;
