@@ -133,8 +133,7 @@ def test_single_small_fp32p(dev):
             pg, pk = run_single(dev, w.t, w.y, w.f_min, w.f_max, w.n_f, form=lsp.FORM_FP32P, k=k,
                                 recurrence=rec)
             err = assert_fp32_close(pg, ora_pg, f"single_256 fp32p k={k} rec={rec}")
-            say(f"    max |dP| = {err:.3g}")
-            assert err < 1e-4, f"k={k}: max |dP| {err:.3g} is far above the expected FP32 level"
+            say(f"    max |dP| = {err:.3g} (bound {FP32_ATOL})")
             assert peak_ok(ora_pg, ora_pk["index"], pk["index"], 2 * FP32_ATOL, bins=1)
 
 
@@ -226,7 +225,13 @@ def test_bad_csr_range(dev, form):
 @pytest.mark.parametrize("form", [lsp.FORM_FP64, lsp.FORM_FP32P])
 def test_degenerate_frequencies_even_sampling(dev, form):
     """f = 0 and the Nyquist frequency of evenly sampled data make one shifted
-    regressor vanish; the FP32 form must hand those bins to its FP64 fix-up."""
+    regressor vanish; the FP32 form must hand those bins to its FP64 fix-up.
+    The 33 bins form a single tile, which holds those ill-conditioned bins, so
+    the fix-up recomputes all of it in FP64 and stores each value rounded to
+    FP32 (the FP32 form's output precision): the FP32 form is held to the FP64
+    bound plus half an FP32 ulp, 1e-9 max(P, 1e-3) + 2^-24 P.  The bins' sum is
+    1 (the sum rule pinned on the oracle), so it is within 32 (1e-9 + 2^-24)
+    < 1e-6 of 1."""
     rng = np.random.default_rng(5)
     n = 64
     t = np.arange(n, dtype=np.float64)
@@ -238,7 +243,9 @@ def test_degenerate_frequencies_even_sampling(dev, form):
     if form == lsp.FORM_FP64:
         assert_fp64_close(pg, ora_pg, "even sampling fp64")
     else:
-        assert_fp32_close(pg, ora_pg, "even sampling fp32p", atol=1e-6)
+        err = np.abs(pg - ora_pg)
+        bound = FP64_RTOL * np.maximum(ora_pg, FP64_FLOOR) + 2.0 ** -24 * ora_pg
+        assert np.all(err <= bound), f"even sampling fp32p: worst {np.max(err / bound):.3g} x bound"
     assert abs(pg[0]) < 1e-12
     assert np.sum(pg[1:]) == pytest.approx(1.0, abs=1e-6)  # Nyquist sum rule
 
@@ -253,8 +260,9 @@ def test_tiny_series(dev, form):
     if form == lsp.FORM_FP64:
         assert_fp64_close(pg, ora_pg, "tiny fp64")
     else:
-        assert_fp32_close(pg, ora_pg, "tiny fp32p", atol=1e-4)
-    assert np.max(np.abs(pg[:2] - 1.0)) <= (1e-9 if form == lsp.FORM_FP64 else 1e-4)
+        assert_fp32_close(pg, ora_pg, "tiny fp32p")
+    # two points fit any sinusoid exactly: P = 1 at every bin, within the bound of the form
+    assert np.max(np.abs(pg[:2] - 1.0)) <= (1e-9 if form == lsp.FORM_FP64 else FP32_ATOL)
 
 
 # --------------------------------------------------------------------- options
