@@ -228,7 +228,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     c->tiles_per_row = (n_f + c->tile_freqs - 1) / c->tile_freqs;
     if (c->tiles_per_row * rows.rows_per_group > kMaxGrid / rows.n_rows / c->split)
         return LSP_EUNSUPPORTED;
-    // The standard FP32 form gives each work item up to 16 consecutive
+    // The FP32 forms give each work item up to 16 consecutive
     // frequency tiles of one row -- one queue pop and one peak-key merge per
     // item, and an object that fits in one staging pass is staged once --
     // while items stay small against one wave's share of the launch: about
@@ -237,7 +237,7 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
     // item) 0.5% faster; batch_10k (1 M tiles) 6% slower at 14 per item,
     // where this rule keeps 1.
     c->tiles_per_item = 1;
-    if (o->form == LSP_FORM_FP32P && !method.gen && c->split == 1) {
+    if (o->form == LSP_FORM_FP32P && c->split == 1) {
         int64_t tpi = rows.n_rows * c->tiles_per_row / (200 * 4096);
         if (tpi > 16) tpi = 16;
         if (tpi > c->tiles_per_row) tpi = c->tiles_per_row;

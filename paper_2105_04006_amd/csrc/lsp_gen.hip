@@ -33,148 +33,179 @@ __device__ __forceinline__ void gen_item(const MainParams& P, int64_t item, doub
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int64_t tile_freqs = (int64_t)kWave * K * W;
-    const int64_t rank_tile = item / P.n_split;
-    const int split = (int)(item - rank_tile * P.n_split);
-    const int64_t rank = rank_tile / P.tiles_per_row;
-    const int64_t ftile = rank_tile - rank * P.tiles_per_row;
+    // item = (row, chunk of tiles_per_item consecutive frequency tiles,
+    // observation split); a split object has one tile per chunk
+    const int64_t chunk_id = item / P.n_split;
+    const int split = (int)(item - chunk_id * P.n_split);
+    const int64_t rank = chunk_id / P.chunks_per_row;
+    const int64_t chunk = chunk_id - rank * P.chunks_per_row;
     const int64_t row = item_row(P.row_perm, rank);
-    const int64_t tile = row * P.tiles_per_row + ftile;  // the tile's flag bit
     const RowRange rr =
         decode_row(P.row_obj, P.row_band, P.band_bins, P.rows_per_group, P.n_obj, P.n_f, row);
     const int64_t obj = rr.obj;
-    const int64_t i0 = rr.f_lo + ftile * tile_freqs + (int64_t)wave * kWave * K + lane;
+    const int64_t t_lo = chunk * P.tiles_per_item;
+    const int64_t t_hi = t_lo + P.tiles_per_item < P.tiles_per_row ? t_lo + P.tiles_per_item
+                                                                   : P.tiles_per_row;
+    const int64_t lane_off = (int64_t)wave * kWave * K + lane;
     const int64_t f_hi = rr.f_hi;
-    // invalid row or empty tile: no bin, nothing to record
-    if (obj < 0 || rr.f_lo + ftile * tile_freqs >= f_hi) return;
+    // invalid row or empty chunk: no bin, nothing to record
+    if (obj < 0 || rr.f_lo + t_lo * tile_freqs >= f_hi) return;
     const ObjMeta m = P.meta[obj];
 
     if (m.status != LSP_OBJ_OK) {
         if (P.n_split == 1 && P.pgram) {
             const double v = fill_value(m.status);
+            for (int64_t ft = t_lo; ft < t_hi; ++ft)
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int64_t i = i0 + (int64_t)kWave * k;
-                if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
-            }
+                for (int k = 0; k < K; ++k) {
+                    const int64_t i = rr.f_lo + ft * tile_freqs + lane_off + (int64_t)kWave * k;
+                    if (i < f_hi) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, v);
+                }
         }
         return;
     }
 
-    const int64_t chunk = (m.n + P.n_split - 1) / P.n_split;
-    const int64_t lo = (int64_t)split * chunk < m.n ? (int64_t)split * chunk : m.n;
-    const int64_t hi = lo + chunk < m.n ? lo + chunk : m.n;
+    const int64_t span = (m.n + P.n_split - 1) / P.n_split;
+    const int64_t lo = (int64_t)split * span < m.n ? (int64_t)split * span : m.n;
+    const int64_t hi = lo + span < m.n ? lo + span : m.n;
     const int64_t js = m.j0 + lo, je = m.j0 + hi;
-    const double fl = grid_freq(P.f_min, P.df, i0) * P.to_cyc;
     const double swn = sqrt(m.wnorm);
+    // an object that fits in one staging pass is staged once for all the
+    // chunk's tiles
+    const bool one_pass = je - js <= kTile;
 
-    float c1[K], s1[K], yc[K], ys[K], wcc[K], wcs[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) c1[k] = s1[k] = yc[k] = ys[k] = wcc[k] = wcs[k] = 0.0f;
+    unsigned long long best = 0ull;  // this lane's best key over the chunk's resolvable tiles
+    for (int64_t ft = t_lo; ft < t_hi; ++ft) {
+        if (rr.f_lo + ft * tile_freqs >= f_hi) break;
+        const int64_t i0 = rr.f_lo + ft * tile_freqs + lane_off;
+        const double fl = grid_freq(P.f_min, P.df, i0) * P.to_cyc;
 
-    for (int64_t jt = js; jt < je; jt += kTile) {
-        const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
-        __syncthreads();
-        for (int q = threadIdx.x; q < cnt; q += kWave * W) {
-            const int64_t j = jt + q;
-            const double tc = P.t[j] - m.t0;
-            s_tau[q] = tc;
-            double sp = P.step_cyc * tc;
-            sp -= rint(sp);
-            const float rs = (float)sp;
-            const double sw = P.dy ? swn / P.dy[j] : 1.0;
-            s_obs[q] = make_float4((float)(sw * (P.y[j] - m.ybar)), __builtin_amdgcn_cosf(rs),
-                                   __builtin_amdgcn_sinf(rs), (float)sw);
-        }
-        __syncthreads();
-        for (int q = 0; q < cnt; ++q) {
-            const double tq = s_tau[q];
-            const float4 o = s_obs[q];  // (sqrt(w') yw, cos step, sin step, sqrt(w'))
-            double ph = fl * tq;
-            ph -= rint(ph);
-            const float r = (float)ph;
-            const float two_c = o.y + o.y;
-            float cp = __builtin_amdgcn_cosf(r) * o.w;
-            float sp = __builtin_amdgcn_sinf(r) * o.w;
-            float c = fmaf(cp, o.y, -(sp * o.z));
-            float s = fmaf(sp, o.y, cp * o.z);
-            c1[0] = fmaf(o.w, cp, c1[0]);
-            s1[0] = fmaf(o.w, sp, s1[0]);
-            yc[0] = fmaf(o.x, cp, yc[0]);
-            ys[0] = fmaf(o.x, sp, ys[0]);
-            wcc[0] = fmaf(cp, cp, wcc[0]);
-            wcs[0] = fmaf(cp, sp, wcs[0]);
+        float c1[K], s1[K], yc[K], ys[K], wcc[K], wcs[K];
 #pragma unroll
-            for (int k = 1; k < K; ++k) {
-                c1[k] = fmaf(o.w, c, c1[k]);
-                s1[k] = fmaf(o.w, s, s1[k]);
-                yc[k] = fmaf(o.x, c, yc[k]);
-                ys[k] = fmaf(o.x, s, ys[k]);
-                wcc[k] = fmaf(c, c, wcc[k]);
-                wcs[k] = fmaf(c, s, wcs[k]);
-                if (k + 1 < K) {
-                    const float cn = fmaf(two_c, c, -cp);
-                    const float sn = fmaf(two_c, s, -sp);
-                    cp = c;
-                    sp = s;
-                    c = cn;
-                    s = sn;
+        for (int k = 0; k < K; ++k) c1[k] = s1[k] = yc[k] = ys[k] = wcc[k] = wcs[k] = 0.0f;
+
+        for (int64_t jt = js; jt < je; jt += kTile) {
+            const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
+            if (!one_pass || ft == t_lo) {
+                __syncthreads();
+                for (int q = threadIdx.x; q < cnt; q += kWave * W) {
+                    const int64_t j = jt + q;
+                    const double tc = P.t[j] - m.t0;
+                    s_tau[q] = tc;
+                    double sp = P.step_cyc * tc;
+                    sp -= rint(sp);
+                    const float rs = (float)sp;
+                    const double sw = P.dy ? swn / P.dy[j] : 1.0;
+                    s_obs[q] = make_float4((float)(sw * (P.y[j] - m.ybar)),
+                                           __builtin_amdgcn_cosf(rs), __builtin_amdgcn_sinf(rs),
+                                           (float)sw);
+                }
+                __syncthreads();
+            }
+            for (int q = 0; q < cnt; ++q) {
+                const double tq = s_tau[q];
+                const float4 o = s_obs[q];  // (sqrt(w') yw, cos step, sin step, sqrt(w'))
+                double ph = fl * tq;
+                ph -= rint(ph);
+                const float r = (float)ph;
+                const float two_c = o.y + o.y;
+                float cp = __builtin_amdgcn_cosf(r) * o.w;
+                float sp = __builtin_amdgcn_sinf(r) * o.w;
+                float c = fmaf(cp, o.y, -(sp * o.z));
+                float s = fmaf(sp, o.y, cp * o.z);
+                c1[0] = fmaf(o.w, cp, c1[0]);
+                s1[0] = fmaf(o.w, sp, s1[0]);
+                yc[0] = fmaf(o.x, cp, yc[0]);
+                ys[0] = fmaf(o.x, sp, ys[0]);
+                wcc[0] = fmaf(cp, cp, wcc[0]);
+                wcs[0] = fmaf(cp, sp, wcs[0]);
+#pragma unroll
+                for (int k = 1; k < K; ++k) {
+                    c1[k] = fmaf(o.w, c, c1[k]);
+                    s1[k] = fmaf(o.w, s, s1[k]);
+                    yc[k] = fmaf(o.x, c, yc[k]);
+                    ys[k] = fmaf(o.x, s, ys[k]);
+                    wcc[k] = fmaf(c, c, wcc[k]);
+                    wcs[k] = fmaf(c, s, wcs[k]);
+                    if (k + 1 < K) {
+                        const float cn = fmaf(two_c, c, -cp);
+                        const float sn = fmaf(two_c, s, -sp);
+                        cp = c;
+                        sp = s;
+                        c = cn;
+                        s = sn;
+                    }
                 }
             }
         }
-    }
 
-    if (P.n_split > 1) {
-        const int64_t nf = P.n_f;
-        float* base = P.part + (int64_t)split * 6 * nf;
+        if (P.n_split > 1) {
+            const int64_t nf = P.n_f;
+            float* base = P.part + (int64_t)split * 6 * nf;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int64_t i = i0 + (int64_t)kWave * k;
+                if (i < f_hi) {
+                    base[i] = c1[k];
+                    base[nf + i] = s1[k];
+                    base[2 * nf + i] = yc[k];
+                    base[3 * nf + i] = ys[k];
+                    base[4 * nf + i] = wcc[k];
+                    base[5 * nf + i] = wcs[k];
+                }
+            }
+            continue;
+        }
+
+        unsigned long long tb = 0ull;  // the tile's best key in this lane
+        const float n = (float)m.n;
+        const float scale = (float)m.scale;
+        bool any_ill = false;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int64_t i = i0 + (int64_t)kWave * k;
             if (i < f_hi) {
-                base[i] = c1[k];
-                base[nf + i] = s1[k];
-                base[2 * nf + i] = yc[k];
-                base[3 * nf + i] = ys[k];
-                base[4 * nf + i] = wcc[k];
-                base[5 * nf + i] = wcs[k];
+                bool ill;
+                const float p =
+                    power32_gen(c1[k], s1[k], yc[k], ys[k], wcc[k], wcs[k], n, scale, ill);
+                any_ill |= ill;
+                if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, (double)p);
+                if (p == p) tb = umax64(tb, peak_key(p, i));  // NaN never wins
             }
         }
-        return;
-    }
-
-    PeakRec best{0.0, -1};
-    const float n = (float)m.n;
-    const float scale = (float)m.scale;
-    bool any_ill = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t i = i0 + (int64_t)kWave * k;
-        if (i < f_hi) {
-            bool ill;
-            const double p =
-                (double)power32_gen(c1[k], s1[k], yc[k], ys[k], wcc[k], wcs[k], n, scale, ill);
-            any_ill |= ill;
-            if (P.pgram) store_pgram(P.pgram, P.pgram_f64, obj * P.n_f + i, p);
-            if (better(p, i, best.p, best.i)) best = PeakRec{p, i};
+        // A tile holding an ill-conditioned bin sets its bit for the fix-up
+        // kernel, which recomputes the whole tile in FP64 and merges its best
+        // into the group's key; the other tiles' bins join the running best.
+        any_ill = __syncthreads_or(any_ill);
+        if (any_ill) {
+            if (threadIdx.x == 0) {
+                const int64_t tile = row * P.tiles_per_row + ft;
+                atomicOr(&P.ill_bits[tile >> 5], 1u << (tile & 31));
+            }
+        } else {
+            best = umax64(best, tb);
         }
     }
-    any_ill = __syncthreads_or(any_ill);
-    best = wave_best(best);
-    if (lane == 0) s_red[wave] = best;
+    if (P.n_split > 1) return;
+
+    // the chunk's best bin goes into its group's peak key (one atomic per item)
+    best = wave_max_u64(best);
+    unsigned long long* s_key = reinterpret_cast<unsigned long long*>(s_red);
+    if (lane == 0) s_key[wave] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
-        PeakRec b = s_red[0];
+        unsigned long long b = s_key[0];
 #pragma unroll
-        for (int w = 1; w < W; ++w)
-            if (better(s_red[w].p, s_red[w].i, b.p, b.i)) b = s_red[w];
-        if (any_ill)
-            atomicOr(&P.ill_bits[tile >> 5], 1u << (tile & 31));
-        else if (b.i >= 0)
-            atomicMax(&P.keys[row / P.rows_per_group], peak_key(b.p, b.i));
+        for (int w = 1; w < W; ++w) b = umax64(b, s_key[w]);
+        if (b != 0ull) atomicMax(&P.keys[row / P.rows_per_group], b);
     }
 }
 
+// Six sums per bin: up to K = 12 the kernel keeps four waves per SIMD (at most
+// 128 VGPRs, K = 8) or three (168, K = 12); K = 16 is held to three.
 template <int K, int W>
-__global__ __launch_bounds__(kWave* W) void gen_fp32p_kernel(const MainParams P) {
+__global__ __launch_bounds__(kWave* W)
+    __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 : 3))) void gen_fp32p_kernel(const MainParams P) {
     __shared__ double s_tau[kTile];
     __shared__ float4 s_obs[kTile];
     __shared__ PeakRec s_red[W];
@@ -186,7 +217,7 @@ __global__ __launch_bounds__(kWave* W) void gen_fp32p_kernel(const MainParams P)
         return;
     }
     // each XCD's queue holds the items of one contiguous run of row ranks
-    const int64_t per_row = P.tiles_per_row * P.n_split;
+    const int64_t per_row = P.chunks_per_row * P.n_split;
     const int64_t n_rows = P.n_items / per_row;
     const int x0 = (int)(blockIdx.x % kXcds);
     for (int d = 0; d < kXcds; ++d) {
