@@ -40,6 +40,7 @@ constexpr int kProbes = LSP_FEAT_WINDOW - 11;
 constexpr int kWindowStage = 1024;  // objects up to this many points keep t - t0 in LDS
 
 static_assert(LSP_FEAT_POOL == 8, "pooling uses three lane-exchange steps");
+static_assert(kCoarseW == 1, "the coarse staging loop gives each lane one observation per round");
 static_assert(kTilesPerObj * kCoarseTile == LSP_FEAT_COARSE * LSP_FEAT_POOL, "tile split");
 
 struct FeatParams {
@@ -99,7 +100,7 @@ __device__ __forceinline__ float pool8_max(float v) {
 
 // One (object, 1,024-bin tile) item; called by every thread of the workgroup.
 __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, double* s_tau,
-                                            float4* s_obs, float* s_fix) {
+                                            float4* s_obs, unsigned long long* s_starts) {
     constexpr int K = kCoarseK;
     const int64_t obj = item / kTilesPerObj;
     const int tile = (int)(item - obj * kTilesPerObj);
@@ -135,51 +136,52 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
         auto close_group = [&](int64_t j_next) {
             if (ns >= P.min_obs) {
                 const float N = (float)ns;
-                const float scale2 = syy > 0.0f ? 2.0f / syy : 0.0f;
+                const float scale = syy > 0.0f ? 1.0f / syy : 0.0f;
                 float p32[K];
-                float r2max = 0.0f;  // largest R^2 of this lane's bins
-                // With C2 + i S2 = sum exp(2iwt), R = |C2 + i S2|, A = xc^2 + xs^2
-                // and B R = (xc^2 - xs^2) C2 + 2 xc xs S2, twice P_LS is
-                // (A + B)/(N + R) + (A - B)/(N - R) = 2 (A N - B R)/(N^2 - R^2):
-                // one reciprocal and no square root per bin.  N - R <= N/32
-                // (the main kernel's rule) is R^2 >= (31/32)^2 N^2.
-                const float N2 = N * N;
-                const float ill_r2 = (1.0f - kIllTheta) * (1.0f - kIllTheta) * N2;
+                float det_min = INFINITY;  // smallest det M of this lane's bins
+                // With g = (xc, xs) and the moment matrix M = [[cc, cs],
+                // [cs, N - cc]] of (cos, sin), twice P_LS is g^T M^-1 g =
+                // (xc^2 (N - cc) - 2 xc xs cs + xs^2 cc) / det M, the tau-free
+                // form (A + B)/(N + R) + (A - B)/(N - R) of Eq. 1-2 written out
+                // (N^2 - R^2 = 4 det M): one reciprocal and no square root per
+                // bin.  N - R <= N/32 (the main kernel's rule) is
+                // det M <= (1 - (31/32)^2) N^2 / 4.
+                const float ill_det =
+                    0.25f * (1.0f - (1.0f - kIllTheta) * (1.0f - kIllTheta)) * N * N;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const float C2 = fmaf(2.0f, cc[k], -N);
-                    const float S2 = 2.0f * cs[k];
-                    const float R2 = fmaf(C2, C2, S2 * S2);
-                    const float A = fmaf(xc[k], xc[k], xs[k] * xs[k]);
-                    const float BR =
-                        fmaf(fmaf(xc[k], xc[k], -(xs[k] * xs[k])), C2, 2.0f * xc[k] * xs[k] * S2);
-                    p32[k] = fmaxf(fmaf(A, N, -BR), 0.0f) * __builtin_amdgcn_rcpf(N2 - R2) * scale2;
-                    r2max = fmaxf(r2max, R2);
+                    const float sn = N - cc[k];
+                    const float det = fmaf(cc[k], sn, -(cs[k] * cs[k]));
+                    const float num =
+                        fmaf(xc[k] * sn, xc[k], xs[k] * fmaf(-2.0f, xc[k] * cs[k], xs[k] * cc[k]));
+                    // (a negative value from rounding is clamped to zero with the
+                    // others before pooling)
+                    p32[k] = num * __builtin_amdgcn_rcpf(det) * scale;
+                    det_min = fminf(det_min, det);
                 }
                 // FP64 recompute of the unresolvable bins, one bin at a time
                 // (a rolled loop, so that the FP64 path stays out of the
-                // unrolled code and its registers), through LDS; which bins
-                // they are is worked out only here, where some are
-                if (__any(!(r2max < ill_r2))) {
+                // unrolled code and its registers; the value goes to its bin by
+                // a select over the lane's bins, so no LDS is set aside for
+                // this rare path); which bins they are is worked out only here,
+                // where some are
+                if (__any(!(det_min > ill_det))) {
                     uint32_t ill = 0u;  // bins of this lane FP32 cannot resolve
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
-                        const float C2 = fmaf(2.0f, cc[k], -N);
-                        const float S2 = 2.0f * cs[k];
-                        if (!(fmaf(C2, C2, S2 * S2) < ill_r2)) ill |= 1u << k;
+                        const float det = fmaf(cc[k], N - cc[k], -(cs[k] * cs[k]));
+                        if (!(det > ill_det)) ill |= 1u << k;
                     }
 #pragma unroll 1
                     for (int k = 0; k < K; ++k) {
                         if ((ill >> k) & 1u) {
                             const double f =
                                 grid_freq(P.f_min, P.df, i0 + (int64_t)kWave * k) * P.to_cyc;
-                            s_fix[(wave * K + k) * kWave + lane] =
-                                (float)group_power64(P.t, P.y, m.t0, m.ybar, g0, ns, f);
+                            const float v = (float)group_power64(P.t, P.y, m.t0, m.ybar, g0, ns, f);
+#pragma unroll
+                            for (int u = 0; u < K; ++u) p32[u] = u == k ? v : p32[u];
                         }
                     }
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        if ((ill >> k) & 1u) p32[k] = s_fix[(wave * K + k) * kWave + lane];
                 }
 #pragma unroll
                 for (int k = 0; k < K; ++k)
@@ -197,36 +199,59 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
         for (int64_t jt = m.j0; jt < j_end; jt += kTile) {
             const int cnt = (int)((j_end - jt) < kTile ? (j_end - jt) : kTile);
             __syncthreads();
-            for (int q = threadIdx.x; q < cnt; q += kWave * kCoarseW) {
-                const int64_t j = jt + q;
-                const double tj = P.t[j];
-                const double tc = tj - m.t0;
-                s_tau[q] = tc;
-                double sp = P.step_cyc * tc;
-                sp -= rint(sp);
-                const float rs = (float)sp;
-                // (the previous time is loaded unconditionally, clamped to the
-                // object's first observation, so the two loads go out together)
-                const double tprev = P.t[j > m.j0 ? j - 1 : j];
-                const bool starts = j > m.j0 && tj - tprev > P.gap;
-                // (the new-season flag is kept as integer bits, read back as
-                // a wave-uniform integer)
-                s_obs[q] = make_float4((float)(P.y[j] - m.ybar), __builtin_amdgcn_cosf(rs),
-                                       __builtin_amdgcn_sinf(rs), __int_as_float(starts ? 1 : 0));
+            // Stage the tile in rounds of 64 observations (one per lane); each
+            // round's new-season flags go to LDS as one ballot word.
+            for (int r = 0; r * kWave < cnt; ++r) {
+                const int q = r * kWave + lane;
+                bool starts = false;
+                if (q < cnt) {
+                    const int64_t j = jt + q;
+                    const double tj = P.t[j];
+                    const double tc = tj - m.t0;
+                    s_tau[q] = tc;
+                    double sp = P.step_cyc * tc;
+                    sp -= rint(sp);
+                    const float rs = (float)sp;
+                    // (the previous time is loaded unconditionally, clamped to
+                    // the object's first observation, so the two loads go out
+                    // together)
+                    const double tprev = P.t[j > m.j0 ? j - 1 : j];
+                    starts = j > m.j0 && tj - tprev > P.gap;
+                    s_obs[q] = make_float4((float)(P.y[j] - m.ybar), __builtin_amdgcn_cosf(rs),
+                                           __builtin_amdgcn_sinf(rs), 0.0f);
+                }
+                const unsigned long long word = __ballot(starts);
+                if (lane == 0) s_starts[r] = word;
             }
             __syncthreads();
-            for (int q = 0; q < cnt; ++q) {
-                const float4 o = s_obs[q];
-                const double tq = s_tau[q];  // both reads in flight together
-                // A season boundary closes the current group once it holds
-                // min_obs observations; sparser seasons merge with the next.
-                // Every lane reads the same slot, so the flag is wave-uniform.
-                if (uniform_i32(__float_as_int(o.w)) && ns >= P.min_obs) close_group(jt + q);
-                // the main kernel's hot loop: FP64-reduced seed, hardware
-                // sin/cos, three-term recurrence across the lane's bins
-                accumulate_obs<K, true, LSP_TRIG_HW>(fl, tq, o, xc, xs, cc, cs);
-                ++ns;
-                syy = fmaf(o.x, o.x, syy);
+            // Walk the tile from season boundary to season boundary.  A
+            // boundary closes the current group once it holds min_obs
+            // observations (sparser seasons merge with the next); between
+            // boundaries the loop is the main kernel's hot loop alone.
+            int q = 0;
+            while (q < cnt) {
+                const uint64_t here = (uint64_t)uniform_i64((int64_t)s_starts[q / kWave]);
+                if (((here >> (q % kWave)) & 1ull) && ns >= P.min_obs) close_group(jt + q);
+                // the next boundary after q, or the tile's end
+                int b = cnt;
+                for (int w = (q + 1) / kWave; w * kWave < cnt; ++w) {
+                    uint64_t bits = (uint64_t)uniform_i64((int64_t)s_starts[w]);
+                    if (w == (q + 1) / kWave) bits &= ~0ull << ((q + 1) % kWave);
+                    if (bits) {
+                        b = w * kWave + (int)__builtin_ctzll(bits);
+                        break;
+                    }
+                }
+                for (int j = q; j < b; ++j) {
+                    const float4 o = s_obs[j];
+                    const double tq = s_tau[j];  // both reads in flight together
+                    // the main kernel's hot loop: FP64-reduced seed, hardware
+                    // sin/cos, three-term recurrence across the lane's bins
+                    accumulate_obs<K, true, LSP_TRIG_HW>(fl, tq, o, xc, xs, cc, cs);
+                    syy = fmaf(o.x, o.x, syy);
+                }
+                ns += b - q;
+                q = b;
             }
         }
         close_group(j_end);
@@ -251,8 +276,8 @@ __device__ __forceinline__ void coarse_item(const FeatParams& P, int64_t item, d
 __global__ __launch_bounds__(kWave* kCoarseW)
     __attribute__((amdgpu_waves_per_eu(4))) void coarse_kernel(const FeatParams P) {
     __shared__ double s_tau[kTile];
-    __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, new-season flag bits)
-    __shared__ float s_fix[kCoarseK * kWave * kCoarseW];  // FP64-recomputed bins
+    __shared__ float4 s_obs[kTile];  // (y - ybar, cos step, sin step, 0)
+    __shared__ unsigned long long s_starts[kTile / kWave];  // new-season flags, one bit each
     __shared__ int64_t s_item;
     const int64_t n_items = P.n_obj * kTilesPerObj;
     const int64_t per = (n_items + kXcds - 1) / kXcds;
@@ -263,7 +288,7 @@ __global__ __launch_bounds__(kWave* kCoarseW)
         const int64_t hi = lo + per < n_items ? lo + per : n_items;
         int64_t item = pop_item(&P.queue[x], lo, &s_item);
         while (item < hi) {
-            coarse_item(P, item, s_tau, s_obs, s_fix);
+            coarse_item(P, item, s_tau, s_obs, s_starts);
             item = pop_item(&P.queue[x], lo, &s_item);
         }
     }

@@ -110,3 +110,23 @@ def test_features_long_series(dev):
     ref = features_ref.features(off, w.t, w.y, w.f_min, w.f_max)
     got = gpu_features(dev, off, w.t, w.y, w.f_min, w.f_max)
     assert_features_close(got, ref, "long series")
+
+
+def test_features_season_boundaries_at_word_and_tile_edges(dev):
+    """Season starts on the edges of the kernel's bookkeeping: a staged tile
+    holds 256 observations and its new-season flags are kept as 64-bit words,
+    so starts at observations 63, 64, 65 (word edge, one-point seasons), 128,
+    256 and 257 (tile edge), 511, 512 and the last observation alone, plus the
+    second observation, must group exactly as the reference does."""
+    rng = np.random.default_rng(21)
+    n = 600
+    starts = [1, 63, 64, 65, 127, 128, 256, 257, 300, 511, 512, n - 1]
+    dt = rng.uniform(0.2, 0.6, size=n - 1)
+    dt[np.array(starts) - 1] += 100.0
+    t = np.concatenate([[0.0], np.cumsum(dt)])
+    y = np.sin(2 * np.pi * 1.7 * t) + 0.1 * rng.standard_normal(n)
+    off = np.array([0, n], dtype=np.int64)
+    for min_obs in (2, 8, 70):
+        ref = features_ref.features(off, t, y, 1.0, 12.0, gap=60.0, min_obs=min_obs)
+        got = gpu_features(dev, off, t, y, 1.0, 12.0, season_gap=60.0, min_season_obs=min_obs)
+        assert_features_close(got, ref, f"boundaries min_obs={min_obs}")
