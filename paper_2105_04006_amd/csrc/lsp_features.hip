@@ -9,7 +9,8 @@
 //     longer than `season_gap`), and consecutive seasons are grouped until a
 //     group holds at least `min_season_obs` observations (a trailing group
 //     with fewer is dropped).  For each group, the normalised Lomb-Scargle
-//     power of Section 2 (Eq. 1-2 in the tau-free form) of the object's
+//     power of Section 2 (Eq. 1-2 without tau, through the 2x2 moment
+//     matrix of cos and sin) of the object's
 //     centred magnitudes y - ybar is evaluated on 8,192 bins over
 //     [f_min, f_max), max-pooled over runs of 8 bins and averaged over the
 //     groups -> features [0, 1024).  The group's own mean is not removed
