@@ -83,7 +83,10 @@ enum {
 
 /* How the waves of a workgroup share a frequency tile (FP32 form). */
 enum {
-    LSP_WSPLIT_AUTO = 0, /* the library's choice (currently off)                      */
+    LSP_WSPLIT_AUTO = 0, /* the library's choice: on, with 8 waves and no t_split, for
+                            one object of >= 2,048 points on the whole grid when the
+                            64 K-bin tiles give >= 3,584 waves (standard FP32 form
+                            with waves_per_wg and t_split left at 0); else off     */
     LSP_WSPLIT_OFF = 1,  /* each wave owns 64 K of the tile's bins                   */
     LSP_WSPLIT_ON = 2    /* all waves cover the same 64 K bins and split the
                             observations; sums are added in LDS in wave order        */

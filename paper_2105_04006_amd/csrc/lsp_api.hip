@@ -202,11 +202,24 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         }
         c->persistent = o->schedule == LSP_SCHED_PERSISTENT ||
                         (o->schedule == LSP_SCHED_AUTO && !one_row);
-        // Measured on one 4,096-point object: sharing the waves' bins and
-        // splitting observations inside the workgroup is within a few per
-        // cent of the default (the extra registers cost a wave per SIMD), so
-        // it is used only on request.
         c->ws = c->waves > 1 && o->wave_split == LSP_WSPLIT_ON;
+        // One object on the whole grid: eight waves that share each tile's
+        // bins and split its observations inside the workgroup (sums added in
+        // LDS, no partial sums in HBM, no combine launch) when that alone
+        // gives about 3.5 waves per SIMD and every wave at least a staging
+        // tile of observations to add before the sums meet.  Measured on a
+        // 4,096-point object: 3-5% faster than four waves with the
+        // cross-workgroup observation split from N_f = 5e5 (3,912 waves) to
+        // 4e6, 6-34% slower at 3e5-4e5 (2,344-3,128 waves), where the split
+        // below stays.
+        if (one_row && !method.gen && !variant && o->wave_split == LSP_WSPLIT_AUTO &&
+            !o->waves_per_wg && o->t_split == 0 && n_obs >= 8 * (int64_t)kTile) {
+            const int64_t tw = (int64_t)kWave * c->k;
+            if ((n_f + tw - 1) / tw * 8 >= 3584) {
+                c->waves = 8;
+                c->ws = 1;
+            }
+        }
         // eight waves per workgroup exist only with the wave split
         if (c->waves == 8 && !c->ws) return LSP_EUNSUPPORTED;
         if (o->t_split > 1) {

@@ -114,6 +114,37 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
             // index is wave-uniform, so every lane loads the same address
             for (int64_t j = js; j < je; ++j)
                 accumulate_obs<K, CHEB, TRIG>(fl, P.stage_t[j], P.stage_o[j], xc, xs, cc, cs);
+        } else if (WS && W * kWave > kTile) {
+            // Eight waves that share the bins see only kTile / 8 observations
+            // each between two staging barriers, too few to hide the staging
+            // loads: every thread stages at most one observation of a tile,
+            // and its t and y for the next tile are loaded before the current
+            // tile's accumulation, so that the loads' latency hides behind it
+            const int tid = (int)threadIdx.x;
+            double nt = 0.0, ny = 0.0;
+            if (tid < je - js) {
+                nt = P.t[js + tid];
+                ny = P.y[js + tid];
+            }
+            for (int64_t jt = js; jt < je; jt += kTile) {
+                const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
+                if (!one_pass || ft == t_lo) {
+                    __syncthreads();
+                    if (tid < cnt) {
+                        const double tc = nt - m.t0;
+                        s_tau[tid] = tc;
+                        s_obs[tid] = stage_obs<TRIG>(P.step_cyc, tc, ny - m.ybar);
+                    }
+                    __syncthreads();
+                    const int64_t jn = jt + kTile;
+                    if (jn < je && tid < je - jn) {
+                        nt = P.t[jn + tid];
+                        ny = P.y[jn + tid];
+                    }
+                }
+                for (int q = uniform_i32(wave); q < cnt; q += W)
+                    accumulate_obs<K, CHEB, TRIG>(fl, s_tau[q], s_obs[q], xc, xs, cc, cs);
+            }
         } else {
             for (int64_t jt = js; jt < je; jt += kTile) {
                 const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
@@ -138,19 +169,21 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
             // add the waves' sums into wave 0's, one array at a time, as a
             // tree: in each round the upper half of the remaining waves hands
             // its sums through LDS to the lower half (a fixed order)
+            // (one base address per wave, the bins at fixed offsets from it)
             auto gather = [&](float(&v)[K]) {
 #pragma unroll
                 for (int half = W / 2; half >= 1; half /= 2) {
                     __syncthreads();
                     if (wave >= half && wave < 2 * half) {
+                        float* dst = s_part + (wave - half) * (K * kWave) + lane;
 #pragma unroll
-                        for (int k = 0; k < K; ++k)
-                            s_part[((wave - half) * K + k) * kWave + lane] = v[k];
+                        for (int k = 0; k < K; ++k) dst[k * kWave] = v[k];
                     }
                     __syncthreads();
                     if (wave < half) {
+                        const float* src = s_part + wave * (K * kWave) + lane;
 #pragma unroll
-                        for (int k = 0; k < K; ++k) v[k] += s_part[(wave * K + k) * kWave + lane];
+                        for (int k = 0; k < K; ++k) v[k] += src[k * kWave];
                     }
                 }
             };

@@ -367,16 +367,27 @@ def test_gen_rows_and_plan_argument_errors(L):
 
 def test_describe_launch_resolves_the_shape():
     """lsp_describe_launch reports the configuration the call would use: the
-    cost model's K for the FP32 form, the single-object observation split, the
-    persistent schedule for batches, and the caller's explicit choices."""
+    cost model's K for the FP32 form, the single object's in-workgroup split
+    (eight waves sharing each tile's bins) where it fills the chip and its
+    observation split across workgroups where it does not, the persistent
+    schedule for batches, and the caller's explicit choices."""
     g = lsp.make_grid(0.5, 24.0, 500_000)
     one = lsp.describe_launch(1, 4096, g, lsp.make_options(form=lsp.FORM_FP32P))
-    assert one["k_per_lane"] in (8, 10, 12, 16) and one["waves_per_wg"] == 4
-    assert one["t_split"] > 1 and one["schedule"] == lsp.SCHED_GRID
+    assert one["k_per_lane"] in (8, 10, 12, 16) and one["schedule"] == lsp.SCHED_GRID
+    assert (one["waves_per_wg"], one["wave_split"], one["t_split"]) == (8, lsp.WSPLIT_ON, 1)
     assert one["recurrence"] == lsp.REC_CHEBYSHEV
-    assert one["tile_freqs"] == 64 * one["k_per_lane"] * one["waves_per_wg"]
+    assert one["tile_freqs"] == 64 * one["k_per_lane"]
     tiles = -(-500_000 // one["tile_freqs"])
-    assert one["n_items"] == tiles * one["t_split"]
+    assert one["n_items"] == tiles and tiles * 8 >= 3584
+    # too few tiles for eight waves each, too few observations, or the wave
+    # split turned off: four waves and the observation split across workgroups
+    for n_f, n_obs, ws in ((300_000, 4096, lsp.WSPLIT_AUTO), (500_000, 1000, lsp.WSPLIT_AUTO),
+                           (500_000, 4096, lsp.WSPLIT_OFF)):
+        sp = lsp.describe_launch(1, n_obs, lsp.make_grid(0.5, 24.0, n_f),
+                                 lsp.make_options(form=lsp.FORM_FP32P, wave_split=ws))
+        assert (sp["waves_per_wg"], sp["wave_split"]) == (4, lsp.WSPLIT_OFF)
+        assert sp["t_split"] > 1 and sp["tile_freqs"] == 64 * sp["k_per_lane"] * 4
+        assert sp["n_items"] == -(-n_f // sp["tile_freqs"]) * sp["t_split"]
     gb = lsp.make_grid(0.5, 24.0, 250_000)
     many = lsp.describe_launch(200_000, 52_000_000, gb, lsp.make_options(form=lsp.FORM_FP32P))
     assert many["schedule"] == lsp.SCHED_PERSISTENT and many["t_split"] == 1
@@ -384,7 +395,7 @@ def test_describe_launch_resolves_the_shape():
     tiles_row = -(-250_000 // many["tile_freqs"])
     assert many["tiles_per_item"] == 16  # 49 M tiles: up to 16 consecutive tiles per item
     assert many["n_items"] == 200_000 * -(-tiles_row // 16)
-    assert one["tiles_per_item"] == 1  # a split object keeps one tile per item
+    assert one["tiles_per_item"] == 1 and sp["tiles_per_item"] == 1  # few tiles, split objects
     few = lsp.describe_launch(10, 5000, gb, lsp.make_options(form=lsp.FORM_FP32P))
     assert few["tiles_per_item"] == 1 and few["n_items"] == 10 * -(-250_000 // few["tile_freqs"])
     fixed = lsp.describe_launch(10, 5000, gb, lsp.make_options(
