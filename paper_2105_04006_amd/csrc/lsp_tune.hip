@@ -81,7 +81,9 @@ void cache_store(const char* path, const std::string& key, const lsp_options& o,
 std::vector<lsp_options> candidates(const lsp_options& base, bool single) {
     std::vector<lsp_options> out;
     const int ks[] = {8, 10, 12, 16, 32};
-    const int ws[] = {1, 2, 4};
+    // (eight waves per workgroup exist only with the in-workgroup wave split,
+    // which only a single object's search covers)
+    const int ws[] = {1, 2, 4, 8};
     // One object: the recurrence is fixed to the three-term form (as accurate
     // and cheaper) and the search covers how the object is split instead.
     std::vector<int> recs = single ? std::vector<int>{LSP_REC_CHEBYSHEV}
@@ -95,6 +97,7 @@ std::vector<lsp_options> candidates(const lsp_options& base, bool single) {
                 for (int sc : scheds)
                     for (int sp : splits)
                         for (int wsp = 0; wsp < (single && w > 1 ? 2 : 1); ++wsp) {
+                            if (w == 8 && !wsp) continue;
                             lsp_options o = base;
                             o.form = LSP_FORM_FP32P;
                             o.k_per_lane = k;
