@@ -64,10 +64,14 @@ def valu_ops_per_eval_gen(k):
     return (6 * k + 4 + 2 * (k - 2) + 12) / k
 
 
+# the kernel's sources and the file that resolves its launch shape (waves,
+# splits, items), on which the counters depend as much
 KERNEL_SOURCES = {
-    "standard": ["paper_2105_04006_amd/csrc/lsp_fp32p.hip", "paper_2105_04006_amd/csrc/lsp_common.h"],
+    "standard": ["paper_2105_04006_amd/csrc/lsp_fp32p.hip", "paper_2105_04006_amd/csrc/lsp_common.h",
+                 "paper_2105_04006_amd/csrc/lsp_api.hip"],
     "generalized": ["paper_2105_04006_amd/csrc/lsp_gen.hip",
-                    "paper_2105_04006_amd/csrc/lsp_common.h"],
+                    "paper_2105_04006_amd/csrc/lsp_common.h",
+                    "paper_2105_04006_amd/csrc/lsp_api.hip"],
 }
 TRAFFIC_FILES = {
     "standard": os.path.join(ROOT, "profiles", "fp32p_single_4096_traffic.json"),

@@ -227,10 +227,17 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
             c->split = o->t_split;
         } else if (o->t_split == 0 && n_obj == 1 && whole) {
             // Too few frequency tiles to occupy 1024 SIMDs with a few waves
-            // each: split the observation axis as well.
+            // each: split the observation axis as well, into as many parts as
+            // fill the chip's resident wave slots once (four waves per SIMD;
+            // three for the generalized kernel from K = 12, whose registers
+            // allow no more).  Measured on one 4,096-point object with errors
+            // (N_f = 5e5, K = 16): splits 6 / 8 / 12 (0.96 / 1.28 / 1.92
+            // rounds of its 3,072 slots) ran the main kernel in 0.383 / 0.389
+            // / 0.367 ms and a split of 7 (1.12 rounds) in 0.436 ms.
             const int64_t tpw = (int64_t)kWave * c->k * (c->ws ? 1 : c->waves);
             const int64_t waves_total = ((n_f + tpw - 1) / tpw) * c->waves;
-            int64_t want = 4096 / (waves_total > 0 ? waves_total : 1);
+            const int64_t slots = (int64_t)1024 * (method.gen && c->k > 8 ? 3 : 4);
+            int64_t want = slots / (waves_total > 0 ? waves_total : 1);
             int64_t cap = n_obs / kTile;
             if (cap > 64) cap = 64;
             if (want > cap) want = cap;
