@@ -493,3 +493,16 @@ def test_row_order_argument_errors(L):
     assert call(n_rows=20, rpg=2, ws=ctypes.c_void_p((1 << 20) + 8)) == lsp.EINVAL
     assert call(row_obj=FAKE, n_rows=1 << 31) == lsp.EINVAL
     assert call(ws_bytes=nb - 1) == lsp.ENOMEM
+
+
+def test_single_object_in_workgroup_split_keeps_no_partial_sums():
+    """The single-object default on a wide grid adds its waves' sums on chip:
+    its workspace holds no observation-split partial sums (16 B per bin and
+    split), which the split across workgroups needs."""
+    g = lsp.make_grid(0.5, 24.0, 500_000)
+    ws8 = lsp.workspace_bytes(1, 4096, g, lsp.make_options(form=lsp.FORM_FP32P))
+    opt_off = lsp.make_options(form=lsp.FORM_FP32P, wave_split=lsp.WSPLIT_OFF)
+    off = lsp.workspace_bytes(1, 4096, g, opt_off)
+    split = lsp.describe_launch(1, 4096, g, opt_off)["t_split"]
+    assert split > 1 and off - ws8 >= 16 * 500_000 * split
+    assert ws8 < 4096  # metadata, one peak key, flags and queue counters only
