@@ -52,6 +52,10 @@ __device__ __forceinline__ float4 stage_obs(double step_cyc, double tc, double y
 // fixed tree over the waves, before the finish.  This multiplies the waves working on one
 // object without the per-split partial sums in HBM that the observation split
 // across workgroups needs.
+// Observations staged per pass: one per thread for the eight-wave split.
+template <int W, bool WS>
+constexpr int stage_tile() { return WS && W * kWave > kTile ? W * kWave : kTile; }
+
 template <int K, int W, bool CHEB, bool WS, int SRC, int TRIG>
 __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, double* s_tau,
                                            float4* s_obs, PeakRec* s_red, float* s_part) {
@@ -97,7 +101,8 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
     const int64_t js = m.j0 + lo, je = m.j0 + hi;
     // an object that fits in one staging pass is staged once for all the
     // chunk's tiles
-    const bool one_pass = je - js <= kTile;
+    constexpr int ST = stage_tile<W, WS>();
+    const bool one_pass = je - js <= ST;
 
     unsigned long long best = 0ull;  // this lane's best key over the chunk's resolvable tiles
     for (int64_t ft = t_lo; ft < t_hi; ++ft) {
@@ -126,8 +131,8 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
                 nt = P.t[js + tid];
                 ny = P.y[js + tid];
             }
-            for (int64_t jt = js; jt < je; jt += kTile) {
-                const int cnt = (int)((je - jt) < kTile ? (je - jt) : kTile);
+            for (int64_t jt = js; jt < je; jt += ST) {
+                const int cnt = (int)((je - jt) < ST ? (je - jt) : ST);
                 if (!one_pass || ft == t_lo) {
                     __syncthreads();
                     if (tid < cnt) {
@@ -136,7 +141,7 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
                         s_obs[tid] = stage_obs<TRIG>(P.step_cyc, tc, ny - m.ybar);
                     }
                     __syncthreads();
-                    const int64_t jn = jt + kTile;
+                    const int64_t jn = jt + ST;
                     if (jn < je && tid < je - jn) {
                         nt = P.t[jn + tid];
                         ny = P.y[jn + tid];
@@ -259,8 +264,8 @@ template <int K, int W, bool CHEB, bool WS, int SRC = LSP_OBS_LDS, int TRIG = LS
 __global__ __launch_bounds__(kWave* W)
     __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : 1))) void fp32p_kernel(
         const MainParams P) {
-    __shared__ double s_tau[kTile];
-    __shared__ float4 s_obs[kTile];
+    __shared__ double s_tau[stage_tile<W, WS>()];
+    __shared__ float4 s_obs[stage_tile<W, WS>()];
     __shared__ PeakRec s_red[W];
     __shared__ int64_t s_item;
     __shared__ float s_part[WS ? (W / 2) * K * kWave : 1];
