@@ -207,11 +207,12 @@ lsp_status resolve(int64_t n_obj, int64_t n_obs, const lsp_grid* g, const lsp_op
         // bins and split its observations inside the workgroup (sums added in
         // LDS, no partial sums in HBM, no combine launch) when that alone
         // gives about 3.5 waves per SIMD and every wave at least a staging
-        // tile of observations to add before the sums meet.  Measured on a
-        // 4,096-point object: 3-5% faster than four waves with the
-        // cross-workgroup observation split from N_f = 5e5 (3,912 waves) to
-        // 4e6, 6-34% slower at 3e5-4e5 (2,344-3,128 waves), where the split
-        // below stays.
+        // tile of observations to add before the sums meet.  Measured against
+        // four waves with the cross-workgroup observation split: on a
+        // 4,096-point object 3-7% faster from N_f = 5e5 (3,912 waves) to 4e6
+        // and 12-32% slower at 3e5-4e5 (2,344-3,128 waves), where the split
+        // below stays; on 2,048-65,536-point objects within 2.5% either way
+        // at 5e5 and 0-5% faster at 1e6.  It writes no partial sums.
         if (one_row && !method.gen && !variant && o->wave_split == LSP_WSPLIT_AUTO &&
             !o->waves_per_wg && o->t_split == 0 && n_obs >= 8 * (int64_t)kTile) {
             const int64_t tw = (int64_t)kWave * c->k;

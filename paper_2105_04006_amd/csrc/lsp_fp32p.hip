@@ -52,6 +52,7 @@ __device__ __forceinline__ float4 stage_obs(double step_cyc, double tc, double y
 // fixed tree over the waves, before the finish.  This multiplies the waves working on one
 // object without the per-split partial sums in HBM that the observation split
 // across workgroups needs.
+
 // Observations staged per pass: one per thread for the eight-wave split.
 template <int W, bool WS>
 constexpr int stage_tile() { return WS && W * kWave > kTile ? W * kWave : kTile; }
@@ -120,11 +121,11 @@ __device__ __forceinline__ void fp32p_item(const MainParams& P, int64_t item, do
             for (int64_t j = js; j < je; ++j)
                 accumulate_obs<K, CHEB, TRIG>(fl, P.stage_t[j], P.stage_o[j], xc, xs, cc, cs);
         } else if (WS && W * kWave > kTile) {
-            // Eight waves that share the bins see only kTile / 8 observations
-            // each between two staging barriers, too few to hide the staging
-            // loads: every thread stages at most one observation of a tile,
-            // and its t and y for the next tile are loaded before the current
-            // tile's accumulation, so that the loads' latency hides behind it
+            // Eight waves that share the bins see only an eighth of each
+            // staging pass, too few observations to hide the staging loads:
+            // a pass stages one observation per thread (512), and each
+            // thread's t and y for the next pass are loaded before the current
+            // pass's accumulation, so that the loads' latency hides behind it
             const int tid = (int)threadIdx.x;
             double nt = 0.0, ny = 0.0;
             if (tid < je - js) {
