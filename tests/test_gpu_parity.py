@@ -418,3 +418,32 @@ def test_full_batch_10k_peaks(dev):
         assert peak_ok(ora_pg[o], ora_pk["index"][o], pk64["index"][o], 1e-9)
         assert_fp64_close([pk64["power"][o]], [ora_pg[o][pk64["index"][o]]], "peak power fp64")
         assert peak_ok(ora_pg[o], ora_pk["index"][o], pk32["index"][o], 2 * FP32_ATOL, bins=1)
+
+
+def test_single_wide_grid_statuses(dev):
+    """Objects that take the single-object default of eight waves sharing each
+    tile (4,096 points, N_f = 5e5), but have no periodogram to compute: a NaN
+    magnitude (NONFINITE: every bin NaN, no peak) and a constant series
+    (DEGENERATE: every bin 0, no peak), written by the tile's owning wave;
+    then a series whose sums the eight waves do add, checked on sampled bins
+    against the oracle."""
+    t, y, _ = synth.sine_object(4096, 77)
+    n_f = 500_000
+    d = lsp.describe_launch(1, len(t), lsp.make_grid(0.5, 24.0, n_f),
+                            lsp.make_options(form=lsp.FORM_FP32P))
+    assert (d["waves_per_wg"], d["wave_split"], d["t_split"]) == (8, lsp.WSPLIT_ON, 1)
+    y_nan = y.copy()
+    y_nan[1234] = np.nan
+    for yy, status, fill in ((y_nan, lsp.OBJ_NONFINITE, np.nan),
+                             (np.full_like(y, 0.25), lsp.OBJ_DEGENERATE, 0.0)):
+        pg, pk = run_single(dev, t, yy, 0.5, 24.0, n_f, form=lsp.FORM_FP32P)
+        assert pk["status"] == status and pk["index"] == -1
+        if np.isnan(fill):
+            assert np.all(np.isnan(pg))
+        else:
+            assert np.all(pg == fill)
+    pg, pk = run_single(dev, t, y, 0.5, 24.0, n_f, form=lsp.FORM_FP32P)
+    bins = np.unique(np.concatenate([np.arange(3, n_f, 4999), [pk["index"]]]))
+    ora = oracle.eval_bins(np.array([0, len(t)], dtype=np.int64), t, y, 0.5, 24.0, n_f,
+                           np.zeros(len(bins), np.int64), bins)
+    assert_fp32_close(pg[bins], ora, "eight-wave single object, sampled bins")
