@@ -547,6 +547,65 @@ lsp_status lsp_adam(float *param, const float *grad, float *m, float *v, int64_t
                     int32_t step, float lr, float beta1, float beta2, float eps,
                     void *param_bf16, void *stream);
 
+/*
+ * The proposal network as a whole (not in the paper: it picks the bands on
+ * which Section 2's power is evaluated; the layer order lives here, behind
+ * the ABI): input
+ * x [n x dims[0]] BF16 -> ReLU(x W_0 + b_0) -> ReLU(. W_1 + b_1) -> . W_2 + b_2
+ * = logits [n x dims[3]] FP32.  W_l is [dims[l] x dims[l+1]] row-major; the
+ * GEMMs read its BF16 copy w_bf16[l], the optimiser updates the FP32 master
+ * w[l] and refreshes the copy.  Every pointer is a caller-owned device
+ * pointer; nothing is allocated or freed.
+ */
+typedef struct {
+    int32_t dims[4]; /* input, first hidden, second hidden, output widths (each >= 1) */
+    float *w[3];     /* FP32 master weights W_l                                        */
+    float *b[3];     /* FP32 biases b_l [dims[l+1]]                                   */
+    void *w_bf16[3]; /* BF16 copies of W_l (the GEMM operands)                        */
+} lsp_mlp;
+
+/* Per-parameter arrays shaped like lsp_mlp's w and b: gradients, or Adam's
+ * first and second moments. */
+typedef struct {
+    float *w[3];
+    float *b[3];
+} lsp_mlp_grads;
+
+/* Forward pass of n rows: the two hidden activations go to h1 [n x dims[1]]
+ * and h2 [n x dims[2]] (BF16, kept for lsp_mlp_backward) and the logits to
+ * logits [n x dims[3]] (FP32).  Errors: LSP_EINVAL for a NULL or malformed
+ * net (a width < 1 or a NULL parameter), n < 0, NULL arrays with n > 0. */
+lsp_status lsp_mlp_forward(const lsp_mlp *net, const void *x_bf16, int64_t n, void *h1_bf16,
+                           void *h2_bf16, float *logits, void *stream);
+
+/* Device scratch lsp_mlp_backward needs for n rows (0 for a malformed net or
+ * n < 1).  Its layout, for callers that inspect the intermediate gradients:
+ * dlogits FP32 [n x dims[3]], dlogits BF16, dz2 FP32 [n x dims[2]], dz2 BF16,
+ * dz1 FP32 [n x dims[1]], dz1 BF16, in that order, each section starting on
+ * a 256-byte boundary (dz_l: the gradient at hidden layer l's
+ * pre-activation). */
+size_t lsp_mlp_workspace_bytes(const lsp_mlp *net, int64_t n);
+
+/* Gradients of sum_i scale * loss_i, with loss_i the softmax cross-entropy of
+ * row i's logits against labels[i] (a label outside [0, dims[3]) contributes
+ * nothing), from the activations and logits of lsp_mlp_forward on the same
+ * x: dW_l, db_l into grads (overwritten), and each row's loss into loss_rows
+ * [n] (may be NULL).  The hidden-layer gradients pass through BF16 as the
+ * GEMM operands do.  Errors: LSP_EINVAL for a malformed net or grads, n < 1,
+ * NULL inputs; LSP_ENOMEM if workspace_bytes < lsp_mlp_workspace_bytes. */
+lsp_status lsp_mlp_backward(const lsp_mlp *net, const void *x_bf16, const int32_t *labels,
+                            int64_t n, const void *h1_bf16, const void *h2_bf16,
+                            const float *logits, float scale, const lsp_mlp_grads *grads,
+                            float *loss_rows, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
+/* One Adam step (lsp_adam) on every parameter of net, W_0, b_0, W_1, b_1, W_2,
+ * b_2 in that order, with moments m and v, refreshing the BF16 weight copies.
+ * Errors: LSP_EINVAL for a malformed net, grads or moments, step < 1. */
+lsp_status lsp_mlp_adam(const lsp_mlp *net, const lsp_mlp_grads *grads, const lsp_mlp_grads *m,
+                        const lsp_mlp_grads *v, int32_t step, float lr, float beta1, float beta2,
+                        float eps, void *stream);
+
 /* Per row of logits [n x c] (c <= 128): the k largest entries' indices in
  * decreasing order (lowest index on ties) into idx [n x k], and the softmax
  * probability mass of those k entries into mass [n] (may be NULL). */

@@ -610,6 +610,128 @@ lsp_status lsp_adam(float* param, const float* grad, float* m, float* v, int64_t
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
 
+// ---- the network as a whole: the layer order of lsp_mlp, from the primitives
+
+static bool mlp_ok(const lsp_mlp* net) {
+    if (!net) return false;
+    for (int l = 0; l < 4; ++l)
+        if (net->dims[l] < 1) return false;
+    for (int l = 0; l < 3; ++l)
+        if (!net->w[l] || !net->b[l] || !net->w_bf16[l]) return false;
+    return true;
+}
+
+static bool grads_ok(const lsp_mlp_grads* g) {
+    if (!g) return false;
+    for (int l = 0; l < 3; ++l)
+        if (!g->w[l] || !g->b[l]) return false;
+    return true;
+}
+
+// Backward scratch: dlogits, dz2, dz1 in FP32 and in BF16, 256-byte aligned.
+struct MlpScratch {
+    size_t off[6];
+    size_t total;
+};
+
+static MlpScratch mlp_scratch(const lsp_mlp* net, int64_t n) {
+    const int64_t rows[3] = {net->dims[3], net->dims[2], net->dims[1]};
+    MlpScratch s{};
+    size_t at = 0;
+    for (int q = 0; q < 3; ++q) {
+        s.off[2 * q] = at;
+        at += ((size_t)n * rows[q] * 4 + 255) / 256 * 256;
+        s.off[2 * q + 1] = at;
+        at += ((size_t)n * rows[q] * 2 + 255) / 256 * 256;
+    }
+    s.total = at;
+    return s;
+}
+
+lsp_status lsp_mlp_forward(const lsp_mlp* net, const void* x_bf16, int64_t n, void* h1_bf16,
+                           void* h2_bf16, float* logits, void* stream) {
+    if (!mlp_ok(net) || n < 0 || (n > 0 && (!x_bf16 || !h1_bf16 || !h2_bf16 || !logits)))
+        return LSP_EINVAL;
+    if (n == 0) return LSP_OK;
+    const int64_t d0 = net->dims[0], d1 = net->dims[1], d2 = net->dims[2], d3 = net->dims[3];
+    lsp_status st = lsp_gemm_bf16(n, d1, d0, x_bf16, d0, 1, net->w_bf16[0], d1, 1, net->b[0],
+                                  nullptr, 1, nullptr, h1_bf16, d1, stream);
+    if (st != LSP_OK) return st;
+    st = lsp_gemm_bf16(n, d2, d1, h1_bf16, d1, 1, net->w_bf16[1], d2, 1, net->b[1], nullptr, 1,
+                       nullptr, h2_bf16, d2, stream);
+    if (st != LSP_OK) return st;
+    return lsp_gemm_bf16(n, d3, d2, h2_bf16, d2, 1, net->w_bf16[2], d3, 1, net->b[2], nullptr, 0,
+                         logits, nullptr, d3, stream);
+}
+
+size_t lsp_mlp_workspace_bytes(const lsp_mlp* net, int64_t n) {
+    if (!net || n < 1) return 0;
+    for (int l = 0; l < 4; ++l)
+        if (net->dims[l] < 1) return 0;
+    return mlp_scratch(net, n).total;
+}
+
+lsp_status lsp_mlp_backward(const lsp_mlp* net, const void* x_bf16, const int32_t* labels,
+                            int64_t n, const void* h1_bf16, const void* h2_bf16,
+                            const float* logits, float scale, const lsp_mlp_grads* grads,
+                            float* loss_rows, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+    if (!mlp_ok(net) || !grads_ok(grads) || n < 1 || !x_bf16 || !labels || !h1_bf16 ||
+        !h2_bf16 || !logits || !workspace)
+        return LSP_EINVAL;
+    const MlpScratch sc = mlp_scratch(net, n);
+    if (workspace_bytes < sc.total) return LSP_ENOMEM;
+    const int64_t d0 = net->dims[0], d1 = net->dims[1], d2 = net->dims[2], d3 = net->dims[3];
+    char* ws = static_cast<char*>(workspace);
+    float* g3 = reinterpret_cast<float*>(ws + sc.off[0]);
+    void* g3b = ws + sc.off[1];
+    float* dz2 = reinterpret_cast<float*>(ws + sc.off[2]);
+    void* dz2b = ws + sc.off[3];
+    float* dz1 = reinterpret_cast<float*>(ws + sc.off[4]);
+    void* dz1b = ws + sc.off[5];
+    lsp_status st = lsp_softmax_xent(logits, labels, n, (int32_t)d3, scale, g3, g3b, loss_rows,
+                                     stream);
+    if (st != LSP_OK) return st;
+    // layer 3: dW_2 = h2^T g3, db_2 = column sums of g3, dz2 = (g3 W_2^T) where h2 > 0
+    if ((st = lsp_gemm_bf16(d2, d3, n, h2_bf16, 1, d2, g3b, d3, 1, nullptr, nullptr, 0,
+                            grads->w[2], nullptr, d3, stream)) != LSP_OK)
+        return st;
+    if ((st = lsp_col_sums(g3, n, (int32_t)d3, grads->b[2], stream)) != LSP_OK) return st;
+    if ((st = lsp_gemm_bf16(n, d2, d3, g3b, d3, 1, net->w_bf16[2], 1, d3, nullptr, h2_bf16, 0,
+                            dz2, dz2b, d2, stream)) != LSP_OK)
+        return st;
+    // layer 2
+    if ((st = lsp_gemm_bf16(d1, d2, n, h1_bf16, 1, d1, dz2b, d2, 1, nullptr, nullptr, 0,
+                            grads->w[1], nullptr, d2, stream)) != LSP_OK)
+        return st;
+    if ((st = lsp_col_sums(dz2, n, (int32_t)d2, grads->b[1], stream)) != LSP_OK) return st;
+    if ((st = lsp_gemm_bf16(n, d1, d2, dz2b, d2, 1, net->w_bf16[1], 1, d2, nullptr, h1_bf16, 0,
+                            dz1, dz1b, d1, stream)) != LSP_OK)
+        return st;
+    // layer 1
+    if ((st = lsp_gemm_bf16(d0, d1, n, x_bf16, 1, d0, dz1b, d1, 1, nullptr, nullptr, 0,
+                            grads->w[0], nullptr, d1, stream)) != LSP_OK)
+        return st;
+    return lsp_col_sums(dz1, n, (int32_t)d1, grads->b[0], stream);
+}
+
+lsp_status lsp_mlp_adam(const lsp_mlp* net, const lsp_mlp_grads* grads, const lsp_mlp_grads* m,
+                        const lsp_mlp_grads* v, int32_t step, float lr, float beta1, float beta2,
+                        float eps, void* stream) {
+    if (!mlp_ok(net) || !grads_ok(grads) || !grads_ok(m) || !grads_ok(v) || step < 1)
+        return LSP_EINVAL;
+    for (int l = 0; l < 3; ++l) {
+        const int64_t nw = (int64_t)net->dims[l] * net->dims[l + 1];
+        lsp_status st = lsp_adam(net->w[l], grads->w[l], m->w[l], v->w[l], nw, step, lr, beta1,
+                                 beta2, eps, net->w_bf16[l], stream);
+        if (st != LSP_OK) return st;
+        st = lsp_adam(net->b[l], grads->b[l], m->b[l], v->b[l], net->dims[l + 1], step, lr,
+                      beta1, beta2, eps, nullptr, stream);
+        if (st != LSP_OK) return st;
+    }
+    return LSP_OK;
+}
+
 lsp_status lsp_top_k(const float* logits, int64_t n, int32_t c, int32_t k, int32_t* idx,
                      float* mass, void* stream) {
     if (n < 0 || c < 1 || c > 128 || k < 1 || k > c || (n > 0 && (!logits || !idx)))

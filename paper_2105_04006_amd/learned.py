@@ -120,6 +120,25 @@ class BandNet:
         self.mean = None
         self.inv_std = None
         self._bufs = {}
+        # the library's view of the network (lsp_mlp) and of its Adam moments;
+        # the tensors behind the pointers live as long as this object
+        self.c_net = lsp.Mlp()
+        self.c_net.dims[:] = list(self.dims)
+        for l in range(3):
+            self.c_net.w[l] = self.master[2 * l].data_ptr()
+            self.c_net.b[l] = self.master[2 * l + 1].data_ptr()
+            self.c_net.w_bf16[l] = self.w_bf16[l].data_ptr()
+        self.c_m, self.c_v = self._c_grads(self.m), self._c_grads(self.v)
+        self.grads = [torch.empty_like(p) for p in self.master]
+        self.c_grads = self._c_grads(self.grads)
+
+    @staticmethod
+    def _c_grads(arrays):
+        g = lsp.MlpGrads()
+        for l in range(3):
+            g.w[l] = arrays[2 * l].data_ptr()
+            g.b[l] = arrays[2 * l + 1].data_ptr()
+        return g
 
     # ------------------------------------------------------------- buffers
     def _buf(self, name, shape, dtype):
@@ -162,63 +181,56 @@ class BandNet:
 
     # ------------------------------------------------------------ forward
     def forward(self, x_bf16, logits=None, stream=None):
-        """x_bf16: [n, 1088] int16 (BF16 bits).  Returns FP32 logits [n, 64]."""
+        """x_bf16: [n, 1088] int16 (BF16 bits).  Returns FP32 logits [n, 64]
+        (lsp_mlp_forward; the hidden activations stay in this object's
+        buffers for gradients)."""
         n = x_bf16.shape[0]
         d0, d1, d2, d3 = self.dims
         h1 = self._buf("h1", (n, d1), torch.int16)
         h2 = self._buf("h2", (n, d2), torch.int16)
         logits = torch.empty((n, d3), dtype=torch.float32, device=self.device) \
             if logits is None else logits
-        W1, W2, W3 = self.w_bf16
-        b1, b2, b3 = self.master[1], self.master[3], self.master[5]
-        gemm(x_bf16, W1, n, d1, d0, d0, 1, d1, 1, C_bf16=h1, bias=b1, relu=True, stream=stream)
-        gemm(h1, W2, n, d2, d1, d1, 1, d2, 1, C_bf16=h2, bias=b2, relu=True, stream=stream)
-        gemm(h2, W3, n, d3, d2, d2, 1, d3, 1, C=logits, bias=b3, stream=stream)
+        _ok(lsp.lib().lsp_mlp_forward(ctypes.byref(self.c_net), _p(x_bf16), n, _p(h1), _p(h2),
+                                      _p(logits), _s(stream)), "lsp_mlp_forward")
         return logits
 
     # ----------------------------------------------------------- training
     def gradients(self, x_bf16, labels, stream=None):
-        """Forward + backward on one batch; returns (loss rows, [dW1, db1, ...])."""
+        """Forward + backward on one batch (lsp_mlp_forward, lsp_mlp_backward:
+        the mean softmax cross-entropy over the batch); returns (loss rows,
+        [dW1, db1, dW2, db2, dW3, db3])."""
         n = x_bf16.shape[0]
-        d0, d1, d2, d3 = self.dims
         logits = self.forward(x_bf16, stream=stream)
         h1, h2 = self._bufs["h1"], self._bufs["h2"]
-        W1, W2, W3 = self.w_bf16
-        g3 = self._buf("dlogits", (n, d3), torch.float32)
-        g3b = self._buf("dlogits_bf16", (n, d3), torch.int16)
         loss_rows = self._buf("loss", (n,), torch.float32)
-        _ok(lsp.lib().lsp_softmax_xent(_p(logits), _p(labels), n, d3, ctypes.c_float(1.0 / n),
-                                       _p(g3), _p(g3b), _p(loss_rows), _s(stream)),
-            "lsp_softmax_xent")
-        grads = [self._buf(f"grad{i}", tuple(p.shape), torch.float32)
-                 for i, p in enumerate(self.master)]
-        dW1, db1, dW2, db2, dW3, db3 = grads
-        # layer 3: dW3 = h2^T g3, db3 = sum g3, dz2 = (g3 W3^T) * (h2 > 0)
-        gemm(h2, g3b, d2, d3, n, 1, d2, d3, 1, C=dW3, stream=stream)
-        _ok(lsp.lib().lsp_col_sums(_p(g3), n, d3, _p(db3), _s(stream)), "lsp_col_sums")
-        dz2 = self._buf("dz2", (n, d2), torch.float32)
-        dz2b = self._buf("dz2b", (n, d2), torch.int16)
-        gemm(g3b, W3, n, d2, d3, d3, 1, 1, d3, C=dz2, C_bf16=dz2b, mask=h2, stream=stream)
-        # layer 2
-        gemm(h1, dz2b, d1, d2, n, 1, d1, d2, 1, C=dW2, stream=stream)
-        _ok(lsp.lib().lsp_col_sums(_p(dz2), n, d2, _p(db2), _s(stream)), "lsp_col_sums")
-        dz1 = self._buf("dz1", (n, d1), torch.float32)
-        dz1b = self._buf("dz1b", (n, d1), torch.int16)
-        gemm(dz2b, W2, n, d1, d2, d2, 1, 1, d2, C=dz1, C_bf16=dz1b, mask=h1, stream=stream)
-        # layer 1
-        gemm(x_bf16, dz1b, d0, d1, n, 1, d0, d1, 1, C=dW1, stream=stream)
-        _ok(lsp.lib().lsp_col_sums(_p(dz1), n, d1, _p(db1), _s(stream)), "lsp_col_sums")
-        return loss_rows, grads
+        nb = int(lsp.lib().lsp_mlp_workspace_bytes(ctypes.byref(self.c_net), n))
+        ws = self._buf("mlp_ws", (nb,), torch.uint8)
+        _ok(lsp.lib().lsp_mlp_backward(ctypes.byref(self.c_net), _p(x_bf16), _p(labels), n,
+                                       _p(h1), _p(h2), _p(logits), ctypes.c_float(1.0 / n),
+                                       ctypes.byref(self.c_grads), _p(loss_rows), _p(ws), nb,
+                                       _s(stream)), "lsp_mlp_backward")
+        return loss_rows, self.grads
+
+    def scratch_views(self, n):
+        """Named views of the last lsp_mlp_backward workspace for n rows, in
+        its documented layout: dlogits, dlogits_bf16, dz2, dz2b, dz1, dz1b."""
+        ws = self._bufs["mlp_ws"]
+        views, at = {}, 0
+        for name, low, c in (("dlogits", "dlogits_bf16", self.dims[3]),
+                             ("dz2", "dz2b", self.dims[2]), ("dz1", "dz1b", self.dims[1])):
+            views[name] = ws[at:at + n * c * 4].view(torch.float32).view(n, c)
+            at += -(-n * c * 4 // 256) * 256
+            views[low] = ws[at:at + n * c * 2].view(torch.int16).view(n, c)
+            at += -(-n * c * 2 // 256) * 256
+        return views
 
     def train_step(self, x_bf16, labels, lr=1e-3, stream=None):
-        loss_rows, grads = self.gradients(x_bf16, labels, stream=stream)
+        loss_rows, _ = self.gradients(x_bf16, labels, stream=stream)
         self.step += 1
-        for i, (p, g) in enumerate(zip(self.master, grads)):
-            wb = self.w_bf16[i // 2] if i % 2 == 0 else None
-            _ok(lsp.lib().lsp_adam(_p(p), _p(g), _p(self.m[i]), _p(self.v[i]), p.numel(),
-                                   self.step, ctypes.c_float(lr), ctypes.c_float(0.9),
-                                   ctypes.c_float(0.999), ctypes.c_float(1e-8), _p(wb),
-                                   _s(stream)), "lsp_adam")
+        _ok(lsp.lib().lsp_mlp_adam(ctypes.byref(self.c_net), ctypes.byref(self.c_grads),
+                                   ctypes.byref(self.c_m), ctypes.byref(self.c_v), self.step,
+                                   ctypes.c_float(lr), ctypes.c_float(0.9), ctypes.c_float(0.999),
+                                   ctypes.c_float(1e-8), _s(stream)), "lsp_mlp_adam")
         return loss_rows
 
     def params_numpy(self):

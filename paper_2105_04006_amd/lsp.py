@@ -59,6 +59,18 @@ class FeatureOptions(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class Mlp(ctypes.Structure):
+    """lsp_mlp: layer widths and device pointers to the FP32 weights, biases
+    and BF16 weight copies."""
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("w", ctypes.c_void_p * 3),
+                ("b", ctypes.c_void_p * 3), ("w_bf16", ctypes.c_void_p * 3)]
+
+
+class MlpGrads(ctypes.Structure):
+    """lsp_mlp_grads: device pointers shaped like lsp_mlp's w and b."""
+    _fields_ = [("w", ctypes.c_void_p * 3), ("b", ctypes.c_void_p * 3)]
+
+
 FEAT_COARSE, FEAT_POOL, FEAT_WINDOW = 1024, 8, 64
 FEAT_DIM = FEAT_COARSE + FEAT_WINDOW
 
@@ -162,6 +174,15 @@ def lib():
         L.lsp_cast_bf16.argtypes = [vp, i64, vp, vp]
         L.lsp_adam.restype = ctypes.c_int
         L.lsp_adam.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp, vp]
+        pm, pg = ctypes.POINTER(Mlp), ctypes.POINTER(MlpGrads)
+        L.lsp_mlp_forward.restype = ctypes.c_int
+        L.lsp_mlp_forward.argtypes = [pm, vp, i64, vp, vp, vp, vp]
+        L.lsp_mlp_workspace_bytes.restype = sz
+        L.lsp_mlp_workspace_bytes.argtypes = [pm, i64]
+        L.lsp_mlp_backward.restype = ctypes.c_int
+        L.lsp_mlp_backward.argtypes = [pm, vp, vp, i64, vp, vp, vp, f32, pg, vp, vp, sz, vp]
+        L.lsp_mlp_adam.restype = ctypes.c_int
+        L.lsp_mlp_adam.argtypes = [pm, pg, pg, pg, i32, f32, f32, f32, f32, vp]
         L.lsp_top_k.restype = ctypes.c_int
         L.lsp_top_k.argtypes = [vp, i64, i32, i32, vp, vp, vp]
         L.lsp_band_max.restype = ctypes.c_int

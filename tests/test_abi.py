@@ -506,3 +506,70 @@ def test_single_object_in_workgroup_split_keeps_no_partial_sums():
     split = lsp.describe_launch(1, 4096, g, opt_off)["t_split"]
     assert split > 1 and off - ws8 >= 16 * 500_000 * split
     assert ws8 < 4096  # metadata, one peak key, flags and queue counters only
+
+
+def test_mlp_structs_match_header(tmp_path):
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "mlp.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lsp.h"\nint main(void) {\n'
+                   '  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lsp_mlp), '
+                   'offsetof(lsp_mlp, w), offsetof(lsp_mlp, b), offsetof(lsp_mlp, w_bf16), '
+                   'sizeof(lsp_mlp_grads), offsetof(lsp_mlp_grads, w), '
+                   'offsetof(lsp_mlp_grads, b));\n  return 0;\n}\n')
+    exe = tmp_path / "mlp"
+    subprocess.run(["gcc", "-std=c11", "-I", str(lsp.HEADER.rsplit("/", 1)[0]), str(src), "-o",
+                    str(exe)], check=True)
+    out = [int(v) for v in
+           subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out == [ctypes.sizeof(lsp.Mlp), lsp.Mlp.w.offset, lsp.Mlp.b.offset,
+                   lsp.Mlp.w_bf16.offset, ctypes.sizeof(lsp.MlpGrads), lsp.MlpGrads.w.offset,
+                   lsp.MlpGrads.b.offset]
+
+
+def _fake_mlp(dims=(1088, 512, 256, 64)):
+    net = lsp.Mlp()
+    net.dims[:] = list(dims)
+    for l in range(3):
+        net.w[l] = net.b[l] = net.w_bf16[l] = FAKE.value
+    g = lsp.MlpGrads()
+    for l in range(3):
+        g.w[l] = g.b[l] = FAKE.value
+    return net, g
+
+
+@cpu_only
+def test_mlp_argument_errors(L):
+    f32, byref = ctypes.c_float, ctypes.byref
+    net, g = _fake_mlp()
+    fwd = L.lsp_mlp_forward
+    assert fwd(None, FAKE, 4, FAKE, FAKE, FAKE, None) == lsp.EINVAL
+    assert fwd(byref(net), FAKE, -1, FAKE, FAKE, FAKE, None) == lsp.EINVAL
+    assert fwd(byref(net), None, 4, FAKE, FAKE, FAKE, None) == lsp.EINVAL
+    assert fwd(byref(net), FAKE, 0, None, None, None, None) == lsp.OK  # nothing to do
+    bad, _ = _fake_mlp((1088, 0, 256, 64))
+    assert fwd(byref(bad), FAKE, 4, FAKE, FAKE, FAKE, None) == lsp.EINVAL
+    bad, _ = _fake_mlp()
+    bad.b[1] = None
+    assert fwd(byref(bad), FAKE, 4, FAKE, FAKE, FAKE, None) == lsp.EINVAL
+    # scratch: dlogits, dz2 and dz1 in FP32 and BF16, each 256-byte aligned
+    assert L.lsp_mlp_workspace_bytes(None, 4) == 0
+    assert L.lsp_mlp_workspace_bytes(byref(net), 0) == 0
+    want = sum(-(-4 * c * b // 256) * 256 for c in (64, 256, 512) for b in (4, 2))
+    nb = L.lsp_mlp_workspace_bytes(byref(net), 4)
+    assert nb == want
+    bwd = L.lsp_mlp_backward
+    args = (FAKE, FAKE, 4, FAKE, FAKE, FAKE, f32(0.25))
+    assert bwd(byref(net), FAKE, FAKE, 0, FAKE, FAKE, FAKE, f32(1), byref(g), None, FAKE, nb,
+               None) == lsp.EINVAL
+    assert bwd(byref(net), *args, None, None, FAKE, nb, None) == lsp.EINVAL
+    assert bwd(byref(net), *args, byref(g), None, FAKE, nb - 1, None) == lsp.ENOMEM
+    assert bwd(byref(net), *args, byref(g), None, None, nb, None) == lsp.EINVAL
+    adam = L.lsp_mlp_adam
+    hp = (f32(1e-3), f32(0.9), f32(0.999), f32(1e-8), None)
+    assert adam(byref(net), byref(g), byref(g), byref(g), 0, *hp) == lsp.EINVAL
+    assert adam(byref(net), byref(g), None, byref(g), 1, *hp) == lsp.EINVAL
+    bad_g = lsp.MlpGrads()
+    assert adam(byref(net), byref(bad_g), byref(g), byref(g), 1, *hp) == lsp.EINVAL

@@ -196,7 +196,8 @@ def test_training_step_matches_reference(dev):
     lab = torch.as_tensor(labels, device=dev)
     loss_rows, grads = net.gradients(xb, lab)
     torch.cuda.synchronize()
-    B = net._bufs
+    B = dict(net._bufs)
+    B.update(net.scratch_views(n))
     W1, W2, W3 = (bf16_of(w) for w in net.w_bf16)
     b1, b2, b3 = (net.master[i].double().cpu().numpy() for i in (1, 3, 5))
     a = np.abs
@@ -473,3 +474,72 @@ def test_trim_bands(dev):
             assert got[i][valid][0] == idx[i][valid][0]
             k = got[i, :n_net] >= 0
             assert not np.any(k[1:] & ~k[:-1]) or np.any(idx[i, :n_net] < 0)
+
+
+def test_network_entry_points_equal_their_primitives(dev):
+    """lsp_mlp_forward, lsp_mlp_backward and lsp_mlp_adam run the layer order
+    that the primitives express (three GEMMs with bias and ReLU; softmax
+    cross-entropy; per layer the weight GEMM, the bias column sums and the
+    masked back-propagating GEMM; one Adam step per parameter array): their
+    results are bitwise those of the same primitives called one by one."""
+    rng = np.random.default_rng(8)
+    n = 80
+    d0, d1, d2, d3 = mlp_ref.DIMS
+    params = mlp_ref.init_params(4)
+    for pp in params[1::2]:
+        pp += rng.normal(0, 0.05, size=pp.shape)
+    x = bits(mlp_ref.bf16_round(rng.normal(size=(n, d0))), dev)
+    labels = rng.integers(0, d3, size=n).astype(np.int32)
+    labels[3] = -1  # ignored row
+    lab = torch.as_tensor(labels, device=dev)
+    net = learned.BandNet(dev, params=params)
+    say("lsp_mlp_forward / backward / adam")
+    loss, grads = net.gradients(x, lab)
+    got_logits = net.forward(x).clone()
+    got = [g.clone() for g in grads]
+    got_loss = loss.clone()
+    net.train_step(x, lab, lr=1e-3)
+    torch.cuda.synchronize()
+    got_params = [q.clone() for q in net.master] + [w.clone() for w in net.w_bf16]
+
+    # the same step, primitive by primitive, on a fresh copy of the network
+    ref = learned.BandNet(dev, params=params)
+    L = lsp.lib()
+    W1, W2, W3 = ref.w_bf16
+    b1, b2, b3 = ref.master[1], ref.master[3], ref.master[5]
+    h1 = torch.empty((n, d1), dtype=torch.int16, device=dev)
+    h2 = torch.empty((n, d2), dtype=torch.int16, device=dev)
+    z = torch.empty((n, d3), dtype=torch.float32, device=dev)
+    learned.gemm(x, W1, n, d1, d0, d0, 1, d1, 1, C_bf16=h1, bias=b1, relu=True)
+    learned.gemm(h1, W2, n, d2, d1, d1, 1, d2, 1, C_bf16=h2, bias=b2, relu=True)
+    learned.gemm(h2, W3, n, d3, d2, d2, 1, d3, 1, C=z, bias=b3)
+    g3 = torch.empty((n, d3), dtype=torch.float32, device=dev)
+    g3b = torch.empty((n, d3), dtype=torch.int16, device=dev)
+    rows = torch.empty(n, dtype=torch.float32, device=dev)
+    assert L.lsp_softmax_xent(z.data_ptr(), lab.data_ptr(), n, d3, ctypes.c_float(1.0 / n),
+                              g3.data_ptr(), g3b.data_ptr(), rows.data_ptr(), None) == lsp.OK
+    g = [torch.empty_like(q) for q in ref.master]
+    learned.gemm(h2, g3b, d2, d3, n, 1, d2, d3, 1, C=g[4])
+    assert L.lsp_col_sums(g3.data_ptr(), n, d3, g[5].data_ptr(), None) == lsp.OK
+    dz2 = torch.empty((n, d2), dtype=torch.float32, device=dev)
+    dz2b = torch.empty((n, d2), dtype=torch.int16, device=dev)
+    learned.gemm(g3b, W3, n, d2, d3, d3, 1, 1, d3, C=dz2, C_bf16=dz2b, mask=h2)
+    learned.gemm(h1, dz2b, d1, d2, n, 1, d1, d2, 1, C=g[2])
+    assert L.lsp_col_sums(dz2.data_ptr(), n, d2, g[3].data_ptr(), None) == lsp.OK
+    dz1 = torch.empty((n, d1), dtype=torch.float32, device=dev)
+    dz1b = torch.empty((n, d1), dtype=torch.int16, device=dev)
+    learned.gemm(dz2b, W2, n, d1, d2, d2, 1, 1, d2, C=dz1, C_bf16=dz1b, mask=h1)
+    learned.gemm(x, dz1b, d0, d1, n, 1, d0, d1, 1, C=g[0])
+    assert L.lsp_col_sums(dz1.data_ptr(), n, d1, g[1].data_ptr(), None) == lsp.OK
+    for i, (q, gi) in enumerate(zip(ref.master, g)):
+        wb = ref.w_bf16[i // 2].data_ptr() if i % 2 == 0 else None
+        assert L.lsp_adam(q.data_ptr(), gi.data_ptr(), ref.m[i].data_ptr(), ref.v[i].data_ptr(),
+                          q.numel(), 1, ctypes.c_float(1e-3), ctypes.c_float(0.9),
+                          ctypes.c_float(0.999), ctypes.c_float(1e-8), wb, None) == lsp.OK
+    torch.cuda.synchronize()
+    assert torch.equal(got_logits, z)
+    assert torch.equal(got_loss, rows) and got_loss[3].item() == 0.0
+    for name, a, b in zip(["dW1", "db1", "dW2", "db2", "dW3", "db3"], got, g):
+        assert torch.equal(a, b), name
+    for a, b in zip(got_params, list(ref.master) + list(ref.w_bf16)):
+        assert torch.equal(a, b)
