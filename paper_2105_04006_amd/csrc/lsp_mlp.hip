@@ -24,7 +24,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 64, kBN = 64, kBK = 32;
+constexpr int kBK = 32;
 constexpr int kLdsK = kBK + 8;  // padded row: 80 bytes, keeps 16-byte fragment reads aligned
 constexpr int kGemmThreads = 256;
 
@@ -53,64 +53,100 @@ struct GemmArgs {
     float* Cf;             // FP32 output or NULL
     uint16_t* Cb;          // BF16 output or NULL
     int64_t ldc;
+    int32_t a_mode, b_mode;  // how each operand is staged: kLoad*
 };
 
+// How an operand tile is read from global memory: 8 consecutive k in one
+// 16-byte load, 8 consecutive rows (m of A, n of B) in one 16-byte load that
+// is transposed on its way into LDS, or element by element.
+enum { kLoadK = 0, kLoadRows = 1, kLoadScalar = 2 };
+
+// Stage rows [o0, o0 + BO) x k [k0, k0 + kBK) of an operand whose element
+// (o, k) is X[o * so + k * sk] into Xs[o][k] (k contiguous, padded rows);
+// outside the matrix the tile holds zeros.
+template <int BO>
+__device__ __forceinline__ void stage_operand(uint16_t* Xs, const uint16_t* X, int64_t so,
+                                              int64_t sk, int64_t O, int64_t K, int64_t o0,
+                                              int64_t k0, int mode, int tid) {
+    constexpr int kChunks = BO * (kBK / 8);  // 8 elements each
+#pragma unroll
+    for (int c0 = 0; c0 < kChunks; c0 += kGemmThreads) {
+        const int c = c0 + tid;
+        if (mode == kLoadRows) {
+            // 8 consecutive rows at one k
+            const int kk = c / (BO / 8), oc = (c % (BO / 8)) * 8;
+            const int64_t o = o0 + oc, k = k0 + kk;
+            uint16_t v[8];
+            if (o + 8 <= O && k < K) {
+                const uint4 q = *reinterpret_cast<const uint4*>(X + o + k * sk);
+                memcpy(v, &q, sizeof q);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (o + e < O && k < K) ? X[(o + e) + k * sk] : 0;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Xs[(oc + e) * kLdsK + kk] = v[e];
+        } else {
+            // 8 consecutive k of one row
+            const int oo = c / (kBK / 8), kc = (c % (kBK / 8)) * 8;
+            const int64_t o = o0 + oo, k = k0 + kc;
+            uint4 q;
+            if (mode == kLoadK && o < O && k + 8 <= K) {
+                q = *reinterpret_cast<const uint4*>(X + o * so + k);
+            } else {
+                uint16_t v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (o < O && k + e < K) ? X[o * so + (k + e) * sk] : 0;
+                memcpy(&q, v, sizeof q);
+            }
+            *reinterpret_cast<uint4*>(&Xs[oo * kLdsK + kc]) = q;
+        }
+    }
+}
+
+// C (BM x BN tile per workgroup) = A B on the matrix cores: four waves in a
+// 2 x 2 arrangement, each accumulating (BM / 2) x (BN / 2) from 16 x 16 x 32
+// BF16 products into FP32.
+template <int BM, int BN>
 __global__ __launch_bounds__(kGemmThreads) void gemm_bf16_kernel(const GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLdsK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLdsK];
+    constexpr int TI = BM / 32, TJ = BN / 32;  // 16 x 16 fragments per wave
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM * kLdsK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * kLdsK];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int64_t m0 = (int64_t)blockIdx.y * kBM, n0 = (int64_t)blockIdx.x * kBN;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
 
-    f32x4 acc[2][2];
+    f32x4 acc[TI][TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // staging assignment: thread -> (row of the tile, 8 consecutive k)
-    const int srow = tid >> 2, sk = (tid & 3) * 8;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int64_t k0 = 0; k0 < g.K; k0 += kBK) {
-        {
-            const int64_t m = m0 + srow;
-            uint16_t v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int64_t k = k0 + sk + e;
-                v[e] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) As[srow * kLdsK + sk + e] = v[e];
-            const int64_t n = n0 + srow;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int64_t k = k0 + sk + e;
-                v[e] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) Bs[srow * kLdsK + sk + e] = v[e];
-        }
+        stage_operand<BM>(As, g.A, g.sam, g.sak, g.M, g.K, m0, k0, g.a_mode, tid);
+        stage_operand<BN>(Bs, g.B, g.sbn, g.sbk, g.N, g.K, n0, k0, g.b_mode, tid);
         __syncthreads();
-        const int fr = lane & 15, fk = (lane >> 4) * 8;
+        bf16x8 a[TI], b[TJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 a =
-                *reinterpret_cast<const bf16x8*>(&As[(wm + 16 * i + fr) * kLdsK + fk]);
+        for (int i = 0; i < TI; ++i)
+            a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm + 16 * i + fr) * kLdsK + fk]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 b =
-                    *reinterpret_cast<const bf16x8*>(&Bs[(wn + 16 * j + fr) * kLdsK + fk]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
-            }
-        }
+        for (int j = 0; j < TJ; ++j)
+            b[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn + 16 * j + fr) * kLdsK + fk]);
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
 
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
@@ -526,8 +562,7 @@ lsp_status lsp_gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t
     if (M < 0 || N < 0 || K < 0 || (M > 0 && N > 0 && (!A || !B)) || (!C && !C_bf16) ||
         ldc < N || (relu != 0 && relu != 1))
         return LSP_EINVAL;
-    if ((M + lsp::kBM - 1) / lsp::kBM > 65535 || (N + lsp::kBN - 1) / lsp::kBN > 65535)
-        return LSP_EUNSUPPORTED;
+    if ((M + 63) / 64 > 65535 || (N + 63) / 64 > 65535) return LSP_EUNSUPPORTED;
     if (M == 0 || N == 0) return LSP_OK;
     lsp::GemmArgs g;
     g.M = M;
@@ -546,10 +581,27 @@ lsp_status lsp_gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t
     g.Cf = C;
     g.Cb = static_cast<uint16_t*>(C_bf16);
     g.ldc = ldc;
-    const dim3 grid((unsigned)((N + lsp::kBN - 1) / lsp::kBN),
-                    (unsigned)((M + lsp::kBM - 1) / lsp::kBM));
-    hipLaunchKernelGGL(lsp::gemm_bf16_kernel, grid, dim3(lsp::kGemmThreads), 0,
-                       static_cast<hipStream_t>(stream), g);
+    // 16-byte loads where an operand's k (or its rows) are contiguous and
+    // every 8-element chunk the tiles read starts on a 16-byte boundary
+    auto mode = [](const void* X, int64_t so, int64_t sk) {
+        const bool aligned = (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+        if (aligned && sk == 1 && so % 8 == 0) return (int32_t)lsp::kLoadK;
+        if (aligned && so == 1 && sk % 8 == 0) return (int32_t)lsp::kLoadRows;
+        return (int32_t)lsp::kLoadScalar;
+    };
+    g.a_mode = mode(A, sam, sak);
+    g.b_mode = mode(B, sbn, sbk);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // 128 x 128 tiles where they still give a few hundred workgroups, else 64 x 64
+    if (M >= 128 && N >= 128 && ((M + 127) / 128) * ((N + 127) / 128) >= 256) {
+        const dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
+        hipLaunchKernelGGL((lsp::gemm_bf16_kernel<128, 128>), grid, dim3(lsp::kGemmThreads), 0,
+                           s, g);
+    } else {
+        const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+        hipLaunchKernelGGL((lsp::gemm_bf16_kernel<64, 64>), grid, dim3(lsp::kGemmThreads), 0, s,
+                           g);
+    }
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
 
