@@ -447,3 +447,30 @@ def test_single_wide_grid_statuses(dev):
     ora = oracle.eval_bins(np.array([0, len(t)], dtype=np.int64), t, y, 0.5, 24.0, n_f,
                            np.zeros(len(bins), np.int64), bins)
     assert_fp32_close(pg[bins], ora, "eight-wave single object, sampled bins")
+
+
+def test_single_wide_grid_fixup_tiles(dev):
+    """Evenly sampled 4,096-point object on [0, 2) c/d with 5e5 bins, run by
+    the single-object default of eight waves sharing each 1,024-bin tile: f = 0
+    and 1 (every phase an integer) and the Nyquist frequency 0.5 and 1.5 make
+    a shifted regressor vanish, so the tiles holding those bins must be the
+    ones the FP64 fix-up recomputes.  Those tiles match the FP64 form to its
+    bound plus half an FP32 ulp (the fix-up stores FP32); every bin is within
+    the FP32 bound of it."""
+    rng = np.random.default_rng(13)
+    n, n_f = 4096, 500_000
+    t = np.arange(n, dtype=np.float64)
+    y = rng.normal(size=n)
+    d = lsp.describe_launch(1, n, lsp.make_grid(0.0, 2.0, n_f),
+                            lsp.make_options(form=lsp.FORM_FP32P))
+    assert (d["waves_per_wg"], d["wave_split"], d["tile_freqs"]) == (8, lsp.WSPLIT_ON, 1024)
+    pg64, _ = run_single(dev, t, y, 0.0, 2.0, n_f, form=lsp.FORM_FP64, pgram_dtype=lsp.PGRAM_F64)
+    pg32, _ = run_single(dev, t, y, 0.0, 2.0, n_f, form=lsp.FORM_FP32P, pgram_dtype=lsp.PGRAM_F64)
+    assert_fp32_close(pg32, pg64, "even sampling, wide grid")
+    ill = np.array([0, n_f // 4, n_f // 2, 3 * n_f // 4])  # f = 0, 0.5, 1, 1.5
+    for i in ill:
+        lo = (i // 1024) * 1024
+        a, b = pg32[lo:lo + 1024], pg64[lo:lo + 1024]
+        bound = 2.0 * FP64_RTOL * np.maximum(b, FP64_FLOOR) + 2.0 ** -24 * b
+        assert np.all(np.abs(a - b) <= bound), f"tile of bin {i} not recomputed in FP64"
+    assert pg32[0] < 1e-12 and pg64[0] < 1e-12
