@@ -573,3 +573,25 @@ def test_mlp_argument_errors(L):
     assert adam(byref(net), byref(g), None, byref(g), 1, *hp) == lsp.EINVAL
     bad_g = lsp.MlpGrads()
     assert adam(byref(net), byref(bad_g), byref(g), byref(g), 1, *hp) == lsp.EINVAL
+
+
+def test_single_object_launch_rule_thresholds():
+    """The eight-wave in-workgroup split is chosen exactly when its 1,024-bin
+    tiles (K = 16) give at least 3,584 waves and the object has at least
+    2,048 observations."""
+    opt = lsp.make_options(form=lsp.FORM_FP32P)
+    cases = [(448 * 1024, 4096, True), (447 * 1024, 4096, False),
+             (500_000, 2048, True), (500_000, 2047, False)]
+    for n_f, n_obs, ws8 in cases:
+        d = lsp.describe_launch(1, n_obs, lsp.make_grid(0.5, 24.0, n_f), opt)
+        assert d["k_per_lane"] == 16
+        got = (d["waves_per_wg"], d["wave_split"]) == (8, lsp.WSPLIT_ON) and d["t_split"] == 1
+        assert got == ws8, (n_f, n_obs, d)
+        if not ws8:
+            assert d["waves_per_wg"] == 4 and d["wave_split"] == lsp.WSPLIT_OFF
+    # batches, row mode and explicit shapes never get it by default
+    many = lsp.describe_launch(2, 8192, lsp.make_grid(0.5, 24.0, 500_000), opt)
+    assert many["wave_split"] == lsp.WSPLIT_OFF
+    fixed = lsp.describe_launch(1, 4096, lsp.make_grid(0.5, 24.0, 500_000),
+                                lsp.make_options(form=lsp.FORM_FP32P, waves=4))
+    assert fixed["waves_per_wg"] == 4 and fixed["wave_split"] == lsp.WSPLIT_OFF
