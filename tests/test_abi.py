@@ -595,3 +595,17 @@ def test_single_object_launch_rule_thresholds():
     fixed = lsp.describe_launch(1, 4096, lsp.make_grid(0.5, 24.0, 500_000),
                                 lsp.make_options(form=lsp.FORM_FP32P, waves=4))
     assert fixed["waves_per_wg"] == 4 and fixed["wave_split"] == lsp.WSPLIT_OFF
+
+
+def test_generalized_single_object_split_fills_resident_slots():
+    """The generalized kernel holds three waves per SIMD from K = 12 and four
+    below: a single object's observation split fills those 3,072 or 4,096
+    resident wave slots once."""
+    g = lsp.make_grid(0.5, 24.0, 500_000)
+    d = lsp.describe_launch(1, 4096, g, lsp.make_options(form=lsp.FORM_FP32P), generalized=True)
+    waves = -(-500_000 // d["tile_freqs"]) * d["waves_per_wg"]
+    assert d["k_per_lane"] == 16 and d["t_split"] == 3072 // waves == 6
+    d8 = lsp.describe_launch(1, 4096, g, lsp.make_options(form=lsp.FORM_FP32P, k=8),
+                             generalized=True)
+    waves8 = -(-500_000 // d8["tile_freqs"]) * d8["waves_per_wg"]
+    assert d8["t_split"] == 4096 // waves8 == 4
