@@ -26,7 +26,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBK = 32;
 constexpr int kLdsK = kBK + 8;  // padded row: 80 bytes, keeps 16-byte fragment reads aligned
-constexpr int kGemmThreads = 256;
+constexpr int kGemmThreads = 256;  // the 64 x 64 tile's four waves
 
 __host__ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
     uint32_t u;
@@ -64,13 +64,13 @@ enum { kLoadK = 0, kLoadRows = 1, kLoadScalar = 2 };
 // Stage rows [o0, o0 + BO) x k [k0, k0 + kBK) of an operand whose element
 // (o, k) is X[o * so + k * sk] into Xs[o][k] (k contiguous, padded rows);
 // outside the matrix the tile holds zeros.
-template <int BO>
+template <int BO, int NT>
 __device__ __forceinline__ void stage_operand(uint16_t* Xs, const uint16_t* X, int64_t so,
                                               int64_t sk, int64_t O, int64_t K, int64_t o0,
                                               int64_t k0, int mode, int tid) {
     constexpr int kChunks = BO * (kBK / 8);  // 8 elements each
 #pragma unroll
-    for (int c0 = 0; c0 < kChunks; c0 += kGemmThreads) {
+    for (int c0 = 0; c0 < kChunks; c0 += NT) {
         const int c = c0 + tid;
         if (mode == kLoadRows) {
             // 8 consecutive rows at one k
@@ -104,18 +104,19 @@ __device__ __forceinline__ void stage_operand(uint16_t* Xs, const uint16_t* X, i
     }
 }
 
-// C (BM x BN tile per workgroup) = A B on the matrix cores: four waves in a
-// 2 x 2 arrangement, each accumulating (BM / 2) x (BN / 2) from 16 x 16 x 32
-// BF16 products into FP32.
-template <int BM, int BN>
-__global__ __launch_bounds__(kGemmThreads) void gemm_bf16_kernel(const GemmArgs g) {
-    constexpr int TI = BM / 32, TJ = BN / 32;  // 16 x 16 fragments per wave
+// C (BM x BN tile per workgroup) = A B on the matrix cores: WM x WN waves,
+// each accumulating (BM / WM) x (BN / WN) from 16 x 16 x 32 BF16 products
+// into FP32.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_bf16_kernel(const GemmArgs g) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr int TI = BM / WM / 16, TJ = BN / WN / 16;  // 16 x 16 fragments per wave
     __shared__ __attribute__((aligned(16))) uint16_t As[BM * kLdsK];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * kLdsK];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
-    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int wm = (wave / WN) * (BM / WM), wn = (wave % WN) * (BN / WN);
 
     f32x4 acc[TI][TJ];
 #pragma unroll
@@ -125,8 +126,8 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16_kernel(const GemmArgs 
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int64_t k0 = 0; k0 < g.K; k0 += kBK) {
-        stage_operand<BM>(As, g.A, g.sam, g.sak, g.M, g.K, m0, k0, g.a_mode, tid);
-        stage_operand<BN>(Bs, g.B, g.sbn, g.sbk, g.N, g.K, n0, k0, g.b_mode, tid);
+        stage_operand<BM, NT>(As, g.A, g.sam, g.sak, g.M, g.K, m0, k0, g.a_mode, tid);
+        stage_operand<BN, NT>(Bs, g.B, g.sbn, g.sbk, g.N, g.K, n0, k0, g.b_mode, tid);
         __syncthreads();
         bf16x8 a[TI], b[TJ];
 #pragma unroll
@@ -592,15 +593,15 @@ lsp_status lsp_gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t
     g.a_mode = mode(A, sam, sak);
     g.b_mode = mode(B, sbn, sbk);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    // 128 x 128 tiles where they still give a few hundred workgroups, else 64 x 64
+    // 128 x 128 tiles (eight waves of 64 x 32) where they still give a few
+    // hundred workgroups, else 64 x 64 (four waves of 32 x 32)
     if (M >= 128 && N >= 128 && ((M + 127) / 128) * ((N + 127) / 128) >= 256) {
         const dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
-        hipLaunchKernelGGL((lsp::gemm_bf16_kernel<128, 128>), grid, dim3(lsp::kGemmThreads), 0,
-                           s, g);
+        hipLaunchKernelGGL((lsp::gemm_bf16_kernel<128, 128, 2, 4>), grid, dim3(512), 0, s, g);
     } else {
         const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-        hipLaunchKernelGGL((lsp::gemm_bf16_kernel<64, 64>), grid, dim3(lsp::kGemmThreads), 0, s,
-                           g);
+        hipLaunchKernelGGL((lsp::gemm_bf16_kernel<64, 64, 2, 2>), grid, dim3(lsp::kGemmThreads), 0,
+                           s, g);
     }
     return hipGetLastError() == hipSuccess ? LSP_OK : LSP_EHIP;
 }
