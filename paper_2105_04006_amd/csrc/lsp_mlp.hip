@@ -82,7 +82,8 @@ __device__ __forceinline__ void stage_operand(uint16_t* Xs, const uint16_t* X, i
                 memcpy(v, &q, sizeof q);
             } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = (o + e < O && k < K) ? X[(o + e) + k * sk] : 0;
+                for (int e = 0; e < 8; ++e)
+                    v[e] = (o + e < O && k < K) ? X[(o + e) + k * sk] : 0;
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e) Xs[(oc + e) * kLdsK + kk] = v[e];
@@ -96,7 +97,8 @@ __device__ __forceinline__ void stage_operand(uint16_t* Xs, const uint16_t* X, i
             } else {
                 uint16_t v[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = (o < O && k + e < K) ? X[o * so + (k + e) * sk] : 0;
+                for (int e = 0; e < 8; ++e)
+                    v[e] = (o < O && k + e < K) ? X[o * so + (k + e) * sk] : 0;
                 memcpy(&q, v, sizeof q);
             }
             *reinterpret_cast<uint4*>(&Xs[oo * kLdsK + kc]) = q;
