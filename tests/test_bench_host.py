@@ -60,3 +60,28 @@ def test_instruction_models():
     assert abs(bench.valu_ops_per_eval_gen(16) - 140 / 16) < 1e-12
     assert bench.FLOPS_PER_EVAL["chebyshev"] == 12 and bench.FLOPS_PER_EVAL_GEN == 16
     assert abs(bench.PEAK_FP32_TFLOPS - 157.3) < 0.1
+
+
+def test_committed_traffic_records_are_consistent():
+    """Each committed counter record's bytes follow from its KiB counters and
+    copy-calibration scales, and its commands name its kernel and workload."""
+    import glob
+    import os
+    files = sorted(glob.glob(os.path.join(bench.ROOT, "profiles", "*_traffic.json")))
+    assert len(files) >= 4
+    for path in files:
+        rec = json.load(open(path))
+        for side in ("fetch", "write"):
+            got = rec[f"{side}_bytes_per_launch"]
+            want = rec[f"{side}_size_kib"] * 1024 * rec[f"{side}_scale"]
+            assert abs(got - want) <= 2e-3 * want + 1024, (path, side)
+        assert rec["bytes_per_launch"] == rec["fetch_bytes_per_launch"] + \
+            rec["write_bytes_per_launch"]
+        assert 1.99 < rec["fetch_scale"] < 2.01 and 0.99 < rec["write_scale"] < 1.01
+        assert len(rec["kernel_hash"]) == 16
+        kernel = rec["kernel"].split("<")[0]
+        assert kernel in ("fp32p_kernel", "gen_fp32p_kernel")
+        runs = [c for c in rec["commands"] if "--mode copy" not in c]
+        assert runs and all(kernel in c for c in runs), path
+        if rec["workload_name"] != "lsst_200k":  # the bench's default workload
+            assert all(f"--workload {rec['workload_name']}" in c for c in runs), path
