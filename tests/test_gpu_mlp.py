@@ -543,3 +543,36 @@ def test_network_entry_points_equal_their_primitives(dev):
         assert torch.equal(a, b), name
     for a, b in zip(got_params, list(ref.master) + list(ref.w_bf16)):
         assert torch.equal(a, b)
+
+
+def test_gemm_large_tiles_all_load_modes(dev):
+    """A product large enough for the 128 x 128 tiles (>= 256 workgroups),
+    with ragged M, N and a K that is no multiple of the 32-deep k tile, read
+    with 16-byte loads along k, with 16-byte loads along the rows transposed
+    into LDS, and element by element (leading dimensions that are not
+    multiples of 8): each within gamma(K) sum |a||b| of the FP64 product."""
+    rng = np.random.default_rng(17)
+    M, N, K = 6600, 520, 1000
+    assert -(-M // 128) * -(-N // 128) >= 256
+    A = mlp_ref.bf16_round(rng.normal(size=(M, K)))
+    B = mlp_ref.bf16_round(rng.normal(size=(K, N)))
+    ref = A @ B
+    tol = gamma(K) * (np.abs(A) @ np.abs(B))
+    C = torch.empty((M, N), dtype=torch.float32, device=dev)
+    say("gemm 128x128 tiles: k-contiguous A, row-contiguous B")
+    learned.gemm(bits(A, dev), bits(B, dev), M, N, K, K, 1, N, 1, C=C)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= tol)
+    say("gemm 128x128 tiles: row-contiguous A, k-contiguous B")
+    At, Bt = bits(np.ascontiguousarray(A.T), dev), bits(np.ascontiguousarray(B.T), dev)
+    learned.gemm(At, Bt, M, N, K, 1, M, 1, K, C=C)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= tol)
+    say("gemm 128x128 tiles: leading dimensions not multiples of 8")
+    Ap = np.zeros((M, K + 3))
+    Ap[:, :K] = A
+    Bp = np.zeros((K, N + 5))
+    Bp[:, :N] = B
+    learned.gemm(bits(Ap, dev), bits(Bp, dev), M, N, K, K + 3, 1, N + 5, 1, C=C)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= tol)
